@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""AD-LBR hot-path benchmark on one MI355X.
+
+Default workload: coherence-enhancing diffusion on a 2048x2048 FP32 image
+(synthetic oriented stripes with noise and interrupted lines).  Every 10
+explicit steps the diffusion tensor is recomputed from the structure tensor
+of u (sigma = 1, rho = 4, alpha = 1e-4, C = 1e-5), the AD-LBR stencils are
+rebuilt and the operator re-assembled; 1000 explicit steps in all.
+
+One benchmark "step" is one such period: structure tensor -> stencils ->
+operator assembly -> 10 explicit Euler steps at 0.9 x the CFL bound.  The
+value is whole-job throughput in Mpoint-steps/s (grid points x explicit
+steps / wall time), inputs resident in HBM before the timed region.
+
+Other workloads (--workload): "c3" is the 256^3 3D field stepped in FP32
+without rebuilds (kappa <= 50), "c1" the 64^2 FP64 run.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# algorithmic bytes per point-step of the step kernel: u in + u out +
+# S weights + compact slots (2D: 4 int8, 3D: 12 bytes)
+ALGO_BYTES = {(2, 8): 16 + 3 * 8 + 4, (2, 4): 8 + 3 * 4 + 4, (2, 2): 4 + 3 * 2 + 4,
+              (3, 8): 16 + 6 * 8 + 12, (3, 4): 8 + 6 * 4 + 12, (3, 2): 4 + 6 * 2 + 12}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--dtype", default=None, help="storage dtype for c3: f64|f32|bf16|f16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline_c2(u0_np, n_full):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload:
+    one rebuild period on the 1024x1024 centre crop."""
+    import numpy as np
+    import oracle
+    m = 1024
+    img = u0_np.reshape(n_full, n_full)
+    o = (n_full - m) // 2
+    crop = np.ascontiguousarray(img[o:o + m, o:o + m]).reshape(-1).astype(np.float64)
+    t0 = time.perf_counter()
+    D = oracle.structure_tensor_d(crop, (m, m), 1.0, 4.0, 1e-4, 1e-5)
+    off, w, _ = oracle.stencil2d(D)
+    A = oracle.operator_matrix((m, m), off, w)
+    dt = 0.9 * oracle.cfl(A)
+    oracle.explicit_steps(A, crop, dt, 10)
+    t = time.perf_counter() - t0
+    return {"value": m * m * 10 / t / 1e6, "unit": "Mpoint-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "one rebuild period (structure tensor, stencils, assembly, 10 explicit "
+                      "steps) on the 1024x1024 centre crop, FP64, single thread",
+            "seconds": round(t, 3)}
+
+
+def cpu_baseline_steps(dims, D_np, u0_np, nsteps):
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    off, w, _ = oracle.stencil(D_np)
+    A = oracle.operator_matrix(dims, off, w)
+    oracle.explicit_steps(A, u0_np.astype(np.float64), 0.9 * oracle.cfl(A), nsteps)
+    t = time.perf_counter() - t0
+    n = int(np.prod(dims))
+    return {"value": n * nsteps / t / 1e6, "unit": "Mpoint-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"stencils + assembly + {nsteps} explicit steps on {'x'.join(map(str, dims))}"
+                      ", FP64, single thread", "seconds": round(t, 3)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "decomposition is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_1301_3925_amd as adlbr
+    from paper_1301_3925_amd import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    if args.workload == "c2":
+        n = 2048
+        dims = (n, n)
+        N = n * n
+        K = args.steps if args.steps is not None else 100
+        sub = 10
+        u0 = synth.ced_image2d(1302, n, n)
+        u = torch.from_numpy(u0).float().to(dev)
+        tmp = torch.empty_like(u)
+        Dbuf = torch.empty((3, N), dtype=torch.float32, device=dev)
+        tws = torch.empty(1, dtype=torch.uint8, device=dev)
+        outs = (torch.empty((3, 2, N), dtype=torch.int16, device=dev),
+                torch.empty((3, N), dtype=torch.float32, device=dev),
+                torch.empty(2, dtype=torch.int32, device=dev))
+        opws = [None]
+        # size the workspaces once
+        nb = adlbr.capi.Grid()
+        import ctypes
+        sz = ctypes.c_size_t()
+        g = adlbr.grid(dims)
+        adlbr.capi.check(adlbr.capi.load().adlbr_tensor_workspace(ctypes.byref(g), adlbr.capi.F32,
+                                                                  ctypes.byref(sz)))
+        tws = torch.empty(sz.value, dtype=torch.uint8, device=dev)
+        adlbr.capi.check(adlbr.capi.load().adlbr_operator_workspace(
+            ctypes.byref(g), adlbr.capi.F32, 0, ctypes.byref(sz)))
+        opws = torch.empty(sz.value, dtype=torch.uint8, device=dev)
+        ev = []
+
+        def period(record):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if record else None
+            if record:
+                e[0].record(stream)
+            adlbr.structure_tensor(u, dims, 1.0, 4.0, 1e-4, 1e-5, out=Dbuf, workspace=tws)
+            if record:
+                e[1].record(stream)
+            off, w, st = adlbr.build_stencils(Dbuf, dims, out=outs)
+            if record:
+                e[2].record(stream)
+            op = adlbr.Operator(dims, off, w, storage=torch.float32, workspace=opws)
+            if record:
+                e[3].record(stream)
+            op.step(u, 0.9, sub, cfl_fraction=True, u_tmp=tmp)
+            if record:
+                e[4].record(stream)
+                ev.append(e)
+            return op
+
+        for _ in range(args.warmup):
+            period(False)
+        u.copy_(torch.from_numpy(u0).float().to(dev))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            op = period(True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = outs[2].cpu().numpy()
+        ost = op.status.cpu().numpy()
+        if st[0] != -1 or ost[0] != -1:
+            print(f"status error: stencils {st.tolist()} operator {ost.tolist()}", file=sys.stderr)
+            sys.exit(1)
+        phase = np.zeros(4)
+        for e in ev:
+            for k in range(4):
+                phase[k] += e[k].elapsed_time(e[k + 1])
+        phase /= K
+        step_kernel_s = phase[3] / 1e3 / sub
+        abytes = ALGO_BYTES[(2, 4)] * N
+        achieved = abytes / step_kernel_s / 1e9
+        value = N * sub * K / wall / 1e6
+        res = {
+            "metric": "Mpoint-steps/s", "value": round(value, 2), "unit": "Mpoint-steps/s",
+            "n_gpus": 1, "steps": K, "warmup": args.warmup,
+            "ms_per_step": round(wall / K * 1e3, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "ced2d-2048x2048-f32", "n": [n, n], "explicit_steps": K * sub,
+                       "rebuild_every": sub, "sigma": 1.0, "rho": 4.0, "alpha": 1e-4,
+                       "C": 1e-5, "dt": "0.9/max A_zz", "seed": 1302},
+            "phases_ms_per_period": {"structure_tensor": round(phase[0], 4),
+                                     "stencils": round(phase[1], 4),
+                                     "assembly": round(phase[2], 4),
+                                     "explicit_steps_x10": round(phase[3], 4)},
+            "roofline": {"bound": "hbm", "kernel": "k_apply (explicit step, 2D FP32)",
+                         "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                         "algo_bytes_per_point": ALGO_BYTES[(2, 4)],
+                         "avg_launch_us": round(step_kernel_s * 1e6, 3)},
+        }
+        if not args.no_cpu_baseline:
+            res["cpu_baseline"] = cpu_baseline_c2(u0, n)
+        print(json.dumps(res), flush=True)
+        return
+
+    # c1 / c3: fixed operator, explicit steps only
+    if args.workload == "c1":
+        dims, kappa, seed, sdt = (64, 64), 10.0, 1301, args.dtype or "f64"
+        D = synth.tensor2d_field(seed, 64, 64, kappa)
+        K = args.steps if args.steps is not None else 100
+    else:
+        dims, kappa, seed, sdt = (256, 256, 256), 50.0, 1303, args.dtype or "f32"
+        D = synth.tensor3d_field(seed, dims, kappa)
+        K = args.steps if args.steps is not None else 200
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
+           "f16": torch.float16}[sdt]
+    N = int(np.prod(dims))
+    dim = len(dims)
+    Dg = torch.from_numpy(D).to(dev)
+    off, w, st = adlbr.build_stencils(Dg, dims)
+    op = adlbr.Operator(dims, off, w, storage=tdt)
+    u0 = synth.uniform(seed + 1, N)
+    u = torch.from_numpy(u0).to(tdt).to(dev)
+    tmp = torch.empty_like(u)
+    for _ in range(args.warmup):
+        op.step(u, 0.9, 1, cfl_fraction=True, u_tmp=tmp)
+    u.copy_(torch.from_numpy(u0).to(tdt).to(dev))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    op.step(u, 0.9, K, cfl_fraction=True, u_tmp=tmp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_s = e0.elapsed_time(e1) / 1e3 / K
+    esz = torch.tensor([], dtype=tdt).element_size()
+    abytes = ALGO_BYTES[(dim, esz)] * N
+    achieved = abytes / step_s / 1e9
+    res = {
+        "metric": "Mpoint-steps/s", "value": round(N * K / wall / 1e6, 2),
+        "unit": "Mpoint-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(wall / K * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": sdt, "data": "synthetic",
+        "config": {"workload": ("explicit2d-64x64" if dim == 2 else "explicit3d-256^3") + "-" + sdt,
+                   "n": list(dims), "kappa": kappa, "explicit_steps": K, "seed": seed},
+        "roofline": {"bound": "hbm", "kernel": f"k_apply (explicit step, {dim}D {sdt})",
+                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "algo_bytes_per_point": ALGO_BYTES[(dim, esz)],
+                     "avg_launch_us": round(step_s * 1e6, 3)},
+    }
+    if not args.no_cpu_baseline:
+        if dim == 2:
+            res["cpu_baseline"] = cpu_baseline_steps(dims, D, u0, K)
+        else:
+            m = 64
+            Ds = synth.tensor3d_field(seed, (m, m, m), kappa)
+            res["cpu_baseline"] = cpu_baseline_steps((m, m, m), Ds, synth.uniform(seed + 1, m ** 3), 10)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

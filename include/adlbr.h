@@ -1,0 +1,201 @@
+/*
+ * adlbr.h -- C ABI of the MI355X AD-LBR library (libadlbr.so).
+ *
+ * AD-LBR (Fehrenbach & Mirebeau, "Sparse non-negative stencils for
+ * anisotropic diffusion") discretizes the energy E(u) = int |grad u|_D^2
+ * (Section 1) on a Cartesian grid with, at every point z, a symmetric stencil
+ * V(z) of at most 6 (2D) or 12 (3D) integer offsets and non-negative weights
+ * gamma_z (eq. (def:E*)).  This library builds those stencils on the GPU,
+ * assembles the operator A = 1/2 grad E_h for a gather-based apply, steps
+ * du/dt = -A u explicitly, computes solution-dependent tensors from the
+ * structure tensor, and solves (I + dt A) x = b.
+ *
+ * Conventions shared by every entry point
+ *  - Grids: n[0] is x (fastest), then y, then z; point index
+ *    z = x + n0*(y + n1*z).  Grid spacing h = 1 (a caller with h != 1 scales
+ *    dt by h^-2).  N = n0*n1[*n2] must be < 2^28.
+ *  - Tensor fields are structure-of-arrays planes: 2D (Dxx, Dxy, Dyy) as
+ *    [3][N]; 3D (Dxx, Dxy, Dxz, Dyy, Dyz, Dzz) as [6][N].
+ *  - Stencils are exported as K/2 representative offsets ("slots") per point
+ *    (K/2 = 3 in 2D, 6 in 3D); V(z) is {+o, -o : o a slot} and gamma(+-o) is
+ *    the slot's weight.  offsets: int16 [K/2][d][N]; weights: [K/2][N].
+ *  - Every pointer argument named as device memory must point to GPU memory
+ *    of the current HIP device; host pointers are marked "host".  The caller
+ *    owns all memory.  The library never allocates device memory: calls that
+ *    need scratch take a caller-allocated workspace whose size a *_workspace
+ *    query returns.  Opaque plan objects (adlbr_operator) live in host
+ *    memory and hold only pointers into the caller's workspace.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *    asynchronous on `stream` unless they return a value through a host
+ *    pointer, which synchronizes `stream`.
+ *  - Return value: ADLBR_OK (0) or a negative ADLBR_E_* code; the message of
+ *    the last failing call on the calling thread is adlbr_last_error().  No
+ *    C++ exception crosses this boundary.  Data-dependent problems detected
+ *    on the device (a tensor that is not SPD, an offset out of range) are
+ *    reported through a caller-provided device status word instead, so that
+ *    no call has to synchronize.
+ *  - Device status words (int32[2], device): [0] = smallest offending point
+ *    index or -1, [1] = OR of ADLBR_ST_* flags.  Each call that takes one
+ *    resets it first.
+ */
+#ifndef ADLBR_H
+#define ADLBR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define ADLBR_OK               0
+#define ADLBR_E_INVALID       (-1) /* bad argument (null pointer, size, dtype) */
+#define ADLBR_E_NOT_SPD       (-2) /* reserved for host-side checks          */
+#define ADLBR_E_RANGE         (-3) /* size outside the supported range       */
+#define ADLBR_E_NOMEM         (-4) /* workspace smaller than required        */
+#define ADLBR_E_HIP           (-5) /* a HIP runtime call failed              */
+#define ADLBR_E_NOT_CONVERGED (-6) /* solver hit max_iter                    */
+#define ADLBR_E_UNSUPPORTED   (-7) /* combination not implemented            */
+
+/* device status flags */
+#define ADLBR_ST_NOT_SPD   1  /* tensor not symmetric positive definite or not finite */
+#define ADLBR_ST_RANGE     2  /* an offset does not fit the storage format           */
+#define ADLBR_ST_ITER      4  /* reduction iteration cap reached                     */
+#define ADLBR_ST_CLAMPED   8  /* a weight rounded below 0 was clamped to 0 (benign)  */
+#define ADLBR_ST_STENCIL  16  /* slots are not built from a superbase                */
+#define ADLBR_ST_INCOMING 32  /* more than 255 stencils reach one point              */
+
+typedef enum { ADLBR_F64 = 0, ADLBR_F32 = 1, ADLBR_BF16 = 2, ADLBR_F16 = 3 } adlbr_dtype;
+typedef enum { ADLBR_NEUMANN = 0, ADLBR_PERIODIC = 1 } adlbr_boundary;
+
+typedef struct adlbr_grid {
+    int32_t dim;      /* 2 or 3 */
+    int32_t boundary; /* adlbr_boundary */
+    int64_t n[3];     /* n[2] ignored in 2D */
+} adlbr_grid;
+
+typedef struct adlbr_operator adlbr_operator;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *adlbr_last_error(void);
+
+/* ABI version (major*100 + minor). */
+int adlbr_version(void);
+
+/* ------------------------------------------------------------------ *
+ * Stencil construction (Section 2).
+ * 2D: Lagrange's reduction (eq. (GaussAlgo)) of Z^2 for the metric
+ * M ~ adj(D) starting from the canonical basis; flip f when <e, M f> > 0
+ * (Corollary 2); superbase (e, f, g = -e-f); weights
+ * gamma(+-e_i) = -1/2 <e_{i+1}^perp, D e_{i+2}^perp> (Lemma 1, eq.
+ * (def:GammaZ)).  Slots are exported in the order (e, f, g).
+ * 3D: greedy D-reduced basis (Definition 2), Proposition (MakeObtuse),
+ * then Selling's decomposition: for pairs (i,j) in the order (0,1), (0,2),
+ * (0,3), (1,2), (1,3), (2,3), slot c_ij = e_k x e_l ({k<l} the complement)
+ * with weight -1/2 <e_i, D e_j>.
+ * All decisions are taken in FP64; offsets are exact integers.
+ *
+ *   D        device, [3|6][N] of D_dtype (ADLBR_F64 or ADLBR_F32)
+ *   offsets  device out, int16 [K/2][d][N]
+ *   weights  device out, [K/2][N] of w_dtype (ADLBR_F64 or ADLBR_F32)
+ *   status   device out, int32[2]; flags NOT_SPD, RANGE, ITER (the point's
+ *            slots and weights are then written as 0), CLAMPED.
+ * Errors: ADLBR_E_INVALID for null pointers, dim not 2/3, N out of range
+ * or an unsupported dtype.
+ * ------------------------------------------------------------------ */
+int adlbr_build_stencils(const adlbr_grid *g, const void *D, int D_dtype,
+                         int16_t *offsets, void *weights, int w_dtype,
+                         int32_t *status, void *stream);
+
+/* ------------------------------------------------------------------ *
+ * Operator assembly: A = 1/2 grad E_h with E_h of eq. (def:E*), h = 1.
+ * Row z of A gathers the point's own slots and every other point's slot
+ * that reaches z:
+ *   (A u)(z) = sum_{o in V(z;h)} gamma_z(o) (u(z) - u(z+o))
+ *            + sum_{(y,o): o in V(y;h), y+o = z} gamma_y(o) (u(z) - u(y)).
+ * V(z;h) drops offsets that leave the grid (Neumann truncation, Section 1);
+ * with ADLBR_PERIODIC they wrap instead.  The incoming lists are built once
+ * here, sorted per row, so every apply is deterministic.
+ *
+ * The slots must come from a superbase, as adlbr_build_stencils writes them
+ * (2D: o2 = -o0-o1; 3D: o3 = -(o0+o1), o4 = o0-o2, o5 = o1+o2); otherwise
+ * status gets ADLBR_ST_STENCIL.  Compact offsets are stored as int8 unless
+ * flags has ADLBR_OP_WIDE (int16); an offset that does not fit sets
+ * ADLBR_ST_RANGE.
+ *
+ * adlbr_operator_workspace: bytes of device workspace for this grid,
+ *   storage dtype and flags (an upper bound, independent of the data).
+ * adlbr_operator_create:
+ *   offsets, weights  device, as exported by adlbr_build_stencils
+ *                     (weights ADLBR_F64 or ADLBR_F32, given by w_dtype)
+ *   storage           dtype in which the operator keeps its weights and in
+ *                     which apply/step read and write u: ADLBR_F64 (FP64
+ *                     arithmetic), ADLBR_F32, ADLBR_BF16 or ADLBR_F16 (FP32
+ *                     arithmetic)
+ *   workspace         device, >= adlbr_operator_workspace() bytes, must
+ *                     outlive the operator
+ *   status            device out, int32[2]
+ *   op                host out, the new plan; free with adlbr_operator_destroy
+ * ------------------------------------------------------------------ */
+#define ADLBR_OP_WIDE 1
+
+int adlbr_operator_workspace(const adlbr_grid *g, int storage, int flags,
+                             size_t *bytes);
+int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets,
+                          const void *weights, int w_dtype, int storage,
+                          int flags, void *workspace, size_t ws_bytes,
+                          int32_t *status, void *stream, adlbr_operator **op);
+int adlbr_operator_destroy(adlbr_operator *op);
+
+/* Largest explicit-Euler step keeping I - dt A entrywise non-negative
+ * (discrete maximum principle): 1 / max_z A_zz.  Host out; synchronizes. */
+int adlbr_operator_dt_cfl(adlbr_operator *op, double *dt_max, void *stream);
+
+/* The diagonal A_zz (device out, [N] of dtype ADLBR_F64 or ADLBR_F32). */
+int adlbr_operator_diagonal(adlbr_operator *op, void *diag, int dtype,
+                            void *stream);
+
+/* Au = A u.  u, Au: device [N] in the operator's storage dtype; must not
+ * alias. */
+int adlbr_apply(adlbr_operator *op, const void *u, void *Au, void *stream);
+
+/* Explicit Euler, u^{n+1} = u^n - dt A u^n (Section 5), nsteps times.
+ * u: device [N] in/out (storage dtype); u_tmp: device [N] scratch of the
+ * same dtype.  dt_mode ADLBR_DT_ABS: dt is the step; ADLBR_DT_CFL: the step
+ * is dt * (1 / max A_zz), read on the device (no synchronization). */
+#define ADLBR_DT_ABS 0
+#define ADLBR_DT_CFL 1
+int adlbr_step(adlbr_operator *op, void *u, void *u_tmp, double dt,
+               int dt_mode, int64_t nsteps, void *stream);
+
+/* ------------------------------------------------------------------ *
+ * Solution-dependent diffusion tensor from the structure tensor
+ * (Section 5, coherence-enhancing diffusion; edge-enhancing in 3D):
+ *   u_sigma = K_sigma * u, J = K_rho * (grad u_sigma grad u_sigma^T),
+ *   D = sum_k lambda_k v_k v_k^T over the eigenpairs (mu_k, v_k) of J,
+ *   mu_1 >= mu_2 (>= mu_3), with
+ *   ADLBR_MAP_CED: lambda_1 = alpha,
+ *                  lambda_k = alpha + (1-alpha) exp(-C/(mu_1-mu_k)^2)
+ *   ADLBR_MAP_EED: lambda_k = 1 - exp(-C/mu_k^2) for k < d, lambda_d = 1
+ * sigma and rho are standard deviations; Gaussians truncated at
+ * ceil(3 s) (s <= 10) and normalized; mirror boundary; central differences.
+ *   u  device [N] (ADLBR_F32 or ADLBR_F64, = dtype); D device out
+ *      [3|6][N] of dtype; workspace device >= adlbr_tensor_workspace().
+ * ------------------------------------------------------------------ */
+#define ADLBR_MAP_CED 0
+#define ADLBR_MAP_EED 1
+typedef struct adlbr_tensor_params {
+    double sigma, rho, alpha, C;
+    int32_t eig_map;
+} adlbr_tensor_params;
+
+int adlbr_tensor_workspace(const adlbr_grid *g, int dtype, size_t *bytes);
+int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
+                           const adlbr_tensor_params *p, void *D,
+                           void *workspace, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADLBR_H */

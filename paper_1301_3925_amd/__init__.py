@@ -1,0 +1,205 @@
+"""MI355X-native AD-LBR: Python binding of libadlbr.so.
+
+Thin wrappers with the C ABI's names.  They allocate outputs and workspaces
+as torch tensors on the current device, pass raw pointers and the current
+HIP stream, and raise on a non-zero return code.  Every arithmetic step runs
+in the HIP kernels of libadlbr.so; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import capi
+from .capi import AdlbrError  # noqa: F401
+
+__all__ = ["build_stencils", "Operator", "structure_tensor", "grid", "AdlbrError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    codes = {torch.float64: capi.F64, torch.float32: capi.F32,
+             torch.bfloat16: capi.BF16, torch.float16: capi.F16}
+    if t not in codes:
+        raise TypeError(f"unsupported dtype {t}")
+    return codes[t]
+
+
+def _ptr(x):
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError("tensor must live on the GPU")
+        if not t.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+
+
+def grid(dims, periodic: bool = False) -> capi.Grid:
+    dims = [int(d) for d in dims]
+    g = capi.Grid()
+    g.dim = len(dims)
+    g.boundary = capi.PERIODIC if periodic else capi.NEUMANN
+    for i in range(3):
+        g.n[i] = dims[i] if i < len(dims) else 1
+    return g
+
+
+def _npoints(dims):
+    n = 1
+    for d in dims:
+        n *= int(d)
+    return n
+
+
+def build_stencils(D, dims, w_dtype=None, periodic: bool = False, stream=None, out=None):
+    """AD-LBR stencils of a tensor field (adlbr_build_stencils).
+
+    D: [3|6, N] float64/float32 on the GPU.  Returns (offsets int16
+    [S, d, N], weights [S, N], status int32[2]) on the same device; `out`
+    may pass that triple preallocated."""
+    torch = _torch()
+    lib = capi.load()
+    _require_cuda(D)
+    dims = tuple(int(d) for d in dims)
+    dim = len(dims)
+    S = 3 if dim == 2 else 6
+    N = _npoints(dims)
+    if tuple(D.shape) != ((3 if dim == 2 else 6), N):
+        raise ValueError(f"D must have shape ({3 if dim == 2 else 6}, {N})")
+    w_dtype = w_dtype or D.dtype
+    if out is not None:
+        off, w, st = out
+        w_dtype = w.dtype
+    else:
+        off = torch.empty((S, dim, N), dtype=torch.int16, device=D.device)
+        w = torch.empty((S, N), dtype=w_dtype, device=D.device)
+        st = torch.empty(2, dtype=torch.int32, device=D.device)
+    g = grid(dims, periodic)
+    capi.check(lib.adlbr_build_stencils(ctypes.byref(g), _ptr(D), _dtype_code(D.dtype),
+                                        _ptr(off), _ptr(w), _dtype_code(w_dtype), _ptr(st),
+                                        _stream(stream)))
+    return off, w, st
+
+
+class Operator:
+    """The assembled operator A = 1/2 grad E_h (adlbr_operator_create).
+
+    Holds its device workspace (a torch uint8 tensor) for its lifetime."""
+
+    def __init__(self, dims, offsets, weights, storage=None, periodic: bool = False,
+                 wide: bool = False, stream=None, workspace=None):
+        torch = _torch()
+        lib = capi.load()
+        _require_cuda(offsets, weights)
+        self.dims = tuple(int(d) for d in dims)
+        self.N = _npoints(self.dims)
+        self.storage = storage or torch.float32
+        self.device = weights.device
+        self._grid = grid(self.dims, periodic)
+        flags = capi.OP_WIDE if wide else 0
+        nbytes = ctypes.c_size_t()
+        capi.check(lib.adlbr_operator_workspace(ctypes.byref(self._grid),
+                                                _dtype_code(self.storage), flags,
+                                                ctypes.byref(nbytes)))
+        if workspace is not None and workspace.numel() >= nbytes.value:
+            self.workspace = workspace
+        else:
+            self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.status = torch.empty(2, dtype=torch.int32, device=self.device)
+        h = ctypes.c_void_p()
+        capi.check(lib.adlbr_operator_create(
+            ctypes.byref(self._grid), _ptr(offsets), _ptr(weights), _dtype_code(weights.dtype),
+            _dtype_code(self.storage), flags, _ptr(self.workspace), self.workspace.numel(),
+            _ptr(self.status), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            capi.load().adlbr_operator_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dt_cfl(self, stream=None) -> float:
+        out = ctypes.c_double()
+        capi.check(capi.load().adlbr_operator_dt_cfl(self._h, ctypes.byref(out), _stream(stream)))
+        return out.value
+
+    def diagonal(self, dtype=None, stream=None):
+        torch = _torch()
+        dtype = dtype or torch.float64
+        d = torch.empty(self.N, dtype=dtype, device=self.device)
+        capi.check(capi.load().adlbr_operator_diagonal(self._h, _ptr(d), _dtype_code(dtype),
+                                                       _stream(stream)))
+        return d
+
+    def _check_u(self, u):
+        _require_cuda(u)
+        if u.dtype != self.storage or u.numel() != self.N:
+            raise ValueError(f"u must be {self.N} values of {self.storage}")
+
+    def apply(self, u, out=None, stream=None):
+        """A u (adlbr_apply)."""
+        torch = _torch()
+        self._check_u(u)
+        out = torch.empty_like(u) if out is None else out
+        self._check_u(out)
+        capi.check(capi.load().adlbr_apply(self._h, _ptr(u), _ptr(out), _stream(stream)))
+        return out
+
+    def step(self, u, dt: float, nsteps: int, cfl_fraction: bool = False, u_tmp=None,
+             stream=None):
+        """nsteps explicit Euler steps in place on u (adlbr_step).  With
+        cfl_fraction=True, dt is a fraction of 1 / max A_zz."""
+        torch = _torch()
+        self._check_u(u)
+        u_tmp = torch.empty_like(u) if u_tmp is None else u_tmp
+        self._check_u(u_tmp)
+        mode = capi.DT_CFL if cfl_fraction else capi.DT_ABS
+        capi.check(capi.load().adlbr_step(self._h, _ptr(u), _ptr(u_tmp), float(dt), mode,
+                                          int(nsteps), _stream(stream)))
+        return u
+
+
+def structure_tensor(u, dims, sigma: float, rho: float, alpha: float, C: float,
+                     eig_map: str = "ced", out=None, workspace=None, stream=None):
+    """Diffusion tensor from the structure tensor of u (adlbr_structure_tensor)."""
+    torch = _torch()
+    lib = capi.load()
+    _require_cuda(u)
+    dims = tuple(int(d) for d in dims)
+    g = grid(dims)
+    code = _dtype_code(u.dtype)
+    nbytes = ctypes.c_size_t()
+    capi.check(lib.adlbr_tensor_workspace(ctypes.byref(g), code, ctypes.byref(nbytes)))
+    if workspace is None or workspace.numel() < nbytes.value:
+        workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=u.device)
+    nj = 3 if len(dims) == 2 else 6
+    out = torch.empty((nj, u.numel()), dtype=u.dtype, device=u.device) if out is None else out
+    p = capi.TensorParams(float(sigma), float(rho), float(alpha), float(C),
+                          capi.MAP_CED if eig_map == "ced" else capi.MAP_EED)
+    capi.check(lib.adlbr_structure_tensor(ctypes.byref(g), _ptr(u), code, ctypes.byref(p),
+                                          _ptr(out), _ptr(workspace), workspace.numel(),
+                                          _stream(stream)))
+    return out

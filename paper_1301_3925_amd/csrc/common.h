@@ -1,0 +1,125 @@
+// Internal helpers shared by the HIP sources of libadlbr.so (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "adlbr.h"
+
+namespace adlbr {
+
+typedef long long ll;
+
+// ---------------------------------------------------------------- errors --
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define ADLBR_CHECK_HIP(expr)                                                  \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess) {                                                \
+            ::adlbr::set_error("%s failed: %s", #expr, hipGetErrorString(e_)); \
+            return ADLBR_E_HIP;                                                \
+        }                                                                      \
+    } while (0)
+
+#define ADLBR_LAUNCH_CHECK()                                                   \
+    do {                                                                       \
+        hipError_t e_ = hipGetLastError();                                     \
+        if (e_ != hipSuccess) {                                                \
+            ::adlbr::set_error("kernel launch failed: %s", hipGetErrorString(e_)); \
+            return ADLBR_E_HIP;                                                \
+        }                                                                      \
+    } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ------------------------------------------------------------------ grid --
+struct GridInfo {
+    int dim;
+    int periodic;
+    int nx, ny, nz;
+    long long N;
+};
+
+int check_grid(const adlbr_grid *g, GridInfo *gi);
+
+// --------------------------------------------------------- 16-bit storage --
+struct bf16 { uint16_t b; };
+
+__host__ __device__ inline float bf16_to_f32(bf16 v) {
+    union { uint32_t u; float f; } c;
+    c.u = (uint32_t)v.b << 16;
+    return c.f;
+}
+
+__host__ __device__ inline bf16 f32_to_bf16(float f) {
+    union { uint32_t u; float f; } c;
+    c.f = f;
+    uint32_t u = c.u;
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) {
+        return bf16{(uint16_t)((u >> 16) | 0x40)};  // quiet NaN
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return bf16{(uint16_t)(u >> 16)};
+}
+
+// load storage type -> arithmetic type, and back (round to nearest even)
+template <typename TS, typename TA> struct Conv;
+template <> struct Conv<double, double> {
+    __device__ static double ld(double v) { return v; }
+    __device__ static double st(double v) { return v; }
+};
+template <> struct Conv<float, float> {
+    __device__ static float ld(float v) { return v; }
+    __device__ static float st(float v) { return v; }
+};
+template <> struct Conv<bf16, float> {
+    __device__ static float ld(bf16 v) { return bf16_to_f32(v); }
+    __device__ static bf16 st(float v) { return f32_to_bf16(v); }
+};
+template <> struct Conv<_Float16, float> {
+    __device__ static float ld(_Float16 v) { return (float)v; }
+    __device__ static _Float16 st(float v) { return (_Float16)v; }
+};
+
+inline size_t dtype_size(int dt) {
+    switch (dt) {
+    case ADLBR_F64: return 8;
+    case ADLBR_F32: return 4;
+    case ADLBR_BF16:
+    case ADLBR_F16: return 2;
+    default: return 0;
+    }
+}
+
+inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+// ------------------------------------------------------- status helpers --
+__global__ void k_status_init(int32_t *status);
+__global__ void k_status_final(int32_t *status);
+
+__device__ inline void report(int32_t *status, long long z, int flags) {
+    if (!status || !flags) return;
+    if (flags & (ADLBR_ST_NOT_SPD | ADLBR_ST_RANGE | ADLBR_ST_ITER | ADLBR_ST_STENCIL |
+                 ADLBR_ST_INCOMING))
+        atomicMin(&status[0], (int32_t)z);
+    atomicOr(&status[1], flags);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of an MI355X; remap the
+// hardware block id so that XCD k works on one contiguous range of logical
+// blocks (neighbouring rows share that XCD's L2).
+__device__ inline long long xcd_block(long long b, long long nb) {
+    const long long nx = 8;
+    long long q = nb / nx, r = nb % nx;
+    long long k = b % nx, j = b / nx;
+    long long start = k * q + (k < r ? k : r);
+    return start + j;
+}
+
+}  // namespace adlbr

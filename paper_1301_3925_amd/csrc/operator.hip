@@ -1,0 +1,719 @@
+// AD-LBR operator A = 1/2 grad E_h (eq. (def:E*), h = 1) on the GPU:
+// assembly of the gather form and the matrix-free apply / explicit step.
+//
+// Row z of A has two parts (Section 1; Neumann truncation V(z;h)):
+//   own:      sum over slots o of z and s = +-1 with z + s o in the grid of
+//             w_o(z) (u(z) - u(z + s o))
+//   incoming: sum over directed edges (y, s o) of other points landing on z
+//             of w_o(y) (u(z) - u(y)).
+// The incoming edges are the transpose of the stencils; they are listed
+// once per operator (count -> scan -> fill -> per-row sort), so every apply
+// is a deterministic gather with no atomics.
+//
+// Data layout in the workspace (N points, S = 3 or 6 slots):
+//   sb     compact slots: 2D (o0, o1) as 4 x int8 (or int16), o2 = -o0-o1;
+//          3D (o0, o1, o2) as 12 x int8 (or int16), o3 = -(o0+o1),
+//          o4 = o0-o2, o5 = o1+o2.  One vector load per point.
+//   w      [S][N] weights in the storage dtype.
+//   cnt    [N] uint8 number of incoming edges of each point.
+//   pos    [N] int32 start of each point's incoming list; the apply only
+//          reads the entry at the first point of each 64-point slice and
+//          rebuilds the rest with a wavefront prefix sum of cnt.
+//   ent    incoming entries, int32 ((y - z) << 3 | slot), sorted per row.
+//   diag   [N] A_zz (double for FP64 storage, float otherwise).
+#include <new>
+
+#include "common.h"
+
+struct adlbr_operator {
+    adlbr::GridInfo gi;
+    int slots;    // 3 or 6
+    int storage;  // adlbr_dtype
+    int wide;     // int16 compact offsets
+    void *sb;
+    void *w;
+    uint8_t *cnt;
+    int32_t *pos;
+    int32_t *ent;
+    void *diag;
+    unsigned long long *maxdiag;
+    double *dtcfl;
+    int32_t *tmp;   // [N] counts / cursors during assembly
+    int32_t *bsum;  // scan block sums
+};
+
+namespace adlbr {
+namespace {
+
+constexpr int kBS = 256;         // threads per block of the apply
+constexpr int kScanBlock = 1024;  // elements per scan block
+
+// --------------------------------------------------------- compact slots --
+template <int DIM, bool WIDE> struct Slots;
+template <> struct Slots<2, false> {
+    typedef char4 store_t;
+    int o[3][2];
+    __device__ void load(const store_t *p, long long z) {
+        const char4 v = p[z];
+        o[0][0] = v.x; o[0][1] = v.y; o[1][0] = v.z; o[1][1] = v.w;
+        o[2][0] = -o[0][0] - o[1][0]; o[2][1] = -o[0][1] - o[1][1];
+    }
+    __device__ static bool pack(const int s[6][3], store_t *p, long long z) {
+        for (int q = 0; q < 2; ++q)
+            for (int c = 0; c < 2; ++c)
+                if (s[q][c] > 127 || s[q][c] < -127) {
+                    p[z] = make_char4(0, 0, 0, 0);
+                    return false;
+                }
+        p[z] = make_char4(s[0][0], s[0][1], s[1][0], s[1][1]);
+        return true;
+    }
+};
+template <> struct Slots<2, true> {
+    typedef short4 store_t;
+    int o[3][2];
+    __device__ void load(const store_t *p, long long z) {
+        const short4 v = p[z];
+        o[0][0] = v.x; o[0][1] = v.y; o[1][0] = v.z; o[1][1] = v.w;
+        o[2][0] = -o[0][0] - o[1][0]; o[2][1] = -o[0][1] - o[1][1];
+    }
+    __device__ static bool pack(const int s[6][3], store_t *p, long long z) {
+        p[z] = make_short4(s[0][0], s[0][1], s[1][0], s[1][1]);
+        return true;
+    }
+};
+struct __attribute__((aligned(4))) C3x8 { int8_t v[12]; };
+struct __attribute__((aligned(8))) C3x16 { int16_t v[12]; };
+template <> struct Slots<3, false> {
+    typedef C3x8 store_t;
+    int o[6][3];
+    __device__ void load(const store_t *p, long long z) {
+        const C3x8 v = p[z];
+        for (int q = 0; q < 3; ++q)
+            for (int c = 0; c < 3; ++c) o[q][c] = v.v[3 * q + c];
+        derive();
+    }
+    __device__ void derive() {
+        for (int c = 0; c < 3; ++c) {
+            o[3][c] = -(o[0][c] + o[1][c]);
+            o[4][c] = o[0][c] - o[2][c];
+            o[5][c] = o[1][c] + o[2][c];
+        }
+    }
+    __device__ static bool pack(const int s[6][3], store_t *p, long long z) {
+        C3x8 v;
+        for (int q = 0; q < 3; ++q)
+            for (int c = 0; c < 3; ++c) {
+                if (s[q][c] > 127 || s[q][c] < -127) {
+                    for (int k = 0; k < 12; ++k) v.v[k] = 0;
+                    p[z] = v;
+                    return false;
+                }
+                v.v[3 * q + c] = (int8_t)s[q][c];
+            }
+        v.v[9] = v.v[10] = v.v[11] = 0;
+        p[z] = v;
+        return true;
+    }
+};
+template <> struct Slots<3, true> {
+    typedef C3x16 store_t;
+    int o[6][3];
+    __device__ void load(const store_t *p, long long z) {
+        const C3x16 v = p[z];
+        for (int q = 0; q < 3; ++q)
+            for (int c = 0; c < 3; ++c) o[q][c] = v.v[3 * q + c];
+        for (int c = 0; c < 3; ++c) {
+            o[3][c] = -(o[0][c] + o[1][c]);
+            o[4][c] = o[0][c] - o[2][c];
+            o[5][c] = o[1][c] + o[2][c];
+        }
+    }
+    __device__ static bool pack(const int s[6][3], store_t *p, long long z) {
+        C3x16 v;
+        for (int q = 0; q < 3; ++q)
+            for (int c = 0; c < 3; ++c) v.v[3 * q + c] = (int16_t)s[q][c];
+        v.v[9] = v.v[10] = v.v[11] = 0;
+        p[z] = v;
+        return true;
+    }
+};
+
+// coordinates of a linear index
+struct Coord {
+    int x, y, z;
+};
+__device__ __forceinline__ Coord coords(long long i, const GridInfo &g) {
+    Coord c;
+    const unsigned ui = (unsigned)i;
+    const unsigned t = ui / (unsigned)g.nx;
+    c.x = (int)(ui - t * (unsigned)g.nx);
+    if (g.dim == 2) {
+        c.y = (int)t;
+        c.z = 0;
+    } else {
+        const unsigned t2 = t / (unsigned)g.ny;
+        c.y = (int)(t - t2 * (unsigned)g.ny);
+        c.z = (int)t2;
+    }
+    return c;
+}
+
+__device__ __forceinline__ int wrap(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Target of the directed edge (p, s*o); returns false when it leaves a
+// Neumann grid.
+template <int DIM, bool PER>
+__device__ __forceinline__ bool edge_target(const Coord &p, long long i, const int *o, int s,
+                                            const GridInfo &g, long long &t) {
+    if (PER) {
+        const int x = wrap(p.x + s * o[0], g.nx);
+        const int y = wrap(p.y + s * o[1], g.ny);
+        const int zz = DIM == 3 ? wrap(p.z + s * o[2], g.nz) : 0;
+        t = x + (long long)g.nx * (y + (long long)g.ny * zz);
+        return t != i;  // an offset that wraps onto the point itself is no edge
+    } else {
+        const int x = p.x + s * o[0], y = p.y + s * o[1];
+        const int zz = DIM == 3 ? p.z + s * o[2] : 0;
+        if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || zz < 0 || zz >= g.nz) return false;
+        t = i + s * (o[0] + (long long)g.nx * (o[1] + (long long)g.ny * (DIM == 3 ? o[2] : 0)));
+        return true;
+    }
+}
+
+// ---------------------------------------------------------------- build --
+__global__ void k_fill_i32(int32_t *p, long long n, int32_t v) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_init_scalars(unsigned long long *maxdiag) { *maxdiag = 0ull; }
+
+template <typename TW> __device__ __forceinline__ double ld_w(const TW *w, long long i) {
+    return (double)w[i];
+}
+
+// Pack the slots, convert the weights, count incoming edges per target.
+template <int DIM, bool WIDE, bool PER, typename TWin, typename TS, typename TA>
+__global__ void k_compact(GridInfo g, const int16_t *__restrict__ off, const TWin *__restrict__ win,
+                          typename Slots<DIM, WIDE>::store_t *__restrict__ sb, TS *__restrict__ w,
+                          int32_t *__restrict__ count, int32_t *status) {
+    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= g.N) return;
+    constexpr int S = DIM == 2 ? 3 : 6;
+    const long long N = g.N;
+    int s[6][3];
+    for (int q = 0; q < S; ++q)
+        for (int c = 0; c < 3; ++c) s[q][c] = c < DIM ? (int)off[(DIM * q + c) * N + z] : 0;
+    int st = 0;
+    bool rel = true;
+    if (DIM == 2) {
+        for (int c = 0; c < 2; ++c) rel = rel && s[2][c] == -s[0][c] - s[1][c];
+    } else {
+        for (int c = 0; c < 3; ++c)
+            rel = rel && s[3][c] == -(s[0][c] + s[1][c]) && s[4][c] == s[0][c] - s[2][c] &&
+                  s[5][c] == s[1][c] + s[2][c];
+    }
+    if (!rel) st |= ADLBR_ST_STENCIL;
+    if (!Slots<DIM, WIDE>::pack(s, sb, z)) st |= ADLBR_ST_RANGE;
+    const Coord p = coords(z, g);
+    for (int q = 0; q < S; ++q) {
+        const double wq = (double)win[q * N + z];
+        w[q * N + z] = Conv<TS, TA>::st((TA)wq);
+        if (!(wq > 0.0)) continue;
+        for (int sg = -1; sg <= 1; sg += 2) {
+            long long t;
+            if (edge_target<DIM, PER>(p, z, s[q], sg, g, t)) atomicAdd(&count[t], 1);
+        }
+    }
+    report(status, z, st);
+}
+
+// Block-level exclusive scan helpers (blockDim.x == 256, 4 items per thread).
+__device__ int32_t block_excl_scan256(int32_t v, int32_t *lds, int32_t &total) {
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const int32_t add = t >= d ? lds[t - d] : 0;
+        __syncthreads();
+        lds[t] += add;
+        __syncthreads();
+    }
+    total = lds[255];
+    const int32_t incl = lds[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_scan_reduce(const int32_t *__restrict__ c, long long n, int32_t *bsum) {
+    __shared__ int32_t lds[256];
+    const long long base = (long long)blockIdx.x * kScanBlock + threadIdx.x * 4;
+    int32_t v = 0;
+    for (int k = 0; k < 4; ++k)
+        if (base + k < n) v += min(c[base + k], 255);
+    int32_t total;
+    block_excl_scan256(v, lds, total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void k_scan_top(int32_t *bsum, long long nb) {
+    __shared__ int32_t lds[256];
+    int32_t carry = 0;
+    for (long long b0 = 0; b0 < nb; b0 += 256) {
+        const long long i = b0 + threadIdx.x;
+        const int32_t v = i < nb ? bsum[i] : 0;
+        int32_t total;
+        const int32_t ex = block_excl_scan256(v, lds, total);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ void k_scan_down(const int32_t *__restrict__ c, long long n, const int32_t *bsum,
+                            int32_t *__restrict__ pos, uint8_t *__restrict__ cnt8, int32_t *status) {
+    __shared__ int32_t lds[256];
+    const long long base = (long long)blockIdx.x * kScanBlock + threadIdx.x * 4;
+    // lists longer than 255 are truncated (and flagged): positions use the
+    // clamped counts so that they agree with the uint8 counts the apply scans
+    int32_t v[4], sum = 0;
+    for (int k = 0; k < 4; ++k) {
+        v[k] = base + k < n ? c[base + k] : 0;
+        sum += min(v[k], 255);
+    }
+    int32_t total;
+    int32_t run = bsum[blockIdx.x] + block_excl_scan256(sum, lds, total);
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < n) {
+            pos[base + k] = run;
+            cnt8[base + k] = (uint8_t)(v[k] > 255 ? 255 : v[k]);
+            if (v[k] > 255) report(status, base + k, ADLBR_ST_INCOMING);
+        }
+        run += min(v[k], 255);
+    }
+}
+
+// Write every incoming entry at its target's list (order fixed later).
+template <int DIM, bool WIDE, bool PER, typename TS>
+__global__ void k_fill_entries(GridInfo g, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                               const TS *__restrict__ w, const int32_t *__restrict__ pos,
+                               int32_t *__restrict__ cursor, int32_t *__restrict__ ent,
+                               const int16_t *__restrict__ off, const void *win, int win_f64) {
+    const long long y = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= g.N) return;
+    constexpr int S = DIM == 2 ? 3 : 6;
+    const long long N = g.N;
+    const Coord p = coords(y, g);
+    for (int q = 0; q < S; ++q) {
+        const double wq = win_f64 ? ((const double *)win)[q * N + y] : (double)((const float *)win)[q * N + y];
+        if (!(wq > 0.0)) continue;
+        int o[3];
+        for (int c = 0; c < 3; ++c) o[c] = c < DIM ? (int)off[(DIM * q + c) * N + y] : 0;
+        for (int sg = -1; sg <= 1; sg += 2) {
+            long long t;
+            if (!edge_target<DIM, PER>(p, y, o, sg, g, t)) continue;
+            const int32_t k = atomicAdd(&cursor[t], 1);
+            if (k < 255) ent[pos[t] + k] = (int32_t)(((y - t) << 3) | q);
+        }
+    }
+}
+
+// Sort each incoming list, then A_zz = own in-grid weights + incoming
+// weights, in that fixed order; max over the grid for the CFL bound.
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TD>
+__global__ void k_finalize(GridInfo g, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                           const TS *__restrict__ w, const int32_t *__restrict__ pos,
+                           const uint8_t *__restrict__ cnt, int32_t *__restrict__ ent,
+                           TD *__restrict__ diag, unsigned long long *maxdiag) {
+    __shared__ double red[kBS];
+    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double d = 0.0;
+    if (z < g.N) {
+        constexpr int S = DIM == 2 ? 3 : 6;
+        const long long N = g.N;
+        const int c = cnt[z];
+        int32_t *e = ent + pos[z];
+        for (int i = 1; i < c; ++i) {  // insertion sort by (source, slot)
+            const int32_t key = e[i];
+            int j = i - 1;
+            while (j >= 0 && e[j] > key) {
+                e[j + 1] = e[j];
+                --j;
+            }
+            e[j + 1] = key;
+        }
+        Slots<DIM, WIDE> sl;
+        sl.load(sb, z);
+        const Coord p = coords(z, g);
+        for (int q = 0; q < S; ++q) {
+            const double wq = (double)Conv<TS, TA>::ld(w[q * N + z]);
+            for (int sg = -1; sg <= 1; sg += 2) {
+                long long t;
+                if (edge_target<DIM, PER>(p, z, sl.o[q], sg, g, t)) d += wq;
+            }
+        }
+        for (int k = 0; k < c; ++k) {
+            const int32_t v = e[k];
+            d += (double)Conv<TS, TA>::ld(w[(long long)(v & 7) * N + z + (v >> 3)]);
+        }
+        diag[z] = (TD)d;
+    }
+    red[threadIdx.x] = d;
+    __syncthreads();
+    for (int s = kBS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(maxdiag, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+__global__ void k_cfl(const unsigned long long *maxdiag, double *dtcfl) {
+    const double m = __longlong_as_double((long long)*maxdiag);
+    *dtcfl = m > 0.0 ? 1.0 / m : 0.0;
+}
+
+// ---------------------------------------------------------------- apply --
+__device__ __forceinline__ unsigned wave_excl_scan(unsigned v) {
+    const unsigned lane = threadIdx.x & 63u;
+    unsigned x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned y = __shfl_up(x, d, 64);
+        if (lane >= (unsigned)d) x += y;
+    }
+    return x - v;
+}
+
+// out = A u (STEP = false) or u - dt A u (STEP = true).
+template <int DIM, bool WIDE, bool PER, bool STEP, typename TS, typename TA>
+__global__ __launch_bounds__(kBS) void k_apply(
+    GridInfo g, const TS *__restrict__ u, TS *__restrict__ out,
+    const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
+    const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
+    const int32_t *__restrict__ ent, double dt, const double *__restrict__ dtcfl, int dt_mode) {
+    constexpr int S = DIM == 2 ? 3 : 6;
+    const long long N = g.N;
+    const long long blk = xcd_block(blockIdx.x, gridDim.x);
+    const long long z = blk * kBS + threadIdx.x;
+    const bool live = z < N;
+    const unsigned c = live ? cnt[z] : 0u;
+    const unsigned pre = wave_excl_scan(c);
+    if (!live) return;
+    const long long z0 = z & ~63ll;
+    const long long start = (long long)pos[z0] + pre;
+
+    const TA uz = Conv<TS, TA>::ld(u[z]);
+    TA acc = (TA)0;
+    Slots<DIM, WIDE> sl;
+    sl.load(sb, z);
+    const Coord p = coords(z, g);
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        const TA wq = Conv<TS, TA>::ld(w[q * N + z]);
+        TA part = (TA)0;
+#pragma unroll
+        for (int sg = -1; sg <= 1; sg += 2) {
+            long long t;
+            if (edge_target<DIM, PER>(p, z, sl.o[q], sg, g, t))
+                part += uz - Conv<TS, TA>::ld(u[t]);
+        }
+        acc += wq * part;
+    }
+    for (unsigned k = 0; k < c; ++k) {
+        const int32_t v = ent[start + k];
+        const long long y = z + (v >> 3);
+        const TA wy = Conv<TS, TA>::ld(w[(long long)(v & 7) * N + y]);
+        acc += wy * (uz - Conv<TS, TA>::ld(u[y]));
+    }
+    if (STEP) {
+        const TA h = (TA)(dt_mode == ADLBR_DT_CFL ? dt * dtcfl[0] : dt);
+        out[z] = Conv<TS, TA>::st(uz - h * acc);
+    } else {
+        out[z] = Conv<TS, TA>::st(acc);
+    }
+}
+
+// ------------------------------------------------------------ dispatch --
+struct Launch {
+    hipStream_t s;
+    unsigned nb;
+};
+
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
+int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_f64,
+               int32_t *status, hipStream_t s) {
+    typedef typename Slots<DIM, WIDE>::store_t store_t;
+    const GridInfo g = op->gi;
+    const long long N = g.N;
+    const unsigned nb = (unsigned)((N + kBS - 1) / kBS);
+    const unsigned nscan = (unsigned)((N + kScanBlock - 1) / kScanBlock);
+    TS *w = (TS *)op->w;
+    store_t *sb = (store_t *)op->sb;
+    hipLaunchKernelGGL(k_fill_i32, dim3(nb), dim3(kBS), 0, s, op->tmp, N, 0);
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(1), 0, s, op->maxdiag);
+    if (win_f64)
+        hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, double, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
+                           off, (const double *)win, sb, w, op->tmp, status);
+    else
+        hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, float, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
+                           off, (const float *)win, sb, w, op->tmp, status);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nscan), dim3(256), 0, s, op->tmp, N, op->bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, op->bsum, (long long)nscan);
+    hipLaunchKernelGGL(k_scan_down, dim3(nscan), dim3(256), 0, s, op->tmp, N, op->bsum, op->pos,
+                       op->cnt, status);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nb), dim3(kBS), 0, s, op->tmp, N, 0);
+    hipLaunchKernelGGL((k_fill_entries<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g, sb, w,
+                       op->pos, op->tmp, op->ent, off, win, win_f64);
+    if (op->storage == ADLBR_F64)
+        hipLaunchKernelGGL((k_finalize<DIM, WIDE, PER, TS, TA, double>), dim3(nb), dim3(kBS), 0, s, g,
+                           sb, w, op->pos, op->cnt, op->ent, (double *)op->diag, op->maxdiag);
+    else
+        hipLaunchKernelGGL((k_finalize<DIM, WIDE, PER, TS, TA, float>), dim3(nb), dim3(kBS), 0, s, g,
+                           sb, w, op->pos, op->cnt, op->ent, (float *)op->diag, op->maxdiag);
+    hipLaunchKernelGGL(k_cfl, dim3(1), dim3(1), 0, s, op->maxdiag, op->dtcfl);
+    ADLBR_LAUNCH_CHECK();
+    return ADLBR_OK;
+}
+
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
+int apply_impl(const adlbr_operator *op, const void *u, void *out, bool step, double dt, int dt_mode,
+               hipStream_t s) {
+    typedef typename Slots<DIM, WIDE>::store_t store_t;
+    const GridInfo g = op->gi;
+    const unsigned nb = (unsigned)((g.N + kBS - 1) / kBS);
+    if (step)
+        hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, true, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
+                           (const TS *)u, (TS *)out, (const store_t *)op->sb, (const TS *)op->w,
+                           op->cnt, op->pos, op->ent, dt, op->dtcfl, dt_mode);
+    else
+        hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, false, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
+                           (const TS *)u, (TS *)out, (const store_t *)op->sb, (const TS *)op->w,
+                           op->cnt, op->pos, op->ent, dt, op->dtcfl, dt_mode);
+    return ADLBR_OK;
+}
+
+// Expand the (dim, wide, periodic, storage) choice into template instances.
+template <template <int, bool, bool, typename, typename> class F, typename OpT,
+          typename... Args>
+int dispatch(OpT *op, Args... args) {
+#define ADLBR_D3(DIM, WIDE, PER)                                                         \
+    switch (op->storage) {                                                               \
+    case ADLBR_F64: return F<DIM, WIDE, PER, double, double>::run(op, args...);          \
+    case ADLBR_F32: return F<DIM, WIDE, PER, float, float>::run(op, args...);            \
+    case ADLBR_BF16: return F<DIM, WIDE, PER, bf16, float>::run(op, args...);            \
+    case ADLBR_F16: return F<DIM, WIDE, PER, _Float16, float>::run(op, args...);         \
+    default: return ADLBR_E_UNSUPPORTED;                                                 \
+    }
+    const int dim = op->gi.dim, wide = op->wide, per = op->gi.periodic;
+    if (dim == 2 && !wide && !per) { ADLBR_D3(2, false, false) }
+    if (dim == 2 && !wide && per) { ADLBR_D3(2, false, true) }
+    if (dim == 2 && wide && !per) { ADLBR_D3(2, true, false) }
+    if (dim == 2 && wide && per) { ADLBR_D3(2, true, true) }
+    if (dim == 3 && !wide && !per) { ADLBR_D3(3, false, false) }
+    if (dim == 3 && !wide && per) { ADLBR_D3(3, false, true) }
+    if (dim == 3 && wide && !per) { ADLBR_D3(3, true, false) }
+    if (dim == 3 && wide && per) { ADLBR_D3(3, true, true) }
+#undef ADLBR_D3
+    return ADLBR_E_UNSUPPORTED;
+}
+
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct BuildF {
+    static int run(adlbr_operator *op, const int16_t *off, const void *win, int f64, int32_t *st,
+                   hipStream_t s) {
+        return build_impl<DIM, WIDE, PER, TS, TA>(op, off, win, f64, st, s);
+    }
+};
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct ApplyF {
+    static int run(const adlbr_operator *op, const void *u, void *out, bool step, double dt,
+                   int mode, hipStream_t s) {
+        return apply_impl<DIM, WIDE, PER, TS, TA>(op, u, out, step, dt, mode, s);
+    }
+};
+
+struct Layout {
+    size_t sb, w, cnt, pos, ent, diag, scal, tmp, bsum, total;
+};
+
+Layout layout(const GridInfo &g, int storage, int wide) {
+    const long long N = g.N;
+    const int S = g.dim == 2 ? 3 : 6;
+    const size_t sbsz = g.dim == 2 ? (wide ? 8 : 4) : (wide ? 24 : 12);
+    const size_t nscan = (size_t)((N + kScanBlock - 1) / kScanBlock);
+    Layout L;
+    size_t o = 0;
+    L.sb = o;   o += align_up(sbsz * N);
+    L.w = o;    o += align_up(dtype_size(storage) * S * N);
+    L.cnt = o;  o += align_up((size_t)N + 64);
+    L.pos = o;  o += align_up(4 * (size_t)N + 256);
+    L.ent = o;  o += align_up(4 * (size_t)(2 * S) * N);
+    L.diag = o; o += align_up((storage == ADLBR_F64 ? 8 : 4) * (size_t)N);
+    L.scal = o; o += 256;
+    L.tmp = o;  o += align_up(4 * (size_t)N);
+    L.bsum = o; o += align_up(4 * nscan + 4);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+}  // namespace adlbr
+
+using namespace adlbr;
+
+extern "C" int adlbr_operator_workspace(const adlbr_grid *g, int storage, int flags,
+                                        size_t *bytes) {
+    clear_error();
+    GridInfo gi;
+    int rc = check_grid(g, &gi);
+    if (rc) return rc;
+    if (!bytes || dtype_size(storage) == 0) {
+        set_error("adlbr_operator_workspace: bad storage dtype or null output");
+        return ADLBR_E_INVALID;
+    }
+    *bytes = layout(gi, storage, flags & ADLBR_OP_WIDE).total;
+    return ADLBR_OK;
+}
+
+extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets,
+                                     const void *weights, int w_dtype, int storage, int flags,
+                                     void *workspace, size_t ws_bytes, int32_t *status,
+                                     void *stream, adlbr_operator **op_out) {
+    clear_error();
+    GridInfo gi;
+    int rc = check_grid(g, &gi);
+    if (rc) return rc;
+    if (!offsets || !weights || !workspace || !status || !op_out) {
+        set_error("adlbr_operator_create: null pointer argument");
+        return ADLBR_E_INVALID;
+    }
+    if ((w_dtype != ADLBR_F64 && w_dtype != ADLBR_F32) || dtype_size(storage) == 0) {
+        set_error("adlbr_operator_create: weights must be F64/F32, storage F64/F32/BF16/F16");
+        return ADLBR_E_INVALID;
+    }
+    const int wide = flags & ADLBR_OP_WIDE ? 1 : 0;
+    const Layout L = layout(gi, storage, wide);
+    if (ws_bytes < L.total) {
+        set_error("adlbr_operator_create: workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+        return ADLBR_E_NOMEM;
+    }
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) {
+        set_error("adlbr_operator_create: workspace must be 256-byte aligned");
+        return ADLBR_E_INVALID;
+    }
+    adlbr_operator *op = new (std::nothrow) adlbr_operator;
+    if (!op) {
+        set_error("adlbr_operator_create: out of host memory");
+        return ADLBR_E_NOMEM;
+    }
+    char *b = (char *)workspace;
+    op->gi = gi;
+    op->slots = gi.dim == 2 ? 3 : 6;
+    op->storage = storage;
+    op->wide = wide;
+    op->sb = b + L.sb;
+    op->w = b + L.w;
+    op->cnt = (uint8_t *)(b + L.cnt);
+    op->pos = (int32_t *)(b + L.pos);
+    op->ent = (int32_t *)(b + L.ent);
+    op->diag = b + L.diag;
+    op->maxdiag = (unsigned long long *)(b + L.scal);
+    op->dtcfl = (double *)(b + L.scal + 8);
+    op->tmp = (int32_t *)(b + L.tmp);
+    op->bsum = (int32_t *)(b + L.bsum);
+    hipStream_t s = as_stream(stream);
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(1), 0, s, status);
+    rc = dispatch<BuildF>(op, offsets, weights, (int)(w_dtype == ADLBR_F64), status, s);
+    hipLaunchKernelGGL(k_status_final, dim3(1), dim3(1), 0, s, status);
+    if (rc) {
+        delete op;
+        return rc;
+    }
+    ADLBR_LAUNCH_CHECK();
+    *op_out = op;
+    return ADLBR_OK;
+}
+
+extern "C" int adlbr_operator_destroy(adlbr_operator *op) {
+    delete op;
+    return ADLBR_OK;
+}
+
+extern "C" int adlbr_operator_dt_cfl(adlbr_operator *op, double *dt_max, void *stream) {
+    clear_error();
+    if (!op || !dt_max) {
+        set_error("adlbr_operator_dt_cfl: null argument");
+        return ADLBR_E_INVALID;
+    }
+    hipStream_t s = as_stream(stream);
+    ADLBR_CHECK_HIP(hipMemcpyAsync(dt_max, op->dtcfl, sizeof(double), hipMemcpyDeviceToHost, s));
+    ADLBR_CHECK_HIP(hipStreamSynchronize(s));
+    return ADLBR_OK;
+}
+
+namespace {
+template <typename TI, typename TO>
+__global__ void k_convert(const TI *in, TO *out, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (TO)in[i];
+}
+}  // namespace
+
+extern "C" int adlbr_operator_diagonal(adlbr_operator *op, void *diag, int dtype, void *stream) {
+    clear_error();
+    if (!op || !diag || (dtype != ADLBR_F64 && dtype != ADLBR_F32)) {
+        set_error("adlbr_operator_diagonal: bad argument");
+        return ADLBR_E_INVALID;
+    }
+    hipStream_t s = as_stream(stream);
+    const long long N = op->gi.N;
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    const bool src64 = op->storage == ADLBR_F64;
+    if (src64 && dtype == ADLBR_F64)
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(nb), dim3(256), 0, s, (const double *)op->diag, (double *)diag, N);
+    else if (src64)
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(nb), dim3(256), 0, s, (const double *)op->diag, (float *)diag, N);
+    else if (dtype == ADLBR_F64)
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(nb), dim3(256), 0, s, (const float *)op->diag, (double *)diag, N);
+    else
+        hipLaunchKernelGGL((k_convert<float, float>), dim3(nb), dim3(256), 0, s, (const float *)op->diag, (float *)diag, N);
+    ADLBR_LAUNCH_CHECK();
+    return ADLBR_OK;
+}
+
+extern "C" int adlbr_apply(adlbr_operator *op, const void *u, void *Au, void *stream) {
+    clear_error();
+    if (!op || !u || !Au || u == Au) {
+        set_error("adlbr_apply: null or aliased argument");
+        return ADLBR_E_INVALID;
+    }
+    int rc = dispatch<ApplyF>(op, u, Au, false, 0.0, 0, as_stream(stream));
+    if (rc) return rc;
+    ADLBR_LAUNCH_CHECK();
+    return ADLBR_OK;
+}
+
+extern "C" int adlbr_step(adlbr_operator *op, void *u, void *u_tmp, double dt, int dt_mode,
+                          int64_t nsteps, void *stream) {
+    clear_error();
+    if (!op || !u || !u_tmp || u == u_tmp || nsteps < 0 ||
+        (dt_mode != ADLBR_DT_ABS && dt_mode != ADLBR_DT_CFL)) {
+        set_error("adlbr_step: bad argument");
+        return ADLBR_E_INVALID;
+    }
+    hipStream_t s = as_stream(stream);
+    void *a = u, *b = u_tmp;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        int rc = dispatch<ApplyF>(op, (const void *)a, b, true, dt, dt_mode, s);
+        if (rc) return rc;
+        void *t = a;
+        a = b;
+        b = t;
+    }
+    ADLBR_LAUNCH_CHECK();
+    if (a != u)
+        ADLBR_CHECK_HIP(hipMemcpyAsync(u, a, (size_t)op->gi.N * dtype_size(op->storage),
+                                       hipMemcpyDeviceToDevice, s));
+    return ADLBR_OK;
+}

@@ -1,0 +1,309 @@
+// Solution-dependent diffusion tensor from the structure tensor
+// (Section 5: coherence-enhancing diffusion, 2D and 3D; edge-enhancing
+// diffusion in 3D):
+//   u_sigma = K_sigma * u,  J = K_rho * (grad u_sigma grad u_sigma^T),
+//   D = sum_k lambda_k v_k v_k^T over the eigenpairs of J.
+// Separable Gaussian passes (x, y[, z]) with half-sample mirror boundary,
+// central differences, then a per-point eigen map.  All passes stream the
+// planes through HBM with coalesced x-fastest accesses; the Gaussian taps
+// (truncated at ceil(3 s), normalized) are computed on the host in FP64.
+#include "common.h"
+
+namespace adlbr {
+namespace {
+
+constexpr int kMaxR = 31;
+
+struct Taps {
+    float f[2 * kMaxR + 1];
+    double d[2 * kMaxR + 1];
+    int r;
+};
+
+Taps make_taps(double s) {
+    Taps t;
+    int r = (int)ceil(3.0 * s);
+    if (r < 1) r = 1;
+    t.r = r;
+    double sum = 0.0, g[2 * kMaxR + 1];
+    for (int k = -r; k <= r; ++k) {
+        g[k + r] = exp(-(double)(k * k) / (2.0 * s * s));
+        sum += g[k + r];
+    }
+    for (int k = 0; k < 2 * r + 1; ++k) {
+        t.d[k] = g[k] / sum;
+        t.f[k] = (float)t.d[k];
+    }
+    return t;
+}
+
+template <typename T> __device__ __forceinline__ T tap(const Taps &t, int k);
+template <> __device__ __forceinline__ float tap<float>(const Taps &t, int k) { return t.f[k]; }
+template <> __device__ __forceinline__ double tap<double>(const Taps &t, int k) { return t.d[k]; }
+
+__device__ __forceinline__ int mirror(int i, int n) {
+    // half-sample symmetric extension: -1 -> 0, n -> n-1, period 2n
+    const int p = 2 * n;
+    i %= p;
+    if (i < 0) i += p;
+    return i < n ? i : p - 1 - i;
+}
+
+// Blur `planes` planes along axis `ax`; blockIdx.y selects the plane.
+template <typename T>
+__global__ void k_blur(GridInfo g, const T *__restrict__ in, T *__restrict__ out, int ax, Taps t) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long N = g.N;
+    if (i >= N) return;
+    const long long off = (long long)blockIdx.y * N;
+    const int nx = g.nx, ny = g.ny;
+    const int x = (int)(i % nx);
+    const long long rest = i / nx;
+    const int y = (int)(rest % ny);
+    const int z = (int)(rest / ny);
+    const int p = ax == 0 ? x : (ax == 1 ? y : z);
+    const int len = ax == 0 ? nx : (ax == 1 ? ny : g.nz);
+    const long long stride = ax == 0 ? 1 : (ax == 1 ? (long long)nx : (long long)nx * ny);
+    const T *src = in + off + i - (long long)p * stride;
+    T acc = (T)0;
+    if (p - t.r >= 0 && p + t.r < len) {
+        for (int k = -t.r; k <= t.r; ++k) acc += tap<T>(t, k + t.r) * src[(long long)(p + k) * stride];
+    } else {
+        for (int k = -t.r; k <= t.r; ++k)
+            acc += tap<T>(t, k + t.r) * src[(long long)mirror(p + k, len) * stride];
+    }
+    out[off + i] = acc;
+}
+
+// grad u_sigma by central differences (mirror boundary), outer products.
+template <typename T>
+__global__ void k_grad_outer(GridInfo g, const T *__restrict__ us, T *__restrict__ J) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long N = g.N;
+    if (i >= N) return;
+    const int nx = g.nx, ny = g.ny;
+    const int x = (int)(i % nx);
+    const long long rest = i / nx;
+    const int y = (int)(rest % ny);
+    const int z = (int)(rest / ny);
+    const T half = (T)0.5;
+    const T gx = half * (us[i + (mirror(x + 1, nx) - x)] - us[i + (mirror(x - 1, nx) - x)]);
+    const T gy = half * (us[i + (long long)(mirror(y + 1, ny) - y) * nx] -
+                         us[i + (long long)(mirror(y - 1, ny) - y) * nx]);
+    if (g.dim == 2) {
+        J[i] = gx * gx;
+        J[N + i] = gx * gy;
+        J[2 * N + i] = gy * gy;
+    } else {
+        const long long sz = (long long)nx * ny;
+        const T gz = half * (us[i + (long long)(mirror(z + 1, g.nz) - z) * sz] -
+                             us[i + (long long)(mirror(z - 1, g.nz) - z) * sz]);
+        J[i] = gx * gx;
+        J[N + i] = gx * gy;
+        J[2 * N + i] = gx * gz;
+        J[3 * N + i] = gy * gy;
+        J[4 * N + i] = gy * gz;
+        J[5 * N + i] = gz * gz;
+    }
+}
+
+template <typename T> __device__ __forceinline__ T coh(T C, T dmu) {
+    return dmu == (T)0 ? (T)0 : exp(-C / (dmu * dmu));
+}
+
+template <typename T> __device__ __forceinline__ T eed(T C, T mu) {
+    return mu == (T)0 ? (T)1 : (T)1 - exp(-C / (mu * mu));
+}
+
+// 2D eigen map in closed form: D = lambda_2 Id + (lambda_1 - lambda_2) v1 v1^T
+// with v1 the unit eigenvector of the larger eigenvalue mu_1.
+template <typename T>
+__global__ void k_eigmap2(long long N, const T *__restrict__ J, T *__restrict__ D, T alpha, T C,
+                          int map) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const T a = J[i], b = J[N + i], c = J[2 * N + i];
+    const T hd = (T)0.5 * (a - c);
+    const T disc = sqrt(hd * hd + b * b);
+    const T mid = (T)0.5 * (a + c);
+    const T mu1 = mid + disc, mu2 = mid - disc;
+    T vx, vy;
+    if (disc == (T)0) {
+        vx = (T)1;
+        vy = (T)0;
+    } else if (a >= c) {
+        vx = hd + disc;
+        vy = b;
+    } else {
+        vx = b;
+        vy = disc - hd;
+    }
+    const T nrm = sqrt(vx * vx + vy * vy);
+    vx /= nrm;
+    vy /= nrm;
+    T l1, l2;
+    if (map == ADLBR_MAP_CED) {
+        l1 = alpha;
+        l2 = alpha + ((T)1 - alpha) * coh(C, mu1 - mu2);
+    } else {
+        l1 = eed(C, mu1);
+        l2 = (T)1;
+    }
+    const T dl = l1 - l2;
+    D[i] = l2 + dl * vx * vx;
+    D[N + i] = dl * vx * vy;
+    D[2 * N + i] = l2 + dl * vy * vy;
+}
+
+// 3D eigen map: cyclic Jacobi rotations on the symmetric 3x3 J.
+template <typename T>
+__global__ void k_eigmap3(long long N, const T *__restrict__ J, T *__restrict__ D, T alpha, T C,
+                          int map) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    T A[3][3] = {{J[i], J[N + i], J[2 * N + i]},
+                 {J[N + i], J[3 * N + i], J[4 * N + i]},
+                 {J[2 * N + i], J[4 * N + i], J[5 * N + i]}};
+    T V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    const T eps = sizeof(T) == 8 ? (T)1e-15 : (T)1e-7;
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        const T offd = fabs(A[0][1]) + fabs(A[0][2]) + fabs(A[1][2]);
+        const T scale = fabs(A[0][0]) + fabs(A[1][1]) + fabs(A[2][2]);
+        if (offd == (T)0 || offd <= eps * scale) break;
+#pragma unroll
+        for (int pq = 0; pq < 3; ++pq) {
+            const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+            if (A[p][q] == (T)0) continue;
+            // rotation zeroing A[p][q]: tan 2th = 2 A_pq / (A_qq - A_pp)
+            const T th = (T)0.5 * atan2((T)2 * A[p][q], A[q][q] - A[p][p]);
+            const T cs = cos(th), sn = sin(th);
+            for (int k = 0; k < 3; ++k) {
+                const T akp = A[k][p], akq = A[k][q];
+                A[k][p] = cs * akp - sn * akq;
+                A[k][q] = sn * akp + cs * akq;
+            }
+            for (int k = 0; k < 3; ++k) {
+                const T apk = A[p][k], aqk = A[q][k];
+                A[p][k] = cs * apk - sn * aqk;
+                A[q][k] = sn * apk + cs * aqk;
+            }
+            for (int k = 0; k < 3; ++k) {
+                const T vkp = V[k][p], vkq = V[k][q];
+                V[k][p] = cs * vkp - sn * vkq;
+                V[k][q] = sn * vkp + cs * vkq;
+            }
+        }
+    }
+    int o[3] = {0, 1, 2};
+    for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b)
+            if (A[o[b]][o[b]] > A[o[a]][o[a]]) {
+                const int t = o[a];
+                o[a] = o[b];
+                o[b] = t;
+            }
+    const T mu[3] = {A[o[0]][o[0]], A[o[1]][o[1]], A[o[2]][o[2]]};
+    T lam[3];
+    if (map == ADLBR_MAP_CED) {
+        lam[0] = alpha;
+        lam[1] = alpha + ((T)1 - alpha) * coh(C, mu[0] - mu[1]);
+        lam[2] = alpha + ((T)1 - alpha) * coh(C, mu[0] - mu[2]);
+    } else {
+        lam[0] = eed(C, mu[0]);
+        lam[1] = eed(C, mu[1]);
+        lam[2] = (T)1;
+    }
+    const int pr[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    for (int q = 0; q < 6; ++q) {
+        T acc = (T)0;
+        for (int k = 0; k < 3; ++k) acc += lam[k] * V[pr[q][0]][o[k]] * V[pr[q][1]][o[k]];
+        D[q * N + i] = acc;
+    }
+}
+
+template <typename T>
+int run_tensor(const GridInfo &g, const T *u, const adlbr_tensor_params *p, T *D, T *wa, T *wb,
+               hipStream_t s) {
+    const long long N = g.N;
+    const int nj = g.dim == 2 ? 3 : 6;
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    const Taps ts = make_taps(p->sigma), tr = make_taps(p->rho);
+    // u_sigma
+    if (g.dim == 2) {
+        hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, u, wa, 0, ts);
+        hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, (const T *)wa, wb, 1, ts);
+        hipLaunchKernelGGL(k_grad_outer<T>, dim3(nb), dim3(256), 0, s, g, (const T *)wb, wa);
+        hipLaunchKernelGGL(k_blur<T>, dim3(nb, nj), dim3(256), 0, s, g, (const T *)wa, wb, 0, tr);
+        hipLaunchKernelGGL(k_blur<T>, dim3(nb, nj), dim3(256), 0, s, g, (const T *)wb, wa, 1, tr);
+        hipLaunchKernelGGL(k_eigmap2<T>, dim3(nb), dim3(256), 0, s, N, (const T *)wa, D,
+                           (T)p->alpha, (T)p->C, p->eig_map);
+    } else {
+        hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, u, wa, 0, ts);
+        hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, (const T *)wa, wb, 1, ts);
+        hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, (const T *)wb, wa, 2, ts);
+        hipLaunchKernelGGL(k_grad_outer<T>, dim3(nb), dim3(256), 0, s, g, (const T *)wa, wb);
+        hipLaunchKernelGGL(k_blur<T>, dim3(nb, nj), dim3(256), 0, s, g, (const T *)wb, wa, 0, tr);
+        hipLaunchKernelGGL(k_blur<T>, dim3(nb, nj), dim3(256), 0, s, g, (const T *)wa, wb, 1, tr);
+        hipLaunchKernelGGL(k_blur<T>, dim3(nb, nj), dim3(256), 0, s, g, (const T *)wb, wa, 2, tr);
+        hipLaunchKernelGGL(k_eigmap3<T>, dim3(nb), dim3(256), 0, s, N, (const T *)wa, D,
+                           (T)p->alpha, (T)p->C, p->eig_map);
+    }
+    ADLBR_LAUNCH_CHECK();
+    return ADLBR_OK;
+}
+
+}  // namespace
+}  // namespace adlbr
+
+using namespace adlbr;
+
+extern "C" int adlbr_tensor_workspace(const adlbr_grid *g, int dtype, size_t *bytes) {
+    clear_error();
+    GridInfo gi;
+    int rc = check_grid(g, &gi);
+    if (rc) return rc;
+    if (!bytes || (dtype != ADLBR_F32 && dtype != ADLBR_F64)) {
+        set_error("adlbr_tensor_workspace: dtype must be ADLBR_F32 or ADLBR_F64");
+        return ADLBR_E_INVALID;
+    }
+    const int nj = gi.dim == 2 ? 3 : 6;
+    *bytes = 2 * align_up(dtype_size(dtype) * nj * (size_t)gi.N);
+    return ADLBR_OK;
+}
+
+extern "C" int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
+                                      const adlbr_tensor_params *p, void *D, void *workspace,
+                                      size_t ws_bytes, void *stream) {
+    clear_error();
+    GridInfo gi;
+    int rc = check_grid(g, &gi);
+    if (rc) return rc;
+    if (!u || !p || !D || !workspace) {
+        set_error("adlbr_structure_tensor: null pointer argument");
+        return ADLBR_E_INVALID;
+    }
+    if (dtype != ADLBR_F32 && dtype != ADLBR_F64) {
+        set_error("adlbr_structure_tensor: dtype must be ADLBR_F32 or ADLBR_F64");
+        return ADLBR_E_INVALID;
+    }
+    if (!(p->sigma > 0.0) || !(p->rho > 0.0) || p->sigma > 10.0 || p->rho > 10.0 ||
+        !(p->alpha > 0.0) || !(p->alpha <= 1.0) || !(p->C >= 0.0) ||
+        (p->eig_map != ADLBR_MAP_CED && p->eig_map != ADLBR_MAP_EED)) {
+        set_error("adlbr_structure_tensor: need 0 < sigma, rho <= 10, 0 < alpha <= 1, C >= 0");
+        return ADLBR_E_INVALID;
+    }
+    size_t need;
+    adlbr_tensor_workspace(g, dtype, &need);
+    if (ws_bytes < need) {
+        set_error("adlbr_structure_tensor: workspace has %zu bytes, %zu needed", ws_bytes, need);
+        return ADLBR_E_NOMEM;
+    }
+    const int nj = gi.dim == 2 ? 3 : 6;
+    const size_t half = align_up(dtype_size(dtype) * nj * (size_t)gi.N);
+    char *b = (char *)workspace;
+    hipStream_t s = as_stream(stream);
+    if (dtype == ADLBR_F32)
+        return run_tensor<float>(gi, (const float *)u, p, (float *)D, (float *)b, (float *)(b + half), s);
+    return run_tensor<double>(gi, (const double *)u, p, (double *)D, (double *)b,
+                              (double *)(b + half), s);
+}
