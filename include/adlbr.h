@@ -195,6 +195,59 @@ int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
                            const adlbr_tensor_params *p, void *D,
                            void *workspace, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------ *
+ * Implicit step: solve K x = b with K = I + dt A by conjugate gradients.
+ * This is the linear system of the restoration problem
+ * -lambda div(D grad u) + u = v (Section 5, eq. (elliptic), lambda = dt,
+ * which the paper solves by CG) and of one backward-Euler step of the
+ * diffusion equation.  Vectors are in the operator's storage dtype, which
+ * must be ADLBR_F32 or ADLBR_F64; scalars and dot products are FP64.
+ *
+ * ADLBR_SOLVE_JACOBI_PCG: preconditioned CG with P = diag(K)^-1.
+ * ADLBR_SOLVE_FCG_NET:    flexible CG (truncation 1,
+ *     beta_k = <z_k, r_k - r_{k-1}> / <z_{k-1}, r_{k-1}>) with the learned
+ *     preconditioner z = r / diag(K) + N(r) of adlbr_net; if a direction is
+ *     not a descent direction (<z, r> <= 0) or a value is not finite it
+ *     restarts from the current x with Jacobi-PCG (report.fell_back = 1).
+ * Stopping: every check_every iterations the host reads the recurrence
+ * residual; when it is below tol |b| the true residual |b - K x| is
+ * recomputed with FP64 accumulation and the solve stops if that is below
+ * tol |b| too.  report (host out) then holds the iteration count and the
+ * true relative residual.  Returns ADLBR_E_NOT_CONVERGED (report filled)
+ * when max_iter is reached.
+ *   b         device [N] right-hand side
+ *   x         device [N] in/out: initial guess unless x0_zero, then solution
+ *   workspace device >= adlbr_solve_workspace() bytes
+ * Synchronizes `stream` (every check_every iterations and at the end).
+ * ------------------------------------------------------------------ */
+#define ADLBR_SOLVE_JACOBI_PCG 0
+#define ADLBR_SOLVE_FCG_NET 1
+
+typedef struct adlbr_net adlbr_net;
+
+typedef struct adlbr_solve_params {
+    int32_t method;
+    int32_t max_iter;
+    int32_t check_every;
+    int32_t x0_zero;
+    double tol;
+    const adlbr_net *net; /* required for ADLBR_SOLVE_FCG_NET */
+} adlbr_solve_params;
+
+typedef struct adlbr_solve_report {
+    int32_t iters;
+    int32_t converged;
+    int32_t fell_back;
+    int32_t net_iters; /* iterations done with the learned preconditioner */
+    double rel_res;    /* true relative residual, FP64 */
+    double time_ms;    /* wall time of the solve on the stream */
+} adlbr_solve_report;
+
+int adlbr_solve_workspace(adlbr_operator *op, int method, size_t *bytes);
+int adlbr_solve(adlbr_operator *op, double dt, const void *b, void *x,
+                const adlbr_solve_params *p, void *workspace, size_t ws_bytes,
+                adlbr_solve_report *report, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -182,6 +182,33 @@ class Operator:
         return u
 
 
+    def solve(self, b, dt: float, method: str = "jacobi", tol: float = 1e-6,
+              max_iter: int = 10000, check_every: int = 10, x=None, net=None,
+              workspace=None, stream=None):
+        """Solve (I + dt A) x = b (adlbr_solve).  Returns (x, report dict);
+        report["converged"] is 0 when max_iter was reached."""
+        torch = _torch()
+        lib = capi.load()
+        self._check_u(b)
+        code = capi.SOLVE_FCG_NET if method == "fcg" else capi.SOLVE_JACOBI_PCG
+        nbytes = ctypes.c_size_t()
+        capi.check(lib.adlbr_solve_workspace(self._h, code, ctypes.byref(nbytes)))
+        if workspace is None or workspace.numel() < nbytes.value:
+            workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        x0_zero = x is None
+        x = torch.empty_like(b) if x is None else x
+        self._check_u(x)
+        p = capi.SolveParams(code, int(max_iter), int(check_every), int(x0_zero), float(tol),
+                             None if net is None else net.handle)
+        rep = capi.SolveReport()
+        rc = lib.adlbr_solve(self._h, float(dt), _ptr(b), _ptr(x), ctypes.byref(p),
+                             _ptr(workspace), workspace.numel(), ctypes.byref(rep),
+                             _stream(stream))
+        if rc != capi.E_NOT_CONVERGED:
+            capi.check(rc)
+        return x, rep.as_dict()
+
+
 def structure_tensor(u, dims, sigma: float, rho: float, alpha: float, C: float,
                      eig_map: str = "ced", out=None, workspace=None, stream=None):
     """Diffusion tensor from the structure tensor of u (adlbr_structure_tensor)."""

@@ -34,6 +34,24 @@ class TensorParams(ctypes.Structure):
                 ("eig_map", ctypes.c_int32)]
 
 
+class SolveParams(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("x0_zero", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("net", ctypes.c_void_p)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("fell_back", ctypes.c_int32), ("net_iters", ctypes.c_int32),
+                ("rel_res", ctypes.c_double), ("time_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+SOLVE_JACOBI_PCG, SOLVE_FCG_NET = 0, 1
+
+
 class AdlbrError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"adlbr error {code}: {msg}")
@@ -60,6 +78,9 @@ SIGNATURES = {
     "adlbr_apply": ([_P, _P, _P, _P], _I),
     "adlbr_step": ([_P, _P, _P, _D, _I, _I64, _P], _I),
     "adlbr_tensor_workspace": ([_GP, _I, ctypes.POINTER(_SZ)], _I),
+    "adlbr_solve_workspace": ([_P, _I, ctypes.POINTER(_SZ)], _I),
+    "adlbr_solve": ([_P, _D, _P, _P, ctypes.POINTER(SolveParams), _P, _SZ,
+                     ctypes.POINTER(SolveReport), _P], _I),
     "adlbr_structure_tensor": ([_GP, _P, _I, ctypes.POINTER(TensorParams), _P, _P, _SZ, _P], _I),
 }
 

@@ -78,6 +78,10 @@ template <> struct Conv<float, float> {
     __device__ static float ld(float v) { return v; }
     __device__ static float st(float v) { return v; }
 };
+template <> struct Conv<float, double> {
+    __device__ static double ld(float v) { return (double)v; }
+    __device__ static float st(double v) { return (float)v; }
+};
 template <> struct Conv<bf16, float> {
     __device__ static float ld(bf16 v) { return bf16_to_f32(v); }
     __device__ static bf16 st(float v) { return f32_to_bf16(v); }
@@ -121,5 +125,76 @@ __device__ inline long long xcd_block(long long b, long long nb) {
     long long start = k * q + (k < r ? k : r);
     return start + j;
 }
+
+// Device-resident scalars of a (flexible) conjugate-gradient iteration.
+struct CgState {
+    double dt;      // K = I + dt A
+    double rz;      // <z_k, r_k>
+    double rz_old;  // <z_{k-1}, r_{k-1}>
+    double zr_prev; // <z_k, r_{k-1}> (flexible CG)
+    double pq;      // <p_k, K p_k>
+    double alpha, beta;
+    double rr;      // |r_k|^2
+    double bb;      // |b|^2
+    int32_t bad;    // non-descent direction or non-finite value
+    int32_t iter;
+    int32_t done;   // recurrence residual below tolerance: later kernels are no-ops
+    int32_t pad;
+    uint32_t ticket[4];
+};
+
+struct adlbr_net_impl;
+// Learned preconditioner z = N(r) for K = I + dt A (defined with the CNN).
+int net_apply(const adlbr_net *net, const adlbr_operator *op, double dt, const void *r, void *z,
+              hipStream_t s);
+
+// Internal entry points shared between translation units.
+int cg_direction(const adlbr_operator *op, const void *z, void *q, void *p, CgState *st,
+                 double *partial, int first, hipStream_t s);
+// |b - (I + dt A) x|^2 accumulated in FP64 into *out (deterministic).
+int true_residual(const adlbr_operator *op, double dt, const void *b, const void *x, double *out,
+                  double *partial, uint32_t *ticket, hipStream_t s);
+
+// Block sum of a double over 256 threads, then the last block to arrive sums
+// the per-block partials in block order; returns true in that block's
+// threads, with the total in `total`.
+__device__ inline bool last_block_sum(double v, double *partial, uint32_t *ticket, double &total) {
+    __shared__ double red[256];
+    __shared__ int last;
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = red[0];
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double acc = 0.0;
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += 256)
+        acc += __hip_atomic_load(&partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    total = red[0];
+    if (threadIdx.x == 0) *ticket = 0u;
+    __syncthreads();  // red[] is reused by the caller's next reduction
+    return true;
+}
+const GridInfo &operator_grid(const adlbr_operator *op);
+int operator_storage(const adlbr_operator *op);
+const void *operator_diag(const adlbr_operator *op);
+const void *operator_weights(const adlbr_operator *op);
+const void *operator_slots(const adlbr_operator *op);
+int operator_wide(const adlbr_operator *op);
 
 }  // namespace adlbr

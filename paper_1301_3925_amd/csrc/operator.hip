@@ -185,6 +185,13 @@ __device__ __forceinline__ bool edge_target(const Coord &p, long long i, const i
 }
 
 // ---------------------------------------------------------------- build --
+// Counters of consecutive points live 64 bytes apart (a 64 x 16 transpose
+// inside each 1024-point block), so that the 64 atomics of a wavefront, whose
+// targets are usually consecutive, hit 64 different cache lines.
+__device__ __forceinline__ long long spread(long long t) {
+    return (t & ~1023ll) | ((t & 63ll) << 4) | ((t >> 6) & 15ll);
+}
+
 __global__ void k_fill_i32(int32_t *p, long long n, int32_t v) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -226,7 +233,7 @@ __global__ void k_compact(GridInfo g, const int16_t *__restrict__ off, const TWi
         if (!(wq > 0.0)) continue;
         for (int sg = -1; sg <= 1; sg += 2) {
             long long t;
-            if (edge_target<DIM, PER>(p, z, s[q], sg, g, t)) atomicAdd(&count[t], 1);
+            if (edge_target<DIM, PER>(p, z, s[q], sg, g, t)) atomicAdd(&count[spread(t)], 1);
         }
     }
     report(status, z, st);
@@ -254,7 +261,7 @@ __global__ void k_scan_reduce(const int32_t *__restrict__ c, long long n, int32_
     const long long base = (long long)blockIdx.x * kScanBlock + threadIdx.x * 4;
     int32_t v = 0;
     for (int k = 0; k < 4; ++k)
-        if (base + k < n) v += min(c[base + k], 255);
+        if (base + k < n) v += min(c[spread(base + k)], 255);
     int32_t total;
     block_excl_scan256(v, lds, total);
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
@@ -281,7 +288,7 @@ __global__ void k_scan_down(const int32_t *__restrict__ c, long long n, const in
     // clamped counts so that they agree with the uint8 counts the apply scans
     int32_t v[4], sum = 0;
     for (int k = 0; k < 4; ++k) {
-        v[k] = base + k < n ? c[base + k] : 0;
+        v[k] = base + k < n ? c[spread(base + k)] : 0;
         sum += min(v[k], 255);
     }
     int32_t total;
@@ -315,7 +322,7 @@ __global__ void k_fill_entries(GridInfo g, const typename Slots<DIM, WIDE>::stor
         for (int sg = -1; sg <= 1; sg += 2) {
             long long t;
             if (!edge_target<DIM, PER>(p, y, o, sg, g, t)) continue;
-            const int32_t k = atomicAdd(&cursor[t], 1);
+            const int32_t k = atomicAdd(&cursor[spread(t)], 1);
             if (k < 255) ent[pos[t] + k] = (int32_t)(((y - t) << 3) | q);
         }
     }
@@ -336,14 +343,32 @@ __global__ void k_finalize(GridInfo g, const typename Slots<DIM, WIDE>::store_t 
         const long long N = g.N;
         const int c = cnt[z];
         int32_t *e = ent + pos[z];
-        for (int i = 1; i < c; ++i) {  // insertion sort by (source, slot)
-            const int32_t key = e[i];
-            int j = i - 1;
-            while (j >= 0 && e[j] > key) {
-                e[j + 1] = e[j];
-                --j;
+        if (c <= 16) {  // odd-even transposition network on 16 registers
+            int32_t r[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) r[i] = i < c ? e[i] : 0x7fffffff;
+#pragma unroll
+            for (int round = 0; round < 16; ++round) {
+#pragma unroll
+                for (int i = round & 1; i + 1 < 16; i += 2) {
+                    const int32_t a = r[i], b = r[i + 1];
+                    r[i] = min(a, b);
+                    r[i + 1] = max(a, b);
+                }
             }
-            e[j + 1] = key;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i < c) e[i] = r[i];
+        } else {
+            for (int i = 1; i < c; ++i) {  // insertion sort by (source, slot)
+                const int32_t key = e[i];
+                int j = i - 1;
+                while (j >= 0 && e[j] > key) {
+                    e[j + 1] = e[j];
+                    --j;
+                }
+                e[j + 1] = key;
+            }
         }
         Slots<DIM, WIDE> sl;
         sl.load(sb, z);
@@ -387,25 +412,16 @@ __device__ __forceinline__ unsigned wave_excl_scan(unsigned v) {
     return x - v;
 }
 
-// out = A u (STEP = false) or u - dt A u (STEP = true).
-template <int DIM, bool WIDE, bool PER, bool STEP, typename TS, typename TA>
-__global__ __launch_bounds__(kBS) void k_apply(
-    GridInfo g, const TS *__restrict__ u, TS *__restrict__ out,
-    const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
-    const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, double dt, const double *__restrict__ dtcfl, int dt_mode) {
+// Row z of A applied to u, given the wave-rebuilt start of z's incoming
+// list: own slots first (both signs, in-grid only), then incoming entries in
+// their sorted order.
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
+__device__ __forceinline__ TA row_Au(const GridInfo &g, long long z, TA uz, const TS *__restrict__ u,
+                                     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                                     const TS *__restrict__ w, const int32_t *__restrict__ ent,
+                                     long long start, unsigned c) {
     constexpr int S = DIM == 2 ? 3 : 6;
     const long long N = g.N;
-    const long long blk = xcd_block(blockIdx.x, gridDim.x);
-    const long long z = blk * kBS + threadIdx.x;
-    const bool live = z < N;
-    const unsigned c = live ? cnt[z] : 0u;
-    const unsigned pre = wave_excl_scan(c);
-    if (!live) return;
-    const long long z0 = z & ~63ll;
-    const long long start = (long long)pos[z0] + pre;
-
-    const TA uz = Conv<TS, TA>::ld(u[z]);
     TA acc = (TA)0;
     Slots<DIM, WIDE> sl;
     sl.load(sb, z);
@@ -422,12 +438,43 @@ __global__ __launch_bounds__(kBS) void k_apply(
         }
         acc += wq * part;
     }
-    for (unsigned k = 0; k < c; ++k) {
-        const int32_t v = ent[start + k];
-        const long long y = z + (v >> 3);
-        const TA wy = Conv<TS, TA>::ld(w[(long long)(v & 7) * N + y]);
-        acc += wy * (uz - Conv<TS, TA>::ld(u[y]));
+    // incoming entries: load a batch of 8 first so that all the dependent
+    // gathers of the batch are in flight together
+    for (unsigned k0 = 0; k0 < c; k0 += 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = k0 + j < c ? ent[start + k0 + j] : 0;
+        TA wy[8], uy[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const long long y = z + (v[j] >> 3);
+            const bool ok = k0 + j < c;
+            wy[j] = ok ? Conv<TS, TA>::ld(w[(long long)(v[j] & 7) * N + y]) : (TA)0;
+            uy[j] = ok ? Conv<TS, TA>::ld(u[y]) : uz;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc += wy[j] * (uz - uy[j]);
     }
+    return acc;
+}
+
+// out = A u (STEP = false) or u - dt A u (STEP = true).
+template <int DIM, bool WIDE, bool PER, bool STEP, typename TS, typename TA>
+__global__ __launch_bounds__(kBS) void k_apply(
+    GridInfo g, const TS *__restrict__ u, TS *__restrict__ out,
+    const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
+    const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
+    const int32_t *__restrict__ ent, double dt, const double *__restrict__ dtcfl, int dt_mode) {
+    const long long N = g.N;
+    const long long blk = xcd_block(blockIdx.x, gridDim.x);
+    const long long z = blk * kBS + threadIdx.x;
+    const bool live = z < N;
+    const unsigned c = live ? cnt[z] : 0u;
+    const unsigned pre = wave_excl_scan(c);
+    if (!live) return;
+    const long long start = (long long)pos[z & ~63ll] + pre;
+    const TA uz = Conv<TS, TA>::ld(u[z]);
+    const TA acc = row_Au<DIM, WIDE, PER, TS, TA>(g, z, uz, u, sb, w, ent, start, c);
     if (STEP) {
         const TA h = (TA)(dt_mode == ADLBR_DT_CFL ? dt * dtcfl[0] : dt);
         out[z] = Conv<TS, TA>::st(uz - h * acc);
@@ -436,11 +483,98 @@ __global__ __launch_bounds__(kBS) void k_apply(
     }
 }
 
-// ------------------------------------------------------------ dispatch --
-struct Launch {
-    hipStream_t s;
-    unsigned nb;
-};
+// Conjugate-gradient direction with K = I + dt A (dt from the state):
+//   q = K z + beta q,  p = z + beta p  (beta = 0 on the first iteration),
+// so that q = K p without a second gather.  Each block writes its partial
+// <p, q> in FP64; the last block to finish sums the partials in block order
+// (deterministic) and sets alpha = <z, r> / <p, q>.
+template <int DIM, bool WIDE, bool PER, typename T>
+__global__ __launch_bounds__(kBS) void k_cg_direction(
+    GridInfo g, const T *__restrict__ zv, T *__restrict__ q, T *__restrict__ p,
+    const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const T *__restrict__ w,
+    const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
+    const int32_t *__restrict__ ent, CgState *st, double *partial, int first) {
+    __shared__ double red[kBS];
+    const long long N = g.N;
+    const long long blk = xcd_block(blockIdx.x, gridDim.x);
+    const long long z = blk * kBS + threadIdx.x;
+    const bool live = z < N;
+    const unsigned c = live ? cnt[z] : 0u;
+    const unsigned pre = wave_excl_scan(c);
+    double pqz = 0.0;
+    const bool skip = st->bad || st->done;
+    if (live && !skip) {
+        const long long start = (long long)pos[z & ~63ll] + pre;
+        const T zz = zv[z];
+        const T acc = row_Au<DIM, WIDE, PER, T, T>(g, z, zz, zv, sb, w, ent, start, c);
+        const T dt = (T)st->dt;
+        const T beta = first ? (T)0 : (T)st->beta;
+        const T qn = zz + dt * acc + (first ? (T)0 : beta * q[z]);
+        const T pn = zz + (first ? (T)0 : beta * p[z]);
+        q[z] = qn;
+        p[z] = pn;
+        pqz = (double)pn * (double)qn;
+    }
+    red[threadIdx.x] = pqz;
+    __syncthreads();
+    for (int s = kBS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blk] = red[0];
+        __threadfence();
+        const unsigned t = atomicAdd(&st->ticket[0], 1u);
+        red[0] = (t == gridDim.x - 1) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (red[0] != 0.0) {  // last block: ordered sum of all partials
+        __threadfence();
+        double acc = 0.0;
+        for (long long b = threadIdx.x; b < gridDim.x; b += kBS)
+            acc += __hip_atomic_load(&partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = kBS / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (!skip) {
+                const double pq = red[0];
+                st->pq = pq;
+                if (!(pq > 0.0) || !isfinite(pq)) st->bad = 1;
+                st->alpha = st->bad ? 0.0 : st->rz / pq;
+            }
+            st->ticket[0] = 0u;
+        }
+    }
+}
+
+// |b - (x + dt A x)|^2 with FP64 arithmetic (weights promoted).
+template <int DIM, bool WIDE, bool PER, typename T>
+__global__ __launch_bounds__(kBS) void k_residual(
+    GridInfo g, const T *__restrict__ b, const T *__restrict__ x,
+    const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const T *__restrict__ w,
+    const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
+    const int32_t *__restrict__ ent, double dt, double *out, double *partial, uint32_t *ticket) {
+    const long long N = g.N;
+    const long long z = (long long)blockIdx.x * kBS + threadIdx.x;
+    const bool live = z < N;
+    const unsigned c = live ? cnt[z] : 0u;
+    const unsigned pre = wave_excl_scan(c);
+    double r2 = 0.0;
+    if (live) {
+        const long long start = (long long)pos[z & ~63ll] + pre;
+        const double xz = (double)x[z];
+        const double ax = row_Au<DIM, WIDE, PER, T, double>(g, z, xz, x, sb, w, ent, start, c);
+        const double r = (double)b[z] - (xz + dt * ax);
+        r2 = r * r;
+    }
+    double tot;
+    if (last_block_sum(r2, partial, ticket, tot) && threadIdx.x == 0) *out = tot;
+}
 
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
 int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_f64,
@@ -452,7 +586,9 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
     const unsigned nscan = (unsigned)((N + kScanBlock - 1) / kScanBlock);
     TS *w = (TS *)op->w;
     store_t *sb = (store_t *)op->sb;
-    hipLaunchKernelGGL(k_fill_i32, dim3(nb), dim3(kBS), 0, s, op->tmp, N, 0);
+    const long long Npad = (N + 1023) / 1024 * 1024;
+    const unsigned nbp = (unsigned)(Npad / kBS);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nbp), dim3(kBS), 0, s, op->tmp, Npad, 0);
     hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(1), 0, s, op->maxdiag);
     if (win_f64)
         hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, double, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
@@ -464,7 +600,7 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, op->bsum, (long long)nscan);
     hipLaunchKernelGGL(k_scan_down, dim3(nscan), dim3(256), 0, s, op->tmp, N, op->bsum, op->pos,
                        op->cnt, status);
-    hipLaunchKernelGGL(k_fill_i32, dim3(nb), dim3(kBS), 0, s, op->tmp, N, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nbp), dim3(kBS), 0, s, op->tmp, Npad, 0);
     hipLaunchKernelGGL((k_fill_entries<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g, sb, w,
                        op->pos, op->tmp, op->ent, off, win, win_f64);
     if (op->storage == ADLBR_F64)
@@ -533,6 +669,57 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct ApplyF 
     }
 };
 
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct CgDirF {
+    static int run(const adlbr_operator *op, const void *z, void *q, void *p, CgState *st,
+                   double *partial, int first, hipStream_t s) {
+        typedef typename Slots<DIM, WIDE>::store_t store_t;
+        const GridInfo g = op->gi;
+        const unsigned nb = (unsigned)((g.N + kBS - 1) / kBS);
+        if (op->storage != ADLBR_F32 && op->storage != ADLBR_F64) return ADLBR_E_UNSUPPORTED;
+        hipLaunchKernelGGL((k_cg_direction<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g,
+                           (const TS *)z, (TS *)q, (TS *)p, (const store_t *)op->sb,
+                           (const TS *)op->w, op->cnt, op->pos, op->ent, st, partial, first);
+        return ADLBR_OK;
+    }
+};
+template <int DIM, bool WIDE, bool PER> struct CgDirF<DIM, WIDE, PER, bf16, float> {
+    static int run(const adlbr_operator *, const void *, void *, void *, CgState *, double *, int,
+                   hipStream_t) {
+        return ADLBR_E_UNSUPPORTED;
+    }
+};
+template <int DIM, bool WIDE, bool PER> struct CgDirF<DIM, WIDE, PER, _Float16, float> {
+    static int run(const adlbr_operator *, const void *, void *, void *, CgState *, double *, int,
+                   hipStream_t) {
+        return ADLBR_E_UNSUPPORTED;
+    }
+};
+
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct ResidualF {
+    static int run(const adlbr_operator *op, double dt, const void *b, const void *x, double *out,
+                   double *partial, uint32_t *ticket, hipStream_t s) {
+        typedef typename Slots<DIM, WIDE>::store_t store_t;
+        const GridInfo g = op->gi;
+        const unsigned nb = (unsigned)((g.N + kBS - 1) / kBS);
+        hipLaunchKernelGGL((k_residual<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g,
+                           (const TS *)b, (const TS *)x, (const store_t *)op->sb,
+                           (const TS *)op->w, op->cnt, op->pos, op->ent, dt, out, partial, ticket);
+        return ADLBR_OK;
+    }
+};
+template <int DIM, bool WIDE, bool PER> struct ResidualF<DIM, WIDE, PER, bf16, float> {
+    static int run(const adlbr_operator *, double, const void *, const void *, double *, double *,
+                   uint32_t *, hipStream_t) {
+        return ADLBR_E_UNSUPPORTED;
+    }
+};
+template <int DIM, bool WIDE, bool PER> struct ResidualF<DIM, WIDE, PER, _Float16, float> {
+    static int run(const adlbr_operator *, double, const void *, const void *, double *, double *,
+                   uint32_t *, hipStream_t) {
+        return ADLBR_E_UNSUPPORTED;
+    }
+};
+
 struct Layout {
     size_t sb, w, cnt, pos, ent, diag, scal, tmp, bsum, total;
 };
@@ -551,13 +738,31 @@ Layout layout(const GridInfo &g, int storage, int wide) {
     L.ent = o;  o += align_up(4 * (size_t)(2 * S) * N);
     L.diag = o; o += align_up((storage == ADLBR_F64 ? 8 : 4) * (size_t)N);
     L.scal = o; o += 256;
-    L.tmp = o;  o += align_up(4 * (size_t)N);
+    L.tmp = o;  o += align_up(4 * (size_t)((N + 1023) / 1024 * 1024));
     L.bsum = o; o += align_up(4 * nscan + 4);
     L.total = o;
     return L;
 }
 
 }  // namespace
+
+int cg_direction(const adlbr_operator *op, const void *z, void *q, void *p, CgState *st,
+                 double *partial, int first, hipStream_t s) {
+    return dispatch<CgDirF>(op, z, q, p, st, partial, first, s);
+}
+
+int true_residual(const adlbr_operator *op, double dt, const void *b, const void *x, double *out,
+                  double *partial, uint32_t *ticket, hipStream_t s) {
+    return dispatch<ResidualF>(op, dt, b, x, out, partial, ticket, s);
+}
+
+const GridInfo &operator_grid(const adlbr_operator *op) { return op->gi; }
+int operator_storage(const adlbr_operator *op) { return op->storage; }
+const void *operator_diag(const adlbr_operator *op) { return op->diag; }
+const void *operator_weights(const adlbr_operator *op) { return op->w; }
+const void *operator_slots(const adlbr_operator *op) { return op->sb; }
+int operator_wide(const adlbr_operator *op) { return op->wide; }
+
 }  // namespace adlbr
 
 using namespace adlbr;

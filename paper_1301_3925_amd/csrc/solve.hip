@@ -1,0 +1,399 @@
+// Implicit step K x = b, K = I + dt A, by preconditioned conjugate gradients.
+//
+// All scalars live on the device (CgState); every reduction is a per-block
+// FP64 partial sum finished by the last block in block order, so a solve is
+// deterministic and needs no host round trip per iteration.  The update
+// kernel raises `done` when the recurrence residual drops below tol |b|;
+// later kernels of the same batch are then no-ops, so the iteration count is
+// exact although the host only looks every check_every iterations.  The host
+// confirms convergence with the true residual |b - K x| in FP64.
+//
+// Jacobi-PCG per iteration: update (x, r, z = r / diag K, <r,z>, <r,r>,
+// beta) -> direction (q = K z + beta q, p = z + beta p, <p,q>, alpha).
+// Flexible CG (Section 5 solves the restoration system by CG; the flexible
+// variant admits the learned preconditioner): update (x, r, <r,r>) ->
+// z = N(r) -> dots (<z,r>, <z,r_prev>, beta) -> direction.
+#include <algorithm>
+#include <cstring>
+
+#include "common.h"
+
+namespace adlbr {
+namespace {
+
+constexpr int kBS = 256;
+
+struct SolveState {
+    CgState cg;
+    double tol2bb;  // tol^2 |b|^2
+    double rr_true;
+    uint32_t tickets[8];
+};
+
+template <typename TD> __device__ __forceinline__ double inv_kd(const TD *diag, long long z, double dt) {
+    return 1.0 / (1.0 + dt * (double)diag[z]);
+}
+
+// r = b (x0 = 0) or r = b - q with q = K x; z = r / diag K (Jacobi);
+// sums <r, z> and <b, b>.
+template <typename T, typename TD>
+__global__ void k_init(long long N, const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r,
+                       T *__restrict__ z, const T *__restrict__ q, const TD *__restrict__ diag,
+                       int x0_zero, int jacobi, SolveState *st, double *part, double tol2) {
+    const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
+    double rz = 0.0, bb = 0.0;
+    if (i < N) {
+        const T bi = b[i];
+        T ri;
+        if (x0_zero) {
+            x[i] = (T)0;
+            ri = bi;
+        } else {
+            ri = bi - q[i];
+        }
+        r[i] = ri;
+        if (jacobi) {
+            const T zi = (T)((double)ri * inv_kd(diag, i, st->cg.dt));
+            z[i] = zi;
+            rz = (double)ri * (double)zi;
+        }
+        bb = (double)bi * (double)bi;
+    }
+    double t;
+    if (last_block_sum(rz, part, &st->tickets[0], t) && threadIdx.x == 0) {
+        st->cg.rz = t;
+        st->cg.beta = 0.0;
+        st->cg.iter = 0;
+        st->cg.bad = 0;
+        st->cg.done = 0;
+    }
+    if (last_block_sum(bb, part + gridDim.x, &st->tickets[1], t) && threadIdx.x == 0) {
+        st->cg.bb = t;
+        st->tol2bb = tol2 * t;
+        st->cg.rr = t;
+    }
+}
+
+// Jacobi-PCG update.
+template <typename T, typename TD>
+__global__ void k_pcg_update(long long N, T *__restrict__ x, T *__restrict__ r, T *__restrict__ z,
+                             const T *__restrict__ p, const T *__restrict__ q,
+                             const TD *__restrict__ diag, SolveState *st, double *part,
+                             double *hist) {
+    const bool skip = st->cg.done || st->cg.bad;
+    const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (i < N && !skip) {
+        const T a = (T)st->cg.alpha;
+        x[i] += a * p[i];
+        const T ri = r[i] - a * q[i];
+        r[i] = ri;
+        const T zi = (T)((double)ri * inv_kd(diag, i, st->cg.dt));
+        z[i] = zi;
+        rz = (double)ri * (double)zi;
+        rr = (double)ri * (double)ri;
+    }
+    double t_rz, t_rr;
+    const bool l1 = last_block_sum(rz, part, &st->tickets[2], t_rz);
+    const bool l2 = last_block_sum(rr, part + gridDim.x, &st->tickets[3], t_rr);
+    if (l1 && threadIdx.x == 0 && !skip) st->cg.zr_prev = t_rz;  // staged <r,z>
+    if (l2 && threadIdx.x == 0 && !skip) st->cg.rr = t_rr;
+}
+
+// Finish a PCG iteration: beta, history, convergence flag (one thread).
+__global__ void k_pcg_scalars(SolveState *st, double *hist, int max_hist) {
+    if (st->cg.done || st->cg.bad) return;
+    const double rzn = st->cg.zr_prev;
+    const double rr = st->cg.rr;
+    if (!isfinite(rzn) || !isfinite(rr) || !(st->cg.rz > 0.0)) st->cg.bad = 1;
+    st->cg.beta = st->cg.bad ? 0.0 : rzn / st->cg.rz;
+    st->cg.rz_old = st->cg.rz;
+    st->cg.rz = rzn;
+    const int it = st->cg.iter + 1;
+    st->cg.iter = it;
+    if (it < max_hist) hist[it] = rr;
+    if (rr <= st->tol2bb) st->cg.done = 1;
+}
+
+// Flexible-CG update: x += alpha p, r_new = r - alpha q, <r_new, r_new>.
+template <typename T>
+__global__ void k_fcg_update(long long N, T *__restrict__ x, const T *__restrict__ r,
+                             T *__restrict__ rn, const T *__restrict__ p, const T *__restrict__ q,
+                             SolveState *st, double *part, double *hist, int max_hist) {
+    const bool skip = st->cg.done || st->cg.bad;
+    const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
+    double rr = 0.0;
+    if (i < N && !skip) {
+        const T a = (T)st->cg.alpha;
+        x[i] += a * p[i];
+        const T ri = r[i] - a * q[i];
+        rn[i] = ri;
+        rr = (double)ri * (double)ri;
+    }
+    double t;
+    if (last_block_sum(rr, part, &st->tickets[4], t) && threadIdx.x == 0 && !skip) {
+        st->cg.rr = t;
+        const int it = st->cg.iter + 1;
+        st->cg.iter = it;
+        if (it < max_hist) hist[it] = t;
+        if (!isfinite(t)) st->cg.bad = 1;
+        if (t <= st->tol2bb) st->cg.done = 1;
+    }
+}
+
+// Flexible-CG dots: <z, r>, <z, r_prev> -> beta (first: beta = 0).
+template <typename T>
+__global__ void k_fcg_dots(long long N, const T *__restrict__ z, const T *__restrict__ r,
+                           const T *__restrict__ rp, int first, SolveState *st, double *part) {
+    const bool skip = st->cg.done || st->cg.bad;
+    const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
+    double zr = 0.0, zrp = 0.0;
+    if (i < N && !skip) {
+        const double zi = (double)z[i];
+        zr = zi * (double)r[i];
+        if (!first) zrp = zi * (double)rp[i];
+    }
+    double t1, t2;
+    const bool l1 = last_block_sum(zr, part, &st->tickets[5], t1);
+    const bool l2 = last_block_sum(zrp, part + gridDim.x, &st->tickets[6], t2);
+    if (l1 && threadIdx.x == 0 && !skip) st->cg.zr_prev = t1;  // staged <z, r>
+    if (l2 && threadIdx.x == 0 && !skip) st->cg.pq = t2;       // staged <z, r_prev>
+}
+
+__global__ void k_fcg_scalars(SolveState *st, int first) {
+    if (st->cg.done || st->cg.bad) return;
+    const double zr = st->cg.zr_prev, zrp = st->cg.pq;
+    if (!isfinite(zr) || !(zr > 0.0) || !isfinite(zrp)) {
+        st->cg.bad = 1;
+        return;
+    }
+    st->cg.beta = first ? 0.0 : (zr - zrp) / st->cg.rz;
+    st->cg.rz_old = st->cg.rz;
+    st->cg.rz = zr;
+}
+
+__global__ void k_clear_done(SolveState *st) { st->cg.done = 0; }
+
+template <typename T> __global__ void k_copy(long long N, const T *a, T *b) {
+    const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
+    if (i < N) b[i] = a[i];
+}
+
+struct SolveLayout {
+    size_t st, hist, part, vec[6], total;
+};
+
+SolveLayout solve_layout(long long N, size_t esz, int max_hist) {
+    SolveLayout L;
+    size_t o = 0;
+    const size_t nb = (size_t)((N + kBS - 1) / kBS);
+    L.st = o;   o += align_up(sizeof(SolveState));
+    L.hist = o; o += align_up(8 * (size_t)max_hist);
+    L.part = o; o += align_up(8 * 2 * nb + 64);
+    for (int k = 0; k < 6; ++k) {
+        L.vec[k] = o;
+        o += align_up(esz * (size_t)N);
+    }
+    L.total = o;
+    return L;
+}
+
+constexpr int kMaxHist = 1 << 16;
+
+template <typename T, typename TD>
+int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solve_params *p,
+               char *ws, adlbr_solve_report *rep, hipStream_t s) {
+    const GridInfo &g = operator_grid(op);
+    const long long N = g.N;
+    const unsigned nb = (unsigned)((N + kBS - 1) / kBS);
+    const SolveLayout L = solve_layout(N, sizeof(T), kMaxHist);
+    SolveState *st = (SolveState *)(ws + L.st);
+    double *hist = (double *)(ws + L.hist);
+    double *part = (double *)(ws + L.part);
+    T *r = (T *)(ws + L.vec[0]);
+    T *r2 = (T *)(ws + L.vec[1]);
+    T *z = (T *)(ws + L.vec[2]);
+    T *pv = (T *)(ws + L.vec[3]);
+    T *q = (T *)(ws + L.vec[4]);
+    const TD *diag = (const TD *)operator_diag(op);
+    const bool net = p->method == ADLBR_SOLVE_FCG_NET;
+    CgState *cg = &st->cg;
+
+    hipEvent_t e0, e1;
+    ADLBR_CHECK_HIP(hipEventCreate(&e0));
+    ADLBR_CHECK_HIP(hipEventCreate(&e1));
+    ADLBR_CHECK_HIP(hipEventRecord(e0, s));
+    // clear the state (tickets must start at 0), set dt
+    SolveState init;
+    std::memset(&init, 0, sizeof init);
+    init.cg.dt = dt;
+    ADLBR_CHECK_HIP(hipMemcpyAsync(st, &init, sizeof init, hipMemcpyHostToDevice, s));
+    if (!p->x0_zero) {
+        int rc = cg_direction(op, x, q, pv, cg, part, 1, s);  // q = K x
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL((k_init<T, TD>), dim3(nb), dim3(kBS), 0, s, N, b, x, r, z, (const T *)q, diag,
+                       p->x0_zero, (int)!net, st, part, p->tol * p->tol);
+    int rc = ADLBR_OK;
+    bool use_net = net;
+    int fell_back = 0, net_iters = 0;
+    int first = 1;
+    T *rc_ = r, *ro = r2;  // current and previous residual (flexible CG)
+    auto start_iteration = [&]() -> int {
+        if (use_net) {
+            int e = net_apply(p->net, op, dt, rc_, z, s);
+            if (e) return e;
+            hipLaunchKernelGGL((k_fcg_dots<T>), dim3(nb), dim3(kBS), 0, s, N, (const T *)z,
+                               (const T *)rc_, (const T *)ro, first, st, part);
+            hipLaunchKernelGGL(k_fcg_scalars, dim3(1), dim3(1), 0, s, st, first);
+        }
+        int e = cg_direction(op, z, q, pv, cg, part, first, s);
+        first = 0;
+        return e;
+    };
+    rc = start_iteration();
+    if (rc) return rc;
+    const int check = p->check_every > 0 ? p->check_every : 10;
+    int issued = 0;
+    bool converged = false;
+    struct Host {
+        int32_t done, bad, iter;
+    } h;
+    while (issued < p->max_iter) {
+        const int batch = std::min(check, p->max_iter - issued);
+        for (int k = 0; k < batch; ++k) {
+            if (use_net) {
+                hipLaunchKernelGGL((k_fcg_update<T>), dim3(nb), dim3(kBS), 0, s, N, x,
+                                   (const T *)rc_, ro, (const T *)pv, (const T *)q, st, part, hist,
+                                   kMaxHist);
+                std::swap(rc_, ro);  // ro now holds r_k (previous), rc_ r_{k+1}
+            } else {
+                hipLaunchKernelGGL((k_pcg_update<T, TD>), dim3(nb), dim3(kBS), 0, s, N, x, rc_, z,
+                                   (const T *)pv, (const T *)q, diag, st, part, hist);
+                hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(1), 0, s, st, hist, kMaxHist);
+            }
+            rc = start_iteration();
+            if (rc) return rc;
+        }
+        issued += batch;
+        ADLBR_CHECK_HIP(hipMemcpyAsync(&h.done, &cg->done, 4, hipMemcpyDeviceToHost, s));
+        ADLBR_CHECK_HIP(hipMemcpyAsync(&h.bad, &cg->bad, 4, hipMemcpyDeviceToHost, s));
+        ADLBR_CHECK_HIP(hipMemcpyAsync(&h.iter, &cg->iter, 4, hipMemcpyDeviceToHost, s));
+        ADLBR_CHECK_HIP(hipStreamSynchronize(s));
+        if (use_net) net_iters = h.iter;
+        if (h.bad) {
+            if (!use_net) break;  // Jacobi-PCG broke down: report as not converged
+            // learned preconditioner failed: restart from x with Jacobi-PCG
+            use_net = false;
+            fell_back = 1;
+            first = 1;
+            const int keep_iter = h.iter;
+            SolveState re;
+            std::memset(&re, 0, sizeof re);
+            re.cg.dt = dt;
+            ADLBR_CHECK_HIP(hipMemcpyAsync(st, &re, sizeof re, hipMemcpyHostToDevice, s));
+            rc = cg_direction(op, x, q, pv, cg, part, 1, s);
+            if (rc) return rc;
+            hipLaunchKernelGGL((k_init<T, TD>), dim3(nb), dim3(kBS), 0, s, N, b, x, r, z,
+                               (const T *)q, diag, 0, 1, st, part, p->tol * p->tol);
+            rc_ = r;
+            ro = r2;
+            rc = start_iteration();
+            if (rc) return rc;
+            issued = keep_iter;
+            net_iters = keep_iter;
+            continue;
+        }
+        if (h.done) {
+            rc = true_residual(op, dt, b, x, &st->rr_true, part, &st->tickets[7], s);
+            if (rc) return rc;
+            double rt = 0.0, t2 = 0.0;
+            ADLBR_CHECK_HIP(hipMemcpyAsync(&rt, &st->rr_true, 8, hipMemcpyDeviceToHost, s));
+            ADLBR_CHECK_HIP(hipMemcpyAsync(&t2, &st->tol2bb, 8, hipMemcpyDeviceToHost, s));
+            ADLBR_CHECK_HIP(hipStreamSynchronize(s));
+            if (rt <= t2) {
+                converged = true;
+                break;
+            }
+            hipLaunchKernelGGL(k_clear_done, dim3(1), dim3(1), 0, s, st);
+        }
+    }
+    // final report
+    int32_t iters = 0;
+    double bb = 0.0;
+    rc = true_residual(op, dt, b, x, &st->rr_true, part, &st->tickets[7], s);
+    if (rc) return rc;
+    double rt = 0.0;
+    ADLBR_CHECK_HIP(hipMemcpyAsync(&iters, &cg->iter, 4, hipMemcpyDeviceToHost, s));
+    ADLBR_CHECK_HIP(hipMemcpyAsync(&bb, &cg->bb, 8, hipMemcpyDeviceToHost, s));
+    ADLBR_CHECK_HIP(hipMemcpyAsync(&rt, &st->rr_true, 8, hipMemcpyDeviceToHost, s));
+    ADLBR_CHECK_HIP(hipEventRecord(e1, s));
+    ADLBR_CHECK_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rep) {
+        rep->iters = fell_back ? net_iters + iters : iters;
+        rep->converged = converged;
+        rep->fell_back = fell_back;
+        rep->net_iters = net ? (fell_back ? net_iters : iters) : 0;
+        rep->rel_res = bb > 0.0 ? sqrt(rt / bb) : 0.0;
+        rep->time_ms = ms;
+    }
+    if (!converged) {
+        set_error("adlbr_solve: not converged after %d iterations (relative residual %.3e)",
+                  rep ? rep->iters : iters, bb > 0.0 ? sqrt(rt / bb) : 0.0);
+        return ADLBR_E_NOT_CONVERGED;
+    }
+    return ADLBR_OK;
+}
+
+}  // namespace
+}  // namespace adlbr
+
+using namespace adlbr;
+
+extern "C" int adlbr_solve_workspace(adlbr_operator *op, int method, size_t *bytes) {
+    clear_error();
+    if (!op || !bytes || (method != ADLBR_SOLVE_JACOBI_PCG && method != ADLBR_SOLVE_FCG_NET)) {
+        set_error("adlbr_solve_workspace: bad argument");
+        return ADLBR_E_INVALID;
+    }
+    const int sto = operator_storage(op);
+    if (sto != ADLBR_F32 && sto != ADLBR_F64) {
+        set_error("adlbr_solve_workspace: the operator's storage must be ADLBR_F32 or ADLBR_F64");
+        return ADLBR_E_UNSUPPORTED;
+    }
+    *bytes = solve_layout(operator_grid(op).N, dtype_size(sto), kMaxHist).total;
+    return ADLBR_OK;
+}
+
+extern "C" int adlbr_solve(adlbr_operator *op, double dt, const void *b, void *x,
+                           const adlbr_solve_params *p, void *workspace, size_t ws_bytes,
+                           adlbr_solve_report *report, void *stream) {
+    clear_error();
+    if (!op || !b || !x || !p || !workspace || b == x) {
+        set_error("adlbr_solve: null or aliased argument");
+        return ADLBR_E_INVALID;
+    }
+    if (!(dt >= 0.0) || !(p->tol > 0.0) || p->max_iter < 1 ||
+        (p->method != ADLBR_SOLVE_JACOBI_PCG && p->method != ADLBR_SOLVE_FCG_NET) ||
+        (p->method == ADLBR_SOLVE_FCG_NET && !p->net)) {
+        set_error("adlbr_solve: need dt >= 0, tol > 0, max_iter >= 1, a known method (and a net for FCG)");
+        return ADLBR_E_INVALID;
+    }
+    size_t need = 0;
+    int rc = adlbr_solve_workspace(op, p->method, &need);
+    if (rc) return rc;
+    if (ws_bytes < need) {
+        set_error("adlbr_solve: workspace has %zu bytes, %zu needed", ws_bytes, need);
+        return ADLBR_E_NOMEM;
+    }
+    hipStream_t s = as_stream(stream);
+    if (operator_storage(op) == ADLBR_F32)
+        return solve_impl<float, float>(op, dt, (const float *)b, (float *)x, p, (char *)workspace,
+                                        report, s);
+    return solve_impl<double, double>(op, dt, (const double *)b, (double *)x, p, (char *)workspace,
+                                      report, s);
+}
