@@ -201,7 +201,10 @@ int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
  * -lambda div(D grad u) + u = v (Section 5, eq. (elliptic), lambda = dt,
  * which the paper solves by CG) and of one backward-Euler step of the
  * diffusion equation.  Vectors are in the operator's storage dtype, which
- * must be ADLBR_F32 or ADLBR_F64; scalars and dot products are FP64.
+ * must be ADLBR_F32 or ADLBR_F64; scalars and dot products are FP64, and
+ * the iterate itself is accumulated in FP64 (an FP32-rounded solution could
+ * not reach a small true residual when |K| is large); x receives its
+ * rounding and report.rel_res is the true residual of the FP64 iterate.
  *
  * ADLBR_SOLVE_JACOBI_PCG: preconditioned CG with P = diag(K)^-1.
  * ADLBR_SOLVE_FCG_NET:    flexible CG (truncation 1,
@@ -223,7 +226,82 @@ int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
 #define ADLBR_SOLVE_JACOBI_PCG 0
 #define ADLBR_SOLVE_FCG_NET 1
 
-typedef struct adlbr_net adlbr_net;
+/* ------------------------------------------------------------------ *
+ * Learned preconditioner (an extension; the paper has none).
+ *   z = r / diag(K) + N(r),  K = I + dt A,
+ * N: four zero-padded 3x3 (3x3x3) convolutions on r, width channels
+ * (1 -> W -> W -> W -> 1, no bias), each output multiplied point-wise by
+ * gates G = sigmoid(WB relu(conv(F; WA) + bA) + bB) (3W + 1 channels) that a
+ * small gate net computes once per operator from per-point features F:
+ *   F = [1/diag(K), dt w_q / diag(K) (S slots), D / tr D (3 or 6)],
+ *   D = sum_{e in V(z)} gamma e e^T recovered from the stencil (eq. (DSum)).
+ * N is linear in r, so flexible CG sees a fixed linear preconditioner.
+ * params: FP32, in this order (T = 3^d taps, (dz,) dy, dx row-major over
+ * offsets -1, 0, +1):
+ *   WA [hidden][nfeat][T], bA [hidden], WB [3W+1][hidden], bB [3W+1],
+ *   W1 [W][1][T], W2 [W][W][T], W3 [W][W][T], W4 [1][W][T].
+ * The struct is plain data owned by the caller; every array is device
+ * memory of the operator's grid (N points):
+ *   features [nfeat][N] FP32   (adlbr_net_features)
+ *   hidden   [hidden][N] FP32  pre-activation of the gate net (adlbr_net_gates)
+ *   gates    [3W+1][N] FP32    (adlbr_net_gates)
+ *   gates16  [N][3W+1] BF16    packed copy for the inference kernel
+ *   scratch  [2W][N] FP32      working planes of the FP32 forward path
+ * ------------------------------------------------------------------ */
+typedef struct adlbr_net {
+    int32_t dim;    /* 2 or 3 */
+    int32_t width;  /* r-path channels, 16 */
+    int32_t hidden; /* gate-net channels, 16 */
+    int32_t nfeat;  /* 7 in 2D, 13 in 3D */
+    float *params;
+    float *features;
+    float *hidden_act;
+    float *gates;
+    uint16_t *gates16;
+    float *scratch;
+} adlbr_net;
+
+/* Number of FP32 parameters for (dim, width, hidden). */
+int adlbr_net_param_count(int dim, int width, int hidden, size_t *count);
+/* Features of the operator at time step dt into net->features. */
+int adlbr_net_features(adlbr_operator *op, double dt, adlbr_net *net, void *stream);
+/* Gate net forward: net->hidden_act, net->gates and net->gates16. */
+int adlbr_net_gates(adlbr_operator *op, adlbr_net *net, void *stream);
+/* z = r / diag(K) + N(r).  r, z: device [N] FP32.  If saved is not null
+ * (device [3W+1][N] FP32) the pre-gate outputs of the four layers are kept
+ * for adlbr_net_backward. */
+int adlbr_net_forward(adlbr_operator *op, const adlbr_net *net, const float *r, float *z,
+                      float *saved, void *stream);
+/* The inference path flexible CG uses: in 2D with net->gates16 set, the
+ * fused BF16 MFMA kernel (activations and weights rounded to BF16, FP32
+ * accumulation); otherwise the FP32 path of adlbr_net_forward. */
+int adlbr_net_precondition(adlbr_operator *op, const adlbr_net *net, const float *r, float *z,
+                           void *stream);
+/* Backward of sum(gz * z) for one sample: adds the r-path weight
+ * gradients to gparams (device, param_count FP32) and the gate gradients
+ * to ggates (device [3W+1][N] FP32).  workspace >= adlbr_net_workspace(). */
+int adlbr_net_backward(adlbr_operator *op, const adlbr_net *net, const float *r,
+                       const float *gz, const float *saved, float *gparams, float *ggates,
+                       void *workspace, size_t ws_bytes, void *stream);
+/* Backward through the gate net: adds the gate-net weight gradients from
+ * ggates (accumulated over a batch) to gparams. */
+int adlbr_net_gates_backward(adlbr_operator *op, const adlbr_net *net, const float *ggates,
+                             float *gparams, void *workspace, size_t ws_bytes, void *stream);
+int adlbr_net_workspace(adlbr_operator *op, const adlbr_net *net, size_t *bytes);
+/* Energy loss of the preconditioned residual, the training objective:
+ * loss += (1/2 z^T K z - z^T r) / (r^T r)  (device double), and
+ * gz = (K z - r) / (r^T r).  r, z, gz: device [N] FP32. */
+int adlbr_net_loss_grad(adlbr_operator *op, double dt, const float *r, const float *z,
+                        float *gz, double *loss, void *workspace, size_t ws_bytes,
+                        void *stream);
+/* Adam step (step counts from 1): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr mhat / (sqrt(vhat) + eps).  All device FP32 [n]. */
+int adlbr_net_adam(float *params, const float *grads, float *m, float *v, int64_t n,
+                   int32_t step, double lr, double beta1, double beta2, double eps,
+                   void *stream);
+/* r = b - (I + dt A) x (device, the operator's storage dtype). */
+int adlbr_residual(adlbr_operator *op, double dt, const void *b, const void *x, void *r,
+                   void *stream);
 
 typedef struct adlbr_solve_params {
     int32_t method;

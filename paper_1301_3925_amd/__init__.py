@@ -230,3 +230,178 @@ def structure_tensor(u, dims, sigma: float, rho: float, alpha: float, C: float,
                                           _ptr(out), _ptr(workspace), workspace.numel(),
                                           _stream(stream)))
     return out
+
+
+class Net:
+    """Learned preconditioner z = r / diag(K) + N(r) of an FP32 operator
+    (adlbr_net_*).  Holds the parameters and the per-operator buffers."""
+
+    def __init__(self, op: "Operator", params=None, seed: int = 0):
+        torch = _torch()
+        lib = capi.load()
+        self.op = op
+        self.dim = len(op.dims)
+        self.N = op.N
+        cnt = ctypes.c_size_t()
+        capi.check(lib.adlbr_net_param_count(self.dim, 16, 16, ctypes.byref(cnt)))
+        self.nparams = cnt.value
+        dev = op.device
+        if params is None:
+            params = self.init_params(self.dim, seed)
+        self.params = params.to(device=dev, dtype=torch.float32).contiguous()
+        if self.params.numel() != self.nparams:
+            raise ValueError(f"need {self.nparams} parameters")
+        nf = 7 if self.dim == 2 else 13
+        N = self.N
+        self.features = torch.empty((nf, N), dtype=torch.float32, device=dev)
+        self.hidden_act = torch.empty((16, N), dtype=torch.float32, device=dev)
+        self.gates = torch.empty((49, N), dtype=torch.float32, device=dev)
+        self.gates16 = torch.empty((N, 49), dtype=torch.int16, device=dev)
+        self.scratch = torch.empty((32, N), dtype=torch.float32, device=dev)
+        self._s = capi.NetStruct(self.dim, 16, 16, nf, self.params.data_ptr(),
+                                 self.features.data_ptr(), self.hidden_act.data_ptr(),
+                                 self.gates.data_ptr(), self.gates16.data_ptr(),
+                                 self.scratch.data_ptr())
+        self._ws = None
+
+    @staticmethod
+    def init_params(dim: int, seed: int = 0):
+        """He-style random initialization (host, seeded); gate biases +2 and a
+        small output layer, so the untrained net is a mild perturbation of
+        Jacobi.  Order as in adlbr.h."""
+        import numpy as np
+        torch = _torch()
+        rng = np.random.Generator(np.random.PCG64(seed))
+        T = 3 ** dim
+        nf = 7 if dim == 2 else 13
+        parts = [rng.normal(0, (2.0 / (nf * T)) ** 0.5, 16 * nf * T), np.zeros(16),
+                 rng.normal(0, (2.0 / 16) ** 0.5, 49 * 16), np.full(49, 2.0),
+                 rng.normal(0, (2.0 / T) ** 0.5, 16 * T),
+                 rng.normal(0, (2.0 / (16 * T)) ** 0.5, 16 * 16 * T),
+                 rng.normal(0, (2.0 / (16 * T)) ** 0.5, 16 * 16 * T),
+                 rng.normal(0, 0.1 / (16 * T) ** 0.5, 16 * T)]
+        return torch.from_numpy(np.concatenate(parts)).float()
+
+    @property
+    def handle(self):
+        return ctypes.cast(ctypes.pointer(self._s), ctypes.c_void_p)
+
+    def workspace(self):
+        torch = _torch()
+        if self._ws is None:
+            nb = ctypes.c_size_t()
+            capi.check(capi.load().adlbr_net_workspace(self.op.handle, self.handle,
+                                                       ctypes.byref(nb)))
+            self._ws = torch.empty(nb.value, dtype=torch.uint8, device=self.op.device)
+        return self._ws
+
+    def prepare(self, dt: float, stream=None):
+        """Features of the operator at dt, then the gates (adlbr_net_features,
+        adlbr_net_gates)."""
+        lib = capi.load()
+        capi.check(lib.adlbr_net_features(self.op.handle, float(dt), self.handle, _stream(stream)))
+        self.refresh_gates(stream)
+
+    def refresh_gates(self, stream=None):
+        capi.check(capi.load().adlbr_net_gates(self.op.handle, self.handle, _stream(stream)))
+
+    def forward(self, r, saved=None, out=None, stream=None):
+        torch = _torch()
+        z = torch.empty_like(r) if out is None else out
+        capi.check(capi.load().adlbr_net_forward(self.op.handle, self.handle, _ptr(r), _ptr(z),
+                                                 None if saved is None else _ptr(saved),
+                                                 _stream(stream)))
+        return z
+
+    def precondition(self, r, out=None, stream=None):
+        """The inference path used inside flexible CG (adlbr_net_precondition)."""
+        torch = _torch()
+        z = torch.empty_like(r) if out is None else out
+        capi.check(capi.load().adlbr_net_precondition(self.op.handle, self.handle, _ptr(r),
+                                                      _ptr(z), _stream(stream)))
+        return z
+
+    def backward(self, r, gz, saved, gparams, ggates, stream=None):
+        ws = self.workspace()
+        capi.check(capi.load().adlbr_net_backward(self.op.handle, self.handle, _ptr(r), _ptr(gz),
+                                                  _ptr(saved), _ptr(gparams), _ptr(ggates),
+                                                  _ptr(ws), ws.numel(), _stream(stream)))
+
+    def gates_backward(self, ggates, gparams, stream=None):
+        ws = self.workspace()
+        capi.check(capi.load().adlbr_net_gates_backward(self.op.handle, self.handle, _ptr(ggates),
+                                                        _ptr(gparams), _ptr(ws), ws.numel(),
+                                                        _stream(stream)))
+
+    def loss_grad(self, dt, r, z, gz, loss, stream=None):
+        ws = self.workspace()
+        capi.check(capi.load().adlbr_net_loss_grad(self.op.handle, float(dt), _ptr(r), _ptr(z),
+                                                   _ptr(gz), _ptr(loss), _ptr(ws), ws.numel(),
+                                                   _stream(stream)))
+
+
+def residual(op: "Operator", b, x, dt: float, out=None, stream=None):
+    """r = b - (I + dt A) x (adlbr_residual)."""
+    torch = _torch()
+    r = torch.empty_like(b) if out is None else out
+    capi.check(capi.load().adlbr_residual(op.handle, float(dt), _ptr(b), _ptr(x), _ptr(r),
+                                          _stream(stream)))
+    return r
+
+
+def adam(params, grads, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
+         stream=None):
+    capi.check(capi.load().adlbr_net_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v),
+                                          params.numel(), int(step), float(lr), float(beta1),
+                                          float(beta2), float(eps), _stream(stream)))
+
+
+def train_net(op: "Operator", dt: float, rhs_seeds, steps: int = 400, batch: int = 4,
+              lr: float = 2e-3, seed: int = 0, snapshot_iters=(1, 2, 4, 8, 16, 32),
+              log_every: int = 0):
+    """Train the preconditioner on residuals the solver itself generates:
+    for each right-hand side, Jacobi-PCG stopped after k iterations leaves a
+    residual r_k = b - K x_k (adlbr_residual); each Adam step takes `batch`
+    of them, minimizes the energy loss (adlbr_net_loss_grad) through the
+    network's own backward kernels and updates with adlbr_net_adam.
+    Returns (net, history of losses)."""
+    import numpy as np
+    from . import synth
+    torch = _torch()
+    dev = op.device
+    net = Net(op, seed=seed)
+    net.prepare(dt)
+    samples = []
+    for s in rhs_seeds:
+        b = torch.from_numpy(synth.uniform(s, op.N)).float().to(dev)
+        for k in snapshot_iters:
+            x, _ = op.solve(b, dt, max_iter=k, check_every=k)
+            samples.append(residual(op, b, x, dt))
+    R = torch.stack(samples)
+    saved = torch.empty((batch, 49, op.N), dtype=torch.float32, device=dev)
+    z = torch.empty((batch, op.N), dtype=torch.float32, device=dev)
+    gz = torch.empty_like(z)
+    gparams = torch.zeros(net.nparams, dtype=torch.float32, device=dev)
+    ggates = torch.zeros((49, op.N), dtype=torch.float32, device=dev)
+    m = torch.zeros_like(gparams)
+    v = torch.zeros_like(gparams)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    hist = []
+    for it in range(1, steps + 1):
+        idx = rng.choice(R.shape[0], size=batch, replace=False)
+        gparams.zero_()
+        ggates.zero_()
+        loss.zero_()
+        for j, k in enumerate(idx):
+            r = R[int(k)]
+            net.forward(r, saved=saved[j], out=z[j])
+            net.loss_grad(dt, r, z[j], gz[j], loss)
+            net.backward(r, gz[j], saved[j], gparams, ggates)
+        net.gates_backward(ggates, gparams)
+        gparams.mul_(1.0 / batch)
+        adam(net.params, gparams, m, v, it, lr)
+        net.refresh_gates()
+        if log_every and (it % log_every == 0 or it == 1):
+            hist.append((it, float(loss.item()) / batch))
+    return net, hist

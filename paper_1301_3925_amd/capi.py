@@ -52,6 +52,14 @@ class SolveReport(ctypes.Structure):
 SOLVE_JACOBI_PCG, SOLVE_FCG_NET = 0, 1
 
 
+class NetStruct(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("hidden", ctypes.c_int32), ("nfeat", ctypes.c_int32),
+                ("params", ctypes.c_void_p), ("features", ctypes.c_void_p),
+                ("hidden_act", ctypes.c_void_p), ("gates", ctypes.c_void_p),
+                ("gates16", ctypes.c_void_p), ("scratch", ctypes.c_void_p)]
+
+
 class AdlbrError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"adlbr error {code}: {msg}")
@@ -82,6 +90,17 @@ SIGNATURES = {
     "adlbr_solve": ([_P, _D, _P, _P, ctypes.POINTER(SolveParams), _P, _SZ,
                      ctypes.POINTER(SolveReport), _P], _I),
     "adlbr_structure_tensor": ([_GP, _P, _I, ctypes.POINTER(TensorParams), _P, _P, _SZ, _P], _I),
+    "adlbr_net_param_count": ([_I, _I, _I, ctypes.POINTER(_SZ)], _I),
+    "adlbr_net_features": ([_P, _D, _P, _P], _I),
+    "adlbr_net_gates": ([_P, _P, _P], _I),
+    "adlbr_net_forward": ([_P, _P, _P, _P, _P, _P], _I),
+    "adlbr_net_precondition": ([_P, _P, _P, _P, _P], _I),
+    "adlbr_net_backward": ([_P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], _I),
+    "adlbr_net_gates_backward": ([_P, _P, _P, _P, _P, _SZ, _P], _I),
+    "adlbr_net_workspace": ([_P, _P, ctypes.POINTER(_SZ)], _I),
+    "adlbr_net_loss_grad": ([_P, _D, _P, _P, _P, _P, _P, _SZ, _P], _I),
+    "adlbr_net_adam": ([_P, _P, _P, _P, _I64, ctypes.c_int32, _D, _D, _D, _D, _P], _I),
+    "adlbr_residual": ([_P, _D, _P, _P, _P, _P], _I),
 }
 
 _lib = None

@@ -151,9 +151,11 @@ int net_apply(const adlbr_net *net, const adlbr_operator *op, double dt, const v
 // Internal entry points shared between translation units.
 int cg_direction(const adlbr_operator *op, const void *z, void *q, void *p, CgState *st,
                  double *partial, int first, hipStream_t s);
-// |b - (I + dt A) x|^2 accumulated in FP64 into *out (deterministic).
-int true_residual(const adlbr_operator *op, double dt, const void *b, const void *x, double *out,
-                  double *partial, uint32_t *ticket, hipStream_t s);
+// |b - (I + dt A) x|^2 for an FP64 iterate x, accumulated in FP64 into
+// *out (deterministic); the residual itself goes to rout (storage dtype) if
+// rout is not null.
+int true_residual(const adlbr_operator *op, double dt, const void *b, const double *x,
+                  double *out, double *partial, uint32_t *ticket, void *rout, hipStream_t s);
 
 // Block sum of a double over 256 threads, then the last block to arrive sums
 // the per-block partials in block order; returns true in that block's

@@ -19,7 +19,9 @@
 //   pos    [N] int32 start of each point's incoming list; the apply only
 //          reads the entry at the first point of each 64-point slice and
 //          rebuilds the rest with a wavefront prefix sum of cnt.
-//   ent    incoming entries, int32 ((y - z) << 3 | slot), sorted per row.
+//   ent    incoming entries, int32 ((y - z) << 9 | slot << 6 | lane), lane =
+//          z mod 64 (the target's position in its wavefront), sorted per row;
+//          |y - z| < 2^22.
 //   diag   [N] A_zz (double for FP64 storage, float otherwise).
 #include <new>
 
@@ -185,12 +187,6 @@ __device__ __forceinline__ bool edge_target(const Coord &p, long long i, const i
 }
 
 // ---------------------------------------------------------------- build --
-// Counters of consecutive points live 64 bytes apart (a 64 x 16 transpose
-// inside each 1024-point block), so that the 64 atomics of a wavefront, whose
-// targets are usually consecutive, hit 64 different cache lines.
-__device__ __forceinline__ long long spread(long long t) {
-    return (t & ~1023ll) | ((t & 63ll) << 4) | ((t >> 6) & 15ll);
-}
 
 __global__ void k_fill_i32(int32_t *p, long long n, int32_t v) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -233,7 +229,11 @@ __global__ void k_compact(GridInfo g, const int16_t *__restrict__ off, const TWi
         if (!(wq > 0.0)) continue;
         for (int sg = -1; sg <= 1; sg += 2) {
             long long t;
-            if (edge_target<DIM, PER>(p, z, s[q], sg, g, t)) atomicAdd(&count[spread(t)], 1);
+            if (!edge_target<DIM, PER>(p, z, s[q], sg, g, t)) continue;
+            // entries store z - t in 23 bits; such an edge is flagged and
+            // left out of both the count and the fill
+            if (z - t >= (1ll << 22) || z - t <= -(1ll << 22)) continue;
+            atomicAdd(&count[t], 1);
         }
     }
     report(status, z, st);
@@ -261,7 +261,7 @@ __global__ void k_scan_reduce(const int32_t *__restrict__ c, long long n, int32_
     const long long base = (long long)blockIdx.x * kScanBlock + threadIdx.x * 4;
     int32_t v = 0;
     for (int k = 0; k < 4; ++k)
-        if (base + k < n) v += min(c[spread(base + k)], 255);
+        if (base + k < n) v += min(c[base + k], 255);
     int32_t total;
     block_excl_scan256(v, lds, total);
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
@@ -288,7 +288,7 @@ __global__ void k_scan_down(const int32_t *__restrict__ c, long long n, const in
     // clamped counts so that they agree with the uint8 counts the apply scans
     int32_t v[4], sum = 0;
     for (int k = 0; k < 4; ++k) {
-        v[k] = base + k < n ? c[spread(base + k)] : 0;
+        v[k] = base + k < n ? c[base + k] : 0;
         sum += min(v[k], 255);
     }
     int32_t total;
@@ -308,7 +308,8 @@ template <int DIM, bool WIDE, bool PER, typename TS>
 __global__ void k_fill_entries(GridInfo g, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
                                const TS *__restrict__ w, const int32_t *__restrict__ pos,
                                int32_t *__restrict__ cursor, int32_t *__restrict__ ent,
-                               const int16_t *__restrict__ off, const void *win, int win_f64) {
+                               const int16_t *__restrict__ off, const void *win, int win_f64,
+                               int32_t *status) {
     const long long y = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (y >= g.N) return;
     constexpr int S = DIM == 2 ? 3 : 6;
@@ -322,8 +323,13 @@ __global__ void k_fill_entries(GridInfo g, const typename Slots<DIM, WIDE>::stor
         for (int sg = -1; sg <= 1; sg += 2) {
             long long t;
             if (!edge_target<DIM, PER>(p, y, o, sg, g, t)) continue;
-            const int32_t k = atomicAdd(&cursor[spread(t)], 1);
-            if (k < 255) ent[pos[t] + k] = (int32_t)(((y - t) << 3) | q);
+            const long long dlt = y - t;
+            if (dlt >= (1ll << 22) || dlt <= -(1ll << 22)) {
+                report(status, y, ADLBR_ST_RANGE);
+                continue;
+            }
+            const int32_t k = atomicAdd(&cursor[t], 1);
+            if (k < 255) ent[pos[t] + k] = (int32_t)((dlt << 9) | (q << 6) | (t & 63));
         }
     }
 }
@@ -382,7 +388,7 @@ __global__ void k_finalize(GridInfo g, const typename Slots<DIM, WIDE>::store_t 
         }
         for (int k = 0; k < c; ++k) {
             const int32_t v = e[k];
-            d += (double)Conv<TS, TA>::ld(w[(long long)(v & 7) * N + z + (v >> 3)]);
+            d += (double)Conv<TS, TA>::ld(w[(long long)((v >> 6) & 7) * N + z + (v >> 9)]);
         }
         diag[z] = (TD)d;
     }
@@ -401,7 +407,7 @@ __global__ void k_cfl(const unsigned long long *maxdiag, double *dtcfl) {
 }
 
 // ---------------------------------------------------------------- apply --
-__device__ __forceinline__ unsigned wave_excl_scan(unsigned v) {
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned v) {
     const unsigned lane = threadIdx.x & 63u;
     unsigned x = v;
 #pragma unroll
@@ -409,17 +415,37 @@ __device__ __forceinline__ unsigned wave_excl_scan(unsigned v) {
         const unsigned y = __shfl_up(x, d, 64);
         if (lane >= (unsigned)d) x += y;
     }
-    return x - v;
+    return x;
 }
 
-// Row z of A applied to u, given the wave-rebuilt start of z's incoming
-// list: own slots first (both signs, in-grid only), then incoming entries in
-// their sorted order.
-template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
-__device__ __forceinline__ TA row_Au(const GridInfo &g, long long z, TA uz, const TS *__restrict__ u,
-                                     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
-                                     const TS *__restrict__ w, const int32_t *__restrict__ ent,
-                                     long long start, unsigned c) {
+// Where a wavefront's incoming lists are: the 64 consecutive rows of the
+// wave own the entries [start, start + total) in row order; this lane's row
+// owns [lo, hi) relative to start.
+struct WaveLists {
+    long long start;
+    unsigned total, lo, hi;
+};
+
+__device__ __forceinline__ WaveLists wave_lists(const uint8_t *__restrict__ cnt,
+                                                const int32_t *__restrict__ pos, long long z,
+                                                long long N) {
+    WaveLists L;
+    const unsigned c = z < N ? cnt[z] : 0u;
+    const unsigned incl = wave_incl_scan(c);
+    L.total = __shfl(incl, 63, 64);
+    L.lo = incl - c;
+    L.hi = incl;
+    const long long z0 = z & ~63ll;
+    L.start = z0 < N ? (long long)pos[z0] : 0;
+    return L;
+}
+
+// Own part of row z: sum over slots o and signs s with z + s o in the grid
+// of w_o(z) (u(z) - u(z + s o)).
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TU>
+__device__ __forceinline__ TA row_own(const GridInfo &g, long long z, TA uz, const TU *__restrict__ u,
+                                      const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                                      const TS *__restrict__ w) {
     constexpr int S = DIM == 2 ? 3 : 6;
     const long long N = g.N;
     TA acc = (TA)0;
@@ -434,26 +460,48 @@ __device__ __forceinline__ TA row_Au(const GridInfo &g, long long z, TA uz, cons
         for (int sg = -1; sg <= 1; sg += 2) {
             long long t;
             if (edge_target<DIM, PER>(p, z, sl.o[q], sg, g, t))
-                part += uz - Conv<TS, TA>::ld(u[t]);
+                part += uz - Conv<TU, TA>::ld(u[t]);
         }
         acc += wq * part;
     }
-    // incoming entries: load a batch of 8 first so that all the dependent
-    // gathers of the batch are in flight together
-    for (unsigned k0 = 0; k0 < c; k0 += 8) {
-        int32_t v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = k0 + j < c ? ent[start + k0 + j] : 0;
-        TA wy[8], uy[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const long long y = z + (v[j] >> 3);
-            const bool ok = k0 + j < c;
-            wy[j] = ok ? Conv<TS, TA>::ld(w[(long long)(v[j] & 7) * N + y]) : (TA)0;
-            uy[j] = ok ? Conv<TS, TA>::ld(u[y]) : uz;
+    return acc;
+}
+
+// Incoming part of the rows of one wavefront, computed cooperatively: the
+// wave's entries are taken 64 at a time (coalesced loads, every lane busy),
+// each lane evaluates one edge w_slot(y) (u(row) - u(y)), and a segmented
+// inclusive scan over the lanes (entries are grouped by row, rows ascend)
+// sums each row's run; every lane then picks up its own row's sum from the
+// lane holding the end of that run.  The order of additions is fixed, so the
+// result is deterministic.  All 64 lanes must call this.
+template <typename TS, typename TA, typename TU>
+__device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, long long N, TA uz,
+                                            const TU *__restrict__ u, const TS *__restrict__ w,
+                                            const int32_t *__restrict__ ent) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const long long z0 = z & ~63ll;
+    TA acc = (TA)0;
+    for (unsigned e0 = 0; e0 < L.total; e0 += 64) {
+        const unsigned e = e0 + lane;
+        const bool valid = e < L.total;
+        const int32_t v = valid ? ent[L.start + e] : 0;
+        const int row = valid ? (v & 63) : 64;
+        const TA ur = __shfl(uz, row & 63, 64);
+        TA val = (TA)0;
+        if (valid) {
+            const long long y = z0 + (v & 63) + (v >> 9);
+            val = Conv<TS, TA>::ld(w[(long long)((v >> 6) & 7) * N + y]) * (ur - Conv<TU, TA>::ld(u[y]));
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc += wy[j] * (uz - uy[j]);
+        for (int d = 1; d < 64; d <<= 1) {
+            const TA vu = __shfl_up(val, d, 64);
+            const int ru = __shfl_up(row, d, 64);
+            if (lane >= d && ru == row) val += vu;
+        }
+        const unsigned lo = L.lo > e0 ? L.lo : e0;
+        const unsigned hi = L.hi < e0 + 64 ? L.hi : e0 + 64;
+        const TA mine = __shfl(val, (int)((hi - 1 - e0) & 63u), 64);
+        if (hi > lo) acc += mine;
     }
     return acc;
 }
@@ -469,12 +517,11 @@ __global__ __launch_bounds__(kBS) void k_apply(
     const long long blk = xcd_block(blockIdx.x, gridDim.x);
     const long long z = blk * kBS + threadIdx.x;
     const bool live = z < N;
-    const unsigned c = live ? cnt[z] : 0u;
-    const unsigned pre = wave_excl_scan(c);
+    const WaveLists L = wave_lists(cnt, pos, z, N);
+    const TA uz = live ? Conv<TS, TA>::ld(u[z]) : (TA)0;
+    TA acc = wave_incoming<TS, TA, TS>(L, z, N, uz, u, w, ent);
     if (!live) return;
-    const long long start = (long long)pos[z & ~63ll] + pre;
-    const TA uz = Conv<TS, TA>::ld(u[z]);
-    const TA acc = row_Au<DIM, WIDE, PER, TS, TA>(g, z, uz, u, sb, w, ent, start, c);
+    acc += row_own<DIM, WIDE, PER, TS, TA, TS>(g, z, uz, u, sb, w);
     if (STEP) {
         const TA h = (TA)(dt_mode == ADLBR_DT_CFL ? dt * dtcfl[0] : dt);
         out[z] = Conv<TS, TA>::st(uz - h * acc);
@@ -499,14 +546,13 @@ __global__ __launch_bounds__(kBS) void k_cg_direction(
     const long long blk = xcd_block(blockIdx.x, gridDim.x);
     const long long z = blk * kBS + threadIdx.x;
     const bool live = z < N;
-    const unsigned c = live ? cnt[z] : 0u;
-    const unsigned pre = wave_excl_scan(c);
     double pqz = 0.0;
     const bool skip = st->bad || st->done;
+    const WaveLists L = wave_lists(cnt, pos, z, N);
+    const T zz = live ? zv[z] : (T)0;
+    T acc = skip ? (T)0 : wave_incoming<T, T, T>(L, z, N, zz, zv, w, ent);
     if (live && !skip) {
-        const long long start = (long long)pos[z & ~63ll] + pre;
-        const T zz = zv[z];
-        const T acc = row_Au<DIM, WIDE, PER, T, T>(g, z, zz, zv, sb, w, ent, start, c);
+        acc += row_own<DIM, WIDE, PER, T, T, T>(g, z, zz, zv, sb, w);
         const T dt = (T)st->dt;
         const T beta = first ? (T)0 : (T)st->beta;
         const T qn = zz + dt * acc + (first ? (T)0 : beta * q[z]);
@@ -555,22 +601,23 @@ __global__ __launch_bounds__(kBS) void k_cg_direction(
 // |b - (x + dt A x)|^2 with FP64 arithmetic (weights promoted).
 template <int DIM, bool WIDE, bool PER, typename T>
 __global__ __launch_bounds__(kBS) void k_residual(
-    GridInfo g, const T *__restrict__ b, const T *__restrict__ x,
+    GridInfo g, const T *__restrict__ b, const double *__restrict__ x,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const T *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, double dt, double *out, double *partial, uint32_t *ticket) {
+    const int32_t *__restrict__ ent, double dt, double *out, double *partial, uint32_t *ticket,
+    T *__restrict__ rout) {
     const long long N = g.N;
     const long long z = (long long)blockIdx.x * kBS + threadIdx.x;
     const bool live = z < N;
-    const unsigned c = live ? cnt[z] : 0u;
-    const unsigned pre = wave_excl_scan(c);
     double r2 = 0.0;
+    const WaveLists L = wave_lists(cnt, pos, z, N);
+    const double xz = live ? x[z] : 0.0;
+    double ax = wave_incoming<T, double, double>(L, z, N, xz, x, w, ent);
     if (live) {
-        const long long start = (long long)pos[z & ~63ll] + pre;
-        const double xz = (double)x[z];
-        const double ax = row_Au<DIM, WIDE, PER, T, double>(g, z, xz, x, sb, w, ent, start, c);
+        ax += row_own<DIM, WIDE, PER, T, double, double>(g, z, xz, x, sb, w);
         const double r = (double)b[z] - (xz + dt * ax);
         r2 = r * r;
+        if (rout) rout[z] = (T)r;
     }
     double tot;
     if (last_block_sum(r2, partial, ticket, tot) && threadIdx.x == 0) *out = tot;
@@ -602,7 +649,7 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
                        op->cnt, status);
     hipLaunchKernelGGL(k_fill_i32, dim3(nbp), dim3(kBS), 0, s, op->tmp, Npad, 0);
     hipLaunchKernelGGL((k_fill_entries<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g, sb, w,
-                       op->pos, op->tmp, op->ent, off, win, win_f64);
+                       op->pos, op->tmp, op->ent, off, win, win_f64, status);
     if (op->storage == ADLBR_F64)
         hipLaunchKernelGGL((k_finalize<DIM, WIDE, PER, TS, TA, double>), dim3(nb), dim3(kBS), 0, s, g,
                            sb, w, op->pos, op->cnt, op->ent, (double *)op->diag, op->maxdiag);
@@ -696,26 +743,26 @@ template <int DIM, bool WIDE, bool PER> struct CgDirF<DIM, WIDE, PER, _Float16, 
 };
 
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct ResidualF {
-    static int run(const adlbr_operator *op, double dt, const void *b, const void *x, double *out,
-                   double *partial, uint32_t *ticket, hipStream_t s) {
+    static int run(const adlbr_operator *op, double dt, const void *b, const double *x,
+                   double *out, double *partial, uint32_t *ticket, void *rout, hipStream_t s) {
         typedef typename Slots<DIM, WIDE>::store_t store_t;
         const GridInfo g = op->gi;
         const unsigned nb = (unsigned)((g.N + kBS - 1) / kBS);
         hipLaunchKernelGGL((k_residual<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g,
-                           (const TS *)b, (const TS *)x, (const store_t *)op->sb,
-                           (const TS *)op->w, op->cnt, op->pos, op->ent, dt, out, partial, ticket);
+                           (const TS *)b, x, (const store_t *)op->sb, (const TS *)op->w, op->cnt,
+                           op->pos, op->ent, dt, out, partial, ticket, (TS *)rout);
         return ADLBR_OK;
     }
 };
 template <int DIM, bool WIDE, bool PER> struct ResidualF<DIM, WIDE, PER, bf16, float> {
-    static int run(const adlbr_operator *, double, const void *, const void *, double *, double *,
-                   uint32_t *, hipStream_t) {
+    static int run(const adlbr_operator *, double, const void *, const double *, double *,
+                   double *, uint32_t *, void *, hipStream_t) {
         return ADLBR_E_UNSUPPORTED;
     }
 };
 template <int DIM, bool WIDE, bool PER> struct ResidualF<DIM, WIDE, PER, _Float16, float> {
-    static int run(const adlbr_operator *, double, const void *, const void *, double *, double *,
-                   uint32_t *, hipStream_t) {
+    static int run(const adlbr_operator *, double, const void *, const double *, double *,
+                   double *, uint32_t *, void *, hipStream_t) {
         return ADLBR_E_UNSUPPORTED;
     }
 };
@@ -751,9 +798,14 @@ int cg_direction(const adlbr_operator *op, const void *z, void *q, void *p, CgSt
     return dispatch<CgDirF>(op, z, q, p, st, partial, first, s);
 }
 
-int true_residual(const adlbr_operator *op, double dt, const void *b, const void *x, double *out,
-                  double *partial, uint32_t *ticket, hipStream_t s) {
-    return dispatch<ResidualF>(op, dt, b, x, out, partial, ticket, s);
+// out = (I + dt A) u, written as one explicit step with step -dt.
+int apply_K(const adlbr_operator *op, const void *u, void *out, double dt, hipStream_t s) {
+    return dispatch<ApplyF>(op, u, out, true, -dt, (int)ADLBR_DT_ABS, s);
+}
+
+int true_residual(const adlbr_operator *op, double dt, const void *b, const double *x,
+                  double *out, double *partial, uint32_t *ticket, void *rout, hipStream_t s) {
+    return dispatch<ResidualF>(op, dt, b, x, out, partial, ticket, rout, s);
 }
 
 const GridInfo &operator_grid(const adlbr_operator *op) { return op->gi; }

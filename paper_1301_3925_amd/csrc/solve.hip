@@ -15,6 +15,8 @@
 // z = N(r) -> dots (<z,r>, <z,r_prev>, beta) -> direction.
 #include <algorithm>
 #include <cstring>
+#include <utility>
+#include <vector>
 
 #include "common.h"
 
@@ -34,11 +36,11 @@ template <typename TD> __device__ __forceinline__ double inv_kd(const TD *diag, 
     return 1.0 / (1.0 + dt * (double)diag[z]);
 }
 
-// r = b (x0 = 0) or r = b - q with q = K x; z = r / diag K (Jacobi);
-// sums <r, z> and <b, b>.
+// x0 = 0: x64 = 0, r = b; otherwise r = b - K x64 is already in r.
+// z = r / diag K (Jacobi); sums <r, z> and <b, b>.
 template <typename T, typename TD>
-__global__ void k_init(long long N, const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r,
-                       T *__restrict__ z, const T *__restrict__ q, const TD *__restrict__ diag,
+__global__ void k_init(long long N, const T *__restrict__ b, double *__restrict__ x64,
+                       T *__restrict__ r, T *__restrict__ z, const TD *__restrict__ diag,
                        int x0_zero, int jacobi, SolveState *st, double *part, double tol2) {
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
     double rz = 0.0, bb = 0.0;
@@ -46,12 +48,12 @@ __global__ void k_init(long long N, const T *__restrict__ b, T *__restrict__ x, 
         const T bi = b[i];
         T ri;
         if (x0_zero) {
-            x[i] = (T)0;
+            x64[i] = 0.0;
             ri = bi;
+            r[i] = ri;
         } else {
-            ri = bi - q[i];
+            ri = r[i];
         }
-        r[i] = ri;
         if (jacobi) {
             const T zi = (T)((double)ri * inv_kd(diag, i, st->cg.dt));
             z[i] = zi;
@@ -76,7 +78,7 @@ __global__ void k_init(long long N, const T *__restrict__ b, T *__restrict__ x, 
 
 // Jacobi-PCG update.
 template <typename T, typename TD>
-__global__ void k_pcg_update(long long N, T *__restrict__ x, T *__restrict__ r, T *__restrict__ z,
+__global__ void k_pcg_update(long long N, double *__restrict__ x, T *__restrict__ r, T *__restrict__ z,
                              const T *__restrict__ p, const T *__restrict__ q,
                              const TD *__restrict__ diag, SolveState *st, double *part,
                              double *hist) {
@@ -85,7 +87,7 @@ __global__ void k_pcg_update(long long N, T *__restrict__ x, T *__restrict__ r, 
     double rz = 0.0, rr = 0.0;
     if (i < N && !skip) {
         const T a = (T)st->cg.alpha;
-        x[i] += a * p[i];
+        x[i] += st->cg.alpha * (double)p[i];
         const T ri = r[i] - a * q[i];
         r[i] = ri;
         const T zi = (T)((double)ri * inv_kd(diag, i, st->cg.dt));
@@ -117,7 +119,7 @@ __global__ void k_pcg_scalars(SolveState *st, double *hist, int max_hist) {
 
 // Flexible-CG update: x += alpha p, r_new = r - alpha q, <r_new, r_new>.
 template <typename T>
-__global__ void k_fcg_update(long long N, T *__restrict__ x, const T *__restrict__ r,
+__global__ void k_fcg_update(long long N, double *__restrict__ x, const T *__restrict__ r,
                              T *__restrict__ rn, const T *__restrict__ p, const T *__restrict__ q,
                              SolveState *st, double *part, double *hist, int max_hist) {
     const bool skip = st->cg.done || st->cg.bad;
@@ -125,7 +127,7 @@ __global__ void k_fcg_update(long long N, T *__restrict__ x, const T *__restrict
     double rr = 0.0;
     if (i < N && !skip) {
         const T a = (T)st->cg.alpha;
-        x[i] += a * p[i];
+        x[i] += st->cg.alpha * (double)p[i];
         const T ri = r[i] - a * q[i];
         rn[i] = ri;
         rr = (double)ri * (double)ri;
@@ -174,13 +176,13 @@ __global__ void k_fcg_scalars(SolveState *st, int first) {
 
 __global__ void k_clear_done(SolveState *st) { st->cg.done = 0; }
 
-template <typename T> __global__ void k_copy(long long N, const T *a, T *b) {
+template <typename TA, typename TB> __global__ void k_convert(long long N, const TA *a, TB *b) {
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
-    if (i < N) b[i] = a[i];
+    if (i < N) b[i] = (TB)a[i];
 }
 
 struct SolveLayout {
-    size_t st, hist, part, vec[6], total;
+    size_t st, hist, part, x64, vec[6], total;
 };
 
 SolveLayout solve_layout(long long N, size_t esz, int max_hist) {
@@ -190,6 +192,7 @@ SolveLayout solve_layout(long long N, size_t esz, int max_hist) {
     L.st = o;   o += align_up(sizeof(SolveState));
     L.hist = o; o += align_up(8 * (size_t)max_hist);
     L.part = o; o += align_up(8 * 2 * nb + 64);
+    L.x64 = o;  o += align_up(8 * (size_t)N);
     for (int k = 0; k < 6; ++k) {
         L.vec[k] = o;
         o += align_up(esz * (size_t)N);
@@ -215,6 +218,7 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     T *z = (T *)(ws + L.vec[2]);
     T *pv = (T *)(ws + L.vec[3]);
     T *q = (T *)(ws + L.vec[4]);
+    double *x64 = (double *)(ws + L.x64);
     const TD *diag = (const TD *)operator_diag(op);
     const bool net = p->method == ADLBR_SOLVE_FCG_NET;
     CgState *cg = &st->cg;
@@ -228,11 +232,14 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     std::memset(&init, 0, sizeof init);
     init.cg.dt = dt;
     ADLBR_CHECK_HIP(hipMemcpyAsync(st, &init, sizeof init, hipMemcpyHostToDevice, s));
+    // the iterate is accumulated in FP64 (x64); the vectors and recurrences
+    // are in the storage dtype
     if (!p->x0_zero) {
-        int rc = cg_direction(op, x, q, pv, cg, part, 1, s);  // q = K x
+        hipLaunchKernelGGL((k_convert<T, double>), dim3(nb), dim3(kBS), 0, s, N, (const T *)x, x64);
+        int rc = true_residual(op, dt, b, x64, &st->rr_true, part, &st->tickets[7], r, s);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL((k_init<T, TD>), dim3(nb), dim3(kBS), 0, s, N, b, x, r, z, (const T *)q, diag,
+    hipLaunchKernelGGL((k_init<T, TD>), dim3(nb), dim3(kBS), 0, s, N, b, x64, r, z, diag,
                        p->x0_zero, (int)!net, st, part, p->tol * p->tol);
     int rc = ADLBR_OK;
     bool use_net = net;
@@ -258,17 +265,21 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     bool converged = false;
     struct Host {
         int32_t done, bad, iter;
+        double rr;
     } h;
+    // stall detection for the learned preconditioner: (iteration, |r|^2)
+    // at each host check
+    std::vector<std::pair<int, double>> trail;
     while (issued < p->max_iter) {
         const int batch = std::min(check, p->max_iter - issued);
         for (int k = 0; k < batch; ++k) {
             if (use_net) {
-                hipLaunchKernelGGL((k_fcg_update<T>), dim3(nb), dim3(kBS), 0, s, N, x,
+                hipLaunchKernelGGL((k_fcg_update<T>), dim3(nb), dim3(kBS), 0, s, N, x64,
                                    (const T *)rc_, ro, (const T *)pv, (const T *)q, st, part, hist,
                                    kMaxHist);
                 std::swap(rc_, ro);  // ro now holds r_k (previous), rc_ r_{k+1}
             } else {
-                hipLaunchKernelGGL((k_pcg_update<T, TD>), dim3(nb), dim3(kBS), 0, s, N, x, rc_, z,
+                hipLaunchKernelGGL((k_pcg_update<T, TD>), dim3(nb), dim3(kBS), 0, s, N, x64, rc_, z,
                                    (const T *)pv, (const T *)q, diag, st, part, hist);
                 hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(1), 0, s, st, hist, kMaxHist);
             }
@@ -279,8 +290,18 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
         ADLBR_CHECK_HIP(hipMemcpyAsync(&h.done, &cg->done, 4, hipMemcpyDeviceToHost, s));
         ADLBR_CHECK_HIP(hipMemcpyAsync(&h.bad, &cg->bad, 4, hipMemcpyDeviceToHost, s));
         ADLBR_CHECK_HIP(hipMemcpyAsync(&h.iter, &cg->iter, 4, hipMemcpyDeviceToHost, s));
+        ADLBR_CHECK_HIP(hipMemcpyAsync(&h.rr, &cg->rr, 8, hipMemcpyDeviceToHost, s));
         ADLBR_CHECK_HIP(hipStreamSynchronize(s));
-        if (use_net) net_iters = h.iter;
+        if (use_net) {
+            net_iters = h.iter;
+            // stall: the residual norm fell by less than 1% over >= 20 iterations
+            for (auto it = trail.rbegin(); it != trail.rend(); ++it)
+                if (h.iter - it->first >= 20) {
+                    if (!h.done && h.rr > 0.99 * 0.99 * it->second) h.bad = 1;
+                    break;
+                }
+            trail.emplace_back(h.iter, h.rr);
+        }
         if (h.bad) {
             if (!use_net) break;  // Jacobi-PCG broke down: report as not converged
             // learned preconditioner failed: restart from x with Jacobi-PCG
@@ -292,10 +313,10 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
             std::memset(&re, 0, sizeof re);
             re.cg.dt = dt;
             ADLBR_CHECK_HIP(hipMemcpyAsync(st, &re, sizeof re, hipMemcpyHostToDevice, s));
-            rc = cg_direction(op, x, q, pv, cg, part, 1, s);
+            rc = true_residual(op, dt, b, x64, &st->rr_true, part, &st->tickets[7], r, s);
             if (rc) return rc;
-            hipLaunchKernelGGL((k_init<T, TD>), dim3(nb), dim3(kBS), 0, s, N, b, x, r, z,
-                               (const T *)q, diag, 0, 1, st, part, p->tol * p->tol);
+            hipLaunchKernelGGL((k_init<T, TD>), dim3(nb), dim3(kBS), 0, s, N, b, x64, r, z, diag,
+                               0, 1, st, part, p->tol * p->tol);
             rc_ = r;
             ro = r2;
             rc = start_iteration();
@@ -305,7 +326,7 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
             continue;
         }
         if (h.done) {
-            rc = true_residual(op, dt, b, x, &st->rr_true, part, &st->tickets[7], s);
+            rc = true_residual(op, dt, b, x64, &st->rr_true, part, &st->tickets[7], nullptr, s);
             if (rc) return rc;
             double rt = 0.0, t2 = 0.0;
             ADLBR_CHECK_HIP(hipMemcpyAsync(&rt, &st->rr_true, 8, hipMemcpyDeviceToHost, s));
@@ -321,8 +342,9 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     // final report
     int32_t iters = 0;
     double bb = 0.0;
-    rc = true_residual(op, dt, b, x, &st->rr_true, part, &st->tickets[7], s);
+    rc = true_residual(op, dt, b, x64, &st->rr_true, part, &st->tickets[7], nullptr, s);
     if (rc) return rc;
+    hipLaunchKernelGGL((k_convert<double, T>), dim3(nb), dim3(kBS), 0, s, N, (const double *)x64, x);
     double rt = 0.0;
     ADLBR_CHECK_HIP(hipMemcpyAsync(&iters, &cg->iter, 4, hipMemcpyDeviceToHost, s));
     ADLBR_CHECK_HIP(hipMemcpyAsync(&bb, &cg->bb, 8, hipMemcpyDeviceToHost, s));

@@ -221,6 +221,165 @@ __global__ void k_eigmap3(long long N, const T *__restrict__ J, T *__restrict__ 
     }
 }
 
+// ---------------------------------------------------------- tiled 2D --
+// Kernel 1: u -> u_sigma -> central differences -> J = grad grad^T on a
+// 32x32 tile, all in LDS.  The tile is loaded with mirrored indices; since
+// the half-sample symmetric extension of u is symmetric about -1/2 and n-1/2
+// and the Gaussian is symmetric, blurring the extended tile equals blurring
+// with a mirror boundary at every pass, and u_sigma at a mirrored halo point
+// equals u_sigma at its mirror image.
+constexpr int kTile = 32;
+
+template <typename T, int RS>
+__global__ __launch_bounds__(256) void k_st_grad_tiled(int nx, int ny, const T *__restrict__ u,
+                                                       T *__restrict__ J, Taps ts) {
+    constexpr int E = kTile + 2 + 2 * RS;   // u region edge
+    constexpr int EU = kTile + 2;           // u_sigma region edge
+    __shared__ T su[E * E];
+    __shared__ T sx[E * EU];                // blurred along x
+    __shared__ T ss[EU * EU];               // u_sigma
+    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    for (int k = threadIdx.x; k < E * E; k += 256) {
+        const int gx = mirror(x0 - 1 - RS + k % E, nx), gy = mirror(y0 - 1 - RS + k / E, ny);
+        su[k] = u[(long long)gy * nx + gx];
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < E * EU; k += 256) {
+        const int yy = k / EU, xx = k % EU;
+        T a = (T)0;
+#pragma unroll
+        for (int j = 0; j <= 2 * RS; ++j) a += tap<T>(ts, j) * su[yy * E + xx + j];
+        sx[k] = a;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < EU * EU; k += 256) {
+        const int yy = k / EU, xx = k % EU;
+        T a = (T)0;
+#pragma unroll
+        for (int j = 0; j <= 2 * RS; ++j) a += tap<T>(ts, j) * sx[(yy + j) * EU + xx];
+        ss[k] = a;
+    }
+    __syncthreads();
+    const long long N = (long long)nx * ny;
+    for (int k = threadIdx.x; k < kTile * kTile; k += 256) {
+        const int ty = k / kTile, tx = k % kTile;
+        const int gx = x0 + tx, gy = y0 + ty;
+        if (gx >= nx || gy >= ny) continue;
+        const int c = (ty + 1) * EU + (tx + 1);
+        const T half = (T)0.5;
+        const T gxv = half * (ss[c + 1] - ss[c - 1]);
+        const T gyv = half * (ss[c + EU] - ss[c - EU]);
+        const long long i = (long long)gy * nx + gx;
+        J[i] = gxv * gxv;
+        J[N + i] = gxv * gyv;
+        J[2 * N + i] = gyv * gyv;
+    }
+}
+
+// Kernel 2: J -> K_rho * J (x then y, mirrored tile) -> eigen map -> D.
+template <typename T, int RR>
+__global__ __launch_bounds__(256) void k_st_smooth_map_tiled(int nx, int ny,
+                                                             const T *__restrict__ J,
+                                                             T *__restrict__ D, Taps tr, T alpha,
+                                                             T C, int map) {
+    constexpr int E = kTile + 2 * RR;
+    __shared__ T sj[3][E * E];
+    __shared__ T sx[3][E * kTile];
+    const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
+    const long long N = (long long)nx * ny;
+    for (int k = threadIdx.x; k < E * E; k += 256) {
+        const int gx = mirror(x0 - RR + k % E, nx), gy = mirror(y0 - RR + k / E, ny);
+        const long long i = (long long)gy * nx + gx;
+        sj[0][k] = J[i];
+        sj[1][k] = J[N + i];
+        sj[2][k] = J[2 * N + i];
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < E * kTile; k += 256) {
+        const int yy = k / kTile, xx = k % kTile;
+        T a0 = (T)0, a1 = (T)0, a2 = (T)0;
+#pragma unroll
+        for (int j = 0; j <= 2 * RR; ++j) {
+            const T w = tap<T>(tr, j);
+            const int q = yy * E + xx + j;
+            a0 += w * sj[0][q];
+            a1 += w * sj[1][q];
+            a2 += w * sj[2][q];
+        }
+        sx[0][k] = a0;
+        sx[1][k] = a1;
+        sx[2][k] = a2;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kTile * kTile; k += 256) {
+        const int ty = k / kTile, tx = k % kTile;
+        const int gx = x0 + tx, gy = y0 + ty;
+        if (gx >= nx || gy >= ny) continue;
+        T a = (T)0, b = (T)0, c = (T)0;
+#pragma unroll
+        for (int j = 0; j <= 2 * RR; ++j) {
+            const T w = tap<T>(tr, j);
+            const int q = (ty + j) * kTile + tx;
+            a += w * sx[0][q];
+            b += w * sx[1][q];
+            c += w * sx[2][q];
+        }
+        const T hd = (T)0.5 * (a - c);
+        const T disc = sqrt(hd * hd + b * b);
+        const T mid = (T)0.5 * (a + c);
+        const T mu1 = mid + disc, mu2 = mid - disc;
+        T vx, vy;
+        if (disc == (T)0) {
+            vx = (T)1;
+            vy = (T)0;
+        } else if (a >= c) {
+            vx = hd + disc;
+            vy = b;
+        } else {
+            vx = b;
+            vy = disc - hd;
+        }
+        const T nrm = sqrt(vx * vx + vy * vy);
+        vx /= nrm;
+        vy /= nrm;
+        T l1, l2;
+        if (map == ADLBR_MAP_CED) {
+            l1 = alpha;
+            l2 = alpha + ((T)1 - alpha) * coh(C, mu1 - mu2);
+        } else {
+            l1 = eed(C, mu1);
+            l2 = (T)1;
+        }
+        const T dl = l1 - l2;
+        const long long i = (long long)gy * nx + gx;
+        D[i] = l2 + dl * vx * vx;
+        D[N + i] = dl * vx * vy;
+        D[2 * N + i] = l2 + dl * vy * vy;
+    }
+}
+
+// The tiled path covers the common radii (sigma <= 1: r_sigma <= 3;
+// rho <= 4: r_rho <= 12) in FP32; other cases use the streaming passes.
+template <typename T> bool run_tensor_tiled(const GridInfo &g, const T *u, const Taps &ts,
+                                            const Taps &tr, const adlbr_tensor_params *p, T *D,
+                                            T *wa, hipStream_t s) {
+    if (g.dim != 2 || sizeof(T) != 4) return false;
+    const dim3 grid((g.nx + kTile - 1) / kTile, (g.ny + kTile - 1) / kTile);
+#define ADLBR_ST1(RS)                                                                       \
+    if (ts.r == RS) hipLaunchKernelGGL((k_st_grad_tiled<T, RS>), grid, dim3(256), 0, s, g.nx, g.ny, u, wa, ts);
+    if (ts.r < 1 || ts.r > 3) return false;
+    if (tr.r < 1 || tr.r > 12) return false;
+    ADLBR_ST1(1) ADLBR_ST1(2) ADLBR_ST1(3)
+#undef ADLBR_ST1
+#define ADLBR_ST2(RR)                                                                        \
+    if (tr.r == RR) hipLaunchKernelGGL((k_st_smooth_map_tiled<T, RR>), grid, dim3(256), 0, s, g.nx, \
+                                       g.ny, (const T *)wa, D, tr, (T)p->alpha, (T)p->C, p->eig_map);
+    ADLBR_ST2(1) ADLBR_ST2(2) ADLBR_ST2(3) ADLBR_ST2(4) ADLBR_ST2(5) ADLBR_ST2(6)
+    ADLBR_ST2(7) ADLBR_ST2(8) ADLBR_ST2(9) ADLBR_ST2(10) ADLBR_ST2(11) ADLBR_ST2(12)
+#undef ADLBR_ST2
+    return true;
+}
+
 template <typename T>
 int run_tensor(const GridInfo &g, const T *u, const adlbr_tensor_params *p, T *D, T *wa, T *wb,
                hipStream_t s) {
@@ -228,6 +387,10 @@ int run_tensor(const GridInfo &g, const T *u, const adlbr_tensor_params *p, T *D
     const int nj = g.dim == 2 ? 3 : 6;
     const unsigned nb = (unsigned)((N + 255) / 256);
     const Taps ts = make_taps(p->sigma), tr = make_taps(p->rho);
+    if (run_tensor_tiled<T>(g, u, ts, tr, p, D, wa, s)) {
+        ADLBR_LAUNCH_CHECK();
+        return ADLBR_OK;
+    }
     // u_sigma
     if (g.dim == 2) {
         hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, u, wa, 0, ts);

@@ -46,11 +46,15 @@ def test_tensor3d(lib, eig_map):
     assert _rel(D.double().cpu().numpy(), ref) <= 1e-5
 
 
-def test_tensor_small_grid_mirror(lib):
-    """Grids smaller than the Gaussian radius exercise repeated mirroring."""
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("dims", [(7, 5), (45, 33)])
+def test_tensor_small_grid_mirror(lib, dtype, dims):
+    """Grids smaller than the Gaussian radius exercise repeated mirroring
+    (FP32 goes through the LDS-tiled kernels, FP64 through the passes)."""
     import torch
-    dims = (7, 5)
-    u = torch.from_numpy(synth.uniform(3, 35)).double().cuda()
-    D = lib.structure_tensor(u, dims, 1.0, 4.0, 1e-2, 1e-3).cpu().numpy()
-    ref = oracle.structure_tensor_d(u.cpu().numpy(), dims, 1.0, 4.0, 1e-2, 1e-3)
-    assert _rel(D, ref) <= 1e-12
+    td = {"f32": torch.float32, "f64": torch.float64}[dtype]
+    n = dims[0] * dims[1]
+    u = torch.from_numpy(synth.uniform(3, n)).to(td).cuda()
+    D = lib.structure_tensor(u, dims, 1.0, 4.0, 1e-2, 1e-3).double().cpu().numpy()
+    ref = oracle.structure_tensor_d(u.double().cpu().numpy(), dims, 1.0, 4.0, 1e-2, 1e-3)
+    assert _rel(D, ref) <= (1e-5 if dtype == "f32" else 1e-12)
