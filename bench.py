@@ -13,7 +13,12 @@ value is whole-job throughput in Mpoint-steps/s (grid points x explicit
 steps / wall time), inputs resident in HBM before the timed region.
 
 Other workloads (--workload): "c3" is the 256^3 3D field stepped in FP32
-without rebuilds (kappa <= 50), "c1" the 64^2 FP64 run.
+without rebuilds (kappa <= 50), "c1" the 64^2 FP64 run, "c5" the implicit
+step (I + dt A) x = b on 1024^2 (kappa = 200, dt = 50 x the explicit CFL
+bound): time to 1e-6 relative residual for Jacobi-PCG and for flexible CG
+with the learned preconditioner (trained first, on the GPU, on residuals of
+other right-hand sides; training time reported separately), "c5-3d" the
+same on 128^3.
 
 Prints ONE JSON line.
 """
@@ -41,7 +46,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5", "c5-3d"])
+    ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--dtype", default=None, help="storage dtype for c3: f64|f32|bf16|f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
@@ -193,6 +199,10 @@ def main():
         print(json.dumps(res), flush=True)
         return
 
+    if args.workload in ("c5", "c5-3d"):
+        run_c5(args, dev, stream)
+        return
+
     # c1 / c3: fixed operator, explicit steps only
     if args.workload == "c1":
         dims, kappa, seed, sdt = (64, 64), 10.0, 1301, args.dtype or "f64"
@@ -247,6 +257,68 @@ def main():
             m = 64
             Ds = synth.tensor3d_field(seed, (m, m, m), kappa)
             res["cpu_baseline"] = cpu_baseline_steps((m, m, m), Ds, synth.uniform(seed + 1, m ** 3), 10)
+    print(json.dumps(res), flush=True)
+
+
+def run_c5(args, dev, stream):
+    import numpy as np
+    import torch
+    import paper_1301_3925_amd as adlbr
+    from paper_1301_3925_amd import synth
+    three = args.workload == "c5-3d"
+    if three:
+        dims = (128, 128, 128)
+        D = synth.tensor3d_field(1305, dims, 200.0)
+    else:
+        dims = (1024, 1024)
+        D = synth.tensor2d_field(1305, 1024, 1024, 200.0)
+    N = int(np.prod(dims))
+    off, w, st = adlbr.build_stencils(torch.from_numpy(D).to(dev), dims)
+    op = adlbr.Operator(dims, off, w, storage=torch.float32)
+    dt = 50.0 * op.dt_cfl()
+    b = torch.from_numpy(synth.uniform(1305, N)).float().to(dev)
+    reps = max(1, args.steps if args.steps is not None else 3)
+
+    def timed(method, net=None):
+        ws = None
+        best = None
+        for _ in range(args.warmup + reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, rep = op.solve(b, dt, method=method, net=net, tol=1e-6, check_every=10)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            best = t if best is None else min(best, t)
+        return x, rep, best
+
+    _, rj, tj = timed("jacobi")
+    untrained = adlbr.Net(op, seed=0)
+    untrained.prepare(dt)
+    _, ru, tu = timed("fcg", untrained)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net, hist = adlbr.train_net(op, dt, rhs_seeds=range(2001, 2017), steps=args.train_steps,
+                                batch=4, lr=3e-3, seed=0, log_every=50)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    _, rt, tt = timed("fcg", net)
+    res = {
+        "metric": "time to 1e-6 relative residual", "value": round(tt * 1e3, 3), "unit": "ms",
+        "n_gpus": 1, "steps": reps, "warmup": args.warmup, "ms_per_step": round(tt * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": ("implicit3d-128^3" if three else "implicit2d-1024x1024") +
+                               "-kappa200-dt50cfl-f32", "n": list(dims), "tol": 1e-6,
+                   "rhs_seed": 1305, "train_seeds": "2001-2016"},
+        "jacobi_pcg": {"iters": rj["iters"], "ms": round(tj * 1e3, 3), "rel_res": rj["rel_res"]},
+        "fcg_untrained": {"iters": ru["iters"], "ms": round(tu * 1e3, 3),
+                          "fell_back": ru["fell_back"], "rel_res": ru["rel_res"]},
+        "fcg_trained": {"iters": rt["iters"], "ms": round(tt * 1e3, 3),
+                        "fell_back": rt["fell_back"], "rel_res": rt["rel_res"]},
+        "training": {"seconds": round(t_train, 2), "steps": args.train_steps, "batch": 4,
+                     "loss": hist},
+        "speedup_vs_jacobi": round(tj / tt, 3),
+    }
     print(json.dumps(res), flush=True)
 
 

@@ -319,6 +319,8 @@ typedef struct adlbr_solve_report {
     int32_t net_iters; /* iterations done with the learned preconditioner */
     double rel_res;    /* true relative residual, FP64 */
     double time_ms;    /* wall time of the solve on the stream */
+    int32_t restarts;  /* residual replacements (recurrence met tol, true residual did not) */
+    int32_t fallback_reason; /* 0 none, 1 breakdown (<z,r> <= 0 or non-finite), 2 stall */
 } adlbr_solve_report;
 
 int adlbr_solve_workspace(adlbr_operator *op, int method, size_t *bytes);

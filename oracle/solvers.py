@@ -74,9 +74,12 @@ def fcg(K, b, precond, tol=1e-6, max_iter=10000, x0=None, history=False):
     p_k = z_k + beta_k p_{k-1}, alpha_k = <z_k, r_k> / <p_k, K p_k>.
     With a fixed SPD linear preconditioner it generates the PCG iterates.
     Returns (x, iterations, relative residual, fell_back[, history]); on a
-    non-descent direction (<z, r> <= 0), a non-finite value, or a stall
-    (the residual norm fell by less than 1% over the last 20 iterations) it
-    restarts from the current x with Jacobi-PCG."""
+    non-descent direction (<z, r> <= 0 or <p, K p> <= 0), a non-finite
+    value, or a stall
+    (the smallest residual norm of the last 20 iterations is not 1% below
+    the smallest one before them; CG residual norms need not decrease
+    monotonically, hence the minima) it restarts from the current x with
+    Jacobi-PCG."""
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
     r = b - K @ x
@@ -91,7 +94,7 @@ def fcg(K, b, precond, tol=1e-6, max_iter=10000, x0=None, history=False):
             break
         z = precond(r)
         zr = z @ r
-        stalled = it >= 20 and hist[-1] > 0.99 * hist[-21]
+        stalled = it >= 20 and min(hist[-20:]) > 0.99 * min(hist[:-20])
         if not np.isfinite(zr) or zr <= 0.0 or stalled:
             xj, itj, rel = jacobi_pcg(K, b, tol, max_iter - it, x0=x)
             out = (xj, it + itj, rel, True)
@@ -102,7 +105,12 @@ def fcg(K, b, precond, tol=1e-6, max_iter=10000, x0=None, history=False):
             beta = (zr - z @ r_prev) / zr_prev
             p = z + beta * p
         q = K @ p
-        alpha = zr / (p @ q)
+        pq = p @ q
+        if not np.isfinite(pq) or pq <= 0.0:  # breakdown: x is left as it is
+            xj, itj, rel = jacobi_pcg(K, b, tol, max_iter - it, x0=x)
+            out = (xj, it + itj, rel, True)
+            return out + (hist,) if history else out
+        alpha = zr / pq
         x += alpha * p
         r_prev = r.copy()
         r = r - alpha * q

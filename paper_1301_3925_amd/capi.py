@@ -43,7 +43,8 @@ class SolveParams(ctypes.Structure):
 class SolveReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("fell_back", ctypes.c_int32), ("net_iters", ctypes.c_int32),
-                ("rel_res", ctypes.c_double), ("time_ms", ctypes.c_double)]
+                ("rel_res", ctypes.c_double), ("time_ms", ctypes.c_double),
+                ("restarts", ctypes.c_int32), ("fallback_reason", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -40,15 +40,16 @@ struct adlbr_operator {
     void *diag;
     unsigned long long *maxdiag;
     double *dtcfl;
-    int32_t *tmp;   // [N] counts / cursors during assembly
-    int32_t *bsum;  // scan block sums
+    uint32_t *bincnt;  // edges per bin of targets
+    uint32_t *bincur;  // placement cursor per bin
+    uint32_t *binoff;  // exclusive scan of bincnt
+    int2 *binbuf;      // (target, entry) grouped by bin
 };
 
 namespace adlbr {
 namespace {
 
 constexpr int kBS = 256;         // threads per block of the apply
-constexpr int kScanBlock = 1024;  // elements per scan block
 
 // --------------------------------------------------------- compact slots --
 template <int DIM, bool WIDE> struct Slots;
@@ -200,43 +201,252 @@ template <typename TW> __device__ __forceinline__ double ld_w(const TW *w, long 
 }
 
 // Pack the slots, convert the weights, count incoming edges per target.
+// Assembly of the transpose (incoming lists) without per-edge global
+// atomics.  Targets are grouped into bins of kBin consecutive points; the
+// edges of a wavefront mostly land in one or two bins, so counting and
+// placing them costs one atomic per distinct bin per wavefront (leader lane,
+// ballot of the lanes that share its bin).  Each bin is then built by one
+// block with LDS counters.
+constexpr int kBinShift = 10;
+constexpr int kBin = 1 << kBinShift;
+
+// The edges (q, s) of point z, in a fixed order; returns the target of the
+// k-th candidate edge or -1.
+template <int DIM, bool PER>
+__device__ __forceinline__ long long edge_k(const Coord &p, long long z, const int s[6][3],
+                                           const double *wq, int k, const GridInfo &g) {
+    const int q = k >> 1, sg = (k & 1) ? 1 : -1;
+    if (!(wq[q] > 0.0)) return -1;
+    long long t;
+    if (!edge_target<DIM, PER>(p, z, s[q], sg, g, t)) return -1;
+    // entries store z - t in 23 bits; such an edge is flagged and left out
+    if (z - t >= (1ll << 22) || z - t <= -(1ll << 22)) return -2;
+    return t;
+}
+
+// Wave-aggregated "append to bin": every lane with bin >= 0 gets a slot in
+// its bin; the leader of each group of lanes sharing a bin does one atomic.
+// With count_only the slot is not needed.
+__device__ __forceinline__ unsigned bin_append(int bin, uint32_t *counter, bool count_only) {
+    const int lane = (int)(threadIdx.x & 63u);
+    unsigned long long pending = __ballot(bin >= 0);
+    unsigned slot = 0;
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int bl = __shfl(bin, leader, 64);
+        const unsigned long long m = __ballot(bin == bl);
+        unsigned base = 0;
+        if (lane == leader) base = atomicAdd(&counter[bl], (unsigned)__popcll(m));
+        if (!count_only) {
+            base = __shfl(base, leader, 64);
+            if (bin == bl) slot = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+        }
+        pending &= ~m;
+    }
+    return slot;
+}
+
+// Pack the slots, convert the weights, count the edges landing in each bin.
 template <int DIM, bool WIDE, bool PER, typename TWin, typename TS, typename TA>
 __global__ void k_compact(GridInfo g, const int16_t *__restrict__ off, const TWin *__restrict__ win,
                           typename Slots<DIM, WIDE>::store_t *__restrict__ sb, TS *__restrict__ w,
-                          int32_t *__restrict__ count, int32_t *status) {
+                          uint32_t *__restrict__ bincnt, int32_t *status) {
     const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (z >= g.N) return;
+    const bool live = z < g.N;  // every lane takes part in the ballots
     constexpr int S = DIM == 2 ? 3 : 6;
     const long long N = g.N;
     int s[6][3];
-    for (int q = 0; q < S; ++q)
-        for (int c = 0; c < 3; ++c) s[q][c] = c < DIM ? (int)off[(DIM * q + c) * N + z] : 0;
+    double wq[6];
     int st = 0;
-    bool rel = true;
-    if (DIM == 2) {
-        for (int c = 0; c < 2; ++c) rel = rel && s[2][c] == -s[0][c] - s[1][c];
-    } else {
-        for (int c = 0; c < 3; ++c)
-            rel = rel && s[3][c] == -(s[0][c] + s[1][c]) && s[4][c] == s[0][c] - s[2][c] &&
-                  s[5][c] == s[1][c] + s[2][c];
+    for (int q = 0; q < 6; ++q) {
+        wq[q] = 0.0;
+        for (int c = 0; c < 3; ++c) s[q][c] = 0;
     }
-    if (!rel) st |= ADLBR_ST_STENCIL;
-    if (!Slots<DIM, WIDE>::pack(s, sb, z)) st |= ADLBR_ST_RANGE;
-    const Coord p = coords(z, g);
-    for (int q = 0; q < S; ++q) {
-        const double wq = (double)win[q * N + z];
-        w[q * N + z] = Conv<TS, TA>::st((TA)wq);
-        if (!(wq > 0.0)) continue;
-        for (int sg = -1; sg <= 1; sg += 2) {
-            long long t;
-            if (!edge_target<DIM, PER>(p, z, s[q], sg, g, t)) continue;
-            // entries store z - t in 23 bits; such an edge is flagged and
-            // left out of both the count and the fill
-            if (z - t >= (1ll << 22) || z - t <= -(1ll << 22)) continue;
-            atomicAdd(&count[t], 1);
+    Coord p{0, 0, 0};
+    if (live) {
+        for (int q = 0; q < S; ++q)
+            for (int c = 0; c < 3; ++c) s[q][c] = c < DIM ? (int)off[(DIM * q + c) * N + z] : 0;
+        bool rel = true;
+        if (DIM == 2) {
+            for (int c = 0; c < 2; ++c) rel = rel && s[2][c] == -s[0][c] - s[1][c];
+        } else {
+            for (int c = 0; c < 3; ++c)
+                rel = rel && s[3][c] == -(s[0][c] + s[1][c]) && s[4][c] == s[0][c] - s[2][c] &&
+                      s[5][c] == s[1][c] + s[2][c];
+        }
+        if (!rel) st |= ADLBR_ST_STENCIL;
+        if (!Slots<DIM, WIDE>::pack(s, sb, z)) st |= ADLBR_ST_RANGE;
+        p = coords(z, g);
+        for (int q = 0; q < S; ++q) {
+            wq[q] = (double)win[q * N + z];
+            w[q * N + z] = Conv<TS, TA>::st((TA)wq[q]);
         }
     }
-    report(status, z, st);
+    for (int k = 0; k < 2 * S; ++k) {
+        const long long t = live ? edge_k<DIM, PER>(p, z, s, wq, k, g) : -1;
+        if (t == -2) st |= ADLBR_ST_RANGE;
+        bin_append(t >= 0 ? (int)(t >> kBinShift) : -1, bincnt, true);
+    }
+    if (live) report(status, z, st);
+}
+
+// Place every edge (target, entry) in its bin's region of binbuf.
+template <int DIM, bool WIDE, bool PER, typename TWin>
+__global__ void k_bin_fill(GridInfo g, const int16_t *__restrict__ off, const TWin *__restrict__ win,
+                           const uint32_t *__restrict__ binoff, uint32_t *__restrict__ bincur,
+                           int2 *__restrict__ binbuf) {
+    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = z < g.N;
+    constexpr int S = DIM == 2 ? 3 : 6;
+    const long long N = g.N;
+    int s[6][3];
+    double wq[6];
+    for (int q = 0; q < 6; ++q) {
+        wq[q] = 0.0;
+        for (int c = 0; c < 3; ++c) s[q][c] = 0;
+    }
+    Coord p{0, 0, 0};
+    if (live) {
+        for (int q = 0; q < S; ++q) {
+            for (int c = 0; c < 3; ++c) s[q][c] = c < DIM ? (int)off[(DIM * q + c) * N + z] : 0;
+            wq[q] = (double)win[q * N + z];
+        }
+        p = coords(z, g);
+    }
+    for (int k = 0; k < 2 * S; ++k) {
+        const long long t = live ? edge_k<DIM, PER>(p, z, s, wq, k, g) : -1;
+        const int bin = t >= 0 ? (int)(t >> kBinShift) : -1;
+        const unsigned slot = bin_append(bin, bincur, false);
+        if (bin >= 0) {
+            const int32_t e = (int32_t)(((z - t) << 9) | ((k >> 1) << 6) | (t & 63));
+            binbuf[(long long)binoff[bin] + slot] = make_int2((int)t, e);
+        }
+    }
+}
+
+// One block per bin: per-target counts and offsets in LDS, entries placed at
+// their row, rows sorted by (source, slot), diagonal A_zz = own in-grid
+// weights + incoming weights, and the maximum diagonal.
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TD>
+__global__ __launch_bounds__(256) void k_bin_build(
+    GridInfo g, const uint32_t *__restrict__ bincnt, const uint32_t *__restrict__ binoff,
+    const int2 *__restrict__ binbuf, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+    const TS *__restrict__ w, int32_t *__restrict__ pos, uint8_t *__restrict__ cnt,
+    int32_t *__restrict__ ent, TD *__restrict__ diag, unsigned long long *maxdiag, int32_t *status) {
+    __shared__ int32_t lcnt[kBin];
+    __shared__ int32_t loff[kBin];
+    __shared__ int32_t scan[256];
+    __shared__ double red[256];
+    constexpr int S = DIM == 2 ? 3 : 6;
+    const long long N = g.N;
+    const long long b = blockIdx.x;
+    const long long t0 = b << kBinShift;
+    const long long base = binoff[b];
+    const unsigned E = bincnt[b];
+    for (int k = threadIdx.x; k < kBin; k += 256) lcnt[k] = 0;
+    __syncthreads();
+    for (unsigned e = threadIdx.x; e < E; e += 256) atomicAdd(&lcnt[binbuf[base + e].x - t0], 1);
+    __syncthreads();
+    // exclusive scan of the clamped counts (4 per thread)
+    int32_t c4[4], sum = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int tl = threadIdx.x * 4 + k;
+        c4[k] = lcnt[tl];
+        sum += min(c4[k], 255);
+    }
+    scan[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const int32_t add = threadIdx.x >= (unsigned)d ? scan[threadIdx.x - d] : 0;
+        __syncthreads();
+        scan[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int32_t run = scan[threadIdx.x] - sum;
+    for (int k = 0; k < 4; ++k) {
+        const int tl = threadIdx.x * 4 + k;
+        loff[tl] = run;
+        const long long t = t0 + tl;
+        if (t < N) {
+            pos[t] = (int32_t)(base + run);
+            cnt[t] = (uint8_t)min(c4[k], 255);
+            if (c4[k] > 255) report(status, t, ADLBR_ST_INCOMING);
+        }
+        run += min(c4[k], 255);
+        lcnt[tl] = 0;  // becomes the placement cursor
+    }
+    __syncthreads();
+    for (unsigned e = threadIdx.x; e < E; e += 256) {
+        const int2 v = binbuf[base + e];
+        const int tl = v.x - (int)t0;
+        const int k = atomicAdd(&lcnt[tl], 1);
+        if (k < 255) ent[base + loff[tl] + k] = v.y;
+    }
+    __syncthreads();
+    double dmax = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        const int tl = threadIdx.x + 256 * k;
+        const long long z = t0 + tl;
+        if (z >= N) continue;
+        const int c = min(lcnt[tl], 255);
+        int32_t *e = ent + base + loff[tl];
+        if (c <= 16) {  // odd-even transposition network on 16 registers
+            int32_t r[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) r[i] = i < c ? e[i] : 0x7fffffff;
+#pragma unroll
+            for (int round = 0; round < 16; ++round) {
+#pragma unroll
+                for (int i = round & 1; i + 1 < 16; i += 2) {
+                    const int32_t a = r[i], bb = r[i + 1];
+                    r[i] = min(a, bb);
+                    r[i + 1] = max(a, bb);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i < c) e[i] = r[i];
+        } else {
+            for (int i = 1; i < c; ++i) {  // insertion sort by (source, slot)
+                const int32_t key = e[i];
+                int j = i - 1;
+                while (j >= 0 && e[j] > key) {
+                    e[j + 1] = e[j];
+                    --j;
+                }
+                e[j + 1] = key;
+            }
+        }
+        double d = 0.0;
+        Slots<DIM, WIDE> sl;
+        sl.load(sb, z);
+        const Coord p = coords(z, g);
+        for (int q = 0; q < S; ++q) {
+            const double wv = (double)Conv<TS, TA>::ld(w[q * N + z]);
+            for (int sg = -1; sg <= 1; sg += 2) {
+                long long t;
+                if (edge_target<DIM, PER>(p, z, sl.o[q], sg, g, t)) d += wv;
+            }
+        }
+        for (int i = 0; i < c; ++i) {
+            const int32_t v = e[i];
+            d += (double)Conv<TS, TA>::ld(w[(long long)((v >> 6) & 7) * N + z + (v >> 9)]);
+        }
+        diag[z] = (TD)d;
+        dmax = fmax(dmax, d);
+    }
+    red[threadIdx.x] = dmax;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(maxdiag, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+__global__ void k_copy_u32(const uint32_t *a, uint32_t *b, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
 }
 
 // Block-level exclusive scan helpers (blockDim.x == 256, 4 items per thread).
@@ -256,17 +466,6 @@ __device__ int32_t block_excl_scan256(int32_t v, int32_t *lds, int32_t &total) {
     return incl - v;
 }
 
-__global__ void k_scan_reduce(const int32_t *__restrict__ c, long long n, int32_t *bsum) {
-    __shared__ int32_t lds[256];
-    const long long base = (long long)blockIdx.x * kScanBlock + threadIdx.x * 4;
-    int32_t v = 0;
-    for (int k = 0; k < 4; ++k)
-        if (base + k < n) v += min(c[base + k], 255);
-    int32_t total;
-    block_excl_scan256(v, lds, total);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
-}
-
 __global__ void k_scan_top(int32_t *bsum, long long nb) {
     __shared__ int32_t lds[256];
     int32_t carry = 0;
@@ -278,127 +477,6 @@ __global__ void k_scan_top(int32_t *bsum, long long nb) {
         if (i < nb) bsum[i] = carry + ex;
         carry += total;
     }
-}
-
-__global__ void k_scan_down(const int32_t *__restrict__ c, long long n, const int32_t *bsum,
-                            int32_t *__restrict__ pos, uint8_t *__restrict__ cnt8, int32_t *status) {
-    __shared__ int32_t lds[256];
-    const long long base = (long long)blockIdx.x * kScanBlock + threadIdx.x * 4;
-    // lists longer than 255 are truncated (and flagged): positions use the
-    // clamped counts so that they agree with the uint8 counts the apply scans
-    int32_t v[4], sum = 0;
-    for (int k = 0; k < 4; ++k) {
-        v[k] = base + k < n ? c[base + k] : 0;
-        sum += min(v[k], 255);
-    }
-    int32_t total;
-    int32_t run = bsum[blockIdx.x] + block_excl_scan256(sum, lds, total);
-    for (int k = 0; k < 4; ++k) {
-        if (base + k < n) {
-            pos[base + k] = run;
-            cnt8[base + k] = (uint8_t)(v[k] > 255 ? 255 : v[k]);
-            if (v[k] > 255) report(status, base + k, ADLBR_ST_INCOMING);
-        }
-        run += min(v[k], 255);
-    }
-}
-
-// Write every incoming entry at its target's list (order fixed later).
-template <int DIM, bool WIDE, bool PER, typename TS>
-__global__ void k_fill_entries(GridInfo g, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
-                               const TS *__restrict__ w, const int32_t *__restrict__ pos,
-                               int32_t *__restrict__ cursor, int32_t *__restrict__ ent,
-                               const int16_t *__restrict__ off, const void *win, int win_f64,
-                               int32_t *status) {
-    const long long y = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (y >= g.N) return;
-    constexpr int S = DIM == 2 ? 3 : 6;
-    const long long N = g.N;
-    const Coord p = coords(y, g);
-    for (int q = 0; q < S; ++q) {
-        const double wq = win_f64 ? ((const double *)win)[q * N + y] : (double)((const float *)win)[q * N + y];
-        if (!(wq > 0.0)) continue;
-        int o[3];
-        for (int c = 0; c < 3; ++c) o[c] = c < DIM ? (int)off[(DIM * q + c) * N + y] : 0;
-        for (int sg = -1; sg <= 1; sg += 2) {
-            long long t;
-            if (!edge_target<DIM, PER>(p, y, o, sg, g, t)) continue;
-            const long long dlt = y - t;
-            if (dlt >= (1ll << 22) || dlt <= -(1ll << 22)) {
-                report(status, y, ADLBR_ST_RANGE);
-                continue;
-            }
-            const int32_t k = atomicAdd(&cursor[t], 1);
-            if (k < 255) ent[pos[t] + k] = (int32_t)((dlt << 9) | (q << 6) | (t & 63));
-        }
-    }
-}
-
-// Sort each incoming list, then A_zz = own in-grid weights + incoming
-// weights, in that fixed order; max over the grid for the CFL bound.
-template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TD>
-__global__ void k_finalize(GridInfo g, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
-                           const TS *__restrict__ w, const int32_t *__restrict__ pos,
-                           const uint8_t *__restrict__ cnt, int32_t *__restrict__ ent,
-                           TD *__restrict__ diag, unsigned long long *maxdiag) {
-    __shared__ double red[kBS];
-    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    double d = 0.0;
-    if (z < g.N) {
-        constexpr int S = DIM == 2 ? 3 : 6;
-        const long long N = g.N;
-        const int c = cnt[z];
-        int32_t *e = ent + pos[z];
-        if (c <= 16) {  // odd-even transposition network on 16 registers
-            int32_t r[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) r[i] = i < c ? e[i] : 0x7fffffff;
-#pragma unroll
-            for (int round = 0; round < 16; ++round) {
-#pragma unroll
-                for (int i = round & 1; i + 1 < 16; i += 2) {
-                    const int32_t a = r[i], b = r[i + 1];
-                    r[i] = min(a, b);
-                    r[i + 1] = max(a, b);
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (i < c) e[i] = r[i];
-        } else {
-            for (int i = 1; i < c; ++i) {  // insertion sort by (source, slot)
-                const int32_t key = e[i];
-                int j = i - 1;
-                while (j >= 0 && e[j] > key) {
-                    e[j + 1] = e[j];
-                    --j;
-                }
-                e[j + 1] = key;
-            }
-        }
-        Slots<DIM, WIDE> sl;
-        sl.load(sb, z);
-        const Coord p = coords(z, g);
-        for (int q = 0; q < S; ++q) {
-            const double wq = (double)Conv<TS, TA>::ld(w[q * N + z]);
-            for (int sg = -1; sg <= 1; sg += 2) {
-                long long t;
-                if (edge_target<DIM, PER>(p, z, sl.o[q], sg, g, t)) d += wq;
-            }
-        }
-        for (int k = 0; k < c; ++k) {
-            const int32_t v = e[k];
-            d += (double)Conv<TS, TA>::ld(w[(long long)((v >> 6) & 7) * N + z + (v >> 9)]);
-        }
-        diag[z] = (TD)d;
-    }
-    red[threadIdx.x] = d;
-    __syncthreads();
-    for (int s = kBS / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(maxdiag, (unsigned long long)__double_as_longlong(red[0]));
 }
 
 __global__ void k_cfl(const unsigned long long *maxdiag, double *dtcfl) {
@@ -630,32 +708,35 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
     const GridInfo g = op->gi;
     const long long N = g.N;
     const unsigned nb = (unsigned)((N + kBS - 1) / kBS);
-    const unsigned nscan = (unsigned)((N + kScanBlock - 1) / kScanBlock);
+    const long long nbins = (N + kBin - 1) / kBin;
+    const unsigned nbb = (unsigned)((nbins + kBS - 1) / kBS);
     TS *w = (TS *)op->w;
     store_t *sb = (store_t *)op->sb;
-    const long long Npad = (N + 1023) / 1024 * 1024;
-    const unsigned nbp = (unsigned)(Npad / kBS);
-    hipLaunchKernelGGL(k_fill_i32, dim3(nbp), dim3(kBS), 0, s, op->tmp, Npad, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nbb), dim3(kBS), 0, s, (int32_t *)op->bincnt, nbins, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nbb), dim3(kBS), 0, s, (int32_t *)op->bincur, nbins, 0);
     hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(1), 0, s, op->maxdiag);
     if (win_f64)
         hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, double, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
-                           off, (const double *)win, sb, w, op->tmp, status);
+                           off, (const double *)win, sb, w, op->bincnt, status);
     else
         hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, float, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
-                           off, (const float *)win, sb, w, op->tmp, status);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nscan), dim3(256), 0, s, op->tmp, N, op->bsum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, op->bsum, (long long)nscan);
-    hipLaunchKernelGGL(k_scan_down, dim3(nscan), dim3(256), 0, s, op->tmp, N, op->bsum, op->pos,
-                       op->cnt, status);
-    hipLaunchKernelGGL(k_fill_i32, dim3(nbp), dim3(kBS), 0, s, op->tmp, Npad, 0);
-    hipLaunchKernelGGL((k_fill_entries<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g, sb, w,
-                       op->pos, op->tmp, op->ent, off, win, win_f64, status);
-    if (op->storage == ADLBR_F64)
-        hipLaunchKernelGGL((k_finalize<DIM, WIDE, PER, TS, TA, double>), dim3(nb), dim3(kBS), 0, s, g,
-                           sb, w, op->pos, op->cnt, op->ent, (double *)op->diag, op->maxdiag);
+                           off, (const float *)win, sb, w, op->bincnt, status);
+    hipLaunchKernelGGL(k_copy_u32, dim3(nbb), dim3(kBS), 0, s, op->bincnt, op->binoff, nbins);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, (int32_t *)op->binoff, nbins);
+    if (win_f64)
+        hipLaunchKernelGGL((k_bin_fill<DIM, WIDE, PER, double>), dim3(nb), dim3(kBS), 0, s, g, off,
+                           (const double *)win, op->binoff, op->bincur, op->binbuf);
     else
-        hipLaunchKernelGGL((k_finalize<DIM, WIDE, PER, TS, TA, float>), dim3(nb), dim3(kBS), 0, s, g,
-                           sb, w, op->pos, op->cnt, op->ent, (float *)op->diag, op->maxdiag);
+        hipLaunchKernelGGL((k_bin_fill<DIM, WIDE, PER, float>), dim3(nb), dim3(kBS), 0, s, g, off,
+                           (const float *)win, op->binoff, op->bincur, op->binbuf);
+    if (op->storage == ADLBR_F64)
+        hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, double>), dim3((unsigned)nbins),
+                           dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w, op->pos,
+                           op->cnt, op->ent, (double *)op->diag, op->maxdiag, status);
+    else
+        hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, float>), dim3((unsigned)nbins),
+                           dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w, op->pos,
+                           op->cnt, op->ent, (float *)op->diag, op->maxdiag, status);
     hipLaunchKernelGGL(k_cfl, dim3(1), dim3(1), 0, s, op->maxdiag, op->dtcfl);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
@@ -768,14 +849,14 @@ template <int DIM, bool WIDE, bool PER> struct ResidualF<DIM, WIDE, PER, _Float1
 };
 
 struct Layout {
-    size_t sb, w, cnt, pos, ent, diag, scal, tmp, bsum, total;
+    size_t sb, w, cnt, pos, ent, diag, scal, bincnt, bincur, binoff, binbuf, total;
 };
 
 Layout layout(const GridInfo &g, int storage, int wide) {
     const long long N = g.N;
     const int S = g.dim == 2 ? 3 : 6;
     const size_t sbsz = g.dim == 2 ? (wide ? 8 : 4) : (wide ? 24 : 12);
-    const size_t nscan = (size_t)((N + kScanBlock - 1) / kScanBlock);
+    const size_t nbins = (size_t)((N + kBin - 1) / kBin);
     Layout L;
     size_t o = 0;
     L.sb = o;   o += align_up(sbsz * N);
@@ -785,8 +866,10 @@ Layout layout(const GridInfo &g, int storage, int wide) {
     L.ent = o;  o += align_up(4 * (size_t)(2 * S) * N);
     L.diag = o; o += align_up((storage == ADLBR_F64 ? 8 : 4) * (size_t)N);
     L.scal = o; o += 256;
-    L.tmp = o;  o += align_up(4 * (size_t)((N + 1023) / 1024 * 1024));
-    L.bsum = o; o += align_up(4 * nscan + 4);
+    L.bincnt = o; o += align_up(4 * nbins + 4);
+    L.bincur = o; o += align_up(4 * nbins + 4);
+    L.binoff = o; o += align_up(4 * nbins + 4);
+    L.binbuf = o; o += align_up(8 * (size_t)(2 * S) * N);
     L.total = o;
     return L;
 }
@@ -850,6 +933,10 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
         return ADLBR_E_INVALID;
     }
     const int wide = flags & ADLBR_OP_WIDE ? 1 : 0;
+    if ((long long)(gi.dim == 2 ? 6 : 12) * gi.N >= (1ll << 31)) {
+        set_error("adlbr_operator_create: too many edges for 32-bit list positions");
+        return ADLBR_E_RANGE;
+    }
     const Layout L = layout(gi, storage, wide);
     if (ws_bytes < L.total) {
         set_error("adlbr_operator_create: workspace has %zu bytes, %zu needed", ws_bytes, L.total);
@@ -877,8 +964,10 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
     op->diag = b + L.diag;
     op->maxdiag = (unsigned long long *)(b + L.scal);
     op->dtcfl = (double *)(b + L.scal + 8);
-    op->tmp = (int32_t *)(b + L.tmp);
-    op->bsum = (int32_t *)(b + L.bsum);
+    op->bincnt = (uint32_t *)(b + L.bincnt);
+    op->bincur = (uint32_t *)(b + L.bincur);
+    op->binoff = (uint32_t *)(b + L.binoff);
+    op->binbuf = (int2 *)(b + L.binbuf);
     hipStream_t s = as_stream(stream);
     hipLaunchKernelGGL(k_status_init, dim3(1), dim3(1), 0, s, status);
     rc = dispatch<BuildF>(op, offsets, weights, (int)(w_dtype == ADLBR_F64), status, s);

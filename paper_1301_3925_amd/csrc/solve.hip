@@ -14,7 +14,6 @@
 // variant admits the learned preconditioner): update (x, r, <r,r>) ->
 // z = N(r) -> dots (<z,r>, <z,r_prev>, beta) -> direction.
 #include <algorithm>
-#include <cstring>
 #include <utility>
 #include <vector>
 
@@ -174,7 +173,38 @@ __global__ void k_fcg_scalars(SolveState *st, int first) {
     st->cg.rz = zr;
 }
 
-__global__ void k_clear_done(SolveState *st) { st->cg.done = 0; }
+// Zero the whole state (tickets included) and set dt; a kernel rather than a
+// host copy so no host buffer has to outlive the enqueue.
+__global__ void k_state_reset(SolveState *st, double dt) {
+    uint32_t *w = (uint32_t *)st;
+    constexpr int nw = (int)(sizeof(SolveState) / 4);
+    for (int k = threadIdx.x; k < nw; k += blockDim.x) w[k] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) st->cg.dt = dt;
+}
+
+// Residual replacement: r already holds b - K x (from the true residual);
+// recompute the Jacobi z and <r, z>, restart the direction (beta = 0) and
+// keep the iteration count.
+template <typename T, typename TD>
+__global__ void k_restart(long long N, const T *__restrict__ r, T *__restrict__ z,
+                          const TD *__restrict__ diag, int jacobi, SolveState *st, double *part) {
+    const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
+    double rz = 0.0;
+    if (i < N && jacobi) {
+        const T ri = r[i];
+        const T zi = (T)((double)ri * inv_kd(diag, i, st->cg.dt));
+        z[i] = zi;
+        rz = (double)ri * (double)zi;
+    }
+    double t;
+    if (last_block_sum(rz, part, &st->tickets[0], t) && threadIdx.x == 0) {
+        st->cg.rz = t;
+        st->cg.beta = 0.0;
+        st->cg.rr = st->rr_true;
+        st->cg.done = 0;
+    }
+}
 
 template <typename TA, typename TB> __global__ void k_convert(long long N, const TA *a, TB *b) {
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
@@ -228,10 +258,7 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     ADLBR_CHECK_HIP(hipEventCreate(&e1));
     ADLBR_CHECK_HIP(hipEventRecord(e0, s));
     // clear the state (tickets must start at 0), set dt
-    SolveState init;
-    std::memset(&init, 0, sizeof init);
-    init.cg.dt = dt;
-    ADLBR_CHECK_HIP(hipMemcpyAsync(st, &init, sizeof init, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, st, dt);
     // the iterate is accumulated in FP64 (x64); the vectors and recurrences
     // are in the storage dtype
     if (!p->x0_zero) {
@@ -243,7 +270,7 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
                        p->x0_zero, (int)!net, st, part, p->tol * p->tol);
     int rc = ADLBR_OK;
     bool use_net = net;
-    int fell_back = 0, net_iters = 0;
+    int fell_back = 0, net_iters = 0, restarts = 0, reason = 0;
     int first = 1;
     T *rc_ = r, *ro = r2;  // current and previous residual (flexible CG)
     auto start_iteration = [&]() -> int {
@@ -294,12 +321,20 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
         ADLBR_CHECK_HIP(hipStreamSynchronize(s));
         if (use_net) {
             net_iters = h.iter;
-            // stall: the residual norm fell by less than 1% over >= 20 iterations
-            for (auto it = trail.rbegin(); it != trail.rend(); ++it)
-                if (h.iter - it->first >= 20) {
-                    if (!h.done && h.rr > 0.99 * 0.99 * it->second) h.bad = 1;
-                    break;
-                }
+            // stall: the smallest |r|^2 seen at the checks of the last 20
+            // iterations is not (1%)^2 below the smallest one before them
+            // (residual norms of CG are not monotone, hence the minima)
+            double old_min = -1.0, new_min = h.rr;
+            for (const auto &e : trail) {
+                if (h.iter - e.first >= 20)
+                    old_min = old_min < 0.0 ? e.second : std::min(old_min, e.second);
+                else
+                    new_min = std::min(new_min, e.second);
+            }
+            if (!h.done && !h.bad && old_min >= 0.0 && new_min > 0.99 * 0.99 * old_min) {
+                h.bad = 1;
+                reason = 2;
+            }
             trail.emplace_back(h.iter, h.rr);
         }
         if (h.bad) {
@@ -307,12 +342,10 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
             // learned preconditioner failed: restart from x with Jacobi-PCG
             use_net = false;
             fell_back = 1;
+            if (!reason) reason = 1;
             first = 1;
             const int keep_iter = h.iter;
-            SolveState re;
-            std::memset(&re, 0, sizeof re);
-            re.cg.dt = dt;
-            ADLBR_CHECK_HIP(hipMemcpyAsync(st, &re, sizeof re, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, st, dt);
             rc = true_residual(op, dt, b, x64, &st->rr_true, part, &st->tickets[7], r, s);
             if (rc) return rc;
             hipLaunchKernelGGL((k_init<T, TD>), dim3(nb), dim3(kBS), 0, s, N, b, x64, r, z, diag,
@@ -336,7 +369,17 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
                 converged = true;
                 break;
             }
-            hipLaunchKernelGGL(k_clear_done, dim3(1), dim3(1), 0, s, st);
+            // the recurrence residual drifted from the true one: replace it
+            // and restart the direction from the current iterate
+            rc = true_residual(op, dt, b, x64, &st->rr_true, part, &st->tickets[7], rc_, s);
+            if (rc) return rc;
+            hipLaunchKernelGGL((k_restart<T, TD>), dim3(nb), dim3(kBS), 0, s, N, (const T *)rc_, z,
+                               diag, (int)!use_net, st, part);
+            first = 1;
+            rc = start_iteration();
+            if (rc) return rc;
+            trail.clear();
+            ++restarts;
         }
     }
     // final report
@@ -362,6 +405,8 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
         rep->net_iters = net ? (fell_back ? net_iters : iters) : 0;
         rep->rel_res = bb > 0.0 ? sqrt(rt / bb) : 0.0;
         rep->time_ms = ms;
+        rep->restarts = restarts;
+        rep->fallback_reason = reason;
     }
     if (!converged) {
         set_error("adlbr_solve: not converged after %d iterations (relative residual %.3e)",

@@ -158,7 +158,7 @@ def test_fcg_untrained_net_converges(lib, dim):
     net.prepare(dt)
     b = torch.from_numpy(synth.uniform(6, op.N)).float().cuda()
     x, rep = op.solve(b, dt, method="fcg", net=net, tol=1e-6)
-    assert rep["converged"] == 1 and rep["rel_res"] <= 1e-6
+    assert rep["converged"] == 1 and rep["rel_res"] <= 1e-6, rep
     K = solvers.system_matrix(A, dt)
     xr = solvers.jacobi_pcg(K, b.double().cpu().numpy(), tol=1e-9)[0]
     assert _rel(x.double().cpu().numpy(), xr) <= 3e-6
@@ -178,7 +178,7 @@ def test_fcg_falls_back_on_nan_weights(lib):
     net.prepare(dt)
     b = torch.from_numpy(synth.uniform(7, op.N)).float().cuda()
     x, rep = op.solve(b, dt, method="fcg", net=net, tol=1e-6)
-    assert rep["fell_back"] == 1 and rep["converged"] == 1 and rep["rel_res"] <= 1e-6
+    assert rep["fell_back"] == 1 and rep["converged"] == 1 and rep["rel_res"] <= 1e-6, rep
 
 
 def test_training_gains_over_untrained_and_jacobi(lib):

@@ -42,8 +42,8 @@ def test_jacobi_pcg_fp64_matches_oracle(lib, dims, kappa):
     b = synth.uniform(7, op.N)
     xr, itr, relr = solvers.jacobi_pcg(K, b, tol=1e-6)
     x, rep = op.solve(torch.from_numpy(b).cuda(), dt, tol=1e-6, check_every=7)
-    assert rep["converged"] == 1 and rep["rel_res"] <= 1e-6
-    assert abs(rep["iters"] - itr) <= 1
+    assert rep["converged"] == 1 and rep["rel_res"] <= 1e-6, rep
+    assert abs(rep["iters"] - itr) <= 1, (rep, itr)
     xs = np.linalg.solve(K.toarray(), b) if op.N <= 8000 else xr
     assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-5 * np.linalg.norm(xs)
 

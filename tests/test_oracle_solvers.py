@@ -80,6 +80,24 @@ def test_fcg_falls_back_on_bad_preconditioner():
     assert fb and rel <= 1e-6
 
 
+def test_fcg_falls_back_on_stall():
+    """A preconditioner that is SPD but nearly ignores all but eight unknowns
+    (<z, r> > 0 throughout, next to no progress) trips the stall rule;
+    Jacobi-PCG then converges from where FCG stopped."""
+    A, dt, K, _, _ = _system()
+    n = K.shape[0]
+    b = synth.uniform(5, n)
+    m = np.full(n, 1e-9)
+    m[:: n // 8][:8] = 1.0
+
+    x, it, rel, fb, h = solvers.fcg(K, b, lambda r: m * r, tol=1e-6, history=True)
+    assert fb and rel <= 1e-6
+    assert len(h) == 21  # the stall is detected after exactly 20 iterations
+    assert min(h[1:]) > 0.99 * h[0]
+    _, itj, _ = solvers.jacobi_pcg(K, b, tol=1e-6)
+    assert it >= 20 + itj - 5
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_conv_matches_library_correlation(dim):
     """A single-channel layer equals scipy's zero-padded correlation."""
