@@ -145,44 +145,57 @@ def conv(x, W, b):
     return out
 
 
+def conv_adjoint(y, W):
+    """Adjoint of the zero-padded correlation x -> conv(x, W, 0):
+    out[i, p] = sum_{o, t} W[o, i, t] y[o, p - t + 1]."""
+    dim = y.ndim - 1
+    shp = y.shape[1:]
+    gxp = np.zeros((W.shape[1],) + tuple(s + 2 for s in shp))
+    for t in _taps(dim):
+        sl = (slice(None),) + tuple(slice(t[k], t[k] + shp[k]) for k in range(dim))
+        gxp[sl] += np.einsum("oi,o...->i...", W[(slice(None), slice(None)) + t], y)
+    return gxp[(slice(None),) + tuple(slice(1, 1 + s) for s in shp)]
+
+
 def conv_backward(x, W, g):
     """Gradients of sum(g * conv(x, W, b)) w.r.t. x, W and b."""
     dim = x.ndim - 1
     xp = _pad(x, dim)
     shp = x.shape[1:]
-    gxp = np.zeros_like(xp)
     gW = np.zeros_like(W)
     for t in _taps(dim):
         sl = (slice(None),) + tuple(slice(t[k], t[k] + shp[k]) for k in range(dim))
         gW[(slice(None), slice(None)) + t] = (g.reshape(g.shape[0], -1)
                                               @ xp[sl].reshape(xp.shape[0], -1).T)
-        gxp[sl] += np.einsum("oi,o...->i...", W[(slice(None), slice(None)) + t], g)
-    gx = gxp[(slice(None),) + tuple(slice(1, 1 + s) for s in shp)]
     gb = g.reshape(g.shape[0], -1).sum(1)
-    return gx, gW, gb
+    return conv_adjoint(g, W), gW, gb
 
 
 # ------------------------------------------------------ learned preconditioner --
+# z = r / diag(K) + N(r) with N = B^T diag(g2) B and B = C2 diag(g1) C1,
+# C1, C2 zero-padded 3^d correlations (1 -> W -> W channels, no bias) and
+# g1, g2 in (0, 1) gates from a small gate net on per-point features.  N is
+# symmetric positive semi-definite by construction, so the preconditioner
+# diag(K)^-1 + N is SPD and flexible CG never meets <z, r> <= 0 in exact
+# arithmetic.  Applied, it is four correlations: C1, C2, C2^T, C1^T.
 # Parameter layout (flat FP32 vector, in this order):
 #   gate layer A  WA (H, nf, T), bA (H)         conv 3^d, ReLU
-#   gate layer B  WB (G, H),     bB (G)         1x1, sigmoid, G = 3 W + 1
-#   r path        W1 (W, 1, T), W2 (W, W, T), W3 (W, W, T), W4 (1, W, T)
+#   gate layer B  WB (2W, H),    bB (2W)        1x1, sigmoid -> g1, g2
+#   r path        W1 (W, 1, T), W2 (W, W, T)
 # with T = 3^d taps in (dz,) dy, dx row-major order over offsets -1, 0, +1.
 
 def net_shapes(dim, width=16, hidden=16):
-    T = 3 ** dim
     nf = 1 + (3 if dim == 2 else 6) + (3 if dim == 2 else 6)
-    G = 3 * width + 1
+    G = 2 * width
     return [("WA", (hidden, nf) + (3,) * dim), ("bA", (hidden,)),
             ("WB", (G, hidden)), ("bB", (G,)),
-            ("W1", (width, 1) + (3,) * dim), ("W2", (width, width) + (3,) * dim),
-            ("W3", (width, width) + (3,) * dim), ("W4", (1, width) + (3,) * dim)]
+            ("W1", (width, 1) + (3,) * dim), ("W2", (width, width) + (3,) * dim)]
 
 
 def net_init(seed, dim, width=16, hidden=16):
-    """He-style initialization; gate biases start at +2 (gates near 0.88)
-    and the output layer small, so the untrained net is a mild
-    perturbation of Jacobi."""
+    """He-style initialization for the gate net, gate biases +2 (gates near
+    0.88) and r-path weights at 0.3 x He scale, so the untrained N is a mild
+    positive addition to Jacobi."""
     rng = np.random.Generator(np.random.PCG64(seed))
     P = {}
     for name, shp in net_shapes(dim, width, hidden):
@@ -190,7 +203,7 @@ def net_init(seed, dim, width=16, hidden=16):
             P[name] = np.full(shp, 2.0 if name == "bB" else 0.0)
         else:
             fan_in = int(np.prod(shp[1:]))
-            scale = np.sqrt(2.0 / fan_in) if name != "W4" else 0.1 / np.sqrt(fan_in)
+            scale = np.sqrt(2.0 / fan_in) * (0.3 if name in ("W1", "W2") else 1.0)
             P[name] = rng.normal(0.0, scale, size=shp)
     return P
 
@@ -234,7 +247,8 @@ def _sigmoid(x):
 
 
 def net_gates(P, F, keep=False):
-    """Gates G = sigmoid(WB relu(conv(F; WA) + bA) + bB), shape (3W+1,) + spatial."""
+    """Gates G = sigmoid(WB relu(conv(F; WA) + bA) + bB), shape (2W,) + spatial:
+    g1 = G[:W], g2 = G[W:]."""
     h = conv(F, P["WA"], P["bA"])
     hr = np.maximum(h, 0.0)
     g = np.einsum("gh,h...->g...", P["WB"], hr) + P["bB"].reshape((-1,) + (1,) * (F.ndim - 1))
@@ -242,48 +256,51 @@ def net_gates(P, F, keep=False):
     return (G, h, hr) if keep else G
 
 
-def net_apply(P, G, r, kd_shape):
-    """N(r): h1 = conv(r; W1) * G[0:W], h2 = conv(h1; W2) * G[W:2W],
-    h3 = conv(h2; W3) * G[2W:3W], out = conv(h3; W4) * G[3W].  Linear in r.
-    Returns (out, list of pre-gate conv outputs, list of layer inputs)."""
+def _net_B(P, G, v):
+    """B v = C2 (g1 * C1 v); returns (B v, C1 v, g1 * C1 v)."""
     W = P["W1"].shape[0]
-    x = np.asarray(r, dtype=np.float64).reshape((1,) + kd_shape)
-    pres, ins = [], []
-    gsl = [slice(0, W), slice(W, 2 * W), slice(2 * W, 3 * W), slice(3 * W, 3 * W + 1)]
-    zero = lambda c: np.zeros(c)
-    for l, name in enumerate(["W1", "W2", "W3", "W4"]):
-        ins.append(x)
-        a = conv(x, P[name], zero(P[name].shape[0]))
-        pres.append(a)
-        x = a * G[gsl[l]]
-    return x[0], pres, ins
+    a1 = conv(v, P["W1"], np.zeros(W))
+    x1 = a1 * G[:W]
+    return conv(x1, P["W2"], np.zeros(W)), a1, x1
+
+
+def net_apply(P, G, r, shape):
+    """N(r) = B^T (g2 * B r), B^T y = C1^T (g1 * C2^T y)."""
+    W = P["W1"].shape[0]
+    x = np.asarray(r, dtype=np.float64).reshape((1,) + tuple(shape))
+    Br, _, _ = _net_B(P, G, x)
+    y = G[W:] * Br
+    return conv_adjoint(G[:W] * conv_adjoint(y, P["W2"]), P["W1"])[0]
 
 
 def net_precondition(P, G, r, kd):
     """z = r / diag(K) + N(r)."""
     kd = np.asarray(kd, dtype=np.float64)
-    out, _, _ = net_apply(P, G, r, G.shape[1:])
+    out = net_apply(P, G, r, G.shape[1:])
     return np.asarray(r, dtype=np.float64) / kd + out.reshape(-1)
 
 
 def net_backward(P, F, r, gz):
-    """Gradient of sum(gz * z) w.r.t. every parameter (dict of arrays), by
-    the chain rule through the r path, the gates and the gate net."""
+    """Gradient of s = <gz, N(r)> = <B gz, g2 * B r> w.r.t. every parameter
+    (dict of arrays).  The g2 gradient is B gz * B r; B's parameters get the
+    backward of B at input r with cotangent g2 * B gz plus the backward at
+    input gz with cotangent g2 * B r; then the gate net by the chain rule."""
     G, h, hr = net_gates(P, F, keep=True)
     shp = G.shape[1:]
     W = P["W1"].shape[0]
-    _, pres, ins = net_apply(P, G, r, shp)
-    gsl = [slice(0, W), slice(W, 2 * W), slice(2 * W, 3 * W), slice(3 * W, 3 * W + 1)]
-    grads = {}
+    vr = np.asarray(r, dtype=np.float64).reshape((1,) + shp)
+    vg = np.asarray(gz, dtype=np.float64).reshape((1,) + shp)
+    Br, a1r, x1r = _net_B(P, G, vr)
+    Bg, a1g, x1g = _net_B(P, G, vg)
     gG = np.zeros_like(G)
-    g = np.asarray(gz, dtype=np.float64).reshape((1,) + shp)
-    for l in range(3, -1, -1):
-        name = ["W1", "W2", "W3", "W4"][l]
-        gG[gsl[l]] = g * pres[l]
-        ga = g * G[gsl[l]]
-        gx, gW, _ = conv_backward(ins[l], P[name], ga)
-        grads[name] = gW
-        g = gx
+    gG[W:] = Bg * Br
+    grads = {"W1": np.zeros_like(P["W1"]), "W2": np.zeros_like(P["W2"])}
+    for v, a1, x1, cot in ((vr, a1r, x1r, G[W:] * Bg), (vg, a1g, x1g, G[W:] * Br)):
+        gx1, gW2, _ = conv_backward(x1, P["W2"], cot)
+        grads["W2"] += gW2
+        gG[:W] += gx1 * a1
+        _, gW1, _ = conv_backward(v, P["W1"], gx1 * G[:W])
+        grads["W1"] += gW1
     gg = gG * G * (1.0 - G)                       # sigmoid'
     grads["bB"] = gg.reshape(gg.shape[0], -1).sum(1)
     grads["WB"] = gg.reshape(gg.shape[0], -1) @ hr.reshape(hr.shape[0], -1).T

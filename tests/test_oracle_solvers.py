@@ -152,7 +152,7 @@ def test_net_backward_matches_finite_differences(dim):
 
 
 def test_net_is_linear_in_r_and_reduces_to_jacobi():
-    """N is linear in r (gates do not depend on r); with W4 = 0 the
+    """N is linear in r (gates do not depend on r); with W1 = 0 the
     preconditioner is Jacobi and flexible CG reproduces Jacobi-PCG."""
     dims, A, dt, F, P, _ = _net_case(2)
     rng = np.random.default_rng(2)
@@ -163,7 +163,7 @@ def test_net_is_linear_in_r_and_reduces_to_jacobi():
     z = lambda r: solvers.net_precondition(P, G, r, kd)
     assert np.allclose(z(2 * r1 - 3 * r2), 2 * z(r1) - 3 * z(r2), rtol=1e-10, atol=1e-12)
     P0 = dict(P)
-    P0["W4"] = np.zeros_like(P["W4"])
+    P0["W1"] = np.zeros_like(P["W1"])
     G0 = solvers.net_gates(P0, F)
     assert np.allclose(solvers.net_precondition(P0, G0, r1, kd), r1 / kd, rtol=0, atol=0)
     K = solvers.system_matrix(A, dt)
@@ -173,13 +173,46 @@ def test_net_is_linear_in_r_and_reduces_to_jacobi():
     assert not fb and it1 == it2
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_conv_adjoint_identity(dim):
+    """<conv(x, W), y> = <x, conv_adjoint(y, W)> for random multi-channel
+    x, y, W (zero padding on both sides)."""
+    rng = np.random.default_rng(20 + dim)
+    shp = (7, 6) if dim == 2 else (5, 4, 6)
+    x = rng.normal(size=(3,) + shp)
+    y = rng.normal(size=(4,) + shp)
+    W = rng.normal(size=(4, 3) + (3,) * dim)
+    lhs = float(np.sum(solvers.conv(x, W, np.zeros(4)) * y))
+    rhs = float(np.sum(x * solvers.conv_adjoint(y, W)))
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_net_preconditioner_is_spd(dim):
+    """The dense matrix of r -> N(r) (columns from unit vectors) is
+    symmetric and positive semi-definite, so diag(K)^-1 + N is SPD and
+    <z, r> >= <r / diag K, r> for every r."""
+    dims, A, dt, F, P, _ = _net_case(dim)
+    n = int(np.prod(dims))
+    G = solvers.net_gates(P, F)
+    shp = G.shape[1:]
+    M = np.stack([solvers.net_apply(P, G, e, shp).reshape(-1) for e in np.eye(n)], axis=1)
+    scale = np.abs(M).max()
+    assert scale > 0
+    assert np.abs(M - M.T).max() <= 1e-12 * scale
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() >= -1e-12 * scale
+    kd = 1 + dt * A.diagonal()
+    r = np.random.default_rng(3).normal(size=n)
+    assert solvers.net_precondition(P, G, r, kd) @ r >= (r / kd) @ r
+
+
 def test_net_pack_roundtrip():
     P = solvers.net_init(1, 3, width=16, hidden=16)
     flat = solvers.net_pack(P, 3)
     Q = solvers.net_unpack(flat, 3)
     assert all(np.array_equal(P[k], Q[k]) for k in P)
     T = 27
-    assert flat.size == 16 * 13 * T + 16 + 49 * 16 + 49 + 16 * T + 2 * 16 * 16 * T + 16 * T
+    assert flat.size == 16 * 13 * T + 16 + 32 * 16 + 32 + 16 * T + 16 * 16 * T
 
 
 def test_energy_loss_minimum_and_gradient():
