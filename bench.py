@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5", "c5-3d"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5", "c5-3d", "copy"])
     ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--dtype", default=None, help="storage dtype for c3: f64|f32|bf16|f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -199,6 +199,8 @@ def main():
         print(json.dumps(res), flush=True)
         return
 
+    if args.workload == "copy":
+        return run_copy(args, dev, stream)
     if args.workload in ("c5", "c5-3d"):
         run_c5(args, dev, stream)
         return
@@ -258,6 +260,38 @@ def main():
             Ds = synth.tensor3d_field(seed, (m, m, m), kappa)
             res["cpu_baseline"] = cpu_baseline_steps((m, m, m), Ds, synth.uniform(seed + 1, m ** 3), 10)
     print(json.dumps(res), flush=True)
+
+
+def run_copy(args, dev, stream):
+    """HBM anchor: a plain device-to-device copy of 1 GiB (FP32), the
+    reference kernel for the roofline and for scaling the FETCH_SIZE /
+    WRITE_SIZE counters (known bytes read and written per launch)."""
+    import torch
+    n = 1 << 28
+    src = torch.rand(n, device=dev)
+    dst = torch.empty_like(src)
+    K = args.steps if args.steps is not None else 20
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(K):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    gbs = 2 * 4 * n / (ms / 1e3) / 1e9
+    print(json.dumps({"metric": "HBM copy bandwidth", "value": round(gbs, 1), "unit": "GB/s",
+                      "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "copy-1GiB-f32", "bytes_read": 4 * n,
+                                 "bytes_written": 4 * n},
+                      "roofline": {"bound": "hbm", "achieved": round(gbs, 1),
+                                   "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                   "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None}}),
+          flush=True)
 
 
 def run_c5(args, dev, stream):

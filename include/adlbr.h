@@ -229,24 +229,31 @@ int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
 /* ------------------------------------------------------------------ *
  * Learned preconditioner (an extension; the paper has none).
  *   z = r / diag(K) + N(r),  K = I + dt A,
- * N: four zero-padded 3x3 (3x3x3) convolutions on r, width channels
- * (1 -> W -> W -> W -> 1, no bias), each output multiplied point-wise by
- * gates G = sigmoid(WB relu(conv(F; WA) + bA) + bB) (3W + 1 channels) that a
- * small gate net computes once per operator from per-point features F:
+ *   N = B^T diag(g2) B,  B = C2 diag(g1) C1,
+ * C1, C2 zero-padded 3x3 (3x3x3) correlations (1 -> W -> W channels, no
+ * bias); g1, g2 point-wise gates in (0, 1), G = [g1, g2] =
+ * sigmoid(WB relu(conv(F; WA) + bA) + bB) (2W channels), computed once per
+ * operator by a small gate net from per-point features
  *   F = [1/diag(K), dt w_q / diag(K) (S slots), D / tr D (3 or 6)],
  *   D = sum_{e in V(z)} gamma e e^T recovered from the stencil (eq. (DSum)).
- * N is linear in r, so flexible CG sees a fixed linear preconditioner.
+ * N is linear in r and symmetric positive semi-definite, so the
+ * preconditioner is SPD and flexible CG sees a fixed linear one.  It is
+ * applied as four correlations C1, C2, C2^T, C1^T (a 1->W->W->W->1 stack).
  * params: FP32, in this order (T = 3^d taps, (dz,) dy, dx row-major over
  * offsets -1, 0, +1):
- *   WA [hidden][nfeat][T], bA [hidden], WB [3W+1][hidden], bB [3W+1],
- *   W1 [W][1][T], W2 [W][W][T], W3 [W][W][T], W4 [1][W][T].
+ *   WA [hidden][nfeat][T], bA [hidden], WB [2W][hidden], bB [2W],
+ *   W1 [W][1][T], W2 [W][W][T].
  * The struct is plain data owned by the caller; every array is device
- * memory of the operator's grid (N points):
+ * memory (N = the operator's grid points):
  *   features [nfeat][N] FP32   (adlbr_net_features)
  *   hidden   [hidden][N] FP32  pre-activation of the gate net (adlbr_net_gates)
- *   gates    [3W+1][N] FP32    (adlbr_net_gates)
+ *   gates    [3W+1][N] FP32    gates of the four-layer stack, [g1, g2, g1, 1]
+ *                              (adlbr_net_gates)
  *   gates16  [N][3W+1] BF16    packed copy for the inference kernel
  *   scratch  [2W][N] FP32      working planes of the FP32 forward path
+ *   layers   [2W(W+1)T] FP32   weights of the four-layer stack, [W1, W2,
+ *                              flip(W2)^T, flip(W1)^T] (adlbr_net_gates)
+ * adlbr_net_gates must run again after params change.
  * ------------------------------------------------------------------ */
 typedef struct adlbr_net {
     int32_t dim;    /* 2 or 3 */
@@ -259,13 +266,15 @@ typedef struct adlbr_net {
     float *gates;
     uint16_t *gates16;
     float *scratch;
+    float *layers;
 } adlbr_net;
 
 /* Number of FP32 parameters for (dim, width, hidden). */
 int adlbr_net_param_count(int dim, int width, int hidden, size_t *count);
 /* Features of the operator at time step dt into net->features. */
 int adlbr_net_features(adlbr_operator *op, double dt, adlbr_net *net, void *stream);
-/* Gate net forward: net->hidden_act, net->gates and net->gates16. */
+/* Gate net forward: net->hidden_act, net->gates and net->gates16, and the
+ * expanded weights net->layers. */
 int adlbr_net_gates(adlbr_operator *op, adlbr_net *net, void *stream);
 /* z = r / diag(K) + N(r).  r, z: device [N] FP32.  If saved is not null
  * (device [3W+1][N] FP32) the pre-gate outputs of the four layers are kept
@@ -278,8 +287,9 @@ int adlbr_net_forward(adlbr_operator *op, const adlbr_net *net, const float *r, 
 int adlbr_net_precondition(adlbr_operator *op, const adlbr_net *net, const float *r, float *z,
                            void *stream);
 /* Backward of sum(gz * z) for one sample: adds the r-path weight
- * gradients to gparams (device, param_count FP32) and the gate gradients
- * to ggates (device [3W+1][N] FP32).  workspace >= adlbr_net_workspace(). */
+ * gradients (W1, W2, both uses of each tied weight) to gparams (device,
+ * param_count FP32) and the gradients of the four-layer gates to ggates
+ * (device [3W+1][N] FP32).  workspace >= adlbr_net_workspace(). */
 int adlbr_net_backward(adlbr_operator *op, const adlbr_net *net, const float *r,
                        const float *gz, const float *saved, float *gparams, float *ggates,
                        void *workspace, size_t ws_bytes, void *stream);

@@ -258,28 +258,28 @@ class Net:
         self.gates = torch.empty((49, N), dtype=torch.float32, device=dev)
         self.gates16 = torch.empty((N, 49), dtype=torch.int16, device=dev)
         self.scratch = torch.empty((32, N), dtype=torch.float32, device=dev)
+        T = 3 ** self.dim
+        self.layers = torch.empty(2 * 16 * 17 * T, dtype=torch.float32, device=dev)
         self._s = capi.NetStruct(self.dim, 16, 16, nf, self.params.data_ptr(),
                                  self.features.data_ptr(), self.hidden_act.data_ptr(),
                                  self.gates.data_ptr(), self.gates16.data_ptr(),
-                                 self.scratch.data_ptr())
+                                 self.scratch.data_ptr(), self.layers.data_ptr())
         self._ws = None
 
     @staticmethod
     def init_params(dim: int, seed: int = 0):
-        """He-style random initialization (host, seeded); gate biases +2 and a
-        small output layer, so the untrained net is a mild perturbation of
-        Jacobi.  Order as in adlbr.h."""
+        """He-style random initialization (host, seeded) of the gate net, gate
+        biases +2, r-path weights at 0.3 x He scale, so the untrained N is a
+        mild positive addition to Jacobi.  Order as in adlbr.h."""
         import numpy as np
         torch = _torch()
         rng = np.random.Generator(np.random.PCG64(seed))
         T = 3 ** dim
         nf = 7 if dim == 2 else 13
         parts = [rng.normal(0, (2.0 / (nf * T)) ** 0.5, 16 * nf * T), np.zeros(16),
-                 rng.normal(0, (2.0 / 16) ** 0.5, 49 * 16), np.full(49, 2.0),
-                 rng.normal(0, (2.0 / T) ** 0.5, 16 * T),
-                 rng.normal(0, (2.0 / (16 * T)) ** 0.5, 16 * 16 * T),
-                 rng.normal(0, (2.0 / (16 * T)) ** 0.5, 16 * 16 * T),
-                 rng.normal(0, 0.1 / (16 * T) ** 0.5, 16 * T)]
+                 rng.normal(0, (2.0 / 16) ** 0.5, 32 * 16), np.full(32, 2.0),
+                 rng.normal(0, 0.3 * (2.0 / T) ** 0.5, 16 * T),
+                 rng.normal(0, 0.3 * (2.0 / (16 * T)) ** 0.5, 16 * 16 * T)]
         return torch.from_numpy(np.concatenate(parts)).float()
 
     @property

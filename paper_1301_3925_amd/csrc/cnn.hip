@@ -1,9 +1,17 @@
-// Learned preconditioner z = r / diag(K) + N(r) for K = I + dt A: features,
-// gate net, the gated convolution stack on r, its backward pass, the energy
-// loss and Adam -- everything the network needs to be trained and applied
-// on the GPU.  These are FP32 kernels (one thread per grid point, uniform
-// weight reads); the 2D inference path used inside flexible CG has a fused
-// BF16 MFMA kernel in cnn_mfma.hip.
+// Learned preconditioner z = r / diag(K) + N(r) for K = I + dt A with
+// N = B^T diag(g2) B, B = C2 diag(g1) C1 (symmetric positive semi-definite):
+// features, gate net, the convolution stack on r, its backward pass, the
+// energy loss and Adam -- everything the network needs to be trained and
+// applied on the GPU.  These are FP32 kernels (one thread per grid point,
+// uniform weight reads); the 2D inference path used inside flexible CG has
+// a fused BF16 MFMA kernel in cnn_mfma.hip.
+//
+// N runs as a plain four-layer gated stack: the gate net writes expanded
+// gates [g1, g2, g1, 1] and adlbr_net_gates expands the weights to
+// [W1, W2, flip(W2)^T, flip(W1)^T] (the correlation adjoint is the
+// correlation with channel-transposed, spatially flipped taps).  The
+// backward pass runs on the expanded stack and folds the gradients of tied
+// weights and repeated gates back onto the parameters.
 //
 // Layout: activations are [channels][N] FP32 planes; convolutions are 3^d
 // taps with zero padding outside the grid; tap t = ((tz*3)+ty)*3+tx over
@@ -21,8 +29,10 @@ namespace {
 constexpr int kBS = 256;
 
 struct NetDims {
-    int dim, W, H, nf, G, T;
-    size_t oWA, obA, oWB, obB, oW1, oW2, oW3, oW4, count;
+    int dim, W, H, nf, G, GX, T;
+    // parameter offsets; expanded layer offsets (net->layers)
+    size_t oWA, obA, oWB, obB, oW1, oW2, count;
+    size_t l1, l2, l3, l4, lcount;
 };
 
 NetDims net_dims(int dim, int W, int H) {
@@ -32,7 +42,8 @@ NetDims net_dims(int dim, int W, int H) {
     d.H = H;
     d.T = dim == 2 ? 9 : 27;
     d.nf = dim == 2 ? 7 : 13;
-    d.G = 3 * W + 1;
+    d.G = 2 * W;       // gate-net outputs g1, g2
+    d.GX = 3 * W + 1;  // expanded gates of the four-layer stack
     size_t o = 0;
     d.oWA = o; o += (size_t)H * d.nf * d.T;
     d.obA = o; o += H;
@@ -40,15 +51,19 @@ NetDims net_dims(int dim, int W, int H) {
     d.obB = o; o += d.G;
     d.oW1 = o; o += (size_t)W * d.T;
     d.oW2 = o; o += (size_t)W * W * d.T;
-    d.oW3 = o; o += (size_t)W * W * d.T;
-    d.oW4 = o; o += (size_t)W * d.T;
     d.count = o;
+    o = 0;
+    d.l1 = o; o += (size_t)W * d.T;
+    d.l2 = o; o += (size_t)W * W * d.T;
+    d.l3 = o; o += (size_t)W * W * d.T;
+    d.l4 = o; o += (size_t)W * d.T;
+    d.lcount = o;
     return d;
 }
 
 int check_net(const adlbr_operator *op, const adlbr_net *net, NetDims *d) {
-    if (!op || !net || !net->params) {
-        set_error("net: null argument");
+    if (!op || !net || !net->params || !net->layers) {
+        set_error("net: null argument (params and layers are required)");
         return ADLBR_E_INVALID;
     }
     const GridInfo &g = operator_grid(op);
@@ -189,25 +204,86 @@ __global__ __launch_bounds__(kBS) void k_conv(GridInfo g, const float *__restric
     }
 }
 
-// Gate layer B (1x1) + sigmoid: G[k] = 1 / (1 + exp(-(WB[k] . relu(h) + bB[k]))).
-template <int H, int G>
+// Gate layer B (1x1) + sigmoid: g[k] = 1 / (1 + exp(-(WB[k] . relu(h) + bB[k]))),
+// k < 2W, written expanded for the four-layer stack: Gout = [g1, g2, g1, 1]
+// ([3W+1][N]) and G16 the same per point in BF16 ([N][3W+1]).
+template <int H, int W>
 __global__ __launch_bounds__(kBS) void k_gate_b(long long N, const float *__restrict__ h,
                                                 const float *__restrict__ WB,
                                                 const float *__restrict__ bB, float *__restrict__ Gout,
                                                 uint16_t *__restrict__ G16) {
+    constexpr int GX = 3 * W + 1;
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
     if (i >= N) return;
     float hr[H];
 #pragma unroll
     for (int c = 0; c < H; ++c) hr[c] = fmaxf(h[c * N + i], 0.f);
-    for (int k = 0; k < G; ++k) {
+    for (int k = 0; k < 2 * W; ++k) {
         float a = bB[k];
 #pragma unroll
         for (int c = 0; c < H; ++c) a += WB[k * H + c] * hr[c];
         const float gv = 1.f / (1.f + expf(-a));
+        const uint16_t gb = f32_to_bf16(gv).b;
         Gout[k * N + i] = gv;
-        if (G16) G16[i * G + k] = f32_to_bf16(gv).b;
+        if (G16) G16[i * GX + k] = gb;
+        if (k < W) {
+            Gout[(2 * W + k) * N + i] = gv;
+            if (G16) G16[i * GX + 2 * W + k] = gb;
+        }
     }
+    Gout[(GX - 1) * N + i] = 1.f;
+    if (G16) G16[i * GX + GX - 1] = f32_to_bf16(1.f).b;
+}
+
+// Expanded layer weights: L1 = W1, L2 = W2, L3[o][i][t] = W2[i][o][T-1-t],
+// L4[0][i][t] = W1[i][0][T-1-t].
+__global__ void k_expand_weights(const float *__restrict__ W1, const float *__restrict__ W2,
+                                 float *__restrict__ L, int W, int T, size_t l2, size_t l3,
+                                 size_t l4) {
+    const int n1 = W * T, n2 = W * W * T;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += gridDim.x * blockDim.x) {
+        const int t = e % T, io = e / T, i = io % W, o = io / W;  // e = (o * W + i) * T + t
+        L[l2 + e] = W2[e];
+        L[l3 + e] = W2[(i * W + o) * T + (T - 1 - t)];
+        if (e < n1) {
+            const int tt = e % T, c = e / T;  // e = c * T + t
+            L[e] = W1[e];
+            L[l4 + e] = W1[c * T + (T - 1 - tt)];
+        }
+    }
+}
+
+// Fold the expanded-stack gradients onto the tied parameters:
+// gW1 += gL1 + flip(gL4), gW2 += gL2 + flip(gL3)^T.
+__global__ void k_fold_weight_grads(const float *__restrict__ gL, float *__restrict__ gW1,
+                                    float *__restrict__ gW2, int W, int T, size_t l2, size_t l3,
+                                    size_t l4) {
+    const int n1 = W * T, n2 = W * W * T;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += gridDim.x * blockDim.x) {
+        const int t = e % T, io = e / T, i = io % W, o = io / W;  // W2 index (o, i, t)
+        gW2[e] += gL[l2 + e] + gL[l3 + (i * W + o) * T + (T - 1 - t)];
+        if (e < n1) {
+            const int tt = e % T, c = e / T;
+            gW1[e] += gL[e] + gL[l4 + c * T + (T - 1 - tt)];
+        }
+    }
+}
+
+// Fold the expanded gate gradients [3W+1][N] onto g1, g2 ([2W][N]):
+// dg1 = dG[0:W] + dG[2W:3W], dg2 = dG[W:2W]; the constant last gate has none.
+__global__ void k_fold_gate_grads(long long N, int W, const float *__restrict__ gx,
+                                  float *__restrict__ gg) {
+    const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
+    if (i >= N) return;
+    for (int k = 0; k < W; ++k) {
+        gg[k * N + i] = gx[k * N + i] + gx[(2 * W + k) * N + i];
+        gg[(W + k) * N + i] = gx[(W + k) * N + i];
+    }
+}
+
+__global__ void k_fill_f32(float *p, long long n, float v) {
+    const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // z = r * F0 + out   (F0 = 1 / diag K)
@@ -475,14 +551,14 @@ int bwd_w_launch(const GridInfo &g, int cin, int cout, int taps, const float *in
     ADLBR_BW(16, 1, 1)
     ADLBR_BW(7, 16, 1)
     ADLBR_BW(13, 16, 1)
-    ADLBR_BW(16, 49, 4)
+    ADLBR_BW(16, 32, 2)
 #undef ADLBR_BW
     set_error("conv weight gradient: unsupported channel counts");
     return ADLBR_E_UNSUPPORTED;
 }
 
 struct NetWs {
-    float *g0, *g1, *ga, *partials;
+    float *g0, *g1, *ga, *gl, *partials;
     size_t total;
 };
 
@@ -493,10 +569,10 @@ NetWs net_ws(long long N, const NetDims &d, char *base) {
     w.g0 = (float *)(base + o);  o += 16 * plane;
     w.g1 = (float *)(base + o);  o += 16 * plane;
     w.ga = (float *)(base + o);  o += 49 * plane;
+    w.gl = (float *)(base + o);  o += align_up(4 * d.lcount);
     w.partials = (float *)(base + o);
     o += align_up(4 * (size_t)kWgBlocks * (16 * 16 * 27 + 64 + 49 * 16 + 49));
     w.total = o;
-    (void)d;
     return w;
 }
 
@@ -505,19 +581,19 @@ int forward_impl(const adlbr_operator *op, const adlbr_net *net, const NetDims &
                  float *z, float *saved, float *bufA, float *bufB, hipStream_t s) {
     const GridInfo &g = operator_grid(op);
     const long long N = g.N;
-    const float *P = net->params;
+    const float *L = net->layers;
     const float *G = net->gates;
     float *pre = saved;
     int rc;
-    rc = conv_launch<DIM>(g, 1, 16, r, nullptr, P + d.oW1, nullptr, bufA, pre, G, 0, s);
+    rc = conv_launch<DIM>(g, 1, 16, r, nullptr, L + d.l1, nullptr, bufA, pre, G, 0, s);
     if (rc) return rc;
-    rc = conv_launch<DIM>(g, 16, 16, bufA, nullptr, P + d.oW2, nullptr, bufB,
+    rc = conv_launch<DIM>(g, 16, 16, bufA, nullptr, L + d.l2, nullptr, bufB,
                           pre ? pre + 16 * N : nullptr, G + 16 * N, 0, s);
     if (rc) return rc;
-    rc = conv_launch<DIM>(g, 16, 16, bufB, nullptr, P + d.oW3, nullptr, bufA,
+    rc = conv_launch<DIM>(g, 16, 16, bufB, nullptr, L + d.l3, nullptr, bufA,
                           pre ? pre + 32 * N : nullptr, G + 32 * N, 0, s);
     if (rc) return rc;
-    rc = conv_launch<DIM>(g, 16, 1, bufA, nullptr, P + d.oW4, nullptr, bufB,
+    rc = conv_launch<DIM>(g, 16, 1, bufA, nullptr, L + d.l4, nullptr, bufB,
                           pre ? pre + 48 * N : nullptr, G + 48 * N, 0, s);
     if (rc) return rc;
     hipLaunchKernelGGL(k_precond_out, dim3(nblk(N)), dim3(kBS), 0, s, N, r, net->features, bufB, z);
@@ -616,9 +692,11 @@ extern "C" int adlbr_net_gates(adlbr_operator *op, adlbr_net *net, void *stream)
                     : conv_launch<3>(g, d.nf, 16, net->features, nullptr, P + d.oWA, P + d.obA,
                                      net->hidden_act, nullptr, nullptr, 0, s);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_gate_b<16, 49>), dim3(nblk(g.N)), dim3(kBS), 0, s, g.N,
+    hipLaunchKernelGGL((k_gate_b<16, 16>), dim3(nblk(g.N)), dim3(kBS), 0, s, g.N,
                        (const float *)net->hidden_act, P + d.oWB, P + d.obB, net->gates,
                        net->gates16);
+    hipLaunchKernelGGL(k_expand_weights, dim3(16), dim3(kBS), 0, s, P + d.oW1, P + d.oW2,
+                       net->layers, d.W, d.T, d.l2, d.l3, d.l4);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }
@@ -676,14 +754,17 @@ extern "C" int adlbr_net_backward(adlbr_operator *op, const adlbr_net *net, cons
         return ADLBR_E_NOMEM;
     }
     hipStream_t s = as_stream(stream);
-    const float *P = net->params;
+    const float *L = net->layers;
     const float *G = net->gates;
     const int taps = d.T;
+    // gradients of the expanded layers go to w.gl, then fold onto W1, W2
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblk((long long)d.lcount)), dim3(kBS), 0, s, w.gl,
+                       (long long)d.lcount, 0.f);
     // layer 4: out = pre4 * G[48]; dL/dout = gz
     const float *gcur = gz;
     const size_t offs[4] = {0, 16, 32, 48};
     const int cins[4] = {1, 16, 16, 16}, couts[4] = {16, 16, 16, 1};
-    const size_t oW[4] = {d.oW1, d.oW2, d.oW3, d.oW4};
+    const size_t oW[4] = {d.l1, d.l2, d.l3, d.l4};
     float *gbuf[2] = {w.g0, w.g1};
     for (int l = 3; l >= 0; --l) {
         const long long n = (long long)couts[l] * N;
@@ -693,18 +774,20 @@ extern "C" int adlbr_net_backward(adlbr_operator *op, const adlbr_net *net, cons
         const float *in = l == 0 ? r : saved + offs[l - 1] * N;
         const float *in_gate = l == 0 ? nullptr : G + offs[l - 1] * N;
         rc = g.dim == 2 ? bwd_w_launch<2>(g, cins[l], couts[l], taps, in, in_gate, 0, w.ga,
-                                          w.partials, gparams + oW[l], nullptr, s)
+                                          w.partials, w.gl + oW[l], nullptr, s)
                         : bwd_w_launch<3>(g, cins[l], couts[l], taps, in, in_gate, 0, w.ga,
-                                          w.partials, gparams + oW[l], nullptr, s);
+                                          w.partials, w.gl + oW[l], nullptr, s);
         if (rc) return rc;
         if (l > 0) {
             float *gin = gbuf[l & 1];
-            rc = g.dim == 2 ? bwd_data_launch<2>(g, cins[l], couts[l], w.ga, P + oW[l], gin, s)
-                            : bwd_data_launch<3>(g, cins[l], couts[l], w.ga, P + oW[l], gin, s);
+            rc = g.dim == 2 ? bwd_data_launch<2>(g, cins[l], couts[l], w.ga, L + oW[l], gin, s)
+                            : bwd_data_launch<3>(g, cins[l], couts[l], w.ga, L + oW[l], gin, s);
             if (rc) return rc;
             gcur = gin;
         }
     }
+    hipLaunchKernelGGL(k_fold_weight_grads, dim3(16), dim3(kBS), 0, s, (const float *)w.gl,
+                       gparams + d.oW1, gparams + d.oW2, d.W, d.T, d.l2, d.l3, d.l4);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }
@@ -729,14 +812,16 @@ extern "C" int adlbr_net_gates_backward(adlbr_operator *op, const adlbr_net *net
     }
     hipStream_t s = as_stream(stream);
     const float *P = net->params;
-    // gg (in w.ga) = dG G (1 - G); gh (in w.g0) = WB^T gg * [h > 0]
-    ADLBR_CHECK_HIP(hipMemcpyAsync(w.ga, ggates, 4 * (size_t)d.G * N, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL((k_gate_b_bwd<16, 49>), dim3(nblk(N)), dim3(kBS), 0, s, N, net->gates, w.ga,
+    // fold the expanded gate gradients onto g1, g2 (into w.ga); then
+    // gg = dg g (1 - g) in place (the first 2W expanded gates are g1, g2);
+    // gh (in w.g0) = WB^T gg * [h > 0]
+    hipLaunchKernelGGL(k_fold_gate_grads, dim3(nblk(N)), dim3(kBS), 0, s, N, d.W, ggates, w.ga);
+    hipLaunchKernelGGL((k_gate_b_bwd<16, 32>), dim3(nblk(N)), dim3(kBS), 0, s, N, net->gates, w.ga,
                        net->hidden_act, P + d.oWB, w.g0);
     // WB, bB: 1x1 layer, input relu(h)
-    rc = g.dim == 2 ? bwd_w_launch<2>(g, 16, 49, 1, net->hidden_act, nullptr, 1, w.ga, w.partials,
+    rc = g.dim == 2 ? bwd_w_launch<2>(g, 16, 32, 1, net->hidden_act, nullptr, 1, w.ga, w.partials,
                                       gparams + d.oWB, gparams + d.obB, s)
-                    : bwd_w_launch<3>(g, 16, 49, 1, net->hidden_act, nullptr, 1, w.ga, w.partials,
+                    : bwd_w_launch<3>(g, 16, 32, 1, net->hidden_act, nullptr, 1, w.ga, w.partials,
                                       gparams + d.oWB, gparams + d.obB, s);
     if (rc) return rc;
     // WA, bA: conv on the features

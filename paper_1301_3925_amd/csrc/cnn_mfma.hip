@@ -158,13 +158,12 @@ __global__ __launch_bounds__(256) void k_net2d_fused(int nx, int ny, const float
 int net_apply_mfma(const adlbr_net *net, const adlbr_operator *op, const float *r, float *z,
                    hipStream_t s) {
     const GridInfo &g = operator_grid(op);
-    const float *P = net->params;
-    // parameter offsets for dim 2, width = hidden = 16 (layout of adlbr.h)
-    const size_t oW1 = 16 * 7 * 9 + 16 + 49 * 16 + 49;
-    const size_t oW2 = oW1 + 16 * 9, oW3 = oW2 + 16 * 16 * 9, oW4 = oW3 + 16 * 16 * 9;
+    const float *L = net->layers;
+    // expanded layer offsets for dim 2, width 16: [W1, W2, W3, W4]
+    const size_t l2 = 16 * 9, l3 = l2 + 16 * 16 * 9, l4 = l3 + 16 * 16 * 9;
     dim3 grid((g.nx + kT - 1) / kT, (g.ny + kT - 1) / kT);
     hipLaunchKernelGGL(k_net2d_fused, grid, dim3(256), 0, s, g.nx, g.ny, r, net->features,
-                       net->gates16, P + oW1, P + oW2, P + oW3, P + oW4, z);
+                       net->gates16, L, L + l2, L + l3, L + l4, z);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }

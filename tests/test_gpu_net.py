@@ -1,5 +1,9 @@
 """GPU parity of the learned preconditioner's kernels against the FP64 oracle.
 
+The GPU runs N = B^T diag(g2) B as an expanded four-layer stack with tied
+weights; the oracle applies B and its adjoint directly, so agreement checks
+the expansion and the gradient folding as well.
+
 Forward, gates and features at FP32 tolerance (1e-5 relative L2); backward
 (all parameter gradients through the r path, the gates and the gate net) at
 1e-4; Adam against torch.optim.Adam on the CPU.
@@ -52,7 +56,10 @@ def test_features_gates_forward(lib, dim):
     dims, op, A, dt, net, P, F, diag = _case(lib, dim)
     assert _rel(net.features.cpu().numpy(), F.reshape(F.shape[0], -1)) <= 1e-6
     G = solvers.net_gates(P, F)
-    assert _rel(net.gates.cpu().numpy(), G.reshape(G.shape[0], -1)) <= 1e-5
+    gx = net.gates.cpu().numpy()
+    assert _rel(gx[:32], G.reshape(G.shape[0], -1)) <= 1e-5
+    # the four-layer stack's gates are [g1, g2, g1, 1]
+    assert np.array_equal(gx[32:48], gx[:16]) and np.all(gx[48] == 1.0)
     r = synth.uniform(3, op.N) - 0.5
     z = net.forward(torch.from_numpy(r).float().cuda()).double().cpu().numpy()
     kd = 1.0 + dt * diag
