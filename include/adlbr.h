@@ -170,6 +170,41 @@ int adlbr_step(adlbr_operator *op, void *u, void *u_tmp, double dt,
                int dt_mode, int64_t nsteps, void *stream);
 
 /* ------------------------------------------------------------------ *
+ * Batched explicit steps (an extension: many images and volumes of uneven
+ * sizes advanced together).  Every problem i is one operator ops[i] with
+ * its state u[i] (device [N_i], in/out) and scratch u_tmp[i] (same size
+ * and dtype), stepped as adlbr_step(ops[i], u[i], u_tmp[i], dt[i],
+ * dt_mode, nsteps) would step it -- results are bit-identical.  Problems of
+ * one class (dim, offset width, boundary, storage) share one grouped
+ * launch per step; adlbr_batch_run captures the nsteps of all classes
+ * into one HIP graph (on the batch's own stream, ordered after and before
+ * `stream` by events) and replays it on later calls with the same nsteps.
+ * The operators and buffers must stay valid while the batch lives.
+ *   workspace: device, >= adlbr_batch_workspace(nprob) bytes (descriptors).
+ * ------------------------------------------------------------------ */
+typedef struct adlbr_batch adlbr_batch;
+int adlbr_batch_workspace(int nprob, size_t *bytes);
+int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *const *u,
+                       void *const *u_tmp, const double *dt, int dt_mode, void *workspace,
+                       size_t ws_bytes, void *stream, adlbr_batch **batch);
+/* Autotuner: for every class, time each launch variant (bit 0: XCD-
+ * contiguous block order; bit 1: largest problems first) over `steps`
+ * grouped steps from u into u_tmp (u is not modified) and keep the
+ * fastest; the choice is cached per process by class, total size and
+ * problem count, and reused without timing when use_cache is set.
+ * Synchronizes `stream`. */
+int adlbr_batch_tune(adlbr_batch *batch, int steps, int use_cache, void *stream);
+/* Class cls (0-based, in order of first appearance): its class key
+ * (dim*1000 + wide*100 + periodic*10 + storage), chosen variant and
+ * number of problems. */
+int adlbr_batch_variant(const adlbr_batch *batch, int cls, int *key, int *variant, int *nprob);
+/* nsteps explicit steps of every problem; use_graph = 0 launches directly
+ * on `stream` instead of through the captured graph.  The results land in
+ * u (an odd nsteps ends with a grouped copy). */
+int adlbr_batch_run(adlbr_batch *batch, int64_t nsteps, int use_graph, void *stream);
+int adlbr_batch_destroy(adlbr_batch *batch);
+
+/* ------------------------------------------------------------------ *
  * Solution-dependent diffusion tensor from the structure tensor
  * (Section 5, coherence-enhancing diffusion; edge-enhancing in 3D):
  *   u_sigma = K_sigma * u, J = K_rho * (grad u_sigma grad u_sigma^T),

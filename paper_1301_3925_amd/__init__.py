@@ -209,6 +209,70 @@ class Operator:
         return x, rep.as_dict()
 
 
+class Batch:
+    """Many operators stepped together (adlbr_batch_*): one grouped launch
+    per class and step, the whole run captured into one HIP graph.
+    us[i] is stepped in place; tmps[i] (allocated if not given) is scratch.
+    dt is one value or one per problem; dt_mode "cfl" scales each problem's
+    own 1 / max A_zz, "abs" takes dt as the step."""
+
+    def __init__(self, ops, us, tmps=None, dt=0.9, dt_mode: str = "cfl", stream=None):
+        torch = _torch()
+        lib = capi.load()
+        n = len(ops)
+        if n == 0 or len(us) != n:
+            raise ValueError("need one state per operator")
+        for op, u in zip(ops, us):
+            op._check_u(u)
+        self.ops, self.us = list(ops), list(us)
+        self.tmps = [torch.empty_like(u) for u in us] if tmps is None else list(tmps)
+        dts = [float(dt)] * n if isinstance(dt, (int, float)) else [float(d) for d in dt]
+        nb = ctypes.c_size_t()
+        capi.check(lib.adlbr_batch_workspace(n, ctypes.byref(nb)))
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=ops[0].device)
+        P = ctypes.c_void_p * n
+        self._ops = P(*[op.handle.value for op in ops])
+        self._u = P(*[u.data_ptr() for u in self.us])
+        self._t = P(*[t.data_ptr() for t in self.tmps])
+        self._dt = (ctypes.c_double * n)(*dts)
+        h = ctypes.c_void_p()
+        mode = capi.DT_CFL if dt_mode == "cfl" else capi.DT_ABS
+        capi.check(lib.adlbr_batch_create(n, self._ops, self._u, self._t, self._dt, mode,
+                                          _ptr(self.ws), self.ws.numel(), _stream(stream),
+                                          ctypes.byref(h)))
+        self._h = h
+
+    def tune(self, steps: int = 5, use_cache: bool = True, stream=None):
+        capi.check(capi.load().adlbr_batch_tune(self._h, int(steps), int(use_cache),
+                                                _stream(stream)))
+        return self.variants()
+
+    def variants(self):
+        lib = capi.load()
+        out, k = [], 0
+        while True:
+            key, var, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            if lib.adlbr_batch_variant(self._h, k, ctypes.byref(key), ctypes.byref(var),
+                                       ctypes.byref(n)) != 0:
+                return out
+            out.append({"class": key.value, "variant": var.value, "problems": n.value})
+            k += 1
+
+    def run(self, nsteps: int, graph: bool = True, stream=None):
+        capi.check(capi.load().adlbr_batch_run(self._h, int(nsteps), int(graph), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            capi.load().adlbr_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def structure_tensor(u, dims, sigma: float, rho: float, alpha: float, C: float,
                      eig_map: str = "ced", out=None, workspace=None, stream=None):
     """Diffusion tensor from the structure tensor of u (adlbr_structure_tensor)."""

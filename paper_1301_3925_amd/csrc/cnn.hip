@@ -448,19 +448,23 @@ __global__ __launch_bounds__(kBS) void k_gate_b_bwd(long long N, const float *__
 // ------------------------------------------------------------ loss, Adam --
 struct LossState {
     double rr;
-    uint32_t tickets[2];
 };
 
-__global__ void k_dot_self(long long N, const float *r, LossState *ls, double *part) {
+__global__ __launch_bounds__(kBS) void k_dot_self(long long N, const float *r, double *part) {
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
     const double v = i < N ? (double)r[i] * (double)r[i] : 0.0;
-    double t;
-    if (last_block_sum(v, part, &ls->tickets[0], t) && threadIdx.x == 0) ls->rr = t;
+    block_partial_sum(v, part);
 }
 
-// gz = (Kz - r) / rr  (Kz already in gz), loss += (z.Kz/2 - z.r) / rr
-__global__ void k_loss_grad(long long N, const float *z, const float *r, float *gz, LossState *ls,
-                            double *part, double *loss) {
+__global__ __launch_bounds__(kBS) void k_dot_self_fin(LossState *ls, const double *part,
+                                                      long long nb) {
+    const double t = reduce_partials(part, nb);
+    if (threadIdx.x == 0) ls->rr = t;
+}
+
+// gz = (Kz - r) / rr  (Kz already in gz); partials of (z.Kz/2 - z.r) / rr
+__global__ __launch_bounds__(kBS) void k_loss_grad(long long N, const float *z, const float *r,
+                                                   float *gz, const LossState *ls, double *part) {
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
     const double rr = ls->rr;
     double v = 0.0;
@@ -469,8 +473,13 @@ __global__ void k_loss_grad(long long N, const float *z, const float *r, float *
         v = (0.5 * zi * kz - zi * ri) / rr;
         gz[i] = (float)((kz - ri) / rr);
     }
-    double t;
-    if (last_block_sum(v, part, &ls->tickets[1], t) && threadIdx.x == 0) *loss += t;
+    block_partial_sum(v, part);
+}
+
+// loss += sum of the partials
+__global__ __launch_bounds__(kBS) void k_loss_fin(const double *part, long long nb, double *loss) {
+    const double t = reduce_partials(part, nb);
+    if (threadIdx.x == 0) *loss += t;
 }
 
 __global__ void k_adam(float *p, const float *g, float *m, float *v, long long n, float lr,
@@ -851,11 +860,14 @@ extern "C" int adlbr_net_loss_grad(adlbr_operator *op, double dt, const float *r
     hipStream_t s = as_stream(stream);
     LossState *ls = (LossState *)workspace;
     double *part = (double *)((char *)workspace + align_up(sizeof(LossState)));
-    ADLBR_CHECK_HIP(hipMemsetAsync(ls, 0, sizeof(LossState), s));
-    hipLaunchKernelGGL(k_dot_self, dim3(nblk(N)), dim3(kBS), 0, s, N, r, ls, part);
+    const long long nb = nblk(N);
+    hipLaunchKernelGGL(k_dot_self, dim3(nb), dim3(kBS), 0, s, N, r, part);
+    hipLaunchKernelGGL(k_dot_self_fin, dim3(1), dim3(kBS), 0, s, ls, (const double *)part, nb);
     int rc = apply_K(op, z, gz, dt, s);  // gz = K z
     if (rc) return rc;
-    hipLaunchKernelGGL(k_loss_grad, dim3(nblk(N)), dim3(kBS), 0, s, N, z, r, gz, ls, part, loss);
+    hipLaunchKernelGGL(k_loss_grad, dim3(nb), dim3(kBS), 0, s, N, z, r, gz, (const LossState *)ls,
+                       part);
+    hipLaunchKernelGGL(k_loss_fin, dim3(1), dim3(kBS), 0, s, (const double *)part, nb, loss);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }

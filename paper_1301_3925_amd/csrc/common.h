@@ -140,7 +140,6 @@ struct CgState {
     int32_t iter;
     int32_t done;   // recurrence residual below tolerance: later kernels are no-ops
     int32_t pad;
-    uint32_t ticket[4];
 };
 
 struct adlbr_net_impl;
@@ -148,50 +147,98 @@ struct adlbr_net_impl;
 int net_apply(const adlbr_net *net, const adlbr_operator *op, double dt, const void *r, void *z,
               hipStream_t s);
 
+// Device descriptor of one problem of a batch (one operator and its two
+// state buffers); first_block is the problem's first 256-point block in
+// the batch's grid.
+struct BatchProb {
+    GridInfo g;
+    const void *sb;
+    const void *w;
+    const uint8_t *cnt;
+    const int32_t *pos;
+    const int32_t *ent;
+    const double *dtcfl;
+    void *u[2];
+    double dt;
+    int32_t dt_mode;
+    int32_t pad;
+    long long first_block;
+};
+// Class of an operator for batching (dim, offset width, boundary, storage):
+// problems of one class share a kernel instance.
+int batch_class(const adlbr_operator *op);
+// Fill the operator part of a descriptor.
+void batch_describe(const adlbr_operator *op, BatchProb *d);
+// One grouped launch over the problems of one class (rep: any operator of
+// the class): an explicit step from u[parity] to u[parity ^ 1], or (copy)
+// u[0] = u[1].  variant bit 0: XCD-contiguous block order.
+int batch_launch(const adlbr_operator *rep, const BatchProb *probs, int nprob, long long nblocks,
+                 int parity, int variant, int copy, hipStream_t s);
+
 // Internal entry points shared between translation units.
+// Direction update q = K z + beta q, p = z + beta p and alpha = <z,r>/<p,q>
+// (partial: one double per 256-point block).
 int cg_direction(const adlbr_operator *op, const void *z, void *q, void *p, CgState *st,
                  double *partial, int first, hipStream_t s);
 // |b - (I + dt A) x|^2 for an FP64 iterate x, accumulated in FP64 into
 // *out (deterministic); the residual itself goes to rout (storage dtype) if
-// rout is not null.
+// rout is not null.  partial: one double per 256-point block.
 int true_residual(const adlbr_operator *op, double dt, const void *b, const double *x,
-                  double *out, double *partial, uint32_t *ticket, void *rout, hipStream_t s);
+                  double *out, double *partial, void *rout, hipStream_t s);
 
-// Block sum of a double over 256 threads, then the last block to arrive sums
-// the per-block partials in block order; returns true in that block's
-// threads, with the total in `total`.
-__device__ inline bool last_block_sum(double v, double *partial, uint32_t *ticket, double &total) {
+// Reductions are two-phase and atomic-free: every block of a grid-wide
+// kernel writes its partial (block_partial_sum), then a one-block finisher
+// kernel sums the partials in a fixed order (reduce_partials).  Same-address
+// device-scope atomics serialize across the XCDs, so a "last block
+// finishes" ticket costs far more than the extra launch; the fixed order
+// also makes every reduction deterministic.
+// Block sum of v over the block's threads (blockDim.x == 256) into
+// partial[blockIdx.x].  All threads must call it.
+__device__ inline void block_partial_sum(double v, double *partial) {
     __shared__ double red[256];
-    __shared__ int last;
     red[threadIdx.x] = v;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        partial[blockIdx.x] = red[0];
-        __threadfence();
-        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    __syncthreads();  // red[] may be reused by a second call
+}
+
+// Block maximum of v into partial[blockIdx.x] (blockDim.x == 256).
+__device__ inline void block_partial_max(double v, double *partial) {
+    __shared__ double red[256];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
     }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
     __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double acc = 0.0;
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += 256)
-        acc += __hip_atomic_load(&partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
+}
+
+// Sum (or max, when take_max) of partial[0 .. n) by a single block of 256
+// threads in a fixed order; every thread gets the result.
+__device__ inline double reduce_partials(const double *partial, long long n, bool take_max = false) {
+    __shared__ double red[256];
+    double acc = take_max ? -1.0e308 : 0.0;
+    for (long long b = threadIdx.x; b < n; b += 256)
+        acc = take_max ? fmax(acc, partial[b]) : acc + partial[b];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        if ((int)threadIdx.x < s)
+            red[threadIdx.x] = take_max ? fmax(red[threadIdx.x], red[threadIdx.x + s])
+                                        : red[threadIdx.x] + red[threadIdx.x + s];
         __syncthreads();
     }
-    total = red[0];
-    if (threadIdx.x == 0) *ticket = 0u;
-    __syncthreads();  // red[] is reused by the caller's next reduction
-    return true;
+    const double t = red[0];
+    __syncthreads();
+    return t;
 }
+
 const GridInfo &operator_grid(const adlbr_operator *op);
 int operator_storage(const adlbr_operator *op);
 const void *operator_diag(const adlbr_operator *op);

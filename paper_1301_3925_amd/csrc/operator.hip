@@ -8,7 +8,10 @@
 //             of w_o(y) (u(z) - u(y)).
 // The incoming edges are the transpose of the stencils; they are listed
 // once per operator (count -> scan -> fill -> per-row sort), so every apply
-// is a deterministic gather with no atomics.
+// is a deterministic gather with no atomics.  2D grids are assembled by
+// target tiles that gather their edges from a window of sources (LDS
+// atomics only); 3D grids by bins of targets (wave-aggregated global
+// atomics, then one block per bin).
 //
 // Data layout in the workspace (N points, S = 3 or 6 slots):
 //   sb     compact slots: 2D (o0, o1) as 4 x int8 (or int16), o2 = -o0-o1;
@@ -38,12 +41,15 @@ struct adlbr_operator {
     int32_t *pos;
     int32_t *ent;
     void *diag;
-    unsigned long long *maxdiag;
+    double *maxdiag;
     double *dtcfl;
-    uint32_t *bincnt;  // edges per bin of targets
-    uint32_t *bincur;  // placement cursor per bin
-    uint32_t *binoff;  // exclusive scan of bincnt
-    int2 *binbuf;      // (target, entry) grouped by bin
+    int32_t *rmax;     // largest offset component
+    uint8_t *mask;     // bit q: slot q has a positive weight
+    double *part;      // per-block partials of the assembly
+    uint32_t *bincnt;  // 3D: edges per bin of targets; 2D: cnt sums per 1024-point chunk
+    uint32_t *bincur;  // 3D: placement cursor per bin
+    uint32_t *binoff;  // 3D: exclusive scan of bincnt
+    int2 *binbuf;      // 3D: (target, entry) grouped by bin
 };
 
 namespace adlbr {
@@ -194,14 +200,11 @@ __global__ void k_fill_i32(int32_t *p, long long n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-__global__ void k_init_scalars(unsigned long long *maxdiag) { *maxdiag = 0ull; }
-
 template <typename TW> __device__ __forceinline__ double ld_w(const TW *w, long long i) {
     return (double)w[i];
 }
 
-// Pack the slots, convert the weights, count incoming edges per target.
-// Assembly of the transpose (incoming lists) without per-edge global
+// 3D assembly of the transpose (incoming lists) without per-edge global
 // atomics.  Targets are grouped into bins of kBin consecutive points; the
 // edges of a wavefront mostly land in one or two bins, so counting and
 // placing them costs one atomic per distinct bin per wavefront (leader lane,
@@ -246,11 +249,15 @@ __device__ __forceinline__ unsigned bin_append(int bin, uint32_t *counter, bool 
     return slot;
 }
 
-// Pack the slots, convert the weights, count the edges landing in each bin.
-template <int DIM, bool WIDE, bool PER, typename TWin, typename TS, typename TA>
-__global__ void k_compact(GridInfo g, const int16_t *__restrict__ off, const TWin *__restrict__ win,
-                          typename Slots<DIM, WIDE>::store_t *__restrict__ sb, TS *__restrict__ w,
-                          uint32_t *__restrict__ bincnt, int32_t *status) {
+// Pack the slots, convert the weights, record which slots carry a positive
+// weight (mask bit q), the block's largest offset component (rpart), and,
+// for the binned assembly (BINS), count the edges landing in each bin.
+template <int DIM, bool WIDE, bool PER, typename TWin, typename TS, typename TA, bool BINS>
+__global__ __launch_bounds__(256) void k_compact(
+    GridInfo g, const int16_t *__restrict__ off, const TWin *__restrict__ win,
+    typename Slots<DIM, WIDE>::store_t *__restrict__ sb, TS *__restrict__ w,
+    uint8_t *__restrict__ mask, double *__restrict__ rpart, uint32_t *__restrict__ bincnt,
+    int32_t *status) {
     const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = z < g.N;  // every lane takes part in the ballots
     constexpr int S = DIM == 2 ? 3 : 6;
@@ -277,17 +284,88 @@ __global__ void k_compact(GridInfo g, const int16_t *__restrict__ off, const TWi
         if (!rel) st |= ADLBR_ST_STENCIL;
         if (!Slots<DIM, WIDE>::pack(s, sb, z)) st |= ADLBR_ST_RANGE;
         p = coords(z, g);
+        unsigned m = 0;
         for (int q = 0; q < S; ++q) {
             wq[q] = (double)win[q * N + z];
             w[q * N + z] = Conv<TS, TA>::st((TA)wq[q]);
+            if (wq[q] > 0.0) m |= 1u << q;
         }
+        mask[z] = (uint8_t)m;
     }
+    int rmax = 0;
+    for (int q = 0; q < S; ++q)
+        for (int c = 0; c < DIM; ++c) rmax = max(rmax, abs(s[q][c]));
     for (int k = 0; k < 2 * S; ++k) {
         const long long t = live ? edge_k<DIM, PER>(p, z, s, wq, k, g) : -1;
         if (t == -2) st |= ADLBR_ST_RANGE;
-        bin_append(t >= 0 ? (int)(t >> kBinShift) : -1, bincnt, true);
+        if (BINS) bin_append(t >= 0 ? (int)(t >> kBinShift) : -1, bincnt, true);
     }
     if (live) report(status, z, st);
+    block_partial_max((double)rmax, rpart);
+}
+
+// R = the largest offset component over all points (from the block maxima).
+__global__ __launch_bounds__(256) void k_rmax_fin(const double *rpart, long long nb, int32_t *R) {
+    const double r = reduce_partials(rpart, nb, true);
+    if (threadIdx.x == 0) *R = (int32_t)r;
+}
+
+// Sort one row's entries ascending (the order is then independent of the
+// order of placement): a transposition network for up to 16 entries,
+// insertion sort beyond.
+__device__ inline void sort_row(int32_t *e, int c) {
+    if (c <= 16) {
+        int32_t r[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) r[i] = i < c ? e[i] : 0x7fffffff;
+#pragma unroll
+        for (int round = 0; round < 16; ++round) {
+#pragma unroll
+            for (int i = round & 1; i + 1 < 16; i += 2) {
+                const int32_t a = r[i], bb = r[i + 1];
+                r[i] = min(a, bb);
+                r[i + 1] = max(a, bb);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < c) e[i] = r[i];
+    } else {
+        for (int i = 1; i < c; ++i) {
+            const int32_t key = e[i];
+            int j = i - 1;
+            while (j >= 0 && e[j] > key) {
+                e[j + 1] = e[j];
+                --j;
+            }
+            e[j + 1] = key;
+        }
+    }
+}
+
+// A_zz = own in-grid weights (both signs) + weights of the incoming edges.
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
+__device__ inline double row_diag(const GridInfo &g, long long z, const int32_t *e, int c,
+                                  const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                                  const TS *__restrict__ w) {
+    constexpr int S = DIM == 2 ? 3 : 6;
+    const long long N = g.N;
+    double d = 0.0;
+    Slots<DIM, WIDE> sl;
+    sl.load(sb, z);
+    const Coord p = coords(z, g);
+    for (int q = 0; q < S; ++q) {
+        const double wv = (double)Conv<TS, TA>::ld(w[q * N + z]);
+        for (int sg = -1; sg <= 1; sg += 2) {
+            long long t;
+            if (edge_target<DIM, PER>(p, z, sl.o[q], sg, g, t)) d += wv;
+        }
+    }
+    for (int i = 0; i < c; ++i) {
+        const int32_t v = e[i];
+        d += (double)Conv<TS, TA>::ld(w[(long long)((v >> 6) & 7) * N + z + (v >> 9)]);
+    }
+    return d;
 }
 
 // Place every edge (target, entry) in its bin's region of binbuf.
@@ -332,12 +410,10 @@ __global__ __launch_bounds__(256) void k_bin_build(
     GridInfo g, const uint32_t *__restrict__ bincnt, const uint32_t *__restrict__ binoff,
     const int2 *__restrict__ binbuf, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
     const TS *__restrict__ w, int32_t *__restrict__ pos, uint8_t *__restrict__ cnt,
-    int32_t *__restrict__ ent, TD *__restrict__ diag, unsigned long long *maxdiag, int32_t *status) {
+    int32_t *__restrict__ ent, TD *__restrict__ diag, double *__restrict__ dpart, int32_t *status) {
     __shared__ int32_t lcnt[kBin];
     __shared__ int32_t loff[kBin];
     __shared__ int32_t scan[256];
-    __shared__ double red[256];
-    constexpr int S = DIM == 2 ? 3 : 6;
     const long long N = g.N;
     const long long b = blockIdx.x;
     const long long t0 = b << kBinShift;
@@ -390,58 +466,201 @@ __global__ __launch_bounds__(256) void k_bin_build(
         if (z >= N) continue;
         const int c = min(lcnt[tl], 255);
         int32_t *e = ent + base + loff[tl];
-        if (c <= 16) {  // odd-even transposition network on 16 registers
-            int32_t r[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) r[i] = i < c ? e[i] : 0x7fffffff;
-#pragma unroll
-            for (int round = 0; round < 16; ++round) {
-#pragma unroll
-                for (int i = round & 1; i + 1 < 16; i += 2) {
-                    const int32_t a = r[i], bb = r[i + 1];
-                    r[i] = min(a, bb);
-                    r[i + 1] = max(a, bb);
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (i < c) e[i] = r[i];
-        } else {
-            for (int i = 1; i < c; ++i) {  // insertion sort by (source, slot)
-                const int32_t key = e[i];
-                int j = i - 1;
-                while (j >= 0 && e[j] > key) {
-                    e[j + 1] = e[j];
-                    --j;
-                }
-                e[j + 1] = key;
-            }
-        }
-        double d = 0.0;
-        Slots<DIM, WIDE> sl;
-        sl.load(sb, z);
-        const Coord p = coords(z, g);
-        for (int q = 0; q < S; ++q) {
-            const double wv = (double)Conv<TS, TA>::ld(w[q * N + z]);
-            for (int sg = -1; sg <= 1; sg += 2) {
-                long long t;
-                if (edge_target<DIM, PER>(p, z, sl.o[q], sg, g, t)) d += wv;
-            }
-        }
-        for (int i = 0; i < c; ++i) {
-            const int32_t v = e[i];
-            d += (double)Conv<TS, TA>::ld(w[(long long)((v >> 6) & 7) * N + z + (v >> 9)]);
-        }
+        sort_row(e, c);
+        const double d = row_diag<DIM, WIDE, PER, TS, TA>(g, z, e, c, sb, w);
         diag[z] = (TD)d;
         dmax = fmax(dmax, d);
     }
-    red[threadIdx.x] = dmax;
+    block_partial_max(dmax, dpart);
+}
+
+// ------------------------------------------- 2D tile-gather assembly --
+// The incoming lists of a 2D grid are built without any global atomics.
+// Every block owns a kTile x kTile tile of targets; since an edge never
+// reaches further than R (the largest offset component), all edges into the
+// tile start in the tile grown by R on each side (clipped to a Neumann grid,
+// wrapped and capped at the grid size on a periodic one).  The block scans
+// those sources and counts (pass 1) or places (pass 2) the edges that land
+// in its tile with LDS atomics.  Sources are read about (kTile + 2R)^2 /
+// kTile^2 times in all, from L2 for neighbouring tiles.
+constexpr int kTile = 64;
+
+// The window of sources along one axis for the tile [t0, t0 + tw).
+struct Window {
+    int start, len;
+};
+template <bool PER> __device__ inline Window window_axis(int t0, int tw, int R, int n) {
+    Window w;
+    if (PER) {
+        w.len = min(n, tw + 2 * R);
+        w.start = w.len == n ? 0 : t0 - R;
+    } else {
+        w.start = max(0, t0 - R);
+        w.len = min(n, t0 + tw + R) - w.start;
+    }
+    return w;
+}
+
+// Visit every edge (source -> target in this tile) once: f(target local
+// index, target linear index, entry).
+template <bool WIDE, bool PER, typename F>
+__device__ inline void tile_edges(const GridInfo &g, int x0, int y0, int tw, int th, int R,
+                                  const typename Slots<2, WIDE>::store_t *__restrict__ sb,
+                                  const uint8_t *__restrict__ mask, F f) {
+    const Window wx = window_axis<PER>(x0, tw, R, g.nx);
+    const Window wy = window_axis<PER>(y0, th, R, g.ny);
+    const long long W = (long long)wx.len * wy.len;
+    for (long long k = threadIdx.x; k < W; k += blockDim.x) {
+        int x = wx.start + (int)(k % wx.len), y = wy.start + (int)(k / wx.len);
+        if (PER) {
+            x = wrap(x, g.nx);
+            y = wrap(y, g.ny);
+        }
+        const long long z = x + (long long)g.nx * y;
+        const unsigned m = mask[z];
+        if (!m) continue;
+        Slots<2, WIDE> sl;
+        sl.load(sb, z);
+        const Coord p{x, y, 0};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (!(m & (1u << q))) continue;
+#pragma unroll
+            for (int sg = -1; sg <= 1; sg += 2) {
+                int tx = x + sg * sl.o[q][0], ty = y + sg * sl.o[q][1];
+                if (PER) {
+                    tx = wrap(tx, g.nx);
+                    ty = wrap(ty, g.ny);
+                }
+                if (tx < x0 || tx >= x0 + tw || ty < y0 || ty >= y0 + th) continue;
+                long long t;
+                if (!edge_target<2, PER>(p, z, sl.o[q], sg, g, t)) continue;
+                if (z - t >= (1ll << 22) || z - t <= -(1ll << 22)) continue;  // flagged earlier
+                const int32_t e = (int32_t)(((z - t) << 9) | (q << 6) | (t & 63));
+                f((ty - y0) * kTile + (tx - x0), t, e);
+            }
+        }
+    }
+}
+
+// Pass 1: incoming count of every target (clamped to 255, flagged above).
+template <bool WIDE, bool PER>
+__global__ __launch_bounds__(256) void k_tile_count(GridInfo g,
+                                                    const typename Slots<2, WIDE>::store_t *__restrict__ sb,
+                                                    const uint8_t *__restrict__ mask,
+                                                    const int32_t *__restrict__ Rp,
+                                                    uint8_t *__restrict__ cnt, int32_t *status) {
+    __shared__ int32_t lc[kTile * kTile];
+    const int ntx = (g.nx + kTile - 1) / kTile;
+    const int x0 = (int)(blockIdx.x % ntx) * kTile, y0 = (int)(blockIdx.x / ntx) * kTile;
+    const int tw = min(kTile, g.nx - x0), th = min(kTile, g.ny - y0);
+    for (int k = threadIdx.x; k < kTile * kTile; k += blockDim.x) lc[k] = 0;
+    __syncthreads();
+    tile_edges<WIDE, PER>(g, x0, y0, tw, th, *Rp, sb, mask,
+                          [&](int tl, long long, int32_t) { atomicAdd(&lc[tl], 1); });
+    __syncthreads();
+    for (int k = threadIdx.x; k < tw * th; k += blockDim.x) {
+        const int lx = k % tw, ly = k / tw;
+        const long long t = (x0 + lx) + (long long)g.nx * (y0 + ly);
+        const int c = lc[ly * kTile + lx];
+        cnt[t] = (uint8_t)min(c, 255);
+        if (c > 255) report(status, t, ADLBR_ST_INCOMING);
+    }
+}
+
+// Sum of cnt over each chunk of 1024 consecutive points.
+__global__ __launch_bounds__(256) void k_chunk_sum(const uint8_t *__restrict__ cnt, long long N,
+                                                   int32_t *__restrict__ csum) {
+    __shared__ int32_t red[256];
+    const long long base = (long long)blockIdx.x * 1024;
+    int32_t v = 0;
+    for (int k = 0; k < 4; ++k) {
+        const long long z = base + threadIdx.x * 4 + k;
+        if (z < N) v += cnt[z];
+    }
+    red[threadIdx.x] = v;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(maxdiag, (unsigned long long)__double_as_longlong(red[0]));
+    if (threadIdx.x == 0) csum[blockIdx.x] = red[0];
+}
+
+// pos[z] = exclusive prefix of cnt in linear order (chunk offsets coff from
+// the scan of the chunk sums).
+__global__ __launch_bounds__(256) void k_chunk_pos(const uint8_t *__restrict__ cnt, long long N,
+                                                   const int32_t *__restrict__ coff,
+                                                   int32_t *__restrict__ pos) {
+    __shared__ int32_t scan[256];
+    const long long base = (long long)blockIdx.x * 1024;
+    int32_t c4[4], sum = 0;
+    for (int k = 0; k < 4; ++k) {
+        const long long z = base + threadIdx.x * 4 + k;
+        c4[k] = z < N ? cnt[z] : 0;
+        sum += c4[k];
+    }
+    scan[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const int32_t add = threadIdx.x >= (unsigned)d ? scan[threadIdx.x - d] : 0;
+        __syncthreads();
+        scan[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int32_t run = coff[blockIdx.x] + scan[threadIdx.x] - sum;
+    for (int k = 0; k < 4; ++k) {
+        const long long z = base + threadIdx.x * 4 + k;
+        if (z < N) pos[z] = run;
+        run += c4[k];
+    }
+}
+
+// Pass 2: place the entries of every target of the tile, sort each row,
+// diagonal A_zz and the tile's largest diagonal (dpart).
+template <bool WIDE, bool PER, typename TS, typename TA, typename TD>
+__global__ __launch_bounds__(256) void k_tile_fill(GridInfo g,
+                                                   const typename Slots<2, WIDE>::store_t *__restrict__ sb,
+                                                   const uint8_t *__restrict__ mask,
+                                                   const TS *__restrict__ w,
+                                                   const int32_t *__restrict__ Rp,
+                                                   const uint8_t *__restrict__ cnt,
+                                                   const int32_t *__restrict__ pos,
+                                                   int32_t *__restrict__ ent, TD *__restrict__ diag,
+                                                   double *__restrict__ dpart) {
+    __shared__ int32_t lcur[kTile * kTile];
+    __shared__ int32_t lpos[kTile * kTile];
+    __shared__ int32_t lcnt[kTile * kTile];
+    const int ntx = (g.nx + kTile - 1) / kTile;
+    const int x0 = (int)(blockIdx.x % ntx) * kTile, y0 = (int)(blockIdx.x / ntx) * kTile;
+    const int tw = min(kTile, g.nx - x0), th = min(kTile, g.ny - y0);
+    for (int k = threadIdx.x; k < kTile * kTile; k += blockDim.x) {
+        lcur[k] = 0;
+        const int lx = k % kTile, ly = k / kTile;
+        const bool in = lx < tw && ly < th;
+        const long long t = (x0 + lx) + (long long)g.nx * (y0 + ly);
+        lpos[k] = in ? pos[t] : 0;
+        lcnt[k] = in ? cnt[t] : 0;
+    }
+    __syncthreads();
+    // a row never takes more entries than pass 1 counted (clamped to 255)
+    tile_edges<WIDE, PER>(g, x0, y0, tw, th, *Rp, sb, mask, [&](int tl, long long, int32_t e) {
+        const int k = atomicAdd(&lcur[tl], 1);
+        if (k < lcnt[tl]) ent[(long long)lpos[tl] + k] = e;
+    });
+    __syncthreads();
+    double dmax = 0.0;
+    for (int k = threadIdx.x; k < tw * th; k += blockDim.x) {
+        const int lx = k % tw, ly = k / tw;
+        const long long t = (x0 + lx) + (long long)g.nx * (y0 + ly);
+        const int c = lcnt[ly * kTile + lx];
+        int32_t *e = ent + lpos[ly * kTile + lx];
+        sort_row(e, c);
+        const double d = row_diag<2, WIDE, PER, TS, TA>(g, t, e, c, sb, w);
+        diag[t] = (TD)d;
+        dmax = fmax(dmax, d);
+    }
+    block_partial_max(dmax, dpart);
 }
 
 __global__ void k_copy_u32(const uint32_t *a, uint32_t *b, long long n) {
@@ -479,8 +698,12 @@ __global__ void k_scan_top(int32_t *bsum, long long nb) {
     }
 }
 
-__global__ void k_cfl(const unsigned long long *maxdiag, double *dtcfl) {
-    const double m = __longlong_as_double((long long)*maxdiag);
+// dt_CFL = 1 / max_z A_zz from the per-block maxima.
+__global__ __launch_bounds__(256) void k_cfl(const double *dpart, long long nb, double *maxdiag,
+                                             double *dtcfl) {
+    const double m = reduce_partials(dpart, nb, true);
+    if (threadIdx.x != 0) return;
+    *maxdiag = m;
     *dtcfl = m > 0.0 ? 1.0 / m : 0.0;
 }
 
@@ -584,15 +807,16 @@ __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, lon
     return acc;
 }
 
-// out = A u (STEP = false) or u - dt A u (STEP = true).
+// One 256-point block of out = A u (STEP = false) or u - h A u (STEP = true);
+// blk is the block's index within its grid.  Shared by the single-operator
+// and the batched kernels, so both give bit-identical results.
 template <int DIM, bool WIDE, bool PER, bool STEP, typename TS, typename TA>
-__global__ __launch_bounds__(kBS) void k_apply(
-    GridInfo g, const TS *__restrict__ u, TS *__restrict__ out,
+__device__ __forceinline__ void apply_block(
+    const GridInfo &g, long long blk, const TS *__restrict__ u, TS *__restrict__ out,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, double dt, const double *__restrict__ dtcfl, int dt_mode) {
+    const int32_t *__restrict__ ent, TA h) {
     const long long N = g.N;
-    const long long blk = xcd_block(blockIdx.x, gridDim.x);
     const long long z = blk * kBS + threadIdx.x;
     const bool live = z < N;
     const WaveLists L = wave_lists(cnt, pos, z, N);
@@ -600,26 +824,69 @@ __global__ __launch_bounds__(kBS) void k_apply(
     TA acc = wave_incoming<TS, TA, TS>(L, z, N, uz, u, w, ent);
     if (!live) return;
     acc += row_own<DIM, WIDE, PER, TS, TA, TS>(g, z, uz, u, sb, w);
-    if (STEP) {
-        const TA h = (TA)(dt_mode == ADLBR_DT_CFL ? dt * dtcfl[0] : dt);
-        out[z] = Conv<TS, TA>::st(uz - h * acc);
-    } else {
-        out[z] = Conv<TS, TA>::st(acc);
+    out[z] = Conv<TS, TA>::st(STEP ? uz - h * acc : acc);
+}
+
+template <int DIM, bool WIDE, bool PER, bool STEP, typename TS, typename TA>
+__global__ __launch_bounds__(kBS) void k_apply(
+    GridInfo g, const TS *__restrict__ u, TS *__restrict__ out,
+    const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
+    const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
+    const int32_t *__restrict__ ent, double dt, const double *__restrict__ dtcfl, int dt_mode) {
+    const TA h = (TA)(dt_mode == ADLBR_DT_CFL ? dt * dtcfl[0] : dt);
+    apply_block<DIM, WIDE, PER, STEP, TS, TA>(g, xcd_block(blockIdx.x, gridDim.x), u, out, sb, w,
+                                              cnt, pos, ent, h);
+}
+
+// Batched explicit step: one launch advances every problem of a class by one
+// step.  Blocks are laid out problem after problem (first_block ascending);
+// a block finds its problem by binary search over the descriptors, then
+// runs the single-operator block body.  XCD: remap block indices so that each
+// XCD takes a contiguous range (neighbouring blocks share its L2).
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA, bool XCD>
+__global__ __launch_bounds__(kBS) void k_apply_batch(const BatchProb *__restrict__ probs, int nprob,
+                                                     int parity) {
+    const long long b = XCD ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].first_block <= b) lo = mid;
+        else hi = mid - 1;
     }
+    const BatchProb &P = probs[lo];
+    const GridInfo g = P.g;
+    const TA h = (TA)(P.dt_mode == ADLBR_DT_CFL ? P.dt * P.dtcfl[0] : P.dt);
+    apply_block<DIM, WIDE, PER, true, TS, TA>(
+        g, b - P.first_block, (const TS *)P.u[parity], (TS *)P.u[parity ^ 1],
+        (const typename Slots<DIM, WIDE>::store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent, h);
+}
+
+// dst = src for every problem (u[1] -> u[0] after an odd number of steps).
+template <typename TS>
+__global__ __launch_bounds__(kBS) void k_copy_batch(const BatchProb *__restrict__ probs, int nprob) {
+    const long long b = blockIdx.x;
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (probs[mid].first_block <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchProb &P = probs[lo];
+    const long long z = (b - P.first_block) * kBS + threadIdx.x;
+    if (z < P.g.N) ((TS *)P.u[0])[z] = ((const TS *)P.u[1])[z];
 }
 
 // Conjugate-gradient direction with K = I + dt A (dt from the state):
 //   q = K z + beta q,  p = z + beta p  (beta = 0 on the first iteration),
 // so that q = K p without a second gather.  Each block writes its partial
-// <p, q> in FP64; the last block to finish sums the partials in block order
-// (deterministic) and sets alpha = <z, r> / <p, q>.
+// <p, q> in FP64 (partial[blk]); k_cg_alpha sums them in block order and
+// sets alpha = <z, r> / <p, q>.
 template <int DIM, bool WIDE, bool PER, typename T>
 __global__ __launch_bounds__(kBS) void k_cg_direction(
     GridInfo g, const T *__restrict__ zv, T *__restrict__ q, T *__restrict__ p,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const T *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, CgState *st, double *partial, int first) {
-    __shared__ double red[kBS];
+    const int32_t *__restrict__ ent, const CgState *st, double *partial, int first) {
     const long long N = g.N;
     const long long blk = xcd_block(blockIdx.x, gridDim.x);
     const long long z = blk * kBS + threadIdx.x;
@@ -639,51 +906,33 @@ __global__ __launch_bounds__(kBS) void k_cg_direction(
         p[z] = pn;
         pqz = (double)pn * (double)qn;
     }
+    __shared__ double red[kBS];
     red[threadIdx.x] = pqz;
     __syncthreads();
     for (int s = kBS / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        partial[blk] = red[0];
-        __threadfence();
-        const unsigned t = atomicAdd(&st->ticket[0], 1u);
-        red[0] = (t == gridDim.x - 1) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    if (red[0] != 0.0) {  // last block: ordered sum of all partials
-        __threadfence();
-        double acc = 0.0;
-        for (long long b = threadIdx.x; b < gridDim.x; b += kBS)
-            acc += __hip_atomic_load(&partial[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int s = kBS / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            if (!skip) {
-                const double pq = red[0];
-                st->pq = pq;
-                if (!(pq > 0.0) || !isfinite(pq)) st->bad = 1;
-                st->alpha = st->bad ? 0.0 : st->rz / pq;
-            }
-            st->ticket[0] = 0u;
-        }
-    }
+    if (threadIdx.x == 0) partial[blk] = red[0];
 }
 
-// |b - (x + dt A x)|^2 with FP64 arithmetic (weights promoted).
+// alpha = <z, r> / <p, q> from the partials (one block of kBS threads).
+__global__ __launch_bounds__(kBS) void k_cg_alpha(CgState *st, const double *partial, long long nb) {
+    const double pq = reduce_partials(partial, nb);
+    if (threadIdx.x != 0 || st->bad || st->done) return;
+    st->pq = pq;
+    if (!(pq > 0.0) || !isfinite(pq)) st->bad = 1;
+    st->alpha = st->bad ? 0.0 : st->rz / pq;
+}
+
+// |b - (x + dt A x)|^2 with FP64 arithmetic (weights promoted); block
+// partials, finished by k_sum_partials.
 template <int DIM, bool WIDE, bool PER, typename T>
 __global__ __launch_bounds__(kBS) void k_residual(
     GridInfo g, const T *__restrict__ b, const double *__restrict__ x,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const T *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, double dt, double *out, double *partial, uint32_t *ticket,
-    T *__restrict__ rout) {
+    const int32_t *__restrict__ ent, double dt, double *partial, T *__restrict__ rout) {
     const long long N = g.N;
     const long long z = (long long)blockIdx.x * kBS + threadIdx.x;
     const bool live = z < N;
@@ -697,8 +946,13 @@ __global__ __launch_bounds__(kBS) void k_residual(
         r2 = r * r;
         if (rout) rout[z] = (T)r;
     }
-    double tot;
-    if (last_block_sum(r2, partial, ticket, tot) && threadIdx.x == 0) *out = tot;
+    block_partial_sum(r2, partial);
+}
+
+__global__ __launch_bounds__(kBS) void k_sum_partials(const double *partial, long long nb,
+                                                      double *out) {
+    const double t = reduce_partials(partial, nb);
+    if (threadIdx.x == 0) *out = t;
 }
 
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
@@ -712,32 +966,68 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
     const unsigned nbb = (unsigned)((nbins + kBS - 1) / kBS);
     TS *w = (TS *)op->w;
     store_t *sb = (store_t *)op->sb;
-    hipLaunchKernelGGL(k_fill_i32, dim3(nbb), dim3(kBS), 0, s, (int32_t *)op->bincnt, nbins, 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(nbb), dim3(kBS), 0, s, (int32_t *)op->bincur, nbins, 0);
-    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(1), 0, s, op->maxdiag);
+    constexpr bool BINS = DIM == 3;
+    if (BINS) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(nbb), dim3(kBS), 0, s, (int32_t *)op->bincnt, nbins, 0);
+        hipLaunchKernelGGL(k_fill_i32, dim3(nbb), dim3(kBS), 0, s, (int32_t *)op->bincur, nbins, 0);
+    }
     if (win_f64)
-        hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, double, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
-                           off, (const double *)win, sb, w, op->bincnt, status);
+        hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, double, TS, TA, BINS>), dim3(nb), dim3(kBS), 0,
+                           s, g, off, (const double *)win, sb, w, op->mask, op->part, op->bincnt,
+                           status);
     else
-        hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, float, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
-                           off, (const float *)win, sb, w, op->bincnt, status);
-    hipLaunchKernelGGL(k_copy_u32, dim3(nbb), dim3(kBS), 0, s, op->bincnt, op->binoff, nbins);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, (int32_t *)op->binoff, nbins);
-    if (win_f64)
-        hipLaunchKernelGGL((k_bin_fill<DIM, WIDE, PER, double>), dim3(nb), dim3(kBS), 0, s, g, off,
-                           (const double *)win, op->binoff, op->bincur, op->binbuf);
-    else
-        hipLaunchKernelGGL((k_bin_fill<DIM, WIDE, PER, float>), dim3(nb), dim3(kBS), 0, s, g, off,
-                           (const float *)win, op->binoff, op->bincur, op->binbuf);
-    if (op->storage == ADLBR_F64)
-        hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, double>), dim3((unsigned)nbins),
-                           dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w, op->pos,
-                           op->cnt, op->ent, (double *)op->diag, op->maxdiag, status);
-    else
-        hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, float>), dim3((unsigned)nbins),
-                           dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w, op->pos,
-                           op->cnt, op->ent, (float *)op->diag, op->maxdiag, status);
-    hipLaunchKernelGGL(k_cfl, dim3(1), dim3(1), 0, s, op->maxdiag, op->dtcfl);
+        hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, float, TS, TA, BINS>), dim3(nb), dim3(kBS), 0,
+                           s, g, off, (const float *)win, sb, w, op->mask, op->part, op->bincnt,
+                           status);
+    hipLaunchKernelGGL(k_rmax_fin, dim3(1), dim3(256), 0, s, (const double *)op->part,
+                       (long long)nb, op->rmax);
+    long long nparts;
+    if (DIM == 2) {
+        const int ntx = (g.nx + kTile - 1) / kTile, nty = (g.ny + kTile - 1) / kTile;
+        const unsigned ntiles = (unsigned)(ntx * nty);
+        const unsigned nchunk = (unsigned)nbins;  // 1024-point chunks
+        hipLaunchKernelGGL((k_tile_count<WIDE, PER>), dim3(ntiles), dim3(256), 0, s, g,
+                           (const typename Slots<2, WIDE>::store_t *)op->sb, (const uint8_t *)op->mask,
+                           (const int32_t *)op->rmax, op->cnt, status);
+        hipLaunchKernelGGL(k_chunk_sum, dim3(nchunk), dim3(256), 0, s, (const uint8_t *)op->cnt, N,
+                           (int32_t *)op->bincnt);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, (int32_t *)op->bincnt, nbins);
+        hipLaunchKernelGGL(k_chunk_pos, dim3(nchunk), dim3(256), 0, s, (const uint8_t *)op->cnt, N,
+                           (const int32_t *)op->bincnt, op->pos);
+        if (op->storage == ADLBR_F64)
+            hipLaunchKernelGGL((k_tile_fill<WIDE, PER, TS, TA, double>), dim3(ntiles), dim3(256), 0,
+                               s, g, (const typename Slots<2, WIDE>::store_t *)op->sb,
+                               (const uint8_t *)op->mask, (const TS *)w, (const int32_t *)op->rmax,
+                               (const uint8_t *)op->cnt, (const int32_t *)op->pos, op->ent,
+                               (double *)op->diag, op->part);
+        else
+            hipLaunchKernelGGL((k_tile_fill<WIDE, PER, TS, TA, float>), dim3(ntiles), dim3(256), 0,
+                               s, g, (const typename Slots<2, WIDE>::store_t *)op->sb,
+                               (const uint8_t *)op->mask, (const TS *)w, (const int32_t *)op->rmax,
+                               (const uint8_t *)op->cnt, (const int32_t *)op->pos, op->ent,
+                               (float *)op->diag, op->part);
+        nparts = ntiles;
+    } else {
+        hipLaunchKernelGGL(k_copy_u32, dim3(nbb), dim3(kBS), 0, s, op->bincnt, op->binoff, nbins);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, (int32_t *)op->binoff, nbins);
+        if (win_f64)
+            hipLaunchKernelGGL((k_bin_fill<DIM, WIDE, PER, double>), dim3(nb), dim3(kBS), 0, s, g,
+                               off, (const double *)win, op->binoff, op->bincur, op->binbuf);
+        else
+            hipLaunchKernelGGL((k_bin_fill<DIM, WIDE, PER, float>), dim3(nb), dim3(kBS), 0, s, g,
+                               off, (const float *)win, op->binoff, op->bincur, op->binbuf);
+        if (op->storage == ADLBR_F64)
+            hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, double>), dim3((unsigned)nbins),
+                               dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w,
+                               op->pos, op->cnt, op->ent, (double *)op->diag, op->part, status);
+        else
+            hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, float>), dim3((unsigned)nbins),
+                               dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w,
+                               op->pos, op->cnt, op->ent, (float *)op->diag, op->part, status);
+        nparts = nbins;
+    }
+    hipLaunchKernelGGL(k_cfl, dim3(1), dim3(256), 0, s, (const double *)op->part, nparts,
+                       op->maxdiag, op->dtcfl);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }
@@ -797,6 +1087,23 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct ApplyF 
     }
 };
 
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct BatchF {
+    static int run(const adlbr_operator *, const BatchProb *probs, int nprob, long long nblocks,
+                   int parity, int variant, int copy, hipStream_t s) {
+        if (copy) {
+            hipLaunchKernelGGL((k_copy_batch<TS>), dim3((unsigned)nblocks), dim3(kBS), 0, s, probs,
+                               nprob);
+        } else if (variant & 1) {
+            hipLaunchKernelGGL((k_apply_batch<DIM, WIDE, PER, TS, TA, true>), dim3((unsigned)nblocks),
+                               dim3(kBS), 0, s, probs, nprob, parity);
+        } else {
+            hipLaunchKernelGGL((k_apply_batch<DIM, WIDE, PER, TS, TA, false>),
+                               dim3((unsigned)nblocks), dim3(kBS), 0, s, probs, nprob, parity);
+        }
+        return ADLBR_OK;
+    }
+};
+
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct CgDirF {
     static int run(const adlbr_operator *op, const void *z, void *q, void *p, CgState *st,
                    double *partial, int first, hipStream_t s) {
@@ -806,7 +1113,10 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct CgDirF 
         if (op->storage != ADLBR_F32 && op->storage != ADLBR_F64) return ADLBR_E_UNSUPPORTED;
         hipLaunchKernelGGL((k_cg_direction<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)z, (TS *)q, (TS *)p, (const store_t *)op->sb,
-                           (const TS *)op->w, op->cnt, op->pos, op->ent, st, partial, first);
+                           (const TS *)op->w, op->cnt, op->pos, op->ent, (const CgState *)st,
+                           partial, first);
+        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kBS), 0, s, st, (const double *)partial,
+                           (long long)nb);
         return ADLBR_OK;
     }
 };
@@ -825,31 +1135,33 @@ template <int DIM, bool WIDE, bool PER> struct CgDirF<DIM, WIDE, PER, _Float16, 
 
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct ResidualF {
     static int run(const adlbr_operator *op, double dt, const void *b, const double *x,
-                   double *out, double *partial, uint32_t *ticket, void *rout, hipStream_t s) {
+                   double *out, double *partial, void *rout, hipStream_t s) {
         typedef typename Slots<DIM, WIDE>::store_t store_t;
         const GridInfo g = op->gi;
         const unsigned nb = (unsigned)((g.N + kBS - 1) / kBS);
         hipLaunchKernelGGL((k_residual<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)b, x, (const store_t *)op->sb, (const TS *)op->w, op->cnt,
-                           op->pos, op->ent, dt, out, partial, ticket, (TS *)rout);
+                           op->pos, op->ent, dt, partial, (TS *)rout);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBS), 0, s, (const double *)partial,
+                           (long long)nb, out);
         return ADLBR_OK;
     }
 };
 template <int DIM, bool WIDE, bool PER> struct ResidualF<DIM, WIDE, PER, bf16, float> {
     static int run(const adlbr_operator *, double, const void *, const double *, double *,
-                   double *, uint32_t *, void *, hipStream_t) {
+                   double *, void *, hipStream_t) {
         return ADLBR_E_UNSUPPORTED;
     }
 };
 template <int DIM, bool WIDE, bool PER> struct ResidualF<DIM, WIDE, PER, _Float16, float> {
     static int run(const adlbr_operator *, double, const void *, const double *, double *,
-                   double *, uint32_t *, void *, hipStream_t) {
+                   double *, void *, hipStream_t) {
         return ADLBR_E_UNSUPPORTED;
     }
 };
 
 struct Layout {
-    size_t sb, w, cnt, pos, ent, diag, scal, bincnt, bincur, binoff, binbuf, total;
+    size_t sb, w, cnt, pos, ent, diag, scal, mask, part, bincnt, bincur, binoff, binbuf, total;
 };
 
 Layout layout(const GridInfo &g, int storage, int wide) {
@@ -866,15 +1178,38 @@ Layout layout(const GridInfo &g, int storage, int wide) {
     L.ent = o;  o += align_up(4 * (size_t)(2 * S) * N);
     L.diag = o; o += align_up((storage == ADLBR_F64 ? 8 : 4) * (size_t)N);
     L.scal = o; o += 256;
+    L.mask = o; o += align_up((size_t)N + 64);
+    // partials: one per 256-point block, per 2D tile or per 3D bin
+    L.part = o; o += align_up(8 * ((size_t)N / 256 + 64));
     L.bincnt = o; o += align_up(4 * nbins + 4);
-    L.bincur = o; o += align_up(4 * nbins + 4);
-    L.binoff = o; o += align_up(4 * nbins + 4);
-    L.binbuf = o; o += align_up(8 * (size_t)(2 * S) * N);
+    const bool bins = g.dim == 3;  // the 2D tile assembly needs no bins
+    L.bincur = o; o += bins ? align_up(4 * nbins + 4) : 0;
+    L.binoff = o; o += bins ? align_up(4 * nbins + 4) : 0;
+    L.binbuf = o; o += bins ? align_up(8 * (size_t)(2 * S) * N) : 0;
     L.total = o;
     return L;
 }
 
 }  // namespace
+
+int batch_class(const adlbr_operator *op) {
+    return op->gi.dim * 1000 + op->wide * 100 + op->gi.periodic * 10 + op->storage;
+}
+
+void batch_describe(const adlbr_operator *op, BatchProb *d) {
+    d->g = op->gi;
+    d->sb = op->sb;
+    d->w = op->w;
+    d->cnt = op->cnt;
+    d->pos = op->pos;
+    d->ent = op->ent;
+    d->dtcfl = op->dtcfl;
+}
+
+int batch_launch(const adlbr_operator *rep, const BatchProb *probs, int nprob, long long nblocks,
+                 int parity, int variant, int copy, hipStream_t s) {
+    return dispatch<BatchF>(rep, probs, nprob, nblocks, parity, variant, copy, s);
+}
 
 int cg_direction(const adlbr_operator *op, const void *z, void *q, void *p, CgState *st,
                  double *partial, int first, hipStream_t s) {
@@ -887,8 +1222,8 @@ int apply_K(const adlbr_operator *op, const void *u, void *out, double dt, hipSt
 }
 
 int true_residual(const adlbr_operator *op, double dt, const void *b, const double *x,
-                  double *out, double *partial, uint32_t *ticket, void *rout, hipStream_t s) {
-    return dispatch<ResidualF>(op, dt, b, x, out, partial, ticket, rout, s);
+                  double *out, double *partial, void *rout, hipStream_t s) {
+    return dispatch<ResidualF>(op, dt, b, x, out, partial, rout, s);
 }
 
 const GridInfo &operator_grid(const adlbr_operator *op) { return op->gi; }
@@ -962,8 +1297,11 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
     op->pos = (int32_t *)(b + L.pos);
     op->ent = (int32_t *)(b + L.ent);
     op->diag = b + L.diag;
-    op->maxdiag = (unsigned long long *)(b + L.scal);
+    op->maxdiag = (double *)(b + L.scal);
     op->dtcfl = (double *)(b + L.scal + 8);
+    op->rmax = (int32_t *)(b + L.scal + 16);
+    op->mask = (uint8_t *)(b + L.mask);
+    op->part = (double *)(b + L.part);
     op->bincnt = (uint32_t *)(b + L.bincnt);
     op->bincur = (uint32_t *)(b + L.bincur);
     op->binoff = (uint32_t *)(b + L.binoff);

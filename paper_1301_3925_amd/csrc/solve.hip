@@ -1,12 +1,13 @@
 // Implicit step K x = b, K = I + dt A, by preconditioned conjugate gradients.
 //
 // All scalars live on the device (CgState); every reduction is a per-block
-// FP64 partial sum finished by the last block in block order, so a solve is
-// deterministic and needs no host round trip per iteration.  The update
-// kernel raises `done` when the recurrence residual drops below tol |b|;
-// later kernels of the same batch are then no-ops, so the iteration count is
-// exact although the host only looks every check_every iterations.  The host
-// confirms convergence with the true residual |b - K x| in FP64.
+// FP64 partial sum finished by a one-block kernel in block order, so a solve
+// is deterministic and needs no host round trip per iteration.  The update
+// kernel's finisher raises `done` when the recurrence residual drops below
+// tol |b|; later kernels of the same batch are then no-ops, so the iteration
+// count is exact although the host only looks every check_every
+// iterations.  The host confirms convergence with the true residual
+// |b - K x| in FP64.
 //
 // Jacobi-PCG per iteration: update (x, r, z = r / diag K, <r,z>, <r,r>,
 // beta) -> direction (q = K z + beta q, p = z + beta p, <p,q>, alpha).
@@ -28,7 +29,6 @@ struct SolveState {
     CgState cg;
     double tol2bb;  // tol^2 |b|^2
     double rr_true;
-    uint32_t tickets[8];
 };
 
 template <typename TD> __device__ __forceinline__ double inv_kd(const TD *diag, long long z, double dt) {
@@ -36,11 +36,13 @@ template <typename TD> __device__ __forceinline__ double inv_kd(const TD *diag, 
 }
 
 // x0 = 0: x64 = 0, r = b; otherwise r = b - K x64 is already in r.
-// z = r / diag K (Jacobi); sums <r, z> and <b, b>.
+// z = r / diag K (Jacobi); partial sums of <r, z> and <b, b>.
 template <typename T, typename TD>
-__global__ void k_init(long long N, const T *__restrict__ b, double *__restrict__ x64,
-                       T *__restrict__ r, T *__restrict__ z, const TD *__restrict__ diag,
-                       int x0_zero, int jacobi, SolveState *st, double *part, double tol2) {
+__global__ __launch_bounds__(kBS) void k_init(long long N, const T *__restrict__ b,
+                                              double *__restrict__ x64, T *__restrict__ r,
+                                              T *__restrict__ z, const TD *__restrict__ diag,
+                                              int x0_zero, int jacobi, const SolveState *st,
+                                              double *part) {
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
     double rz = 0.0, bb = 0.0;
     if (i < N) {
@@ -60,27 +62,33 @@ __global__ void k_init(long long N, const T *__restrict__ b, double *__restrict_
         }
         bb = (double)bi * (double)bi;
     }
-    double t;
-    if (last_block_sum(rz, part, &st->tickets[0], t) && threadIdx.x == 0) {
-        st->cg.rz = t;
-        st->cg.beta = 0.0;
-        st->cg.iter = 0;
-        st->cg.bad = 0;
-        st->cg.done = 0;
-    }
-    if (last_block_sum(bb, part + gridDim.x, &st->tickets[1], t) && threadIdx.x == 0) {
-        st->cg.bb = t;
-        st->tol2bb = tol2 * t;
-        st->cg.rr = t;
-    }
+    block_partial_sum(rz, part);
+    block_partial_sum(bb, part + gridDim.x);
 }
 
-// Jacobi-PCG update.
+__global__ __launch_bounds__(kBS) void k_init_fin(SolveState *st, const double *part, long long nb,
+                                                  double tol2) {
+    const double rz = reduce_partials(part, nb);
+    const double bb = reduce_partials(part + nb, nb);
+    if (threadIdx.x != 0) return;
+    st->cg.rz = rz;
+    st->cg.beta = 0.0;
+    st->cg.iter = 0;
+    st->cg.bad = 0;
+    st->cg.done = 0;
+    st->cg.bb = bb;
+    st->tol2bb = tol2 * bb;
+    st->cg.rr = bb;
+}
+
+// Jacobi-PCG update: x += alpha p, r -= alpha q, z = r / diag K; partials
+// of <r, z> and <r, r>.
 template <typename T, typename TD>
-__global__ void k_pcg_update(long long N, double *__restrict__ x, T *__restrict__ r, T *__restrict__ z,
-                             const T *__restrict__ p, const T *__restrict__ q,
-                             const TD *__restrict__ diag, SolveState *st, double *part,
-                             double *hist) {
+__global__ __launch_bounds__(kBS) void k_pcg_update(long long N, double *__restrict__ x,
+                                                    T *__restrict__ r, T *__restrict__ z,
+                                                    const T *__restrict__ p, const T *__restrict__ q,
+                                                    const TD *__restrict__ diag,
+                                                    const SolveState *st, double *part) {
     const bool skip = st->cg.done || st->cg.bad;
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
     double rz = 0.0, rr = 0.0;
@@ -94,33 +102,34 @@ __global__ void k_pcg_update(long long N, double *__restrict__ x, T *__restrict_
         rz = (double)ri * (double)zi;
         rr = (double)ri * (double)ri;
     }
-    double t_rz, t_rr;
-    const bool l1 = last_block_sum(rz, part, &st->tickets[2], t_rz);
-    const bool l2 = last_block_sum(rr, part + gridDim.x, &st->tickets[3], t_rr);
-    if (l1 && threadIdx.x == 0 && !skip) st->cg.zr_prev = t_rz;  // staged <r,z>
-    if (l2 && threadIdx.x == 0 && !skip) st->cg.rr = t_rr;
+    block_partial_sum(rz, part);
+    block_partial_sum(rr, part + gridDim.x);
 }
 
-// Finish a PCG iteration: beta, history, convergence flag (one thread).
-__global__ void k_pcg_scalars(SolveState *st, double *hist, int max_hist) {
-    if (st->cg.done || st->cg.bad) return;
-    const double rzn = st->cg.zr_prev;
-    const double rr = st->cg.rr;
+// Finish a PCG iteration: beta, history, convergence flag.
+__global__ __launch_bounds__(kBS) void k_pcg_scalars(SolveState *st, const double *part,
+                                                     long long nb, double *hist, int max_hist) {
+    const double rzn = reduce_partials(part, nb);
+    const double rr = reduce_partials(part + nb, nb);
+    if (threadIdx.x != 0 || st->cg.done || st->cg.bad) return;
     if (!isfinite(rzn) || !isfinite(rr) || !(st->cg.rz > 0.0)) st->cg.bad = 1;
     st->cg.beta = st->cg.bad ? 0.0 : rzn / st->cg.rz;
     st->cg.rz_old = st->cg.rz;
     st->cg.rz = rzn;
+    st->cg.rr = rr;
     const int it = st->cg.iter + 1;
     st->cg.iter = it;
     if (it < max_hist) hist[it] = rr;
     if (rr <= st->tol2bb) st->cg.done = 1;
 }
 
-// Flexible-CG update: x += alpha p, r_new = r - alpha q, <r_new, r_new>.
+// Flexible-CG update: x += alpha p, r_new = r - alpha q; partials of <r_new, r_new>.
 template <typename T>
-__global__ void k_fcg_update(long long N, double *__restrict__ x, const T *__restrict__ r,
-                             T *__restrict__ rn, const T *__restrict__ p, const T *__restrict__ q,
-                             SolveState *st, double *part, double *hist, int max_hist) {
+__global__ __launch_bounds__(kBS) void k_fcg_update(long long N, double *__restrict__ x,
+                                                    const T *__restrict__ r, T *__restrict__ rn,
+                                                    const T *__restrict__ p,
+                                                    const T *__restrict__ q, const SolveState *st,
+                                                    double *part) {
     const bool skip = st->cg.done || st->cg.bad;
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
     double rr = 0.0;
@@ -131,21 +140,26 @@ __global__ void k_fcg_update(long long N, double *__restrict__ x, const T *__res
         rn[i] = ri;
         rr = (double)ri * (double)ri;
     }
-    double t;
-    if (last_block_sum(rr, part, &st->tickets[4], t) && threadIdx.x == 0 && !skip) {
-        st->cg.rr = t;
-        const int it = st->cg.iter + 1;
-        st->cg.iter = it;
-        if (it < max_hist) hist[it] = t;
-        if (!isfinite(t)) st->cg.bad = 1;
-        if (t <= st->tol2bb) st->cg.done = 1;
-    }
+    block_partial_sum(rr, part);
 }
 
-// Flexible-CG dots: <z, r>, <z, r_prev> -> beta (first: beta = 0).
+__global__ __launch_bounds__(kBS) void k_fcg_update_fin(SolveState *st, const double *part,
+                                                        long long nb, double *hist, int max_hist) {
+    const double t = reduce_partials(part, nb);
+    if (threadIdx.x != 0 || st->cg.done || st->cg.bad) return;
+    st->cg.rr = t;
+    const int it = st->cg.iter + 1;
+    st->cg.iter = it;
+    if (it < max_hist) hist[it] = t;
+    if (!isfinite(t)) st->cg.bad = 1;
+    if (t <= st->tol2bb) st->cg.done = 1;
+}
+
+// Flexible-CG dots: partials of <z, r> and <z, r_prev>.
 template <typename T>
-__global__ void k_fcg_dots(long long N, const T *__restrict__ z, const T *__restrict__ r,
-                           const T *__restrict__ rp, int first, SolveState *st, double *part) {
+__global__ __launch_bounds__(kBS) void k_fcg_dots(long long N, const T *__restrict__ z,
+                                                  const T *__restrict__ r, const T *__restrict__ rp,
+                                                  int first, const SolveState *st, double *part) {
     const bool skip = st->cg.done || st->cg.bad;
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
     double zr = 0.0, zrp = 0.0;
@@ -154,16 +168,16 @@ __global__ void k_fcg_dots(long long N, const T *__restrict__ z, const T *__rest
         zr = zi * (double)r[i];
         if (!first) zrp = zi * (double)rp[i];
     }
-    double t1, t2;
-    const bool l1 = last_block_sum(zr, part, &st->tickets[5], t1);
-    const bool l2 = last_block_sum(zrp, part + gridDim.x, &st->tickets[6], t2);
-    if (l1 && threadIdx.x == 0 && !skip) st->cg.zr_prev = t1;  // staged <z, r>
-    if (l2 && threadIdx.x == 0 && !skip) st->cg.pq = t2;       // staged <z, r_prev>
+    block_partial_sum(zr, part);
+    block_partial_sum(zrp, part + gridDim.x);
 }
 
-__global__ void k_fcg_scalars(SolveState *st, int first) {
-    if (st->cg.done || st->cg.bad) return;
-    const double zr = st->cg.zr_prev, zrp = st->cg.pq;
+// beta = (<z, r> - <z, r_prev>) / <z_prev, r_prev> (first: beta = 0).
+__global__ __launch_bounds__(kBS) void k_fcg_scalars(SolveState *st, const double *part,
+                                                     long long nb, int first) {
+    const double zr = reduce_partials(part, nb);
+    const double zrp = reduce_partials(part + nb, nb);
+    if (threadIdx.x != 0 || st->cg.done || st->cg.bad) return;
     if (!isfinite(zr) || !(zr > 0.0) || !isfinite(zrp)) {
         st->cg.bad = 1;
         return;
@@ -173,8 +187,8 @@ __global__ void k_fcg_scalars(SolveState *st, int first) {
     st->cg.rz = zr;
 }
 
-// Zero the whole state (tickets included) and set dt; a kernel rather than a
-// host copy so no host buffer has to outlive the enqueue.
+// Zero the whole state and set dt; a kernel rather than a host copy so no
+// host buffer has to outlive the enqueue.
 __global__ void k_state_reset(SolveState *st, double dt) {
     uint32_t *w = (uint32_t *)st;
     constexpr int nw = (int)(sizeof(SolveState) / 4);
@@ -184,11 +198,12 @@ __global__ void k_state_reset(SolveState *st, double dt) {
 }
 
 // Residual replacement: r already holds b - K x (from the true residual);
-// recompute the Jacobi z and <r, z>, restart the direction (beta = 0) and
-// keep the iteration count.
+// recompute the Jacobi z and partials of <r, z>; k_restart_fin restarts the
+// direction (beta = 0) and keeps the iteration count.
 template <typename T, typename TD>
-__global__ void k_restart(long long N, const T *__restrict__ r, T *__restrict__ z,
-                          const TD *__restrict__ diag, int jacobi, SolveState *st, double *part) {
+__global__ __launch_bounds__(kBS) void k_restart(long long N, const T *__restrict__ r,
+                                                 T *__restrict__ z, const TD *__restrict__ diag,
+                                                 int jacobi, const SolveState *st, double *part) {
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
     double rz = 0.0;
     if (i < N && jacobi) {
@@ -197,13 +212,17 @@ __global__ void k_restart(long long N, const T *__restrict__ r, T *__restrict__ 
         z[i] = zi;
         rz = (double)ri * (double)zi;
     }
-    double t;
-    if (last_block_sum(rz, part, &st->tickets[0], t) && threadIdx.x == 0) {
-        st->cg.rz = t;
-        st->cg.beta = 0.0;
-        st->cg.rr = st->rr_true;
-        st->cg.done = 0;
-    }
+    block_partial_sum(rz, part);
+}
+
+__global__ __launch_bounds__(kBS) void k_restart_fin(SolveState *st, const double *part,
+                                                     long long nb) {
+    const double t = reduce_partials(part, nb);
+    if (threadIdx.x != 0) return;
+    st->cg.rz = t;
+    st->cg.beta = 0.0;
+    st->cg.rr = st->rr_true;
+    st->cg.done = 0;
 }
 
 template <typename TA, typename TB> __global__ void k_convert(long long N, const TA *a, TB *b) {
@@ -257,17 +276,19 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     ADLBR_CHECK_HIP(hipEventCreate(&e0));
     ADLBR_CHECK_HIP(hipEventCreate(&e1));
     ADLBR_CHECK_HIP(hipEventRecord(e0, s));
-    // clear the state (tickets must start at 0), set dt
+    // clear the state, set dt
     hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, st, dt);
     // the iterate is accumulated in FP64 (x64); the vectors and recurrences
     // are in the storage dtype
     if (!p->x0_zero) {
         hipLaunchKernelGGL((k_convert<T, double>), dim3(nb), dim3(kBS), 0, s, N, (const T *)x, x64);
-        int rc = true_residual(op, dt, b, x64, &st->rr_true, part, &st->tickets[7], r, s);
+        int rc = true_residual(op, dt, b, x64, &st->rr_true, part, r, s);
         if (rc) return rc;
     }
     hipLaunchKernelGGL((k_init<T, TD>), dim3(nb), dim3(kBS), 0, s, N, b, x64, r, z, diag,
-                       p->x0_zero, (int)!net, st, part, p->tol * p->tol);
+                       p->x0_zero, (int)!net, (const SolveState *)st, part);
+    hipLaunchKernelGGL(k_init_fin, dim3(1), dim3(kBS), 0, s, st, (const double *)part,
+                       (long long)nb, p->tol * p->tol);
     int rc = ADLBR_OK;
     bool use_net = net;
     int fell_back = 0, net_iters = 0, restarts = 0, reason = 0;
@@ -278,8 +299,9 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
             int e = net_apply(p->net, op, dt, rc_, z, s);
             if (e) return e;
             hipLaunchKernelGGL((k_fcg_dots<T>), dim3(nb), dim3(kBS), 0, s, N, (const T *)z,
-                               (const T *)rc_, (const T *)ro, first, st, part);
-            hipLaunchKernelGGL(k_fcg_scalars, dim3(1), dim3(1), 0, s, st, first);
+                               (const T *)rc_, (const T *)ro, first, (const SolveState *)st, part);
+            hipLaunchKernelGGL(k_fcg_scalars, dim3(1), dim3(kBS), 0, s, st, (const double *)part,
+                               (long long)nb, first);
         }
         int e = cg_direction(op, z, q, pv, cg, part, first, s);
         first = 0;
@@ -290,10 +312,7 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     const int check = p->check_every > 0 ? p->check_every : 10;
     int issued = 0;
     bool converged = false;
-    struct Host {
-        int32_t done, bad, iter;
-        double rr;
-    } h;
+    CgState h;
     // stall detection for the learned preconditioner: (iteration, |r|^2)
     // at each host check
     std::vector<std::pair<int, double>> trail;
@@ -302,22 +321,22 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
         for (int k = 0; k < batch; ++k) {
             if (use_net) {
                 hipLaunchKernelGGL((k_fcg_update<T>), dim3(nb), dim3(kBS), 0, s, N, x64,
-                                   (const T *)rc_, ro, (const T *)pv, (const T *)q, st, part, hist,
-                                   kMaxHist);
+                                   (const T *)rc_, ro, (const T *)pv, (const T *)q,
+                                   (const SolveState *)st, part);
+                hipLaunchKernelGGL(k_fcg_update_fin, dim3(1), dim3(kBS), 0, s, st,
+                                   (const double *)part, (long long)nb, hist, kMaxHist);
                 std::swap(rc_, ro);  // ro now holds r_k (previous), rc_ r_{k+1}
             } else {
                 hipLaunchKernelGGL((k_pcg_update<T, TD>), dim3(nb), dim3(kBS), 0, s, N, x64, rc_, z,
-                                   (const T *)pv, (const T *)q, diag, st, part, hist);
-                hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(1), 0, s, st, hist, kMaxHist);
+                                   (const T *)pv, (const T *)q, diag, (const SolveState *)st, part);
+                hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kBS), 0, s, st, (const double *)part,
+                                   (long long)nb, hist, kMaxHist);
             }
             rc = start_iteration();
             if (rc) return rc;
         }
         issued += batch;
-        ADLBR_CHECK_HIP(hipMemcpyAsync(&h.done, &cg->done, 4, hipMemcpyDeviceToHost, s));
-        ADLBR_CHECK_HIP(hipMemcpyAsync(&h.bad, &cg->bad, 4, hipMemcpyDeviceToHost, s));
-        ADLBR_CHECK_HIP(hipMemcpyAsync(&h.iter, &cg->iter, 4, hipMemcpyDeviceToHost, s));
-        ADLBR_CHECK_HIP(hipMemcpyAsync(&h.rr, &cg->rr, 8, hipMemcpyDeviceToHost, s));
+        ADLBR_CHECK_HIP(hipMemcpyAsync(&h, cg, sizeof h, hipMemcpyDeviceToHost, s));
         ADLBR_CHECK_HIP(hipStreamSynchronize(s));
         if (use_net) {
             net_iters = h.iter;
@@ -346,10 +365,12 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
             first = 1;
             const int keep_iter = h.iter;
             hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, st, dt);
-            rc = true_residual(op, dt, b, x64, &st->rr_true, part, &st->tickets[7], r, s);
+            rc = true_residual(op, dt, b, x64, &st->rr_true, part, r, s);
             if (rc) return rc;
             hipLaunchKernelGGL((k_init<T, TD>), dim3(nb), dim3(kBS), 0, s, N, b, x64, r, z, diag,
-                               0, 1, st, part, p->tol * p->tol);
+                               0, 1, (const SolveState *)st, part);
+            hipLaunchKernelGGL(k_init_fin, dim3(1), dim3(kBS), 0, s, st, (const double *)part,
+                               (long long)nb, p->tol * p->tol);
             rc_ = r;
             ro = r2;
             rc = start_iteration();
@@ -359,7 +380,7 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
             continue;
         }
         if (h.done) {
-            rc = true_residual(op, dt, b, x64, &st->rr_true, part, &st->tickets[7], nullptr, s);
+            rc = true_residual(op, dt, b, x64, &st->rr_true, part, nullptr, s);
             if (rc) return rc;
             double rt = 0.0, t2 = 0.0;
             ADLBR_CHECK_HIP(hipMemcpyAsync(&rt, &st->rr_true, 8, hipMemcpyDeviceToHost, s));
@@ -371,10 +392,12 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
             }
             // the recurrence residual drifted from the true one: replace it
             // and restart the direction from the current iterate
-            rc = true_residual(op, dt, b, x64, &st->rr_true, part, &st->tickets[7], rc_, s);
+            rc = true_residual(op, dt, b, x64, &st->rr_true, part, rc_, s);
             if (rc) return rc;
             hipLaunchKernelGGL((k_restart<T, TD>), dim3(nb), dim3(kBS), 0, s, N, (const T *)rc_, z,
-                               diag, (int)!use_net, st, part);
+                               diag, (int)!use_net, (const SolveState *)st, part);
+            hipLaunchKernelGGL(k_restart_fin, dim3(1), dim3(kBS), 0, s, st, (const double *)part,
+                               (long long)nb);
             first = 1;
             rc = start_iteration();
             if (rc) return rc;
@@ -385,7 +408,7 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     // final report
     int32_t iters = 0;
     double bb = 0.0;
-    rc = true_residual(op, dt, b, x64, &st->rr_true, part, &st->tickets[7], nullptr, s);
+    rc = true_residual(op, dt, b, x64, &st->rr_true, part, nullptr, s);
     if (rc) return rc;
     hipLaunchKernelGGL((k_convert<double, T>), dim3(nb), dim3(kBS), 0, s, N, (const double *)x64, x);
     double rt = 0.0;
