@@ -284,10 +284,12 @@ int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
  *   hidden   [hidden][N] FP32  pre-activation of the gate net (adlbr_net_gates)
  *   gates    [3W+1][N] FP32    gates of the four-layer stack, [g1, g2, g1, 1]
  *                              (adlbr_net_gates)
- *   gates16  [N][3W+1] BF16    packed copy for the inference kernel
+ *   gates16  [N][2W] BF16      g1, g2 per point for the inference kernel
  *   scratch  [2W][N] FP32      working planes of the FP32 forward path
- *   layers   [2W(W+1)T] FP32   weights of the four-layer stack, [W1, W2,
- *                              flip(W2)^T, flip(W1)^T] (adlbr_net_gates)
+ *   layers   [2W(W+1)T + 2304] FP32  weights of the four-layer stack, [W1,
+ *                              W2, flip(W2)^T, flip(W1)^T], then (2D) the
+ *                              BF16 MFMA operands of its two 16->16 layers
+ *                              packed per lane (adlbr_net_gates)
  * adlbr_net_gates must run again after params change.
  * ------------------------------------------------------------------ */
 typedef struct adlbr_net {

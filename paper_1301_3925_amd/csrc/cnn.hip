@@ -23,6 +23,7 @@ namespace adlbr {
 int apply_K(const adlbr_operator *op, const void *u, void *out, double dt, hipStream_t s);
 int net_apply_mfma(const adlbr_net *net, const adlbr_operator *op, const float *r, float *z,
                    hipStream_t s);
+int net_pack_mfma(const adlbr_net *net, hipStream_t s);
 
 namespace {
 
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(kBS) void k_conv(GridInfo g, const float *__restric
 
 // Gate layer B (1x1) + sigmoid: g[k] = 1 / (1 + exp(-(WB[k] . relu(h) + bB[k]))),
 // k < 2W, written expanded for the four-layer stack: Gout = [g1, g2, g1, 1]
-// ([3W+1][N]) and G16 the same per point in BF16 ([N][3W+1]).
+// ([3W+1][N]); G16 holds g1, g2 per point in BF16 ([N][2W]).
 template <int H, int W>
 __global__ __launch_bounds__(kBS) void k_gate_b(long long N, const float *__restrict__ h,
                                                 const float *__restrict__ WB,
@@ -223,16 +224,11 @@ __global__ __launch_bounds__(kBS) void k_gate_b(long long N, const float *__rest
 #pragma unroll
         for (int c = 0; c < H; ++c) a += WB[k * H + c] * hr[c];
         const float gv = 1.f / (1.f + expf(-a));
-        const uint16_t gb = f32_to_bf16(gv).b;
         Gout[k * N + i] = gv;
-        if (G16) G16[i * GX + k] = gb;
-        if (k < W) {
-            Gout[(2 * W + k) * N + i] = gv;
-            if (G16) G16[i * GX + 2 * W + k] = gb;
-        }
+        if (G16) G16[i * 2 * W + k] = f32_to_bf16(gv).b;
+        if (k < W) Gout[(2 * W + k) * N + i] = gv;
     }
     Gout[(GX - 1) * N + i] = 1.f;
-    if (G16) G16[i * GX + GX - 1] = f32_to_bf16(1.f).b;
 }
 
 // Expanded layer weights: L1 = W1, L2 = W2, L3[o][i][t] = W2[i][o][T-1-t],
@@ -706,6 +702,10 @@ extern "C" int adlbr_net_gates(adlbr_operator *op, adlbr_net *net, void *stream)
                        net->gates16);
     hipLaunchKernelGGL(k_expand_weights, dim3(16), dim3(kBS), 0, s, P + d.oW1, P + d.oW2,
                        net->layers, d.W, d.T, d.l2, d.l3, d.l4);
+    if (g.dim == 2) {
+        rc = net_pack_mfma(net, s);
+        if (rc) return rc;
+    }
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }

@@ -19,9 +19,8 @@
 //          o4 = o0-o2, o5 = o1+o2.  One vector load per point.
 //   w      [S][N] weights in the storage dtype.
 //   cnt    [N] uint8 number of incoming edges of each point.
-//   pos    [N] int32 start of each point's incoming list; the apply only
-//          reads the entry at the first point of each 64-point slice and
-//          rebuilds the rest with a wavefront prefix sum of cnt.
+//   pos    [N + 1] int32 start of each point's incoming list; pos[N] is the
+//          total number of entries.
 //   ent    incoming entries, int32 ((y - z) << 9 | slot << 6 | lane), lane =
 //          z mod 64 (the target's position in its wavefront), sorted per row;
 //          |y - z| < 2^22.
@@ -449,6 +448,7 @@ __global__ __launch_bounds__(256) void k_bin_build(
             if (c4[k] > 255) report(status, t, ADLBR_ST_INCOMING);
         }
         run += min(c4[k], 255);
+        if (t == N - 1) pos[N] = (int32_t)(base + run);  // total entry count
         lcnt[tl] = 0;  // becomes the placement cursor
     }
     __syncthreads();
@@ -613,6 +613,7 @@ __global__ __launch_bounds__(256) void k_chunk_pos(const uint8_t *__restrict__ c
         const long long z = base + threadIdx.x * 4 + k;
         if (z < N) pos[z] = run;
         run += c4[k];
+        if (z == N - 1) pos[N] = run;  // total entry count
     }
 }
 
@@ -721,7 +722,8 @@ __device__ __forceinline__ unsigned wave_incl_scan(unsigned v) {
 
 // Where a wavefront's incoming lists are: the 64 consecutive rows of the
 // wave own the entries [start, start + total) in row order; this lane's row
-// owns [lo, hi) relative to start.
+// owns [lo, hi) relative to start.  pos holds every row's start and, at
+// index N, the total entry count, so no scan is needed.
 struct WaveLists {
     long long start;
     unsigned total, lo, hi;
@@ -731,13 +733,14 @@ __device__ __forceinline__ WaveLists wave_lists(const uint8_t *__restrict__ cnt,
                                                 const int32_t *__restrict__ pos, long long z,
                                                 long long N) {
     WaveLists L;
-    const unsigned c = z < N ? cnt[z] : 0u;
-    const unsigned incl = wave_incl_scan(c);
-    L.total = __shfl(incl, 63, 64);
-    L.lo = incl - c;
-    L.hi = incl;
     const long long z0 = z & ~63ll;
+    const long long zend = z0 + 64 < N ? z0 + 64 : N;
+    const unsigned c = z < N ? cnt[z] : 0u;
+    const long long pz = z < N ? (long long)pos[z] : 0;
     L.start = z0 < N ? (long long)pos[z0] : 0;
+    L.total = z0 < N ? (unsigned)((long long)pos[zend] - L.start) : 0u;
+    L.lo = z < N ? (unsigned)(pz - L.start) : 0u;
+    L.hi = L.lo + c;
     return L;
 }
 
@@ -773,8 +776,11 @@ __device__ __forceinline__ TA row_own(const GridInfo &g, long long z, TA uz, con
 // each lane evaluates one edge w_slot(y) (u(row) - u(y)), and a segmented
 // inclusive scan over the lanes (entries are grouped by row, rows ascend)
 // sums each row's run; every lane then picks up its own row's sum from the
-// lane holding the end of that run.  The order of additions is fixed, so the
-// result is deterministic.  All 64 lanes must call this.
+// lane holding the end of that run.  Up to kPre chunks are loaded before any
+// is reduced, so their memory latencies overlap.  The order of additions is
+// fixed, so the result is deterministic.  All 64 lanes must call this.
+constexpr int kPre = 4;
+
 template <typename TS, typename TA, typename TU>
 __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, long long N, TA uz,
                                             const TU *__restrict__ u, const TS *__restrict__ w,
@@ -782,27 +788,44 @@ __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, lon
     const int lane = (int)(threadIdx.x & 63u);
     const long long z0 = z & ~63ll;
     TA acc = (TA)0;
-    for (unsigned e0 = 0; e0 < L.total; e0 += 64) {
-        const unsigned e = e0 + lane;
-        const bool valid = e < L.total;
-        const int32_t v = valid ? ent[L.start + e] : 0;
-        const int row = valid ? (v & 63) : 64;
-        const TA ur = __shfl(uz, row & 63, 64);
-        TA val = (TA)0;
-        if (valid) {
-            const long long y = z0 + (v & 63) + (v >> 9);
-            val = Conv<TS, TA>::ld(w[(long long)((v >> 6) & 7) * N + y]) * (ur - Conv<TU, TA>::ld(u[y]));
+    for (unsigned eb = 0; eb < L.total; eb += 64 * kPre) {
+        int32_t v[kPre];
+        TA val[kPre];
+#pragma unroll
+        for (int j = 0; j < kPre; ++j) {
+            const unsigned e = eb + 64 * j + lane;
+            v[j] = e < L.total ? ent[L.start + e] : -1;
         }
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const TA vu = __shfl_up(val, d, 64);
-            const int ru = __shfl_up(row, d, 64);
-            if (lane >= d && ru == row) val += vu;
+        for (int j = 0; j < kPre; ++j) {
+            const bool ok = eb + 64 * j + lane < L.total;
+            const TA ur = __shfl(uz, ok ? (v[j] & 63) : 0, 64);  // all lanes take part
+            TA wy = (TA)0, uy = (TA)0;
+            if (ok) {
+                const long long y = z0 + (v[j] & 63) + (v[j] >> 9);
+                wy = Conv<TS, TA>::ld(w[(long long)((v[j] >> 6) & 7) * N + y]);
+                uy = Conv<TU, TA>::ld(u[y]);
+            }
+            val[j] = ok ? wy * (ur - uy) : (TA)0;
         }
-        const unsigned lo = L.lo > e0 ? L.lo : e0;
-        const unsigned hi = L.hi < e0 + 64 ? L.hi : e0 + 64;
-        const TA mine = __shfl(val, (int)((hi - 1 - e0) & 63u), 64);
-        if (hi > lo) acc += mine;
+#pragma unroll
+        for (int j = 0; j < kPre; ++j) {
+            const unsigned e0 = eb + 64 * j;
+            if (e0 >= L.total) break;  // wave-uniform
+            const bool valid = e0 + lane < L.total;
+            const int row = valid ? (v[j] & 63) : 64;
+            TA x = val[j];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const TA xu = __shfl_up(x, d, 64);
+                const int ru = __shfl_up(row, d, 64);
+                if (lane >= d && ru == row) x += xu;
+            }
+            const unsigned lo = L.lo > e0 ? L.lo : e0;
+            const unsigned hi = L.hi < e0 + 64 ? L.hi : e0 + 64;
+            const TA mine = __shfl(x, (int)((hi - 1 - e0) & 63u), 64);
+            if (hi > lo) acc += mine;
+        }
     }
     return acc;
 }

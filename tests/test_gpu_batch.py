@@ -1,0 +1,95 @@
+"""Batched explicit stepping (adlbr_batch_*) against single-operator steps.
+
+The grouped kernel runs the same per-block body as adlbr_step, so every
+problem of a batch must come out bit-identical to stepping it alone, for
+any launch variant, with and without the captured graph, for even and odd
+step counts and for replays of the graph.  One 2D problem is also checked
+against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_3925_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_1301_3925_amd as adlbr
+    assert torch.cuda.is_available()
+    return adlbr
+
+
+def _problems(lib, dtype, periodic=False):
+    import torch
+    specs = [((70, 45), 10.0), ((33, 90), 30.0), ((128, 64), 5.0), ((12, 11, 9), 8.0),
+             ((20, 17, 15), 20.0), ((5, 3), 2.0)]
+    ops, us = [], []
+    for k, (dims, kappa) in enumerate(specs):
+        D = (synth.tensor2d_field(100 + k, *dims, kappa) if len(dims) == 2
+             else synth.tensor3d_field(100 + k, dims, kappa))
+        off, w, _ = lib.build_stencils(torch.from_numpy(D).cuda(), dims)
+        ops.append(lib.Operator(dims, off, w, storage=dtype, periodic=periodic))
+        us.append(torch.from_numpy(synth.uniform(200 + k, int(np.prod(dims)))).to(dtype).cuda())
+    return ops, us
+
+
+@pytest.mark.parametrize("nsteps", [1, 6, 7])
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_matches_single_steps_bitwise(lib, nsteps, graph):
+    import torch
+    ops, us = _problems(lib, torch.float32)
+    ref = [u.clone() for u in us]
+    for op, u in zip(ops, ref):
+        op.step(u, 0.9, nsteps, cfl_fraction=True)
+    b = lib.Batch(ops, us, dt=0.9, dt_mode="cfl")
+    b.run(nsteps, graph=graph)
+    torch.cuda.synchronize()
+    for k, (u, r) in enumerate(zip(us, ref)):
+        assert torch.equal(u, r), k
+
+
+def test_batch_every_variant_and_graph_replay(lib):
+    """The tuner's variants reorder blocks only; replays continue the state."""
+    import torch
+    ops, us = _problems(lib, torch.float64, periodic=True)
+    ref = [u.clone() for u in us]
+    for op, u in zip(ops, ref):
+        op.step(u, 0.5, 8, cfl_fraction=True)
+    b = lib.Batch(ops, us, dt=0.5, dt_mode="cfl")
+    vs = b.tune(steps=2, use_cache=False)
+    assert len(vs) == 2 and sum(v["problems"] for v in vs) == len(ops)
+    assert all(0 <= v["variant"] < 4 for v in vs)
+    b.run(4)
+    b.run(4)  # replay of the captured graph
+    torch.cuda.synchronize()
+    for k, (u, r) in enumerate(zip(us, ref)):
+        assert torch.equal(u, r), k
+
+
+def test_batch_absolute_dt_and_oracle(lib):
+    import torch
+    ops, us = _problems(lib, torch.float64)
+    dts = [0.5 * op.dt_cfl() for op in ops]
+    u0 = us[0].cpu().numpy().copy()
+    b = lib.Batch(ops, us, dt=dts, dt_mode="abs")
+    b.run(10)
+    torch.cuda.synchronize()
+    dims = ops[0].dims
+    off, w, _ = oracle.stencil(synth.tensor2d_field(100, *dims, 10.0))
+    A = oracle.operator_matrix(dims, off, w)
+    ref = oracle.explicit_steps(A, u0, dts[0], 10)
+    got = us[0].cpu().numpy()
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-12
+
+
+def test_batch_rejects_bad_arguments(lib):
+    import torch
+    ops, us = _problems(lib, torch.float32)
+    with pytest.raises(Exception):
+        lib.Batch(ops, us[:-1])
+    with pytest.raises(Exception):
+        lib.Batch(ops[:1], us[:1], tmps=us[:1])  # u aliased with its scratch
