@@ -41,6 +41,31 @@ ALGO_BYTES = {(2, 8): 16 + 3 * 8 + 4, (2, 4): 8 + 3 * 4 + 4, (2, 2): 4 + 3 * 2 +
               (3, 8): 16 + 6 * 8 + 12, (3, 4): 8 + 6 * 4 + 12, (3, 2): 4 + 6 * 2 + 12}
 
 
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by what the same
+# counters read for the 1 GiB copy of --workload copy (FETCH x 2.0, WRITE
+# x 1.0), with the SHA-256 of the kernel sources they were taken on.  A
+# change to those sources makes the figure stale: traffic is then null.
+TRAFFIC = {}
+TRAFFIC_SOURCES = ("paper_1301_3925_amd/csrc/operator.hip", "paper_1301_3925_amd/csrc/common.h")
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_for(workload):
+    rec = TRAFFIC.get(workload)
+    if rec is None or rec["sha256"] != source_digest():
+        return None
+    return rec["bytes_per_launch"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,7 +216,7 @@ def main():
                                      "explicit_steps_x10": round(phase[3], 4)},
             "roofline": {"bound": "hbm", "kernel": "k_apply (explicit step, 2D FP32)",
                          "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                         "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for("c2"),
                          "algo_bytes_per_point": ALGO_BYTES[(2, 4)],
                          "avg_launch_us": round(step_kernel_s * 1e6, 3)},
         }

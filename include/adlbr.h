@@ -284,12 +284,13 @@ int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
  *   hidden   [hidden][N] FP32  pre-activation of the gate net (adlbr_net_gates)
  *   gates    [3W+1][N] FP32    gates of the four-layer stack, [g1, g2, g1, 1]
  *                              (adlbr_net_gates)
- *   gates16  [N][2W] BF16      g1, g2 per point for the inference kernel
+ *   gates8   [N][2W] uint8     g1, g2 per point as round(255 g) for the
+ *                              inference kernel
  *   scratch  [2W][N] FP32      working planes of the FP32 forward path
- *   layers   [2W(W+1)T + 2304] FP32  weights of the four-layer stack, [W1,
+ *   layers   [2W(W+1)T + 3584] FP32  weights of the four-layer stack, [W1,
  *                              W2, flip(W2)^T, flip(W1)^T], then (2D) the
- *                              BF16 MFMA operands of its two 16->16 layers
- *                              packed per lane (adlbr_net_gates)
+ *                              BF16 MFMA operands of its four layers packed
+ *                              per lane (adlbr_net_gates)
  * adlbr_net_gates must run again after params change.
  * ------------------------------------------------------------------ */
 typedef struct adlbr_net {
@@ -301,7 +302,7 @@ typedef struct adlbr_net {
     float *features;
     float *hidden_act;
     float *gates;
-    uint16_t *gates16;
+    uint8_t *gates8;
     float *scratch;
     float *layers;
 } adlbr_net;
@@ -310,7 +311,7 @@ typedef struct adlbr_net {
 int adlbr_net_param_count(int dim, int width, int hidden, size_t *count);
 /* Features of the operator at time step dt into net->features. */
 int adlbr_net_features(adlbr_operator *op, double dt, adlbr_net *net, void *stream);
-/* Gate net forward: net->hidden_act, net->gates and net->gates16, and the
+/* Gate net forward: net->hidden_act, net->gates and net->gates8, and the
  * expanded weights net->layers. */
 int adlbr_net_gates(adlbr_operator *op, adlbr_net *net, void *stream);
 /* z = r / diag(K) + N(r).  r, z: device [N] FP32.  If saved is not null
@@ -318,9 +319,9 @@ int adlbr_net_gates(adlbr_operator *op, adlbr_net *net, void *stream);
  * for adlbr_net_backward. */
 int adlbr_net_forward(adlbr_operator *op, const adlbr_net *net, const float *r, float *z,
                       float *saved, void *stream);
-/* The inference path flexible CG uses: in 2D with net->gates16 set, the
- * fused BF16 MFMA kernel (activations and weights rounded to BF16, FP32
- * accumulation); otherwise the FP32 path of adlbr_net_forward. */
+/* The inference path flexible CG uses: in 2D with net->gates8 set, the
+ * fused MFMA kernel (BF16 operands, FP32 accumulation, 8-bit gates);
+ * otherwise the FP32 path of adlbr_net_forward. */
 int adlbr_net_precondition(adlbr_operator *op, const adlbr_net *net, const float *r, float *z,
                            void *stream);
 /* Backward of sum(gz * z) for one sample: adds the r-path weight

@@ -58,7 +58,7 @@ class NetStruct(ctypes.Structure):
                 ("hidden", ctypes.c_int32), ("nfeat", ctypes.c_int32),
                 ("params", ctypes.c_void_p), ("features", ctypes.c_void_p),
                 ("hidden_act", ctypes.c_void_p), ("gates", ctypes.c_void_p),
-                ("gates16", ctypes.c_void_p), ("scratch", ctypes.c_void_p),
+                ("gates8", ctypes.c_void_p), ("scratch", ctypes.c_void_p),
                 ("layers", ctypes.c_void_p)]
 
 

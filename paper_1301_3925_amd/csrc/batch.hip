@@ -39,7 +39,6 @@ struct adlbr_batch {
 namespace adlbr {
 namespace {
 
-constexpr int kBS = 256;
 constexpr int kVariants = 4;  // bit 0: XCD-contiguous blocks; bit 1: largest problems first
 
 std::mutex g_cache_mu;
@@ -62,7 +61,7 @@ int upload(adlbr_batch::Class &c, int variant, hipStream_t s) {
     long long fb = 0;
     for (BatchProb &p : d) {
         p.first_block = fb;
-        fb += (p.g.N + kBS - 1) / kBS;
+        fb += (p.g.N + kApplyPoints - 1) / kApplyPoints;
     }
     c.nblocks = fb;
     ADLBR_CHECK_HIP(hipMemcpyAsync(c.dev, d.data(), d.size() * sizeof(BatchProb),
@@ -134,7 +133,7 @@ extern "C" int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *c
             set_error("adlbr_batch_create: problem %d: null or aliased buffer, or dt < 0", i);
             return ADLBR_E_INVALID;
         }
-        if ((operator_grid(ops[i]).N + kBS - 1) / kBS >= (1ll << 31)) {
+        if ((operator_grid(ops[i]).N + kApplyPoints - 1) / kApplyPoints >= (1ll << 31)) {
             set_error("adlbr_batch_create: problem %d too large", i);
             return ADLBR_E_RANGE;
         }
@@ -179,7 +178,7 @@ extern "C" int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *c
     for (auto &c : b->classes) {
         c.dev = (BatchProb *)(base + o);
         o += sizeof(BatchProb) * c.host.size();
-        for (const BatchProb &p : c.host) total_blocks += (p.g.N + kBS - 1) / kBS;
+        for (const BatchProb &p : c.host) total_blocks += (p.g.N + kApplyPoints - 1) / kApplyPoints;
     }
     if (total_blocks >= (1ll << 31)) {
         delete b;

@@ -207,12 +207,13 @@ __global__ __launch_bounds__(kBS) void k_conv(GridInfo g, const float *__restric
 
 // Gate layer B (1x1) + sigmoid: g[k] = 1 / (1 + exp(-(WB[k] . relu(h) + bB[k]))),
 // k < 2W, written expanded for the four-layer stack: Gout = [g1, g2, g1, 1]
-// ([3W+1][N]); G16 holds g1, g2 per point in BF16 ([N][2W]).
+// ([3W+1][N]); G8 holds g1, g2 per point as 8-bit fixed point round(255 g)
+// ([N][2W]) for the inference kernel.
 template <int H, int W>
 __global__ __launch_bounds__(kBS) void k_gate_b(long long N, const float *__restrict__ h,
                                                 const float *__restrict__ WB,
                                                 const float *__restrict__ bB, float *__restrict__ Gout,
-                                                uint16_t *__restrict__ G16) {
+                                                uint8_t *__restrict__ G8) {
     constexpr int GX = 3 * W + 1;
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
     if (i >= N) return;
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(kBS) void k_gate_b(long long N, const float *__rest
         for (int c = 0; c < H; ++c) a += WB[k * H + c] * hr[c];
         const float gv = 1.f / (1.f + expf(-a));
         Gout[k * N + i] = gv;
-        if (G16) G16[i * 2 * W + k] = f32_to_bf16(gv).b;
+        if (G8) G8[i * 2 * W + k] = (uint8_t)__float2int_rn(gv * 255.f);
         if (k < W) Gout[(2 * W + k) * N + i] = gv;
     }
     Gout[(GX - 1) * N + i] = 1.f;
@@ -617,7 +618,7 @@ int net_apply(const adlbr_net *net, const adlbr_operator *op, double dt, const v
         set_error("net: the operator's storage must be ADLBR_F32");
         return ADLBR_E_UNSUPPORTED;
     }
-    if (d.dim == 2 && net->gates16) return net_apply_mfma(net, op, (const float *)r, (float *)z, s);
+    if (d.dim == 2 && net->gates8) return net_apply_mfma(net, op, (const float *)r, (float *)z, s);
     if (!net->scratch) {
         set_error("net: the FP32 inference path needs net->scratch ([2W][N] FP32)");
         return ADLBR_E_INVALID;
@@ -699,7 +700,7 @@ extern "C" int adlbr_net_gates(adlbr_operator *op, adlbr_net *net, void *stream)
     if (rc) return rc;
     hipLaunchKernelGGL((k_gate_b<16, 16>), dim3(nblk(g.N)), dim3(kBS), 0, s, g.N,
                        (const float *)net->hidden_act, P + d.oWB, P + d.obB, net->gates,
-                       net->gates16);
+                       net->gates8);
     hipLaunchKernelGGL(k_expand_weights, dim3(16), dim3(kBS), 0, s, P + d.oW1, P + d.oW2,
                        net->layers, d.W, d.T, d.l2, d.l3, d.l4);
     if (g.dim == 2) {

@@ -147,9 +147,14 @@ struct adlbr_net_impl;
 int net_apply(const adlbr_net *net, const adlbr_operator *op, double dt, const void *r, void *z,
               hipStream_t s);
 
+// Rows per block of the explicit-step kernels: every wave of a 256-thread
+// block takes kApplyPPT groups of 64 consecutive rows.
+constexpr int kApplyPPT = 1;
+constexpr int kApplyPoints = 256 * kApplyPPT;
+
 // Device descriptor of one problem of a batch (one operator and its two
 // state buffers); first_block is the problem's first 256-point block in
-// the batch's grid.
+// the batch's grid (blocks of kApplyPoints rows).
 struct BatchProb {
     GridInfo g;
     const void *sb;

@@ -192,6 +192,25 @@ __device__ __forceinline__ bool edge_target(const Coord &p, long long i, const i
     }
 }
 
+// edge_target in 32-bit arithmetic (N < 2^28), for the apply kernels.
+template <int DIM, bool PER>
+__device__ __forceinline__ bool edge_target32(const Coord &p, int i, const int *o, int s,
+                                              const GridInfo &g, int &t) {
+    if (PER) {
+        const int x = wrap(p.x + s * o[0], g.nx);
+        const int y = wrap(p.y + s * o[1], g.ny);
+        const int zz = DIM == 3 ? wrap(p.z + s * o[2], g.nz) : 0;
+        t = x + g.nx * (y + g.ny * zz);
+        return t != i;
+    } else {
+        const int x = p.x + s * o[0], y = p.y + s * o[1];
+        const int zz = DIM == 3 ? p.z + s * o[2] : 0;
+        if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || zz < 0 || zz >= g.nz) return false;
+        t = i + s * (o[0] + g.nx * (o[1] + g.ny * (DIM == 3 ? o[2] : 0)));
+        return true;
+    }
+}
+
 // ---------------------------------------------------------------- build --
 
 __global__ void k_fill_i32(int32_t *p, long long n, int32_t v) {
@@ -725,7 +744,7 @@ __device__ __forceinline__ unsigned wave_incl_scan(unsigned v) {
 // owns [lo, hi) relative to start.  pos holds every row's start and, at
 // index N, the total entry count, so no scan is needed.
 struct WaveLists {
-    long long start;
+    int start;
     unsigned total, lo, hi;
 };
 
@@ -736,51 +755,128 @@ __device__ __forceinline__ WaveLists wave_lists(const uint8_t *__restrict__ cnt,
     const long long z0 = z & ~63ll;
     const long long zend = z0 + 64 < N ? z0 + 64 : N;
     const unsigned c = z < N ? cnt[z] : 0u;
-    const long long pz = z < N ? (long long)pos[z] : 0;
-    L.start = z0 < N ? (long long)pos[z0] : 0;
-    L.total = z0 < N ? (unsigned)((long long)pos[zend] - L.start) : 0u;
+    const int pz = z < N ? pos[z] : 0;
+    L.start = z0 < N ? pos[z0] : 0;
+    L.total = z0 < N ? (unsigned)(pos[zend] - L.start) : 0u;
     L.lo = z < N ? (unsigned)(pz - L.start) : 0u;
     L.hi = L.lo + c;
     return L;
 }
 
 // Own part of row z: sum over slots o and signs s with z + s o in the grid
-// of w_o(z) (u(z) - u(z + s o)).
-template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TU>
-__device__ __forceinline__ TA row_own(const GridInfo &g, long long z, TA uz, const TU *__restrict__ u,
-                                      const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
-                                      const TS *__restrict__ w) {
-    constexpr int S = DIM == 2 ? 3 : 6;
-    const long long N = g.N;
-    TA acc = (TA)0;
-    Slots<DIM, WIDE> sl;
-    sl.load(sb, z);
-    const Coord p = coords(z, g);
+// of w_o(z) (u(z) - u(z + s o)).  Split in two so that a kernel can issue
+// these loads before the dependent loads of the incoming part: issue()
+// loads the weights and the neighbour values (u(z) where an edge is
+// missing, so its term is exactly 0), sum() adds them up.
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TU> struct OwnPart {
+    static constexpr int S = DIM == 2 ? 3 : 6;
+    TA wq[S];
+    TA un[2 * S];
+    __device__ __forceinline__ void issue(const GridInfo &g, long long z, bool live, TA uz,
+                                          const TU *__restrict__ u,
+                                          const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                                          const TS *__restrict__ w) {
+        const int N = (int)g.N, zi = live ? (int)z : 0;  // N < 2^28, S N < 2^31
+        Slots<DIM, WIDE> sl;
+        if (live) sl.load(sb, zi);
+        const Coord p = coords(zi, g);
 #pragma unroll
-    for (int q = 0; q < S; ++q) {
-        const TA wq = Conv<TS, TA>::ld(w[q * N + z]);
-        TA part = (TA)0;
+        for (int q = 0; q < S; ++q) {
+            wq[q] = live ? Conv<TS, TA>::ld(w[(unsigned)(q * N + zi)]) : (TA)0;
 #pragma unroll
-        for (int sg = -1; sg <= 1; sg += 2) {
-            long long t;
-            if (edge_target<DIM, PER>(p, z, sl.o[q], sg, g, t))
-                part += uz - Conv<TU, TA>::ld(u[t]);
+            for (int k = 0; k < 2; ++k) {
+                int t = 0;
+                const bool ok = live && edge_target32<DIM, PER>(p, zi, sl.o[q], k ? 1 : -1, g, t);
+                un[2 * q + k] = ok ? Conv<TU, TA>::ld(u[(unsigned)t]) : uz;
+            }
         }
-        acc += wq * part;
     }
-    return acc;
+    __device__ __forceinline__ TA sum(TA uz) const {
+        TA acc = (TA)0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            TA part = (TA)0;
+            part += uz - un[2 * q];
+            part += uz - un[2 * q + 1];
+            acc += wq[q] * part;
+        }
+        return acc;
+    }
+};
+
+constexpr int kPre = 4;
+
+// Chunk [e0, e0 + 64) of a wave's entries: this lane's edge value
+// w_slot(y) (u(row) - u(y)), 0 past the end.  All 64 lanes must call it.
+template <typename TS, typename TA, typename TU>
+__device__ __forceinline__ TA incoming_edge(const WaveLists &L, long long z0, long long N, TA uz,
+                                            int32_t v, unsigned e0, const TU *__restrict__ u,
+                                            const TS *__restrict__ w) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const bool ok = e0 + lane < L.total;
+    const TA ur = __shfl(uz, ok ? (v & 63) : 0, 64);  // all lanes take part
+    TA wy = (TA)0, uy = (TA)0;
+    if (ok) {  // N < 2^28 points, S N < 2^31: 32-bit indices
+        const int y = (int)z0 + (v & 63) + (v >> 9);
+        wy = Conv<TS, TA>::ld(w[(unsigned)(((v >> 6) & 7) * (int)N + y)]);
+        uy = Conv<TU, TA>::ld(u[(unsigned)y]);
+    }
+    return ok ? wy * (ur - uy) : (TA)0;
+}
+
+// Cross-lane moves within a wavefront by DPP (no LDS traffic): CTRL is a
+// row_shr:n (0x110 + n) or row_bcast:15 / row_bcast:31 (0x142 / 0x143)
+// control, RM the rows written; lanes without a source read 0.
+template <int CTRL, int RM> __device__ __forceinline__ int dpp_i(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, RM, 0xf, true);
+}
+template <int CTRL, int RM> __device__ __forceinline__ float dpp_v(float x) {
+    return __int_as_float(dpp_i<CTRL, RM>(__float_as_int(x)));
+}
+template <int CTRL, int RM> __device__ __forceinline__ double dpp_v(double x) {
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)dpp_i<CTRL, RM>((int)(unsigned)(b & 0xffffffffll));
+    const unsigned hi = (unsigned)dpp_i<CTRL, RM>((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// One step of the segmented scan: add the moved value when it comes from a
+// lane of the same segment (row).  Lanes without a source get (0, row 0),
+// which adds 0.
+template <int CTRL, int RM, typename TA> __device__ __forceinline__ void seg_step(TA &x, int row) {
+    const TA xs = dpp_v<CTRL, RM>(x);
+    const int rs = dpp_i<CTRL, RM>(row);
+    if (rs == row) x += xs;
+}
+
+// This lane's row sum over chunk [e0, e0 + 64): segmented inclusive scan of
+// the edge values over the lanes (entries are grouped by row, rows ascend;
+// steps of 1, 2, 4, 8 lanes within each row of 16, then the last lane of
+// row 0 into row 1 and of row 2 into row 3, then lane 31 into rows 2 and
+// 3), then the value at the end of this row's run.  Wave-uniform early out
+// past the end.  All 64 lanes must call it.
+template <typename TA>
+__device__ __forceinline__ TA incoming_reduce(const WaveLists &L, int32_t v, TA x, unsigned e0) {
+    if (e0 >= L.total) return (TA)0;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int row = e0 + lane < L.total ? (v & 63) : 64;
+    seg_step<0x111, 0xf>(x, row);
+    seg_step<0x112, 0xf>(x, row);
+    seg_step<0x114, 0xf>(x, row);
+    seg_step<0x118, 0xf>(x, row);
+    seg_step<0x142, 0xa>(x, row);
+    seg_step<0x143, 0xc>(x, row);
+    const unsigned lo = L.lo > e0 ? L.lo : e0;
+    const unsigned hi = L.hi < e0 + 64 ? L.hi : e0 + 64;
+    const TA mine = __shfl(x, (int)((hi - 1 - e0) & 63u), 64);
+    return hi > lo ? mine : (TA)0;
 }
 
 // Incoming part of the rows of one wavefront, computed cooperatively: the
 // wave's entries are taken 64 at a time (coalesced loads, every lane busy),
-// each lane evaluates one edge w_slot(y) (u(row) - u(y)), and a segmented
-// inclusive scan over the lanes (entries are grouped by row, rows ascend)
-// sums each row's run; every lane then picks up its own row's sum from the
-// lane holding the end of that run.  Up to kPre chunks are loaded before any
-// is reduced, so their memory latencies overlap.  The order of additions is
-// fixed, so the result is deterministic.  All 64 lanes must call this.
-constexpr int kPre = 4;
-
+// each lane evaluates one edge, and a segmented scan sums each row's run.
+// Up to kPre chunks are loaded before any is reduced, so their memory
+// latencies overlap.  The order of additions is fixed, so the result is
+// deterministic.  All 64 lanes must call this.
 template <typename TS, typename TA, typename TU>
 __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, long long N, TA uz,
                                             const TU *__restrict__ u, const TS *__restrict__ w,
@@ -797,57 +893,77 @@ __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, lon
             v[j] = e < L.total ? ent[L.start + e] : -1;
         }
 #pragma unroll
-        for (int j = 0; j < kPre; ++j) {
-            const bool ok = eb + 64 * j + lane < L.total;
-            const TA ur = __shfl(uz, ok ? (v[j] & 63) : 0, 64);  // all lanes take part
-            TA wy = (TA)0, uy = (TA)0;
-            if (ok) {
-                const long long y = z0 + (v[j] & 63) + (v[j] >> 9);
-                wy = Conv<TS, TA>::ld(w[(long long)((v[j] >> 6) & 7) * N + y]);
-                uy = Conv<TU, TA>::ld(u[y]);
-            }
-            val[j] = ok ? wy * (ur - uy) : (TA)0;
-        }
+        for (int j = 0; j < kPre; ++j)
+            val[j] = incoming_edge<TS, TA, TU>(L, z0, N, uz, v[j], eb + 64 * j, u, w);
 #pragma unroll
-        for (int j = 0; j < kPre; ++j) {
-            const unsigned e0 = eb + 64 * j;
-            if (e0 >= L.total) break;  // wave-uniform
-            const bool valid = e0 + lane < L.total;
-            const int row = valid ? (v[j] & 63) : 64;
-            TA x = val[j];
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const TA xu = __shfl_up(x, d, 64);
-                const int ru = __shfl_up(row, d, 64);
-                if (lane >= d && ru == row) x += xu;
-            }
-            const unsigned lo = L.lo > e0 ? L.lo : e0;
-            const unsigned hi = L.hi < e0 + 64 ? L.hi : e0 + 64;
-            const TA mine = __shfl(x, (int)((hi - 1 - e0) & 63u), 64);
-            if (hi > lo) acc += mine;
-        }
+        for (int j = 0; j < kPre; ++j) acc += incoming_reduce<TA>(L, v[j], val[j], eb + 64 * j);
     }
     return acc;
 }
 
-// One 256-point block of out = A u (STEP = false) or u - h A u (STEP = true);
-// blk is the block's index within its grid.  Shared by the single-operator
-// and the batched kernels, so both give bit-identical results.
+// One block of out = A u (STEP = false) or u - h A u (STEP = true): every
+// wave takes kApplyPPT consecutive groups of 64 rows (a block kApplyPoints
+// rows) and interleaves them -- all groups' own loads, then the entry loads
+// and gathers of the same chunk in every group, then the reductions -- so
+// several independent memory chains are in flight per wave.  blk is the
+// block's index within its grid.  Shared by the single-operator and the
+// batched kernels, so both give bit-identical results.
 template <int DIM, bool WIDE, bool PER, bool STEP, typename TS, typename TA>
 __device__ __forceinline__ void apply_block(
     const GridInfo &g, long long blk, const TS *__restrict__ u, TS *__restrict__ out,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
     const int32_t *__restrict__ ent, TA h) {
+    constexpr int P = kApplyPPT;
     const long long N = g.N;
-    const long long z = blk * kBS + threadIdx.x;
-    const bool live = z < N;
-    const WaveLists L = wave_lists(cnt, pos, z, N);
-    const TA uz = live ? Conv<TS, TA>::ld(u[z]) : (TA)0;
-    TA acc = wave_incoming<TS, TA, TS>(L, z, N, uz, u, w, ent);
-    if (!live) return;
-    acc += row_own<DIM, WIDE, PER, TS, TA, TS>(g, z, uz, u, sb, w);
-    out[z] = Conv<TS, TA>::st(STEP ? uz - h * acc : acc);
+    const int lane = (int)(threadIdx.x & 63u);
+    const long long zw = blk * kApplyPoints + (long long)(threadIdx.x >> 6) * (64 * P);
+    WaveLists L[P];
+    TA uz[P], acc[P];
+    OwnPart<DIM, WIDE, PER, TS, TA, TS> own[P];
+    unsigned tmax = 0;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const long long z = zw + 64 * k + lane;
+        L[k] = wave_lists(cnt, pos, z, N);
+        uz[k] = z < N ? Conv<TS, TA>::ld(u[z]) : (TA)0;
+        acc[k] = (TA)0;
+        tmax = L[k].total > tmax ? L[k].total : tmax;
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const long long z = zw + 64 * k + lane;
+        own[k].issue(g, z, z < N, uz[k], u, sb, w);
+    }
+    for (unsigned eb = 0; eb < tmax; eb += 64 * kPre) {
+        int32_t v[P][kPre];
+        TA val[P][kPre];
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int j = 0; j < kPre; ++j) {
+                const unsigned e = eb + 64 * j + lane;
+                v[k][j] = e < L[k].total ? ent[L[k].start + e] : -1;
+            }
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int j = 0; j < kPre; ++j)
+                val[k][j] = incoming_edge<TS, TA, TS>(L[k], zw + 64 * k, N, uz[k], v[k][j],
+                                                      eb + 64 * j, u, w);
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int j = 0; j < kPre; ++j)
+                acc[k] += incoming_reduce<TA>(L[k], v[k][j], val[k][j], eb + 64 * j);
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const long long z = zw + 64 * k + lane;
+        if (z >= N) continue;
+        const TA a = acc[k] + own[k].sum(uz[k]);
+        out[z] = Conv<TS, TA>::st(STEP ? uz[k] - h * a : a);
+    }
 }
 
 template <int DIM, bool WIDE, bool PER, bool STEP, typename TS, typename TA>
@@ -895,8 +1011,10 @@ __global__ __launch_bounds__(kBS) void k_copy_batch(const BatchProb *__restrict_
         else hi = mid - 1;
     }
     const BatchProb &P = probs[lo];
-    const long long z = (b - P.first_block) * kBS + threadIdx.x;
-    if (z < P.g.N) ((TS *)P.u[0])[z] = ((const TS *)P.u[1])[z];
+    for (int k = 0; k < kApplyPPT; ++k) {
+        const long long z = (b - P.first_block) * kApplyPoints + k * kBS + threadIdx.x;
+        if (z < P.g.N) ((TS *)P.u[0])[z] = ((const TS *)P.u[1])[z];
+    }
 }
 
 // Conjugate-gradient direction with K = I + dt A (dt from the state):
@@ -918,9 +1036,11 @@ __global__ __launch_bounds__(kBS) void k_cg_direction(
     const bool skip = st->bad || st->done;
     const WaveLists L = wave_lists(cnt, pos, z, N);
     const T zz = live ? zv[z] : (T)0;
+    OwnPart<DIM, WIDE, PER, T, T, T> own;
+    own.issue(g, z, live && !skip, zz, zv, sb, w);
     T acc = skip ? (T)0 : wave_incoming<T, T, T>(L, z, N, zz, zv, w, ent);
     if (live && !skip) {
-        acc += row_own<DIM, WIDE, PER, T, T, T>(g, z, zz, zv, sb, w);
+        acc += own.sum(zz);
         const T dt = (T)st->dt;
         const T beta = first ? (T)0 : (T)st->beta;
         const T qn = zz + dt * acc + (first ? (T)0 : beta * q[z]);
@@ -962,9 +1082,11 @@ __global__ __launch_bounds__(kBS) void k_residual(
     double r2 = 0.0;
     const WaveLists L = wave_lists(cnt, pos, z, N);
     const double xz = live ? x[z] : 0.0;
+    OwnPart<DIM, WIDE, PER, T, double, double> own;
+    own.issue(g, z, live, xz, x, sb, w);
     double ax = wave_incoming<T, double, double>(L, z, N, xz, x, w, ent);
     if (live) {
-        ax += row_own<DIM, WIDE, PER, T, double, double>(g, z, xz, x, sb, w);
+        ax += own.sum(xz);
         const double r = (double)b[z] - (xz + dt * ax);
         r2 = r * r;
         if (rout) rout[z] = (T)r;
@@ -1060,7 +1182,7 @@ int apply_impl(const adlbr_operator *op, const void *u, void *out, bool step, do
                hipStream_t s) {
     typedef typename Slots<DIM, WIDE>::store_t store_t;
     const GridInfo g = op->gi;
-    const unsigned nb = (unsigned)((g.N + kBS - 1) / kBS);
+    const unsigned nb = (unsigned)((g.N + kApplyPoints - 1) / kApplyPoints);
     if (step)
         hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, true, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)u, (TS *)out, (const store_t *)op->sb, (const TS *)op->w,
