@@ -46,7 +46,12 @@ ALGO_BYTES = {(2, 8): 16 + 3 * 8 + 4, (2, 4): 8 + 3 * 4 + 4, (2, 2): 4 + 3 * 2 +
 # counters read for the 1 GiB copy of --workload copy (FETCH x 2.0, WRITE
 # x 1.0), with the SHA-256 of the kernel sources they were taken on.  A
 # change to those sources makes the figure stale: traffic is then null.
-TRAFFIC = {}
+TRAFFIC = {
+    "c2": {"sha256": "d0e025076604f515219cc4e19e5de31c594d2e47c21e87cd0de8fbe3534a8669",
+           "bytes_per_launch": 222244049},
+    "c3": {"sha256": "d0e025076604f515219cc4e19e5de31c594d2e47c21e87cd0de8fbe3534a8669",
+           "bytes_per_launch": 4503009482},
+}
 TRAFFIC_SOURCES = ("paper_1301_3925_amd/csrc/operator.hip", "paper_1301_3925_amd/csrc/common.h")
 
 
@@ -276,7 +281,7 @@ def main():
                    "n": list(dims), "kappa": kappa, "explicit_steps": K, "seed": seed},
         "roofline": {"bound": "hbm", "kernel": f"k_apply (explicit step, {dim}D {sdt})",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for("c3") if (dim == 3 and sdt == "f32") else None,
                      "algo_bytes_per_point": ALGO_BYTES[(dim, esz)],
                      "avg_launch_us": round(step_s * 1e6, 3)},
     }
