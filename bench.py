@@ -77,8 +77,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "c5-3d", "copy"])
-    ap.add_argument("--train-steps", type=int, default=300)
+                    choices=["c1", "c2", "c3", "c3-precision", "c4", "c5", "c5-3d", "copy"])
+    ap.add_argument("--train-steps", type=int, default=1000)
+    ap.add_argument("--on-policy", action="store_true",
+                    help="c5: add flexible-CG residuals to the training pool half-way")
     ap.add_argument("--dtype", default=None, help="storage dtype for c3: f64|f32|bf16|f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
@@ -234,6 +236,8 @@ def main():
         return run_copy(args, dev, stream)
     if args.workload == "c4":
         return run_c4(args, dev, stream)
+    if args.workload == "c3-precision":
+        return run_precision(args, dev, stream)
     if args.workload in ("c5", "c5-3d"):
         run_c5(args, dev, stream)
         return
@@ -293,6 +297,60 @@ def main():
             Ds = synth.tensor3d_field(seed, (m, m, m), kappa)
             res["cpu_baseline"] = cpu_baseline_steps((m, m, m), Ds, synth.uniform(seed + 1, m ** 3), 10)
     print(json.dumps(res), flush=True)
+
+
+def run_precision(args, dev, stream):
+    """Precision variants on the 256^3 field (kappa <= 50): the same 200
+    explicit steps with u and the weights stored in FP64, FP32, BF16 and
+    FP16 (arithmetic in FP64 for FP64 storage, FP32 otherwise; offsets and
+    the stencil build always FP64).  Reports each variant's step rate and its
+    relative L2 difference to the FP64 run (the FP64 GPU path itself matches
+    the FP64 oracle to 1e-12 in the parity tests)."""
+    import numpy as np
+    import torch
+    import paper_1301_3925_amd as adlbr
+    from paper_1301_3925_amd import synth
+    dims, kappa, seed = (256, 256, 256), 50.0, 1303
+    K = args.steps if args.steps is not None else 200
+    N = int(np.prod(dims))
+    D = synth.tensor3d_field(seed, dims, kappa)
+    off, w, st = adlbr.build_stencils(torch.from_numpy(D).to(dev), dims)
+    del D
+    u0 = synth.uniform(seed + 1, N)
+    out, ref = {}, None
+    for sdt, tdt in (("f64", torch.float64), ("f32", torch.float32), ("bf16", torch.bfloat16),
+                     ("f16", torch.float16)):
+        op = adlbr.Operator(dims, off, w, storage=tdt)
+        u = torch.from_numpy(u0).to(tdt).to(dev)
+        tmp = torch.empty_like(u)
+        op.step(u, 0.9, 1, cfl_fraction=True, u_tmp=tmp)  # warm-up
+        u.copy_(torch.from_numpy(u0).to(tdt).to(dev))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        op.step(u, 0.9, K, cfl_fraction=True, u_tmp=tmp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        step_s = e0.elapsed_time(e1) / 1e3 / K
+        res = u.double()
+        if ref is None:
+            ref = res
+        err = float((res - ref).norm() / ref.norm())
+        esz = torch.tensor([], dtype=tdt).element_size()
+        out[sdt] = {"Mpoint_steps_per_s": round(N / step_s / 1e6, 1),
+                    "us_per_step": round(step_s * 1e6, 1),
+                    "rel_l2_vs_f64": err,
+                    "hbm_frac": round(ALGO_BYTES[(3, esz)] * N / step_s / 1e9 / PEAK_HBM_GBS, 4)}
+        del op, u, tmp
+        torch.cuda.empty_cache()
+    print(json.dumps({
+        "metric": "Mpoint-steps/s", "value": out["f32"]["Mpoint_steps_per_s"],
+        "unit": "Mpoint-steps/s", "n_gpus": 1, "steps": K, "warmup": 1,
+        "ms_per_step": round(out["f32"]["us_per_step"] / 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "explicit3d-256^3-precision-variants", "n": list(dims),
+                   "kappa": kappa, "explicit_steps": K, "seed": seed},
+        "precision": out}), flush=True)
 
 
 def run_c4(args, dev, stream):
@@ -437,7 +495,8 @@ def run_c5(args, dev, stream):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     net, hist = adlbr.train_net(op, dt, rhs_seeds=range(2001, 2017), steps=args.train_steps,
-                                batch=4, lr=3e-3, seed=0, log_every=50)
+                                batch=4, lr=3e-3, seed=0, log_every=100,
+                                on_policy=args.on_policy)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     _, rt, tt = timed("fcg", net)
@@ -455,7 +514,7 @@ def run_c5(args, dev, stream):
         "fcg_trained": {"iters": rt["iters"], "ms": round(tt * 1e3, 3),
                         "fell_back": rt["fell_back"], "rel_res": rt["rel_res"]},
         "training": {"seconds": round(t_train, 2), "steps": args.train_steps, "batch": 4,
-                     "loss": hist},
+                     "on_policy": bool(args.on_policy), "loss": hist},
         "speedup_vs_jacobi": round(tj / tt, 3),
     }
     print(json.dumps(res), flush=True)

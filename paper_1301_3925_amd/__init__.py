@@ -422,12 +422,14 @@ def adam(params, grads, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=
 
 def train_net(op: "Operator", dt: float, rhs_seeds, steps: int = 400, batch: int = 4,
               lr: float = 2e-3, seed: int = 0, snapshot_iters=(1, 2, 4, 8, 16, 32),
-              log_every: int = 0):
+              log_every: int = 0, on_policy: bool = False):
     """Train the preconditioner on residuals the solver itself generates:
     for each right-hand side, Jacobi-PCG stopped after k iterations leaves a
     residual r_k = b - K x_k (adlbr_residual); each Adam step takes `batch`
     of them, minimizes the energy loss (adlbr_net_loss_grad) through the
-    network's own backward kernels and updates with adlbr_net_adam.
+    network's own backward kernels and updates with adlbr_net_adam.  With
+    on_policy, half-way through the residuals of flexible CG with the
+    network as it stands (stopped after the same k) join the pool.
     Returns (net, history of losses)."""
     import numpy as np
     from . import synth
@@ -453,6 +455,14 @@ def train_net(op: "Operator", dt: float, rhs_seeds, steps: int = 400, batch: int
     rng = np.random.Generator(np.random.PCG64(seed + 7))
     hist = []
     for it in range(1, steps + 1):
+        if on_policy and it == steps // 2 + 1:
+            more = []
+            for sd in rhs_seeds:
+                b = torch.from_numpy(synth.uniform(sd, op.N)).float().to(dev)
+                for k in snapshot_iters:
+                    x, _ = op.solve(b, dt, method="fcg", net=net, max_iter=k, check_every=k)
+                    more.append(residual(op, b, x, dt))
+            R = torch.cat([R, torch.stack(more)])
         idx = rng.choice(R.shape[0], size=batch, replace=False)
         gparams.zero_()
         ggates.zero_()

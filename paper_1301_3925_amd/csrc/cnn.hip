@@ -22,7 +22,8 @@ namespace adlbr {
 
 int apply_K(const adlbr_operator *op, const void *u, void *out, double dt, hipStream_t s);
 int net_apply_mfma(const adlbr_net *net, const adlbr_operator *op, const float *r, float *z,
-                   hipStream_t s);
+                   const float *rp, double *part, hipStream_t s);
+int net_mfma_blocks(int nx, int ny);
 int net_pack_mfma(const adlbr_net *net, hipStream_t s);
 
 namespace {
@@ -405,6 +406,84 @@ __global__ __launch_bounds__(kBS) void k_conv_bwd_w(GridInfo g, const float *__r
     if ((int)threadIdx.x < COUT) outp[COUT * CIN * T + threadIdx.x] = accb;
 }
 
+// 2D weight gradient on the matrix cores: the same sums as k_conv_bwd_w for
+// 3x3 layers, dW[co][ci][t] = sum_p ga[co](p) x_ci(p + off_t), as GEMMs
+// D_t[co][ci] += A[co][4 points] B_t[4 points][ci] with
+// v_mfma_f32_16x16x4f32 (FP32 operands and accumulation).  Each block
+// walks 16x16 tiles of points: ga on the tile and x on the tile plus a
+// one-point halo (0 outside the grid) are staged in LDS, then every wave
+// takes a quarter of the tile's 64 four-point steps for all 9 taps.  The
+// four waves' results are summed in LDS in a fixed order and written as
+// this block's partials (same layout as k_conv_bwd_w).
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_bwd_w2d_mfma(GridInfo g, const float *__restrict__ in,
+                                                           const float *__restrict__ in_gate,
+                                                           int relu_in,
+                                                           const float *__restrict__ ga,
+                                                           float *__restrict__ partials) {
+    constexpr int TW = 16, HW = TW + 2, T = 9;
+    __shared__ float sx[CIN * HW * HW];
+    __shared__ float sg[COUT * TW * TW];
+    __shared__ float red[4][COUT * CIN * T + COUT];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nx = g.nx, ny = g.ny;
+    const int ntx = (nx + TW - 1) / TW, nty = (ny + TW - 1) / TW;
+    const int i = lane & 15, kk = lane >> 4;  // A row (co) / B column (ci), k
+    f32x4v acc[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    float accb = 0.f;  // bias: sum of ga[co = i] over this lane's points
+    for (int tile = blockIdx.x; tile < ntx * nty; tile += gridDim.x) {
+        const int x0 = (tile % ntx) * TW, y0 = (tile / ntx) * TW;
+        __syncthreads();
+        for (int e = tid; e < CIN * HW * HW; e += 256) {
+            const int ci = e / (HW * HW), q = e % (HW * HW);
+            const int gx = x0 - 1 + q % HW, gy = y0 - 1 + q / HW;
+            float v = 0.f;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                const long long k = (long long)gy * nx + gx;
+                v = in[ci * g.N + k];
+                if (in_gate) v *= in_gate[ci * g.N + k];
+                if (relu_in) v = fmaxf(v, 0.f);
+            }
+            sx[e] = v;
+        }
+        for (int e = tid; e < COUT * TW * TW; e += 256) {
+            const int co = e / (TW * TW), q = e % (TW * TW);
+            const int gx = x0 + q % TW, gy = y0 + q / TW;
+            sg[e] = (gx < nx && gy < ny) ? ga[co * g.N + (long long)gy * nx + gx] : 0.f;
+        }
+        __syncthreads();
+        for (int ks = wave; ks < TW * TW / 4; ks += 4) {
+            const int p = ks * 4 + kk, py = p / TW, px = p % TW;
+            const float a = i < COUT ? sg[i * TW * TW + p] : 0.f;
+            accb += a;
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const float b = i < CIN ? sx[i * HW * HW + (py + t / 3) * HW + (px + t % 3)] : 0.f;
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // D: lane holds D[co = 4 (lane >> 4) + c][ci = lane & 15]
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int co = 4 * kk + c, ci = i;
+            if (co < COUT && ci < CIN) red[wave][(co * CIN + ci) * T + t] = acc[t][c];
+        }
+    // bias: lanes with the same co (i) hold disjoint point sets
+    for (int d = 16; d < 64; d <<= 1) accb += __shfl_xor(accb, d, 64);
+    if (kk == 0 && i < COUT) red[wave][COUT * CIN * T + i] = accb;
+    __syncthreads();
+    constexpr int stride = COUT * CIN * T + COUT;
+    for (int e = tid; e < stride; e += 256)
+        partials[(long long)blockIdx.x * stride + e] =
+            ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+}
+
 // grad[k] += sum over blocks of partials[b][k] (block order: deterministic);
 // weights go to gW[0 .. nw), biases (the last nb entries) to gb (if given).
 __global__ void k_reduce_partials(const float *partials, int nblocks, int stride, int nw,
@@ -545,8 +624,13 @@ int bwd_w_launch(const GridInfo &g, int cin, int cout, int taps, const float *in
                  float *gb, hipStream_t s) {
 #define ADLBR_BW(CI, CO, PPT)                                                                 \
     if (cin == CI && cout == CO) {                                                            \
-        hipLaunchKernelGGL((k_conv_bwd_w<DIM, CI, CO, PPT>), dim3(kWgBlocks), dim3(kBS), 0, s, \
-                           g, in, in_gate, relu_in, ga, partials, taps);                      \
+        if (DIM == 2 && taps == 9 && CI <= 16 && CO <= 16)                                    \
+            hipLaunchKernelGGL((k_conv_bwd_w2d_mfma<CI, (CO <= 16 ? CO : 16)>),               \
+                               dim3(kWgBlocks), dim3(kBS), 0, s, g, in, in_gate, relu_in, ga, \
+                               partials);                                                     \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_conv_bwd_w<DIM, CI, CO, PPT>), dim3(kWgBlocks), dim3(kBS),  \
+                               0, s, g, in, in_gate, relu_in, ga, partials, taps);            \
         const int stride = CO * CI * taps + CO;                                               \
         hipLaunchKernelGGL(k_reduce_partials, dim3((stride + kBS - 1) / kBS), dim3(kBS), 0, s,  \
                            partials, kWgBlocks, stride, CO * CI * taps, gW, gb);              \
@@ -618,7 +702,8 @@ int net_apply(const adlbr_net *net, const adlbr_operator *op, double dt, const v
         set_error("net: the operator's storage must be ADLBR_F32");
         return ADLBR_E_UNSUPPORTED;
     }
-    if (d.dim == 2 && net->gates8) return net_apply_mfma(net, op, (const float *)r, (float *)z, s);
+    if (d.dim == 2 && net->gates8)
+        return net_apply_mfma(net, op, (const float *)r, (float *)z, nullptr, nullptr, s);
     if (!net->scratch) {
         set_error("net: the FP32 inference path needs net->scratch ([2W][N] FP32)");
         return ADLBR_E_INVALID;
@@ -627,6 +712,41 @@ int net_apply(const adlbr_net *net, const adlbr_operator *op, double dt, const v
     float *A = net->scratch, *B = net->scratch + 16 * N;
     return d.dim == 2 ? forward_impl<2>(op, net, d, (const float *)r, (float *)z, nullptr, A, B, s)
                       : forward_impl<3>(op, net, d, (const float *)r, (float *)z, nullptr, A, B, s);
+}
+
+namespace {
+// Partials of <z, r> and <z, rp> (rp may be null) over 256-point blocks.
+__global__ __launch_bounds__(kBS) void k_dots2(long long N, const float *__restrict__ z,
+                                               const float *__restrict__ r,
+                                               const float *__restrict__ rp, double *part) {
+    const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (i < N) {
+        const double zi = (double)z[i];
+        a = zi * (double)r[i];
+        if (rp) b = zi * (double)rp[i];
+    }
+    block_partial_sum(a, part);
+    block_partial_sum(b, part + gridDim.x);
+}
+}  // namespace
+
+int net_apply_dots(const adlbr_net *net, const adlbr_operator *op, const float *r,
+                   const float *rp, float *z, double *part, long long *nparts, hipStream_t s) {
+    NetDims d;
+    int rc = check_net(op, net, &d);
+    if (rc) return rc;
+    const GridInfo &g = operator_grid(op);
+    if (d.dim == 2 && net->gates8 && operator_storage(op) == ADLBR_F32) {
+        *nparts = net_mfma_blocks(g.nx, g.ny);
+        return net_apply_mfma(net, op, r, z, rp, part, s);
+    }
+    rc = net_apply(net, op, 0.0, r, z, s);
+    if (rc) return rc;
+    *nparts = nblk(g.N);
+    hipLaunchKernelGGL(k_dots2, dim3((unsigned)*nparts), dim3(kBS), 0, s, g.N, (const float *)z, r,
+                       rp, part);
+    return ADLBR_OK;
 }
 
 }  // namespace adlbr

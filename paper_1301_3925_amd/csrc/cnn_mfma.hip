@@ -8,10 +8,10 @@
 // tile plus halo.  Every layer runs on the matrix cores as an implicit GEMM
 // with v_mfma_f32_16x16x16_bf16 (BF16 operands, FP32 accumulation), one
 // 16-pixel group per instruction:
-//   layer 1 (1 -> 16):  A[16 px][16 k = taps 0..8, zero-padded] x B[k][co]
-//   layers 2, 3:        sum over the 9 taps of A_t[16 px][16 ci] x B_t[ci][co]
-//   layer 4 (16 -> 1):  the same with only column co = 0 of B_t non-zero.
-// The B operands come pre-packed per lane from adlbr_net_gates.  The gates
+//   layer 1 (1 -> 16):  D[co][16 px] = W1[co][16 k = taps 0..8, zero-padded] X[k][px]
+//   layers 2, 3:        sum over the 9 taps of W_t[co][16 ci] X_t[ci][16 px]
+//   layer 4 (16 -> 1):  the same with only row co = 0 of W_t non-zero.
+// The weight operands come pre-packed per lane from adlbr_net_gates.  The gates
 // g1, g2 are 8-bit fixed point (g = q / 255, so they stay >= 0 and N stays
 // positive semi-definite), staged in LDS once per tile.  Activations are
 // stored as BF16 with a 40-byte pixel stride, which makes the 8-byte
@@ -34,7 +34,7 @@ constexpr int kR2 = kT + 4;   // layer-2 output edge (20), also the g2 region
 constexpr int kR3 = kT + 2;   // layer-3 output edge (18)
 constexpr int kG = 32;        // gate bytes per point (g1, g2)
 
-// packed B operands: [layer 1: 64 lanes][layer 2: 9 x 64][layer 3: 9 x 64][layer 4: 9 x 64]
+// packed weight operands: [layer 1: 64 lanes][layer 2: 9 x 64][layer 3: 9 x 64][layer 4: 9 x 64]
 constexpr int kPack1 = 0, kPack2 = 64, kPack3 = 64 + 9 * 64, kPack4 = 64 + 18 * 64;
 constexpr int kPackEntries = 64 + 27 * 64;
 
@@ -54,10 +54,24 @@ template <int R> struct Px {
     }
 };
 
+// Store four channels c0 .. c0 + 3 of one pixel, each times its 8-bit
+// gate (g4 holds the four gate bytes), as BF16 (one 8-byte LDS write).
+__device__ __forceinline__ void store4(short *dst, f32x4 d, uint32_t g4, bool zero) {
+    float v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = zero ? 0.f : d[c] * q8((g4 >> (8 * c)) & 0xffu);
+    const uint32_t lo = (uint16_t)bfbits(v[0]) | ((uint32_t)(uint16_t)bfbits(v[1]) << 16);
+    const uint32_t hi = (uint16_t)bfbits(v[2]) | ((uint32_t)(uint16_t)bfbits(v[3]) << 16);
+    *(uint2 *)dst = make_uint2(lo, hi);
+}
+
 // One MFMA layer 16 -> 16: input region edge RI (LDS in), output edge RO;
 // output gates from sg (LDS, pixel-major [GR * GR][16]; the output region
-// sits at offset GO inside the gate region).  EDGE: the tile touches the
-// grid boundary, so outputs outside the grid are set to 0.
+// sits at offset GO inside the gate region).  The product is taken as
+// D[co][px] = W[co][ci] X[ci][px] (weights as the A operand, activations as
+// B), so each lane ends with four consecutive channels of one pixel: one
+// 4-byte gate read and one 8-byte store.  EDGE: the tile touches the grid
+// boundary, so outputs outside the grid are set to 0.
 template <int RI, int RO, int GR, int GO, bool EDGE>
 __device__ __forceinline__ void mfma_layer(const short *__restrict__ sin, short *__restrict__ sout,
                                            const bf16x4 *wb, int gx0, int gy0, int nx, int ny,
@@ -65,104 +79,133 @@ __device__ __forceinline__ void mfma_layer(const short *__restrict__ sin, short 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int npx = RO * RO;
     constexpr int ngroups = (npx + 15) / 16;
-    const int i_row = lane & 15;        // A row / D column index
-    const int kq = (lane >> 4) * 4;     // channel quad of A, pixel quad of D
-    const int co = lane & 15;
+    const int n = lane & 15;            // B column / D column: the pixel in the group
+    const int kq = (lane >> 4) * 4;     // channel quad of B (ci) and of D (co)
     for (int grp = wave; grp < ngroups; grp += 4) {
-        const int pa = grp * 16 + i_row;            // this lane's A pixel
+        const int pa = grp * 16 + n;    // this lane's pixel
         const bool va = pa < npx;
         const Px<RO> pxa(va ? pa : 0);
         const short *base = sin + (pxa.y * RI + pxa.x) * kStride + kq;
         f32x4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            bf16x4 a = *(const bf16x4 *)(base + ((t / 3) * RI + (t % 3)) * kStride);
-            if (!va) a = bf16x4{0, 0, 0, 0};
-            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, wb[t], d, 0, 0, 0);
+            bf16x4 b = *(const bf16x4 *)(base + ((t / 3) * RI + (t % 3)) * kStride);
+            if (!va) b = bf16x4{0, 0, 0, 0};
+            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wb[t], b, d, 0, 0, 0);
         }
-        // D: column co, rows (pixels) p0 .. p0 + 3
-        const int p0 = grp * 16 + kq;
-        Px<RO> q(p0 < npx ? p0 : 0);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (p0 + c < npx) {
-                float v = d[c] * q8(sg[((q.y + GO) * GR + (q.x + GO)) * 16 + co]);
-                if (EDGE) {
-                    const int gx = gx0 + q.x, gy = gy0 + q.y;
-                    if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) v = 0.f;
-                }
-                sout[(p0 + c) * kStride + co] = bfbits(v);
-            }
-            q.next();
+        if (!va) continue;
+        const uint32_t g4 = *(const uint32_t *)(sg + ((pxa.y + GO) * GR + (pxa.x + GO)) * 16 + kq);
+        bool zero = false;
+        if (EDGE) {
+            const int gx = gx0 + pxa.x, gy = gy0 + pxa.y;
+            zero = gx < 0 || gx >= nx || gy < 0 || gy >= ny;
         }
+        store4(sout + pa * kStride + kq, d, g4, zero);
     }
 }
 
-template <bool EDGE>
-__device__ __forceinline__ void net_tile(int nx, int ny, const float *__restrict__ r,
-                                         const float *__restrict__ F0,
-                                         const uint8_t *__restrict__ G8,
-                                         const bf16x4 *__restrict__ wpack, float *__restrict__ z,
-                                         float *sr, uint8_t *sg1, uint8_t *sg2, short *s13,
-                                         short *s2) {
-    const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    auto inside = [&](int gx, int gy) {
-        return !EDGE || (gx >= 0 && gx < nx && gy >= 0 && gy < ny);
-    };
-    // r on the 24x24 region, 0 outside the grid; g1 on 22x22, g2 on 20x20
-    for (int k = tid; k < kR0 * kR0; k += 256) {
-        const int gx = x0 - 4 + k % kR0, gy = y0 - 4 + k / kR0;
-        sr[k] = inside(gx, gy) ? r[gy * nx + gx] : 0.f;
+// Inputs of one tile, fetched into registers ahead of time: r on the 24x24
+// region (0 outside the grid), g1 on 22x22 and g2 on 20x20 (16 bytes each).
+constexpr int kRPer = (kR0 * kR0 + 255) / 256;                  // r values per thread
+constexpr int kGPer = (kR1 * kR1 + kR2 * kR2 + 255) / 256;      // gate vectors per thread
+struct TileIn {
+    float r[kRPer];
+    uint4 g[kGPer];
+    float rp;  // r_prev at this thread's pixel of the 16x16 tile (fused dots)
+};
+
+__device__ __forceinline__ void fetch_tile(int x0, int y0, int nx, int ny,
+                                           const float *__restrict__ r,
+                                           const uint8_t *__restrict__ G8,
+                                           const float *__restrict__ rp, TileIn &in) {
+    const int tid = threadIdx.x;
+    {
+        const int gx = x0 + tid % kT, gy = y0 + tid / kT;
+        in.rp = (rp && gx < nx && gy < ny) ? rp[gy * nx + gx] : 0.f;
     }
-    for (int k = tid; k < kR1 * kR1 + kR2 * kR2; k += 256) {
+#pragma unroll
+    for (int j = 0; j < kRPer; ++j) {
+        const int k = tid + 256 * j;
+        const int gx = x0 - 4 + k % kR0, gy = y0 - 4 + k / kR0;
+        in.r[j] = (k < kR0 * kR0 && gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? r[gy * nx + gx]
+                                                                              : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < kGPer; ++j) {
+        const int k = tid + 256 * j;
         const bool first = k < kR1 * kR1;
         const int kk = first ? k : k - kR1 * kR1;
         const int R = first ? kR1 : kR2, h = first ? 3 : 2;
         const int gx = x0 - h + kk % R, gy = y0 - h + kk / R;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (inside(gx, gy)) v = ((const uint4 *)(G8 + (gy * nx + gx) * kG))[first ? 0 : 1];
-        ((uint4 *)(first ? sg1 : sg2))[kk] = v;
+        if (k < kR1 * kR1 + kR2 * kR2 && gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+            v = ((const uint4 *)(G8 + (gy * nx + gx) * kG))[first ? 0 : 1];
+        in.g[j] = v;
     }
-    // B operands, packed per lane
-    const bf16x4 wb1 = wpack[kPack1 + lane];
-    bf16x4 wb2[9], wb3[9], wb4[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        wb2[t] = wpack[kPack2 + t * 64 + lane];
-        wb3[t] = wpack[kPack3 + t * 64 + lane];
-        wb4[t] = wpack[kPack4 + t * 64 + lane];
-    }
-    __syncthreads();
+}
 
-    // layer 1 (1 -> 16) on 22x22: A row = pixel, k = tap (4 per lane quad)
+__device__ __forceinline__ void stage_tile(const TileIn &in, float *sr, uint8_t *sg1, uint8_t *sg2,
+                                           float *srp) {
+    const int tid = threadIdx.x;
+    srp[tid] = in.rp;
+#pragma unroll
+    for (int j = 0; j < kRPer; ++j) {
+        const int k = tid + 256 * j;
+        if (k < kR0 * kR0) sr[k] = in.r[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kGPer; ++j) {
+        const int k = tid + 256 * j;
+        if (k < kR1 * kR1) ((uint4 *)sg1)[k] = in.g[j];
+        else if (k < kR1 * kR1 + kR2 * kR2) ((uint4 *)sg2)[k - kR1 * kR1] = in.g[j];
+    }
+}
+
+// The four layers of one staged tile at (x0, y0).  EDGE: the tile's input
+// region leaves the grid, so outputs outside the grid are zeroed.
+template <bool EDGE>
+__device__ __forceinline__ void net_tile(int x0, int y0, int nx, int ny,
+                                         const float *__restrict__ F0, float *__restrict__ z,
+                                         const float *__restrict__ rp, double &zr, double &zrp,
+                                         const bf16x4 &wb1, const bf16x4 *wb2, const bf16x4 *wb3,
+                                         const bf16x4 *wb4, const float *sr, const uint8_t *sg1,
+                                         const uint8_t *sg2, short *s13, short *s2,
+                                         const float *srp) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    auto inside = [&](int gx, int gy) {
+        return !EDGE || (gx >= 0 && gx < nx && gy >= 0 && gy < ny);
+    };
+    // 1 / diag K at the output pixels of this lane in layer 4 (tile rows
+    // wave, wave + 4, ...; lanes 0..15), loaded now so the load overlaps
+    // layers 1-3
+    float f0v[kT / 4];
+#pragma unroll
+    for (int j = 0; j < kT / 4; ++j) {
+        const int gx = x0 + (lane & 15), gy = y0 + wave + 4 * j;
+        f0v[j] = (lane < 16 && (!EDGE || (gx < nx && gy < ny))) ? F0[gy * nx + gx] : 0.f;
+    }
+
+    // layer 1 (1 -> 16) on 22x22: D[co][px] = W1[co][tap] X[tap][px], the
+    // taps (4 per lane quad, 9..15 zero) as the K dimension
     {
         constexpr int npx = kR1 * kR1;
-        const int i_row = lane & 15, kq = (lane >> 4) * 4, co = lane & 15;
+        const int n = lane & 15, kq = (lane >> 4) * 4;
         for (int grp = wave; grp < (npx + 15) / 16; grp += 4) {
-            const int pa = grp * 16 + i_row;
+            const int pa = grp * 16 + n;
             const bool va = pa < npx;
             const Px<kR1> pxa(va ? pa : 0);
             const float *rb = sr + pxa.y * kR0 + pxa.x;
-            bf16x4 a;
+            bf16x4 b;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const int t = kq + c;  // taps 9..15 and pixels past the end are 0
-                a[c] = (va && t < 9) ? bfbits(rb[(t / 3) * kR0 + (t % 3)]) : (short)0;
+                const int t = kq + c;
+                b[c] = (va && t < 9) ? bfbits(rb[(t / 3) * kR0 + (t % 3)]) : (short)0;
             }
             f32x4 d = {0.f, 0.f, 0.f, 0.f};
-            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, wb1, d, 0, 0, 0);
-            const int p0 = grp * 16 + kq;
-            Px<kR1> q(p0 < npx ? p0 : 0);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (p0 + c < npx) {
-                    float v = d[c] * q8(sg1[(p0 + c) * 16 + co]);
-                    if (!inside(x0 - 3 + q.x, y0 - 3 + q.y)) v = 0.f;
-                    s13[(p0 + c) * kStride + co] = bfbits(v);
-                }
-                q.next();
-            }
+            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wb1, b, d, 0, 0, 0);
+            if (!va) continue;
+            const uint32_t g4 = *(const uint32_t *)(sg1 + pa * 16 + kq);
+            store4(s13 + pa * kStride + kq, d, g4, !inside(x0 - 3 + pxa.x, y0 - 3 + pxa.y));
         }
     }
     __syncthreads();
@@ -171,58 +214,107 @@ __device__ __forceinline__ void net_tile(int nx, int ny, const float *__restrict
     mfma_layer<kR2, kR3, kR1, 2, EDGE>(s2, s13, wb3, x0 - 1, y0 - 1, nx, ny, sg1);
     __syncthreads();
 
-    // layer 4 (16 -> 1, no gate) on the 16x16 tile; column 0 of D is the
-    // output, then z = r / diag K + N(r)
+    // layer 4 (16 -> 1, no gate) on the 16x16 tile: D[co][px] with only row
+    // co = 0 of the weights non-zero, so lanes 0..15 (c = 0) hold the 16
+    // pixels of a tile row; then z = r / diag K + N(r)
     {
-        const int i_row = lane & 15, kq = (lane >> 4) * 4;
-        for (int grp = wave; grp < (kT * kT) / 16; grp += 4) {
-            // group grp = one tile row: pixels (grp, 0..15)
-            const short *base = s13 + (grp * kR3 + i_row) * kStride + kq;
+        const int n = lane & 15, kq = (lane >> 4) * 4;
+#pragma unroll
+        for (int j = 0; j < kT / 4; ++j) {
+            const int grp = wave + 4 * j;  // group grp = one tile row: pixels (grp, 0..15)
+            const short *base = s13 + (grp * kR3 + n) * kStride + kq;
             f32x4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
-                const bf16x4 a = *(const bf16x4 *)(base + ((t / 3) * kR3 + (t % 3)) * kStride);
-                d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, wb4[t], d, 0, 0, 0);
+                const bf16x4 b = *(const bf16x4 *)(base + ((t / 3) * kR3 + (t % 3)) * kStride);
+                d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wb4[t], b, d, 0, 0, 0);
             }
-            if ((lane & 15) == 0) {
-                const int gy = y0 + grp;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int gx = x0 + kq + c;
-                    if (!EDGE || (gx < nx && gy < ny)) {
-                        const int gi = gy * nx + gx;
-                        z[gi] = sr[(grp + 4) * kR0 + (kq + c + 4)] * F0[gi] + d[c];
-                    }
+            if (lane < 16) {
+                const int gx = x0 + n, gy = y0 + grp;
+                if (!EDGE || (gx < nx && gy < ny)) {
+                    const int gi = gy * nx + gx;
+                    const float rv = sr[(grp + 4) * kR0 + (n + 4)];
+                    const float zv = rv * f0v[j] + d[0];
+                    z[gi] = zv;
+                    zr += (double)zv * (double)rv;
+                    if (rp) zrp += (double)zv * (double)srp[grp * kT + n];
                 }
             }
         }
     }
 }
 
+// Persistent over tiles: every block loads the packed weights once, and
+// while it computes one tile the next tile's inputs are already in flight
+// into registers (fetch_tile), then staged into LDS (stage_tile).
+// With part given, the kernel also leaves the flexible-CG dot products
+// <z, r> and <z, rp> (rp may be null) as per-block FP64 partials:
+// part[blockIdx.x] and part[gridDim.x + blockIdx.x].
 __global__ __launch_bounds__(256) void k_net2d_fused(int nx, int ny, const float *__restrict__ r,
                                                      const float *__restrict__ F0,
                                                      const uint8_t *__restrict__ G8,
                                                      const bf16x4 *__restrict__ wpack,
-                                                     float *__restrict__ z) {
-    __shared__ float sr[kR0 * kR0];
+                                                     float *__restrict__ z,
+                                                     const float *__restrict__ rp,
+                                                     double *__restrict__ part) {
+    __shared__ __attribute__((aligned(16))) float sr[kR0 * kR0];
     __shared__ __attribute__((aligned(16))) uint8_t sg1[kR1 * kR1 * 16];
     __shared__ __attribute__((aligned(16))) uint8_t sg2[kR2 * kR2 * 16];
     // layer 1 output, later layer 3 output (s1 is dead once layer 2 has run)
     __shared__ __attribute__((aligned(16))) short s13[kR1 * kR1 * kStride];
     __shared__ __attribute__((aligned(16))) short s2[kR2 * kR2 * kStride];
-    const int x0 = blockIdx.x * kT, y0 = blockIdx.y * kT;
-    // interior tiles (the 24x24 input region inside the grid) skip every
-    // bounds check; the branch is uniform over the block
-    if (x0 >= 4 && y0 >= 4 && x0 + kT + 4 <= nx && y0 + kT + 4 <= ny)
-        net_tile<false>(nx, ny, r, F0, G8, wpack, z, sr, sg1, sg2, s13, s2);
-    else
-        net_tile<true>(nx, ny, r, F0, G8, wpack, z, sr, sg1, sg2, s13, s2);
+    __shared__ float srp[kT * kT];
+    const int lane = threadIdx.x & 63;
+    const int ntx = (nx + kT - 1) / kT, ntiles = ntx * ((ny + kT - 1) / kT);
+    // weight operands, packed per lane
+    const bf16x4 wb1 = wpack[kPack1 + lane];
+    bf16x4 wb2[9], wb3[9], wb4[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        wb2[t] = wpack[kPack2 + t * 64 + lane];
+        wb3[t] = wpack[kPack3 + t * 64 + lane];
+        wb4[t] = wpack[kPack4 + t * 64 + lane];
+    }
+    TileIn in;
+    double zr = 0.0, zrp = 0.0;
+    int tile = blockIdx.x;
+    if (tile < ntiles) fetch_tile((tile % ntx) * kT, (tile / ntx) * kT, nx, ny, r, G8, rp, in);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int x0 = (tile % ntx) * kT, y0 = (tile / ntx) * kT;
+        __syncthreads();  // the previous tile is done with the LDS buffers
+        stage_tile(in, sr, sg1, sg2, srp);
+        const int next = tile + gridDim.x;
+        if (next < ntiles) fetch_tile((next % ntx) * kT, (next / ntx) * kT, nx, ny, r, G8, rp, in);
+        __syncthreads();
+        // interior tiles (the 24x24 input region inside the grid) skip every
+        // bounds check; the branch is uniform over the block
+        if (x0 >= 4 && y0 >= 4 && x0 + kT + 4 <= nx && y0 + kT + 4 <= ny)
+            net_tile<false>(x0, y0, nx, ny, F0, z, rp, zr, zrp, wb1, wb2, wb3, wb4, sr, sg1, sg2,
+                            s13, s2, srp);
+        else
+            net_tile<true>(x0, y0, nx, ny, F0, z, rp, zr, zrp, wb1, wb2, wb3, wb4, sr, sg1, sg2,
+                           s13, s2, srp);
+    }
+    if (part) {  // block sums of the dots, in sr's storage (fixed order)
+        double *red = (double *)sr;  // 256 doubles fit in the 24 x 24 floats
+        for (int k = 0; k < 2; ++k) {
+            __syncthreads();
+            red[threadIdx.x] = k ? zrp : zr;
+            __syncthreads();
+            for (int st = 128; st > 0; st >>= 1) {
+                if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) part[k * gridDim.x + blockIdx.x] = red[0];
+        }
+    }
 }
 
-// Pack the B operands (expanded weights L1..L4) as BF16 in lane order: for
-// layers 2 and 3 lane holds W[co = lane & 15][ci = 4 (lane >> 4) + c][t];
-// for layer 1 W1[co = lane & 15][tap = 4 (lane >> 4) + c] (taps >= 9 are 0);
-// for layer 4 W4[ci = 4 (lane >> 4) + c][t] in column co = 0 only.
+// Pack the weight operands (expanded weights L1..L4, the A operands of
+// D = W X) as BF16 in lane order: for layers 2 and 3 lane holds
+// W[co = lane & 15][ci = 4 (lane >> 4) + c][t]; for layer 1
+// W1[co = lane & 15][tap = 4 (lane >> 4) + c] (taps >= 9 are 0); for layer 4
+// W4[ci = 4 (lane >> 4) + c][t] in row co = 0 only.
 __global__ void k_pack_mfma(const float *__restrict__ L1, const float *__restrict__ L2,
                             const float *__restrict__ L3, const float *__restrict__ L4,
                             bf16x4 *__restrict__ out) {
@@ -240,7 +332,7 @@ __global__ void k_pack_mfma(const float *__restrict__ L1, const float *__restric
         const float *W = second ? L3 : L2;
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[c] = bfbits(W[(co * 16 + k0 + c) * 9 + t]);
-    } else {
+    } else {  // A[co = lane & 15][ci = 4 (lane >> 4) + c], only row co = 0 non-zero
         const int t = (e - kPack4) / 64;
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[c] = co == 0 ? bfbits(L4[(k0 + c) * 9 + t]) : (short)0;
@@ -262,13 +354,19 @@ int net_pack_mfma(const adlbr_net *net, hipStream_t s) {
     return ADLBR_OK;
 }
 
+// Blocks of the persistent inference grid for a grid of nx x ny points.
+int net_mfma_blocks(int nx, int ny) {
+    const int ntiles = ((nx + kT - 1) / kT) * ((ny + kT - 1) / kT);
+    // three 51 KB blocks fit one CU's LDS: a persistent grid of 3 per CU
+    return ntiles < 3 * 256 ? ntiles : 3 * 256;
+}
+
 int net_apply_mfma(const adlbr_net *net, const adlbr_operator *op, const float *r, float *z,
-                   hipStream_t s) {
+                   const float *rp, double *part, hipStream_t s) {
     const GridInfo &g = operator_grid(op);
-    dim3 grid((g.nx + kT - 1) / kT, (g.ny + kT - 1) / kT);
-    hipLaunchKernelGGL(k_net2d_fused, grid, dim3(256), 0, s, g.nx, g.ny, r, net->features,
-                       (const uint8_t *)net->gates8,
-                       (const bf16x4 *)(net->layers + kPackOffset), z);
+    hipLaunchKernelGGL(k_net2d_fused, dim3(net_mfma_blocks(g.nx, g.ny)), dim3(256), 0, s, g.nx,
+                       g.ny, r, net->features, (const uint8_t *)net->gates8,
+                       (const bf16x4 *)(net->layers + kPackOffset), z, rp, part);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }

@@ -146,6 +146,11 @@ struct adlbr_net_impl;
 // Learned preconditioner z = N(r) for K = I + dt A (defined with the CNN).
 int net_apply(const adlbr_net *net, const adlbr_operator *op, double dt, const void *r, void *z,
               hipStream_t s);
+// z = preconditioned r (FP32) and the per-block FP64 partials of <z, r> in
+// part[0 .. nparts) and of <z, rp> in part[nparts .. 2 nparts) (rp may be
+// null); nparts (host out) depends on the inference path taken.
+int net_apply_dots(const adlbr_net *net, const adlbr_operator *op, const float *r,
+                   const float *rp, float *z, double *part, long long *nparts, hipStream_t s);
 
 // Rows per block of the explicit-step kernels: every wave of a 256-thread
 // block takes kApplyPPT groups of 64 consecutive rows.

@@ -977,22 +977,33 @@ __global__ __launch_bounds__(kBS) void k_apply(
                                               cnt, pos, ent, h);
 }
 
+// The problem that block b belongs to (first_block ascending): the lanes of
+// a wave test 64 descriptors at once and the highest lane whose first block
+// is <= b wins, so the search costs one round of loads, not a chain of
+// dependent ones.  Wave-uniform result.
+__device__ __forceinline__ int find_prob(const BatchProb *__restrict__ probs, int nprob, long long b) {
+    const int lane = (int)(threadIdx.x & 63u);
+    int idx = 0;
+    for (int base = 0; base < nprob; base += 64) {
+        const int i = base + lane;
+        const bool le = i < nprob && probs[i].first_block <= b;
+        const unsigned long long m = __ballot(le);
+        if (m) idx = base + 63 - __clzll((long long)m);
+        if (m != ~0ull) break;  // the remaining descriptors start after b
+    }
+    return idx;
+}
+
 // Batched explicit step: one launch advances every problem of a class by one
 // step.  Blocks are laid out problem after problem (first_block ascending);
-// a block finds its problem by binary search over the descriptors, then
-// runs the single-operator block body.  XCD: remap block indices so that each
-// XCD takes a contiguous range (neighbouring blocks share its L2).
+// a block finds its problem (find_prob), then runs the single-operator block
+// body.  XCD: remap block indices so that each XCD takes a contiguous range
+// (neighbouring blocks share its L2).
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA, bool XCD>
 __global__ __launch_bounds__(kBS) void k_apply_batch(const BatchProb *__restrict__ probs, int nprob,
                                                      int parity) {
     const long long b = XCD ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
-    int lo = 0, hi = nprob - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (probs[mid].first_block <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    const BatchProb &P = probs[lo];
+    const BatchProb &P = probs[find_prob(probs, nprob, b)];
     const GridInfo g = P.g;
     const TA h = (TA)(P.dt_mode == ADLBR_DT_CFL ? P.dt * P.dtcfl[0] : P.dt);
     apply_block<DIM, WIDE, PER, true, TS, TA>(
@@ -1004,13 +1015,7 @@ __global__ __launch_bounds__(kBS) void k_apply_batch(const BatchProb *__restrict
 template <typename TS>
 __global__ __launch_bounds__(kBS) void k_copy_batch(const BatchProb *__restrict__ probs, int nprob) {
     const long long b = blockIdx.x;
-    int lo = 0, hi = nprob - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (probs[mid].first_block <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    const BatchProb &P = probs[lo];
+    const BatchProb &P = probs[find_prob(probs, nprob, b)];
     for (int k = 0; k < kApplyPPT; ++k) {
         const long long z = (b - P.first_block) * kApplyPoints + k * kBS + threadIdx.x;
         if (z < P.g.N) ((TS *)P.u[0])[z] = ((const TS *)P.u[1])[z];

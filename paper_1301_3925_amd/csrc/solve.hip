@@ -13,7 +13,8 @@
 // beta) -> direction (q = K z + beta q, p = z + beta p, <p,q>, alpha).
 // Flexible CG (Section 5 solves the restoration system by CG; the flexible
 // variant admits the learned preconditioner): update (x, r, <r,r>) ->
-// z = N(r) -> dots (<z,r>, <z,r_prev>, beta) -> direction.
+// z = N(r) with the dots <z,r>, <z,r_prev> -> scalars (|r|^2 checks, beta)
+// -> direction.
 #include <algorithm>
 #include <utility>
 #include <vector>
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(kBS) void k_fcg_update(long long N, double *__restr
                                                     const T *__restrict__ r, T *__restrict__ rn,
                                                     const T *__restrict__ p,
                                                     const T *__restrict__ q, const SolveState *st,
-                                                    double *part) {
+                                                    double *prr) {
     const bool skip = st->cg.done || st->cg.bad;
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
     double rr = 0.0;
@@ -140,44 +141,35 @@ __global__ __launch_bounds__(kBS) void k_fcg_update(long long N, double *__restr
         rn[i] = ri;
         rr = (double)ri * (double)ri;
     }
-    block_partial_sum(rr, part);
+    block_partial_sum(rr, prr);
 }
 
-__global__ __launch_bounds__(kBS) void k_fcg_update_fin(SolveState *st, const double *part,
-                                                        long long nb, double *hist, int max_hist) {
-    const double t = reduce_partials(part, nb);
-    if (threadIdx.x != 0 || st->cg.done || st->cg.bad) return;
-    st->cg.rr = t;
-    const int it = st->cg.iter + 1;
-    st->cg.iter = it;
-    if (it < max_hist) hist[it] = t;
-    if (!isfinite(t)) st->cg.bad = 1;
-    if (t <= st->tol2bb) st->cg.done = 1;
-}
-
-// Flexible-CG dots: partials of <z, r> and <z, r_prev>.
-template <typename T>
-__global__ __launch_bounds__(kBS) void k_fcg_dots(long long N, const T *__restrict__ z,
-                                                  const T *__restrict__ r, const T *__restrict__ rp,
-                                                  int first, const SolveState *st, double *part) {
-    const bool skip = st->cg.done || st->cg.bad;
-    const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
-    double zr = 0.0, zrp = 0.0;
-    if (i < N && !skip) {
-        const double zi = (double)z[i];
-        zr = zi * (double)r[i];
-        if (!first) zrp = zi * (double)rp[i];
-    }
-    block_partial_sum(zr, part);
-    block_partial_sum(zrp, part + gridDim.x);
-}
-
+// Finish a flexible-CG iteration (one block): unless first, the update's
+// |r|^2 from its partials prr (iteration count, history, breakdown and
+// convergence flags); then, from the dot partials part (nparts each),
 // beta = (<z, r> - <z, r_prev>) / <z_prev, r_prev> (first: beta = 0).
 __global__ __launch_bounds__(kBS) void k_fcg_scalars(SolveState *st, const double *part,
-                                                     long long nb, int first) {
-    const double zr = reduce_partials(part, nb);
-    const double zrp = reduce_partials(part + nb, nb);
+                                                     long long nparts, const double *prr,
+                                                     long long nb, double *hist, int max_hist,
+                                                     int first) {
+    const double rr = first ? 0.0 : reduce_partials(prr, nb);
+    const double zr = reduce_partials(part, nparts);
+    const double zrp = reduce_partials(part + nparts, nparts);
     if (threadIdx.x != 0 || st->cg.done || st->cg.bad) return;
+    if (!first) {
+        st->cg.rr = rr;
+        const int it = st->cg.iter + 1;
+        st->cg.iter = it;
+        if (it < max_hist) hist[it] = rr;
+        if (!isfinite(rr)) {
+            st->cg.bad = 1;
+            return;
+        }
+        if (rr <= st->tol2bb) {
+            st->cg.done = 1;
+            return;
+        }
+    }
     if (!isfinite(zr) || !(zr > 0.0) || !isfinite(zrp)) {
         st->cg.bad = 1;
         return;
@@ -230,6 +222,10 @@ template <typename TA, typename TB> __global__ void k_convert(long long N, const
     if (i < N) b[i] = (TB)a[i];
 }
 
+// Most dot partials the fused inference kernel leaves (its persistent grid
+// has at most 3 blocks per CU on 256 CUs).
+constexpr size_t kDotParts = 768;
+
 struct SolveLayout {
     size_t st, hist, part, x64, vec[6], total;
 };
@@ -240,7 +236,8 @@ SolveLayout solve_layout(long long N, size_t esz, int max_hist) {
     const size_t nb = (size_t)((N + kBS - 1) / kBS);
     L.st = o;   o += align_up(sizeof(SolveState));
     L.hist = o; o += align_up(8 * (size_t)max_hist);
-    L.part = o; o += align_up(8 * 2 * nb + 64);
+    // two regions of dot partials (up to max(nb, kDotParts) each), then |r|^2
+    L.part = o; o += align_up(8 * (2 * std::max(nb, kDotParts) + nb) + 64);
     L.x64 = o;  o += align_up(8 * (size_t)N);
     for (int k = 0; k < 6; ++k) {
         L.vec[k] = o;
@@ -262,6 +259,8 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     SolveState *st = (SolveState *)(ws + L.st);
     double *hist = (double *)(ws + L.hist);
     double *part = (double *)(ws + L.part);
+    // partials of |r|^2 of the flexible-CG update, after the dot partials
+    double *prr = part + 2 * (long long)std::max((size_t)nb, kDotParts);
     T *r = (T *)(ws + L.vec[0]);
     T *r2 = (T *)(ws + L.vec[1]);
     T *z = (T *)(ws + L.vec[2]);
@@ -296,12 +295,13 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     T *rc_ = r, *ro = r2;  // current and previous residual (flexible CG)
     auto start_iteration = [&]() -> int {
         if (use_net) {
-            int e = net_apply(p->net, op, dt, rc_, z, s);
+            // z = N(r) with the dots <z, r>, <z, r_prev> fused where possible
+            long long np = 0;
+            int e = net_apply_dots(p->net, op, (const float *)rc_,
+                                   first ? nullptr : (const float *)ro, (float *)z, part, &np, s);
             if (e) return e;
-            hipLaunchKernelGGL((k_fcg_dots<T>), dim3(nb), dim3(kBS), 0, s, N, (const T *)z,
-                               (const T *)rc_, (const T *)ro, first, (const SolveState *)st, part);
             hipLaunchKernelGGL(k_fcg_scalars, dim3(1), dim3(kBS), 0, s, st, (const double *)part,
-                               (long long)nb, first);
+                               np, (const double *)prr, (long long)nb, hist, kMaxHist, first);
         }
         int e = cg_direction(op, z, q, pv, cg, part, first, s);
         first = 0;
@@ -322,9 +322,7 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
             if (use_net) {
                 hipLaunchKernelGGL((k_fcg_update<T>), dim3(nb), dim3(kBS), 0, s, N, x64,
                                    (const T *)rc_, ro, (const T *)pv, (const T *)q,
-                                   (const SolveState *)st, part);
-                hipLaunchKernelGGL(k_fcg_update_fin, dim3(1), dim3(kBS), 0, s, st,
-                                   (const double *)part, (long long)nb, hist, kMaxHist);
+                                   (const SolveState *)st, prr);
                 std::swap(rc_, ro);  // ro now holds r_k (previous), rc_ r_{k+1}
             } else {
                 hipLaunchKernelGGL((k_pcg_update<T, TD>), dim3(nb), dim3(kBS), 0, s, N, x64, rc_, z,
