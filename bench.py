@@ -78,9 +78,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2",
                     choices=["c1", "c2", "c3", "c3-precision", "c4", "c5", "c5-3d", "copy"])
-    ap.add_argument("--train-steps", type=int, default=1000)
-    ap.add_argument("--on-policy", action="store_true",
-                    help="c5: add flexible-CG residuals to the training pool half-way")
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--off-policy", action="store_true",
+                    help="c5: train on Jacobi-PCG residuals only (no flexible-CG residuals)")
+    ap.add_argument("--refresh", type=int, default=4,
+                    help="c5: how many times flexible-CG residuals join the training pool")
     ap.add_argument("--dtype", default=None, help="storage dtype for c3: f64|f32|bf16|f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
@@ -380,7 +382,7 @@ def run_c4(args, dev, stream):
     nsteps = 100
     K = args.steps if args.steps is not None else 3
     b = adlbr.Batch(ops, us, dt=0.9, dt_mode="cfl")
-    variants = b.tune(steps=3)
+    variants = b.tune(steps=10)
     for _ in range(max(1, args.warmup)):
         b.run(nsteps)
     torch.cuda.synchronize()
@@ -418,7 +420,7 @@ def run_c4(args, dev, stream):
         "per_problem_launches": {"value": round(pts * nsteps / seq / 1e6, 2),
                                  "unit": "Mpoint-steps/s", "seconds": round(seq, 4)},
         "autotuned_variants": variants,
-        "roofline": {"bound": "hbm", "kernel": "k_apply_batch (grouped explicit step, FP32)",
+        "roofline": {"bound": "hbm", "kernel": "k_apply_batch or k_apply (tuned batch step, FP32)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "algo_bytes": abytes, "avg_step_us": round(step_s * 1e6, 2)},
@@ -496,7 +498,7 @@ def run_c5(args, dev, stream):
     t0 = time.perf_counter()
     net, hist = adlbr.train_net(op, dt, rhs_seeds=range(2001, 2017), steps=args.train_steps,
                                 batch=4, lr=3e-3, seed=0, log_every=100,
-                                on_policy=args.on_policy)
+                                on_policy=not args.off_policy, refresh=args.refresh)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     _, rt, tt = timed("fcg", net)
@@ -514,7 +516,8 @@ def run_c5(args, dev, stream):
         "fcg_trained": {"iters": rt["iters"], "ms": round(tt * 1e3, 3),
                         "fell_back": rt["fell_back"], "rel_res": rt["rel_res"]},
         "training": {"seconds": round(t_train, 2), "steps": args.train_steps, "batch": 4,
-                     "on_policy": bool(args.on_policy), "loss": hist},
+                     "on_policy": not args.off_policy, "refresh": args.refresh,
+                     "loss": hist},
         "speedup_vs_jacobi": round(tj / tt, 3),
     }
     print(json.dumps(res), flush=True)

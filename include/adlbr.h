@@ -187,17 +187,32 @@ int adlbr_batch_workspace(int nprob, size_t *bytes);
 int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *const *u,
                        void *const *u_tmp, const double *dt, int dt_mode, void *workspace,
                        size_t ws_bytes, void *stream, adlbr_batch **batch);
-/* Autotuner: for every class, time each launch variant (bit 0: XCD-
- * contiguous block order; bit 1: largest problems first) over `steps`
- * grouped steps from u into u_tmp (u is not modified) and keep the
- * fastest; the choice is cached per process by class, total size and
+/* Autotuner: for every class, time each launch variant with each chunk
+ * budget over `steps` steps from u into u_tmp (u is not modified) and keep
+ * the fastest; the choice is cached per process by class, total size and
  * problem count, and reused without timing when use_cache is set.
- * Synchronizes `stream`. */
+ * Variants, bit by bit: 0 = XCD-contiguous block order of the grouped
+ * launch, 1 = largest problems first, 2 = one launch per problem instead of
+ * one grouped launch (bits 0 and 2 together are not timed).  Chunk budgets
+ * (0, 64, 128, 224 MiB): the class is cut, in the variant's problem order,
+ * into chunks whose working sets (u, u_tmp and the operator's arrays) stay
+ * within the budget, and each chunk takes all its steps before the next
+ * one starts, so that it runs out of the 256 MB last-level cache; 0 keeps
+ * the class whole.  Every choice computes the same bits.  Synchronizes
+ * `stream`. */
 int adlbr_batch_tune(adlbr_batch *batch, int steps, int use_cache, void *stream);
+/* Force launch variant (0..7) and chunk budget (bytes, 0 = no chunks; a
+ * problem larger than the budget gets a chunk of its own) for class cls
+ * instead of tuning.  Synchronizes `stream`; ADLBR_E_INVALID for a bad
+ * class or variant. */
+int adlbr_batch_set_variant(adlbr_batch *batch, int cls, int variant, size_t chunk_bytes,
+                            void *stream);
 /* Class cls (0-based, in order of first appearance): its class key
- * (dim*1000 + wide*100 + periodic*10 + storage), chosen variant and
- * number of problems. */
-int adlbr_batch_variant(const adlbr_batch *batch, int cls, int *key, int *variant, int *nprob);
+ * (dim*1000 + wide*100 + periodic*10 + storage), launch variant, number of
+ * problems and, where the pointers are not NULL, number of chunks and chunk
+ * budget in bytes.  ADLBR_E_INVALID past the last class. */
+int adlbr_batch_variant(const adlbr_batch *batch, int cls, int *key, int *variant, int *nprob,
+                        int *nchunks, size_t *chunk_bytes);
 /* nsteps explicit steps of every problem; use_graph = 0 launches directly
  * on `stream` instead of through the captured graph.  The results land in
  * u (an odd nsteps ends with a grouped copy). */

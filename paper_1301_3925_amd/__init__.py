@@ -247,15 +247,21 @@ class Batch:
                                                 _stream(stream)))
         return self.variants()
 
+    def set_variant(self, cls: int, variant: int, chunk_bytes: int = 0, stream=None):
+        capi.check(capi.load().adlbr_batch_set_variant(self._h, int(cls), int(variant),
+                                                       int(chunk_bytes), _stream(stream)))
+
     def variants(self):
         lib = capi.load()
         out, k = [], 0
         while True:
-            key, var, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            key, var, n, nc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            cb = ctypes.c_size_t()
             if lib.adlbr_batch_variant(self._h, k, ctypes.byref(key), ctypes.byref(var),
-                                       ctypes.byref(n)) != 0:
+                                       ctypes.byref(n), ctypes.byref(nc), ctypes.byref(cb)) != 0:
                 return out
-            out.append({"class": key.value, "variant": var.value, "problems": n.value})
+            out.append({"class": key.value, "variant": var.value, "problems": n.value,
+                        "chunks": nc.value, "chunk_bytes": cb.value})
             k += 1
 
     def run(self, nsteps: int, graph: bool = True, stream=None):
@@ -422,14 +428,15 @@ def adam(params, grads, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=
 
 def train_net(op: "Operator", dt: float, rhs_seeds, steps: int = 400, batch: int = 4,
               lr: float = 2e-3, seed: int = 0, snapshot_iters=(1, 2, 4, 8, 16, 32),
-              log_every: int = 0, on_policy: bool = False):
+              log_every: int = 0, on_policy: bool = False, refresh: int = 1):
     """Train the preconditioner on residuals the solver itself generates:
     for each right-hand side, Jacobi-PCG stopped after k iterations leaves a
     residual r_k = b - K x_k (adlbr_residual); each Adam step takes `batch`
     of them, minimizes the energy loss (adlbr_net_loss_grad) through the
     network's own backward kernels and updates with adlbr_net_adam.  With
-    on_policy, half-way through the residuals of flexible CG with the
-    network as it stands (stopped after the same k) join the pool.
+    on_policy, the residuals of flexible CG with the network as it stands
+    (stopped after the same k) join the pool `refresh` times, evenly spaced
+    after the first half of the steps.
     Returns (net, history of losses)."""
     import numpy as np
     from . import synth
@@ -455,7 +462,8 @@ def train_net(op: "Operator", dt: float, rhs_seeds, steps: int = 400, batch: int
     rng = np.random.Generator(np.random.PCG64(seed + 7))
     hist = []
     for it in range(1, steps + 1):
-        if on_policy and it == steps // 2 + 1:
+        marks = {steps // 2 + 1 + (steps // 2) * j // max(1, refresh) for j in range(refresh)}
+        if on_policy and it in marks:
             more = []
             for sd in rhs_seeds:
                 b = torch.from_numpy(synth.uniform(sd, op.N)).float().to(dev)

@@ -90,8 +90,9 @@ SIGNATURES = {
     "adlbr_batch_workspace": ([_I, ctypes.POINTER(_SZ)], _I),
     "adlbr_batch_create": ([_I, _P, _P, _P, _P, _I, _P, _SZ, _P, ctypes.POINTER(_P)], _I),
     "adlbr_batch_tune": ([_P, _I, _I, _P], _I),
+    "adlbr_batch_set_variant": ([_P, _I, _I, _SZ, _P], _I),
     "adlbr_batch_variant": ([_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
-                             ctypes.POINTER(_I)], _I),
+                             ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_SZ)], _I),
     "adlbr_batch_run": ([_P, _I64, _I, _P], _I),
     "adlbr_batch_destroy": ([_P], _I),
     "adlbr_tensor_workspace": ([_GP, _I, ctypes.POINTER(_SZ)], _I),

@@ -3,12 +3,16 @@
 // Problems are grouped by class (dim, offset width, boundary, storage); one
 // grouped launch advances every problem of a class by one step (blocks laid
 // out problem after problem, each block finds its problem by binary search
-// over a small device descriptor table).  nsteps of all classes are captured
-// once into a HIP graph on the batch's own stream and replayed, so a whole
-// run is one graph launch.  The autotuner times the launch variants of each
-// class on the batch itself (without touching the state: it steps u into
-// u_tmp) and keeps the fastest, also in a per-process cache keyed by the
-// class and its size.
+// over a small device descriptor table).  The problems are independent, so
+// a class may also be cut into chunks whose working sets fit the 256 MB
+// last-level (Infinity) cache, each chunk taking all its steps before the
+// next starts: after the first step a chunk's arrays are served from that
+// cache instead of HBM.  nsteps of all classes are captured once into a HIP
+// graph on the batch's own stream and replayed, so a whole run is one graph
+// launch.  The autotuner times the launch variants of each class on the
+// batch itself (without touching the state: it steps u into u_tmp) and
+// keeps the fastest, also in a per-process cache keyed by the class and its
+// size.
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -23,9 +27,16 @@ struct adlbr_batch {
         int key;
         const adlbr_operator *rep;
         std::vector<adlbr::BatchProb> host;  // descriptors in problem order
+        std::vector<adlbr::BatchProb> order;  // descriptors as uploaded (variant's order)
+        std::vector<size_t> bytes;           // footprint of each problem, problem order
         adlbr::BatchProb *dev;               // descriptor table in the workspace
-        long long nblocks;
+        struct Chunk {
+            int first, count;  // descriptors [first, first + count) of `order`
+            long long nblocks;
+        };
+        std::vector<Chunk> chunks;           // cache-blocking chunks of `order`
         int variant;
+        size_t budget;  // chunk budget in bytes, 0 = the whole class in one chunk
     };
     int nprob;
     std::vector<Class> classes;
@@ -39,10 +50,15 @@ struct adlbr_batch {
 namespace adlbr {
 namespace {
 
-constexpr int kVariants = 4;  // bit 0: XCD-contiguous blocks; bit 1: largest problems first
+// bit 0: XCD-contiguous blocks; bit 1: largest problems first; bit 2: one
+// launch per problem (in the variant's problem order) instead of one grouped
+// launch.  Each is timed with every chunk budget of kChunkMiB (0: no chunks).
+constexpr int kVariants = 8;
+constexpr size_t kChunkMiB[4] = {0, 64, 128, 224};
 
 std::mutex g_cache_mu;
-std::map<long long, int> g_cache;  // (class, log2 points, problems) -> variant
+// (class, log2 points, problems) -> (variant, chunk budget)
+std::map<long long, std::pair<int, size_t>> g_cache;
 
 long long cache_key(const adlbr_batch::Class &c) {
     long long pts = 0;
@@ -52,36 +68,62 @@ long long cache_key(const adlbr_batch::Class &c) {
     return ((long long)c.key * 64 + lg) * 4096 + (long long)std::min<size_t>(c.host.size(), 4095);
 }
 
-// Lay out the class's blocks in the order of the variant and upload.
-int upload(adlbr_batch::Class &c, int variant, hipStream_t s) {
-    std::vector<BatchProb> d = c.host;
+// Lay out the class's problems in the order of the variant, cut them into
+// chunks within the variant's budget (at least one problem each; block
+// numbers restart at 0 in every chunk) and upload.
+int upload(adlbr_batch::Class &c, int variant, size_t budget, hipStream_t s) {
+    std::vector<int> idx(c.host.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
     if (variant & 2)
-        std::stable_sort(d.begin(), d.end(),
-                         [](const BatchProb &a, const BatchProb &b) { return a.g.N > b.g.N; });
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](int a, int b) { return c.host[a].g.N > c.host[b].g.N; });
+    std::vector<BatchProb> d;
+    c.chunks.clear();
+    size_t used = 0;
     long long fb = 0;
-    for (BatchProb &p : d) {
+    for (int i : idx) {
+        const bool fits = budget == 0 || used + c.bytes[i] <= budget;
+        if (c.chunks.empty() || !fits) {
+            c.chunks.push_back({(int)d.size(), 0, 0});
+            used = 0;
+            fb = 0;
+        }
+        BatchProb p = c.host[i];
         p.first_block = fb;
         fb += (p.g.N + kApplyPoints - 1) / kApplyPoints;
+        used += c.bytes[i];
+        d.push_back(p);
+        c.chunks.back().count++;
+        c.chunks.back().nblocks = fb;
     }
-    c.nblocks = fb;
-    ADLBR_CHECK_HIP(hipMemcpyAsync(c.dev, d.data(), d.size() * sizeof(BatchProb),
+    c.order = d;
+    ADLBR_CHECK_HIP(hipMemcpyAsync(c.dev, c.order.data(), d.size() * sizeof(BatchProb),
                                    hipMemcpyHostToDevice, s));
-    ADLBR_CHECK_HIP(hipStreamSynchronize(s));  // d must outlive the copy
+    ADLBR_CHECK_HIP(hipStreamSynchronize(s));
     c.variant = variant;
+    c.budget = budget;
     return ADLBR_OK;
 }
 
+int launch_chunk(const adlbr_batch::Class &c, const adlbr_batch::Class::Chunk &k, int parity,
+                 int variant, int copy, hipStream_t s) {
+    return batch_launch(c.rep, c.dev + k.first, c.order.data() + k.first, k.count, k.nblocks,
+                        parity, variant, copy, s);
+}
+
+// Chunk after chunk, every step of the chunk (u -> u_tmp -> u ...), and the
+// copy back into u after an odd count.
 int enqueue_steps(adlbr_batch *b, long long nsteps, hipStream_t s) {
-    for (long long k = 0; k < nsteps; ++k)
-        for (auto &c : b->classes) {
-            int rc = batch_launch(c.rep, c.dev, (int)c.host.size(), c.nblocks, (int)(k & 1),
-                                  c.variant, 0, s);
-            if (rc) return rc;
-        }
-    if (nsteps & 1)
-        for (auto &c : b->classes) {
-            int rc = batch_launch(c.rep, c.dev, (int)c.host.size(), c.nblocks, 0, c.variant, 1, s);
-            if (rc) return rc;
+    for (auto &c : b->classes)
+        for (const auto &k : c.chunks) {
+            for (long long t = 0; t < nsteps; ++t) {
+                int rc = launch_chunk(c, k, (int)(t & 1), c.variant, 0, s);
+                if (rc) return rc;
+            }
+            if (nsteps & 1) {
+                int rc = launch_chunk(c, k, 0, c.variant, 1, s);
+                if (rc) return rc;
+            }
         }
     return ADLBR_OK;
 }
@@ -159,8 +201,8 @@ extern "C" int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *c
             c.key = key;
             c.rep = ops[i];
             c.dev = nullptr;
-            c.nblocks = 0;
             c.variant = 1;
+            c.budget = 0;
             b->classes.push_back(c);
         }
         BatchProb d;
@@ -171,6 +213,7 @@ extern "C" int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *c
         d.dt = dt[i];
         d.dt_mode = dt_mode;
         b->classes[it->second].host.push_back(d);
+        b->classes[it->second].bytes.push_back(batch_footprint(ops[i]));
     }
     long long total_blocks = 0;
     char *base = (char *)workspace;
@@ -188,13 +231,13 @@ extern "C" int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *c
     hipStream_t s = as_stream(stream);
     int rc = ADLBR_OK;
     for (auto &c : b->classes) {
-        int v = 1;
+        std::pair<int, size_t> v(1, 0);
         {
             std::lock_guard<std::mutex> lk(g_cache_mu);
             auto it = g_cache.find(cache_key(c));
             if (it != g_cache.end()) v = it->second;
         }
-        rc = upload(c, v, s);
+        rc = upload(c, v.first, v.second, s);
         if (rc) break;
     }
     if (!rc && (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
@@ -231,36 +274,47 @@ extern "C" int adlbr_batch_tune(adlbr_batch *b, int steps, int use_cache, void *
             std::lock_guard<std::mutex> lk(g_cache_mu);
             auto it = g_cache.find(key);
             if (it != g_cache.end()) {
-                rc = upload(c, it->second, s);
+                rc = upload(c, it->second.first, it->second.second, s);
                 if (rc) break;
                 continue;
             }
         }
         int best = -1;
+        size_t best_budget = 0;
         float best_ms = 0.f;
-        for (int v = 0; v < kVariants && !rc; ++v) {
-            rc = upload(c, v, s);
+        size_t class_bytes = 0;
+        for (size_t b2 : c.bytes) class_bytes += b2;
+        for (int cand = 0; cand < 4 * kVariants && !rc; ++cand) {
+            const int v = cand % kVariants;
+            const size_t budget = kChunkMiB[cand / kVariants] << 20;
+            if ((v & 4) && (v & 1)) continue;  // bit 0 has no meaning without a grouped launch
+            // a budget that holds the whole class is the same as no chunking
+            if (budget && class_bytes <= budget) continue;
+            rc = upload(c, v, budget, s);
             if (rc) break;
-            // warm-up, then timed; parity 0 only: u is read, u_tmp written
-            rc = batch_launch(c.rep, c.dev, (int)c.host.size(), c.nblocks, 0, v, 0, s);
+            // warm-up over all chunks, then `steps` steps chunk by chunk as a
+            // run takes them; parity 0 only: u is read, u_tmp written
+            for (const auto &k : c.chunks)
+                if (!rc) rc = launch_chunk(c, k, 0, v, 0, s);
             if (rc) break;
             ADLBR_CHECK_HIP(hipEventRecord(e0, s));
-            for (int k = 0; k < steps && !rc; ++k)
-                rc = batch_launch(c.rep, c.dev, (int)c.host.size(), c.nblocks, 0, v, 0, s);
+            for (const auto &k : c.chunks)
+                for (int t = 0; t < steps && !rc; ++t) rc = launch_chunk(c, k, 0, v, 0, s);
             ADLBR_CHECK_HIP(hipEventRecord(e1, s));
             ADLBR_CHECK_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
             ADLBR_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
             if (best < 0 || ms < best_ms) {
                 best = v;
+                best_budget = budget;
                 best_ms = ms;
             }
         }
         if (rc) break;
-        rc = upload(c, best, s);
+        rc = upload(c, best, best_budget, s);
         if (rc) break;
         std::lock_guard<std::mutex> lk(g_cache_mu);
-        g_cache[key] = best;
+        g_cache[key] = std::make_pair(best, best_budget);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -269,16 +323,31 @@ extern "C" int adlbr_batch_tune(adlbr_batch *b, int steps, int use_cache, void *
     return rc;
 }
 
+extern "C" int adlbr_batch_set_variant(adlbr_batch *b, int cls, int variant, size_t chunk_bytes,
+                                       void *stream) {
+    clear_error();
+    if (!b || cls < 0 || cls >= (int)b->classes.size() || variant < 0 || variant >= kVariants) {
+        set_error("adlbr_batch_set_variant: bad class or variant");
+        return ADLBR_E_INVALID;
+    }
+    int rc = upload(b->classes[cls], variant, chunk_bytes, as_stream(stream));
+    drop_graph(b);
+    return rc;
+}
+
 extern "C" int adlbr_batch_variant(const adlbr_batch *b, int cls, int *key, int *variant,
-                                   int *nprob) {
+                                   int *nprob, int *nchunks, size_t *chunk_bytes) {
     clear_error();
     if (!b || cls < 0 || cls >= (int)b->classes.size() || !key || !variant || !nprob) {
         set_error("adlbr_batch_variant: bad argument");
         return ADLBR_E_INVALID;
     }
-    *key = b->classes[cls].key;
-    *variant = b->classes[cls].variant;
-    *nprob = (int)b->classes[cls].host.size();
+    const adlbr_batch::Class &c = b->classes[cls];
+    *key = c.key;
+    *variant = c.variant;
+    *nprob = (int)c.host.size();
+    if (nchunks) *nchunks = (int)c.chunks.size();
+    if (chunk_bytes) *chunk_bytes = c.budget;
     return ADLBR_OK;
 }
 

@@ -179,11 +179,17 @@ struct BatchProb {
 int batch_class(const adlbr_operator *op);
 // Fill the operator part of a descriptor.
 void batch_describe(const adlbr_operator *op, BatchProb *d);
-// One grouped launch over the problems of one class (rep: any operator of
-// the class): an explicit step from u[parity] to u[parity ^ 1], or (copy)
-// u[0] = u[1].  variant bit 0: XCD-contiguous block order.
-int batch_launch(const adlbr_operator *rep, const BatchProb *probs, int nprob, long long nblocks,
-                 int parity, int variant, int copy, hipStream_t s);
+// Device bytes one explicit step of op reads or writes (u, its successor and
+// the operator's arrays), the working set that cache blocking budgets for.
+size_t batch_footprint(const adlbr_operator *op);
+
+// One step of the problems of one class (rep: any operator of the class):
+// an explicit step from u[parity] to u[parity ^ 1], or (copy) u[0] = u[1].
+// probs / hprobs: the descriptors on the device / on the host, in the same
+// order.  variant bit 0: XCD-contiguous block order of the grouped launch;
+// bit 2: one launch per problem instead of the grouped launch.
+int batch_launch(const adlbr_operator *rep, const BatchProb *probs, const BatchProb *hprobs,
+                 int nprob, long long nblocks, int parity, int variant, int copy, hipStream_t s);
 
 // Internal entry points shared between translation units.
 // Direction update q = K z + beta q, p = z + beta p and alpha = <z,r>/<p,q>
@@ -234,8 +240,17 @@ __device__ inline void block_partial_max(double v, double *partial) {
 __device__ inline double reduce_partials(const double *partial, long long n, bool take_max = false) {
     __shared__ double red[256];
     double acc = take_max ? -1.0e308 : 0.0;
-    for (long long b = threadIdx.x; b < n; b += 256)
-        acc = take_max ? fmax(acc, partial[b]) : acc + partial[b];
+    long long b = threadIdx.x;
+    // eight independent loads in flight, then added in the same order as a
+    // plain strided loop would
+    for (; b + 7 * 256 < n; b += 8 * 256) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = partial[b + 256 * j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc = take_max ? fmax(acc, v[j]) : acc + v[j];
+    }
+    for (; b < n; b += 256) acc = take_max ? fmax(acc, partial[b]) : acc + partial[b];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {

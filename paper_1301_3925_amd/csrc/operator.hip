@@ -1238,8 +1238,26 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct ApplyF 
 };
 
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct BatchF {
-    static int run(const adlbr_operator *, const BatchProb *probs, int nprob, long long nblocks,
-                   int parity, int variant, int copy, hipStream_t s) {
+    static int run(const adlbr_operator *, const BatchProb *probs, const BatchProb *hprobs,
+                   int nprob, long long nblocks, int parity, int variant, int copy,
+                   hipStream_t s) {
+        typedef typename Slots<DIM, WIDE>::store_t store_t;
+        if (variant & 4) {  // one launch per problem (same kernel as adlbr_step)
+            for (int i = 0; i < nprob; ++i) {
+                const BatchProb &P = hprobs[i];
+                if (copy) {
+                    ADLBR_CHECK_HIP(hipMemcpyAsync(P.u[0], P.u[1], (size_t)P.g.N * sizeof(TS),
+                                                   hipMemcpyDeviceToDevice, s));
+                    continue;
+                }
+                const unsigned nb = (unsigned)((P.g.N + kApplyPoints - 1) / kApplyPoints);
+                hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, true, TS, TA>), dim3(nb), dim3(kBS), 0, s,
+                                   P.g, (const TS *)P.u[parity], (TS *)P.u[parity ^ 1],
+                                   (const store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent, P.dt,
+                                   P.dtcfl, P.dt_mode);
+            }
+            return ADLBR_OK;
+        }
         if (copy) {
             hipLaunchKernelGGL((k_copy_batch<TS>), dim3((unsigned)nblocks), dim3(kBS), 0, s, probs,
                                nprob);
@@ -1356,9 +1374,19 @@ void batch_describe(const adlbr_operator *op, BatchProb *d) {
     d->dtcfl = op->dtcfl;
 }
 
-int batch_launch(const adlbr_operator *rep, const BatchProb *probs, int nprob, long long nblocks,
-                 int parity, int variant, int copy, hipStream_t s) {
-    return dispatch<BatchF>(rep, probs, nprob, nblocks, parity, variant, copy, s);
+size_t batch_footprint(const adlbr_operator *op) {
+    const size_t ts = dtype_size(op->storage);
+    size_t sbs;
+    if (op->gi.dim == 2) sbs = op->wide ? sizeof(Slots<2, true>::store_t) : sizeof(Slots<2, false>::store_t);
+    else sbs = op->wide ? sizeof(Slots<3, true>::store_t) : sizeof(Slots<3, false>::store_t);
+    // u and its successor, offsets, weights, count, row start, about one
+    // incoming entry per slot
+    return (size_t)op->gi.N * (2 * ts + sbs + (size_t)op->slots * (ts + 4) + 1 + 4);
+}
+
+int batch_launch(const adlbr_operator *rep, const BatchProb *probs, const BatchProb *hprobs,
+                 int nprob, long long nblocks, int parity, int variant, int copy, hipStream_t s) {
+    return dispatch<BatchF>(rep, probs, hprobs, nprob, nblocks, parity, variant, copy, s);
 }
 
 int cg_direction(const adlbr_operator *op, const void *z, void *q, void *p, CgState *st,

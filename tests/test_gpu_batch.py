@@ -62,12 +62,40 @@ def test_batch_every_variant_and_graph_replay(lib):
     b = lib.Batch(ops, us, dt=0.5, dt_mode="cfl")
     vs = b.tune(steps=2, use_cache=False)
     assert len(vs) == 2 and sum(v["problems"] for v in vs) == len(ops)
-    assert all(0 <= v["variant"] < 4 for v in vs)
+    assert all(0 <= v["variant"] < 8 for v in vs)
     b.run(4)
     b.run(4)  # replay of the captured graph
     torch.cuda.synchronize()
     for k, (u, r) in enumerate(zip(us, ref)):
         assert torch.equal(u, r), k
+
+
+@pytest.mark.parametrize("chunk_bytes", [0, 1, 300_000])
+@pytest.mark.parametrize("variant", range(8))
+def test_batch_forced_variant_bitwise(lib, variant, chunk_bytes):
+    """Grouped or per-problem launches, in any block order, whole or cut into
+    chunks (1 byte: one problem per chunk), give the same bits."""
+    import torch
+    ops, us = _problems(lib, torch.float32)
+    ref = [u.clone() for u in us]
+    for op, u in zip(ops, ref):
+        op.step(u, 0.9, 5, cfl_fraction=True)
+    b = lib.Batch(ops, us, dt=0.9, dt_mode="cfl")
+    for cls in range(len(b.variants())):
+        b.set_variant(cls, variant, chunk_bytes)
+    vs = b.variants()
+    assert all(v["variant"] == variant and v["chunk_bytes"] == chunk_bytes for v in vs)
+    if chunk_bytes == 1:
+        assert [v["chunks"] for v in vs] == [v["problems"] for v in vs]
+    if chunk_bytes == 0:
+        assert all(v["chunks"] == 1 for v in vs)
+    b.run(2)
+    b.run(3)  # odd count: the final copy runs through the same variant
+    torch.cuda.synchronize()
+    for k, (u, r) in enumerate(zip(us, ref)):
+        assert torch.equal(u, r), k
+    with pytest.raises(Exception):
+        b.set_variant(0, 8)
 
 
 def test_batch_absolute_dt_and_oracle(lib):
