@@ -126,6 +126,33 @@ __device__ inline long long xcd_block(long long b, long long nb) {
     return start + j;
 }
 
+// 3D traversal in strips of kStripZ planes.  With blocks taken plane after
+// plane, a block's neighbours one plane up or down were last touched a whole
+// plane of blocks ago and have left the L2 by then.  When a plane is a whole
+// number BP of blocks, logical block L is sent instead to a strip of kStripZ
+// planes (fewer for the last strip) walked column by column: within a strip,
+// the blocks at one in-plane position j of all its planes come one after
+// the other, so blocks one plane apart run close together in time.  The
+// map is a bijection of [0, nblocks).
+#ifndef ADLBR_STRIP_Z
+#define ADLBR_STRIP_Z 8
+#endif
+constexpr int kStripZ = ADLBR_STRIP_Z;
+
+__device__ inline long long strip_block(long long L, const GridInfo &g, int points_per_block) {
+    if (g.dim != 3 || kStripZ <= 1) return L;
+    const long long plane = (long long)g.nx * g.ny;
+    if (plane % points_per_block) return L;
+    const unsigned bp = (unsigned)(plane / points_per_block);
+    const unsigned strip = (unsigned)kStripZ * bp;
+    const unsigned s = (unsigned)L / strip;
+    const unsigned z0 = s * (unsigned)kStripZ;
+    const unsigned tz = min((unsigned)kStripZ, (unsigned)g.nz - z0);
+    const unsigned i = (unsigned)L - s * strip;
+    const unsigned j = i / tz, z = z0 + i % tz;
+    return (long long)z * bp + j;
+}
+
 // Device-resident scalars of a (flexible) conjugate-gradient iteration.
 struct CgState {
     double dt;      // K = I + dt A
@@ -167,6 +194,7 @@ struct BatchProb {
     const uint8_t *cnt;
     const int32_t *pos;
     const int32_t *ent;
+    const void *went;
     const double *dtcfl;
     void *u[2];
     double dt;

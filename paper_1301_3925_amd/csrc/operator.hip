@@ -25,6 +25,7 @@
 //          z mod 64 (the target's position in its wavefront), sorted per row;
 //          |y - z| < 2^22.
 //   diag   [N] A_zz (double for FP64 storage, float otherwise).
+#include <algorithm>
 #include <new>
 
 #include "common.h"
@@ -39,12 +40,16 @@ struct adlbr_operator {
     uint8_t *cnt;
     int32_t *pos;
     int32_t *ent;
+    void *went;        // [entries] weight of every incoming entry (storage dtype)
     void *diag;
     double *maxdiag;
     double *dtcfl;
-    int32_t *rmax;     // largest offset component
+    int32_t *rmax;     // 2D: largest tile reach
     uint8_t *mask;     // bit q: slot q has a positive weight
     double *part;      // per-block partials of the assembly
+    int32_t *trmax;    // 2D: reach of every 64 x 64 tile
+    int32_t *brmax;    // 2D: reach of every 4 x 4 brick
+    uint8_t *rank;     // 2D: [6][N] rank of every edge in its target's row
     uint32_t *bincnt;  // 3D: edges per bin of targets; 2D: cnt sums per 1024-point chunk
     uint32_t *bincur;  // 3D: placement cursor per bin
     uint32_t *binoff;  // 3D: exclusive scan of bincnt
@@ -268,14 +273,13 @@ __device__ __forceinline__ unsigned bin_append(int bin, uint32_t *counter, bool 
 }
 
 // Pack the slots, convert the weights, record which slots carry a positive
-// weight (mask bit q), the block's largest offset component (rpart), and,
-// for the binned assembly (BINS), count the edges landing in each bin.
+// weight (mask bit q) and, for the binned assembly (BINS), count the edges
+// landing in each bin.
 template <int DIM, bool WIDE, bool PER, typename TWin, typename TS, typename TA, bool BINS>
 __global__ __launch_bounds__(256) void k_compact(
     GridInfo g, const int16_t *__restrict__ off, const TWin *__restrict__ win,
     typename Slots<DIM, WIDE>::store_t *__restrict__ sb, TS *__restrict__ w,
-    uint8_t *__restrict__ mask, double *__restrict__ rpart, uint32_t *__restrict__ bincnt,
-    int32_t *status) {
+    uint8_t *__restrict__ mask, uint32_t *__restrict__ bincnt, int32_t *status) {
     const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = z < g.N;  // every lane takes part in the ballots
     constexpr int S = DIM == 2 ? 3 : 6;
@@ -310,22 +314,12 @@ __global__ __launch_bounds__(256) void k_compact(
         }
         mask[z] = (uint8_t)m;
     }
-    int rmax = 0;
-    for (int q = 0; q < S; ++q)
-        for (int c = 0; c < DIM; ++c) rmax = max(rmax, abs(s[q][c]));
     for (int k = 0; k < 2 * S; ++k) {
         const long long t = live ? edge_k<DIM, PER>(p, z, s, wq, k, g) : -1;
         if (t == -2) st |= ADLBR_ST_RANGE;
         if (BINS) bin_append(t >= 0 ? (int)(t >> kBinShift) : -1, bincnt, true);
     }
     if (live) report(status, z, st);
-    block_partial_max((double)rmax, rpart);
-}
-
-// R = the largest offset component over all points (from the block maxima).
-__global__ __launch_bounds__(256) void k_rmax_fin(const double *rpart, long long nb, int32_t *R) {
-    const double r = reduce_partials(rpart, nb, true);
-    if (threadIdx.x == 0) *R = (int32_t)r;
 }
 
 // Sort one row's entries ascending (the order is then independent of the
@@ -361,6 +355,15 @@ __device__ inline void sort_row(int32_t *e, int c) {
     }
 }
 
+// Sort row z (entries e[0..c)), store the weight of each of its entries
+// beside it (we[i], in the storage dtype; not when we is null) and return
+// A_zz, summed as row_diag does.  A row of up to 16 entries is sorted in registers and its
+// incoming weights are all requested before any is added.
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
+__device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *e, int c,
+                                       const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                                       const TS *__restrict__ w, TS *__restrict__ we);
+
 // A_zz = own in-grid weights (both signs) + weights of the incoming edges.
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
 __device__ inline double row_diag(const GridInfo &g, long long z, const int32_t *e, int c,
@@ -383,6 +386,57 @@ __device__ inline double row_diag(const GridInfo &g, long long z, const int32_t 
         const int32_t v = e[i];
         d += (double)Conv<TS, TA>::ld(w[(long long)((v >> 6) & 7) * N + z + (v >> 9)]);
     }
+    return d;
+}
+
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
+__device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *e, int c,
+                                       const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                                       const TS *__restrict__ w, TS *__restrict__ we) {
+    const long long N = g.N;
+    if (c > 16) {
+        sort_row(e, c);
+        if (we)
+            for (int i = 0; i < c; ++i) we[i] = w[(long long)((e[i] >> 6) & 7) * N + z + (e[i] >> 9)];
+        return row_diag<DIM, WIDE, PER, TS, TA>(g, z, e, c, sb, w);
+    }
+    constexpr int S = DIM == 2 ? 3 : 6;
+    int32_t r[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) r[i] = i < c ? e[i] : 0x7fffffff;
+#pragma unroll
+    for (int round = 0; round < 16; ++round) {
+#pragma unroll
+        for (int i = round & 1; i + 1 < 16; i += 2) {
+            const int32_t a = r[i], bb = r[i + 1];
+            r[i] = min(a, bb);
+            r[i + 1] = max(a, bb);
+        }
+    }
+    TA wi[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i < c) {
+            e[i] = r[i];
+            const TS wr = w[(long long)((r[i] >> 6) & 7) * N + z + (r[i] >> 9)];
+            if (we) we[i] = wr;
+            wi[i] = Conv<TS, TA>::ld(wr);
+        }
+    }
+    double d = 0.0;
+    Slots<DIM, WIDE> sl;
+    sl.load(sb, z);
+    const Coord p = coords(z, g);
+    for (int q = 0; q < S; ++q) {
+        const double wv = (double)Conv<TS, TA>::ld(w[q * N + z]);
+        for (int sg = -1; sg <= 1; sg += 2) {
+            long long t;
+            if (edge_target<DIM, PER>(p, z, sl.o[q], sg, g, t)) d += wv;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        if (i < c) d += (double)wi[i];
     return d;
 }
 
@@ -428,7 +482,8 @@ __global__ __launch_bounds__(256) void k_bin_build(
     GridInfo g, const uint32_t *__restrict__ bincnt, const uint32_t *__restrict__ binoff,
     const int2 *__restrict__ binbuf, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
     const TS *__restrict__ w, int32_t *__restrict__ pos, uint8_t *__restrict__ cnt,
-    int32_t *__restrict__ ent, TD *__restrict__ diag, double *__restrict__ dpart, int32_t *status) {
+    int32_t *__restrict__ ent, TS *__restrict__ went, TD *__restrict__ diag,
+    double *__restrict__ dpart, int32_t *status) {
     __shared__ int32_t lcnt[kBin];
     __shared__ int32_t loff[kBin];
     __shared__ int32_t scan[256];
@@ -484,25 +539,44 @@ __global__ __launch_bounds__(256) void k_bin_build(
         const long long z = t0 + tl;
         if (z >= N) continue;
         const int c = min(lcnt[tl], 255);
-        int32_t *e = ent + base + loff[tl];
-        sort_row(e, c);
-        const double d = row_diag<DIM, WIDE, PER, TS, TA>(g, z, e, c, sb, w);
+        const double d = sort_row_diag<DIM, WIDE, PER, TS, TA>(g, z, ent + base + loff[tl], c, sb,
+                                                               w, went + base + loff[tl]);
         diag[z] = (TD)d;
         dmax = fmax(dmax, d);
     }
     block_partial_max(dmax, dpart);
 }
 
+// Block-level exclusive scan helpers (blockDim.x == 256, 4 items per thread).
+__device__ int32_t block_excl_scan256(int32_t v, int32_t *lds, int32_t &total) {
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const int32_t add = t >= d ? lds[t - d] : 0;
+        __syncthreads();
+        lds[t] += add;
+        __syncthreads();
+    }
+    total = lds[255];
+    const int32_t incl = lds[t];
+    __syncthreads();
+    return incl - v;
+}
+
 // ------------------------------------------- 2D tile-gather assembly --
 // The incoming lists of a 2D grid are built without any global atomics.
-// Every block owns a kTile x kTile tile of targets; since an edge never
-// reaches further than R (the largest offset component), all edges into the
-// tile start in the tile grown by R on each side (clipped to a Neumann grid,
-// wrapped and capped at the grid size on a periodic one).  The block scans
-// those sources and counts (pass 1) or places (pass 2) the edges that land
-// in its tile with LDS atomics.  Sources are read about (kTile + 2R)^2 /
-// kTile^2 times in all, from L2 for neighbouring tiles.
+// Every block owns a kTile x kTile tile of targets and scans the sources of
+// the edges that can land in it, counting (pass 1) or placing (pass 2) those
+// that do with LDS atomics.  On a Neumann grid each source tile S carries its
+// own reach r_S (largest offset component over its edges of positive
+// weight), so only the band of S within r_S of the target tile is scanned:
+// where the tensor field is near isotropic the bands are one point wide and
+// the sources are read about once, whatever the largest offset elsewhere.
+// On a periodic grid the window is the tile grown by the global R on each
+// side (wrapped and capped at the grid size).
 constexpr int kTile = 64;
+constexpr int kBrick = 4;
 
 // The window of sources along one axis for the tile [t0, t0 + tw).
 struct Window {
@@ -523,8 +597,8 @@ template <bool PER> __device__ inline Window window_axis(int t0, int tw, int R, 
 // Visit every edge (source -> target in this tile) once: f(target local
 // index, target linear index, entry).
 template <bool WIDE, bool PER, typename F>
-__device__ inline void tile_edges(const GridInfo &g, int x0, int y0, int tw, int th, int R,
-                                  const typename Slots<2, WIDE>::store_t *__restrict__ sb,
+__device__ inline void tile_edges(const GridInfo &g, int x0, int y0, int tw, int th, int stride,
+                                  int R, const typename Slots<2, WIDE>::store_t *__restrict__ sb,
                                   const uint8_t *__restrict__ mask, F f) {
     const Window wx = window_axis<PER>(x0, tw, R, g.nx);
     const Window wy = window_axis<PER>(y0, th, R, g.ny);
@@ -556,27 +630,194 @@ __device__ inline void tile_edges(const GridInfo &g, int x0, int y0, int tw, int
                 if (!edge_target<2, PER>(p, z, sl.o[q], sg, g, t)) continue;
                 if (z - t >= (1ll << 22) || z - t <= -(1ll << 22)) continue;  // flagged earlier
                 const int32_t e = (int32_t)(((z - t) << 9) | (q << 6) | (t & 63));
-                f((ty - y0) * kTile + (tx - x0), t, e);
+                f((ty - y0) * stride + (tx - x0), t, e, z, 2 * q + (sg > 0));
             }
         }
     }
 }
 
-// Pass 1: incoming count of every target (clamped to 255, flagged above).
+// The edges of positive weight from source (x, y) into the rectangle
+// [x0, x0 + tw) x [y0, y0 + th) (Neumann grid): f(local index, target,
+// entry, source, edge index 2q + (sign > 0)).
+template <bool WIDE, typename F>
+__device__ inline void source_edges(const GridInfo &g, int x, int y, int x0, int y0, int tw,
+                                    int th, int stride,
+                                    const typename Slots<2, WIDE>::store_t *__restrict__ sb,
+                                    const uint8_t *__restrict__ mask, F f) {
+    const long long z = x + (long long)g.nx * y;
+    Slots<2, WIDE> sl;
+    sl.load(sb, z);  // issued with the mask load, not after it
+    const unsigned m = mask[z];
+    if (!m) return;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (!(m & (1u << q))) continue;
+#pragma unroll
+        for (int sg = -1; sg <= 1; sg += 2) {
+            const int tx = x + sg * sl.o[q][0], ty = y + sg * sl.o[q][1];
+            if (tx < x0 || tx >= x0 + tw || ty < y0 || ty >= y0 + th) continue;
+            const long long t = tx + (long long)g.nx * ty;
+            if (z - t >= (1ll << 22) || z - t <= -(1ll << 22)) continue;  // flagged earlier
+            const int32_t e = (int32_t)(((z - t) << 9) | (q << 6) | (t & 63));
+            f((ty - y0) * stride + (tx - x0), t, e, z, 2 * q + (sg > 0));
+        }
+    }
+}
+
+// The bricks of [bxa, bxa + nbw) x [bya, bya + nbh) whose reach box meets
+// the target rectangle go to the LDS list (at most `nbw * nbh` entries), then
+// every point of every listed brick is visited, one thread per point.
+// Block-uniform (barriers).
+template <bool WIDE, typename F>
+__device__ inline void brick_pass(const GridInfo &g, int x0, int y0, int tw, int th, int stride,
+                                  int bxa, int bya, int nbw, int nbh,
+                                  const int32_t *__restrict__ brmax,
+                                  const typename Slots<2, WIDE>::store_t *__restrict__ sb,
+                                  const uint8_t *__restrict__ mask, int32_t *list, int32_t *nlist,
+                                  F f) {
+    const int nbx = (g.nx + kBrick - 1) / kBrick;
+    if (threadIdx.x == 0) *nlist = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < nbw * nbh; k += blockDim.x) {
+        const int bi = bxa + k % nbw, bj = bya + k / nbw;
+        const int rb = brmax[bj * nbx + bi];
+        if (bi * kBrick - rb < x0 + tw && (bi + 1) * kBrick + rb > x0 &&
+            bj * kBrick - rb < y0 + th && (bj + 1) * kBrick + rb > y0)
+            list[atomicAdd(nlist, 1)] = bj * nbx + bi;
+    }
+    __syncthreads();
+    const int n = *nlist;
+    constexpr int BB = kBrick * kBrick;
+    for (int k = threadIdx.x; k < n * BB; k += blockDim.x) {
+        const int br = list[k / BB], p = k % BB;
+        const int x = (br % nbx) * kBrick + p % kBrick, y = (br / nbx) * kBrick + p / kBrick;
+        if (x < g.nx && y < g.ny) source_edges<WIDE>(g, x, y, x0, y0, tw, th, stride, sb, mask, f);
+    }
+    __syncthreads();
+}
+
+// Every edge into the target rectangle [x0, x0 + tw) x [y0, y0 + th) (f gets
+// the local index (ty - y0) * stride + (tx - x0)).  Neumann grid: a
+// kBrick x kBrick brick of sources is visited only if its reach brmax
+// reaches the rectangle.  When the bricks within the global reach R of the
+// rectangle are at most CAP, they are tested in one pass; otherwise kTile
+// source tile by source tile, skipping the part of each tile beyond its own
+// reach trmax.  list: LDS scratch of CAP + 1 ints (CAP >= (kTile/kBrick)^2).
+// Block-uniform control flow (contains barriers).
+template <bool WIDE, bool PER, int CAP, typename F>
+__device__ inline void tile_sources(const GridInfo &g, int x0, int y0, int tw, int th, int stride,
+                                    int R, const int32_t *__restrict__ trmax,
+                                    const int32_t *__restrict__ brmax,
+                                    const typename Slots<2, WIDE>::store_t *__restrict__ sb,
+                                    const uint8_t *__restrict__ mask, int32_t *list, F f) {
+    static_assert(CAP >= (kTile / kBrick) * (kTile / kBrick), "a tile's bricks fit the list");
+    if (PER) {
+        tile_edges<WIDE, PER>(g, x0, y0, tw, th, stride, R, sb, mask, f);
+        return;
+    }
+    int32_t *nlist = list + CAP;
+    {
+        const int bxa = max(0, x0 - R) / kBrick, bxb = min(g.nx - 1, x0 + tw - 1 + R) / kBrick;
+        const int bya = max(0, y0 - R) / kBrick, byb = min(g.ny - 1, y0 + th - 1 + R) / kBrick;
+        const long long nc = (long long)(bxb - bxa + 1) * (byb - bya + 1);
+        if (nc <= CAP) {
+            brick_pass<WIDE>(g, x0, y0, tw, th, stride, bxa, bya, bxb - bxa + 1, byb - bya + 1,
+                             brmax, sb, mask, list, nlist, f);
+            return;
+        }
+    }
+    const int ntx = (g.nx + kTile - 1) / kTile, nty = (g.ny + kTile - 1) / kTile;
+    const int sxa = max(0, x0 - R) / kTile, sxb = min(ntx - 1, (x0 + tw - 1 + R) / kTile);
+    const int sya = max(0, y0 - R) / kTile, syb = min(nty - 1, (y0 + th - 1 + R) / kTile);
+    for (int sy = sya; sy <= syb; ++sy)
+        for (int sx = sxa; sx <= sxb; ++sx) {
+            const int r = trmax[sy * ntx + sx];
+            const int sx0 = sx * kTile, sy0 = sy * kTile;
+            const int ax = max(sx0, x0 - r), bx = min(min(sx0 + kTile, g.nx), x0 + tw + r);
+            const int ay = max(sy0, y0 - r), by = min(min(sy0 + kTile, g.ny), y0 + th + r);
+            if (ax >= bx || ay >= by) continue;
+            const int bxa = ax / kBrick, bya = ay / kBrick;
+            brick_pass<WIDE>(g, x0, y0, tw, th, stride, bxa, bya, (bx - 1) / kBrick - bxa + 1,
+                             (by - 1) / kBrick - bya + 1, brmax, sb, mask, list, nlist, f);
+        }
+}
+
+// Reach of every kBrick x kBrick brick (brmax) and of every kTile x kTile
+// tile (trmax): the largest offset component over the edges of positive
+// weight that start in it.  One block per tile, one thread per brick.
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_tile_rmax(GridInfo g,
+                                                   const typename Slots<2, WIDE>::store_t *__restrict__ sb,
+                                                   const uint8_t *__restrict__ mask,
+                                                   int32_t *__restrict__ trmax,
+                                                   int32_t *__restrict__ brmax) {
+    static_assert((kTile / kBrick) * (kTile / kBrick) == 256, "one brick per thread");
+    __shared__ int red[4];
+    const int ntx = (g.nx + kTile - 1) / kTile;
+    const int nbx = (g.nx + kBrick - 1) / kBrick, nby = (g.ny + kBrick - 1) / kBrick;
+    const int bi = (int)(blockIdx.x % ntx) * (kTile / kBrick) + (int)threadIdx.x % (kTile / kBrick);
+    const int bj = (int)(blockIdx.x / ntx) * (kTile / kBrick) + (int)threadIdx.x / (kTile / kBrick);
+    int r = 0;
+    if (bi < nbx && bj < nby) {
+        for (int p = 0; p < kBrick * kBrick; ++p) {
+            const int x = bi * kBrick + p % kBrick, y = bj * kBrick + p / kBrick;
+            if (x >= g.nx || y >= g.ny) continue;
+            const long long z = x + (long long)g.nx * y;
+            const unsigned m = mask[z];
+            if (!m) continue;
+            Slots<2, WIDE> sl;
+            sl.load(sb, z);
+            for (int q = 0; q < 3; ++q)
+                if (m & (1u << q)) r = max(r, max(abs(sl.o[q][0]), abs(sl.o[q][1])));
+        }
+        brmax[bj * nbx + bi] = r;
+    }
+    for (int d = 32; d > 0; d >>= 1) r = max(r, __shfl_xor(r, d));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) trmax[blockIdx.x] = max(max(red[0], red[1]), max(red[2], red[3]));
+}
+
+// R = the largest tile reach.
+__global__ __launch_bounds__(256) void k_rmax_tiles(const int32_t *__restrict__ trmax, long long n,
+                                                    int32_t *R) {
+    __shared__ int red[4];
+    int r = 0;
+    for (long long k = threadIdx.x; k < n; k += blockDim.x) r = max(r, trmax[k]);
+    for (int d = 32; d > 0; d >>= 1) r = max(r, __shfl_xor(r, d));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) *R = max(max(red[0], red[1]), max(red[2], red[3]));
+}
+
+// Pass 1: incoming count of every target (clamped to 255, flagged above),
+// and the rank of every edge in its target's row (rank[2q + (sign > 0)][z]
+// for the edge of slot q and that sign from source z; 255 = beyond the
+// clamp).  The ranks of one row are distinct and in no fixed order: the row
+// is sorted once placed.
 template <bool WIDE, bool PER>
 __global__ __launch_bounds__(256) void k_tile_count(GridInfo g,
                                                     const typename Slots<2, WIDE>::store_t *__restrict__ sb,
                                                     const uint8_t *__restrict__ mask,
                                                     const int32_t *__restrict__ Rp,
-                                                    uint8_t *__restrict__ cnt, int32_t *status) {
+                                                    const int32_t *__restrict__ trmax,
+                                                    const int32_t *__restrict__ brmax,
+                                                    uint8_t *__restrict__ cnt,
+                                                    uint8_t *__restrict__ rank, int32_t *status) {
     __shared__ int32_t lc[kTile * kTile];
+    constexpr int CAP = (kTile + 128) / kBrick * ((kTile + 128) / kBrick);  // one pass for R <= 64
+    __shared__ int32_t list[CAP + 1];
     const int ntx = (g.nx + kTile - 1) / kTile;
     const int x0 = (int)(blockIdx.x % ntx) * kTile, y0 = (int)(blockIdx.x / ntx) * kTile;
     const int tw = min(kTile, g.nx - x0), th = min(kTile, g.ny - y0);
     for (int k = threadIdx.x; k < kTile * kTile; k += blockDim.x) lc[k] = 0;
     __syncthreads();
-    tile_edges<WIDE, PER>(g, x0, y0, tw, th, *Rp, sb, mask,
-                          [&](int tl, long long, int32_t) { atomicAdd(&lc[tl], 1); });
+    const long long N = g.N;
+    tile_sources<WIDE, PER, CAP>(g, x0, y0, tw, th, kTile, *Rp, trmax, brmax, sb, mask, list,
+                                 [&](int tl, long long, int32_t, long long z, int k) {
+                                     const int r = atomicAdd(&lc[tl], 1);
+                                     rank[k * N + z] = (uint8_t)min(r, 255);
+                                 });
     __syncthreads();
     for (int k = threadIdx.x; k < tw * th; k += blockDim.x) {
         const int lx = k % tw, ly = k / tw;
@@ -636,49 +877,60 @@ __global__ __launch_bounds__(256) void k_chunk_pos(const uint8_t *__restrict__ c
     }
 }
 
-// Pass 2: place the entries of every target of the tile, sort each row,
-// diagonal A_zz and the tile's largest diagonal (dpart).
-template <bool WIDE, bool PER, typename TS, typename TA, typename TD>
-__global__ __launch_bounds__(256) void k_tile_fill(GridInfo g,
-                                                   const typename Slots<2, WIDE>::store_t *__restrict__ sb,
-                                                   const uint8_t *__restrict__ mask,
-                                                   const TS *__restrict__ w,
-                                                   const int32_t *__restrict__ Rp,
-                                                   const uint8_t *__restrict__ cnt,
-                                                   const int32_t *__restrict__ pos,
-                                                   int32_t *__restrict__ ent, TD *__restrict__ diag,
-                                                   double *__restrict__ dpart) {
-    __shared__ int32_t lcur[kTile * kTile];
-    __shared__ int32_t lpos[kTile * kTile];
-    __shared__ int32_t lcnt[kTile * kTile];
-    const int ntx = (g.nx + kTile - 1) / kTile;
-    const int x0 = (int)(blockIdx.x % ntx) * kTile, y0 = (int)(blockIdx.x / ntx) * kTile;
-    const int tw = min(kTile, g.nx - x0), th = min(kTile, g.ny - y0);
-    for (int k = threadIdx.x; k < kTile * kTile; k += blockDim.x) {
-        lcur[k] = 0;
-        const int lx = k % kTile, ly = k / kTile;
-        const bool in = lx < tw && ly < th;
-        const long long t = (x0 + lx) + (long long)g.nx * (y0 + ly);
-        lpos[k] = in ? pos[t] : 0;
-        lcnt[k] = in ? cnt[t] : 0;
+// Pass 2: every source places its edges at pos[target] + rank (no atomics,
+// one thread per source, the same edges as pass 1).
+template <bool WIDE, bool PER>
+__global__ __launch_bounds__(256) void k_place2d(GridInfo g,
+                                                 const typename Slots<2, WIDE>::store_t *__restrict__ sb,
+                                                 const uint8_t *__restrict__ mask,
+                                                 const uint8_t *__restrict__ rank,
+                                                 const int32_t *__restrict__ pos,
+                                                 int32_t *__restrict__ ent) {
+    const long long N = g.N;
+    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= N) return;
+    Slots<2, WIDE> sl;
+    sl.load(sb, z);
+    const unsigned m = mask[z];
+    if (!m) return;
+    uint8_t rk[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) rk[k] = rank[k * N + z];
+    const Coord p = coords(z, g);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (!(m & (1u << q))) continue;
+#pragma unroll
+        for (int sg = -1; sg <= 1; sg += 2) {
+            long long t;
+            if (!edge_target<2, PER>(p, z, sl.o[q], sg, g, t)) continue;
+            if (z - t >= (1ll << 22) || z - t <= -(1ll << 22)) continue;  // flagged earlier
+            const int r = rk[2 * q + (sg > 0)];
+            if (r == 255) continue;
+            ent[(long long)pos[t] + r] = (int32_t)(((z - t) << 9) | (q << 6) | (t & 63));
+        }
     }
-    __syncthreads();
-    // a row never takes more entries than pass 1 counted (clamped to 255)
-    tile_edges<WIDE, PER>(g, x0, y0, tw, th, *Rp, sb, mask, [&](int tl, long long, int32_t e) {
-        const int k = atomicAdd(&lcur[tl], 1);
-        if (k < lcnt[tl]) ent[(long long)lpos[tl] + k] = e;
-    });
-    __syncthreads();
+}
+
+// Pass 3: sort every row, store the weight of each entry beside it (went,
+// where not null), take the diagonal A_zz and the block's largest diagonal
+// (dpart), one thread per target.
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TD>
+__global__ __launch_bounds__(256) void k_rows(GridInfo g,
+                                              const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                                              const TS *__restrict__ w,
+                                              const uint8_t *__restrict__ cnt,
+                                              const int32_t *__restrict__ pos,
+                                              int32_t *__restrict__ ent, TS *__restrict__ went,
+                                              TD *__restrict__ diag, double *__restrict__ dpart) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double dmax = 0.0;
-    for (int k = threadIdx.x; k < tw * th; k += blockDim.x) {
-        const int lx = k % tw, ly = k / tw;
-        const long long t = (x0 + lx) + (long long)g.nx * (y0 + ly);
-        const int c = lcnt[ly * kTile + lx];
-        int32_t *e = ent + lpos[ly * kTile + lx];
-        sort_row(e, c);
-        const double d = row_diag<2, WIDE, PER, TS, TA>(g, t, e, c, sb, w);
+    if (t < g.N) {
+        const int p = pos[t];
+        const double d = sort_row_diag<DIM, WIDE, PER, TS, TA>(g, t, ent + p, (int)cnt[t], sb, w,
+                                                               went ? went + p : nullptr);
         diag[t] = (TD)d;
-        dmax = fmax(dmax, d);
+        dmax = d;
     }
     block_partial_max(dmax, dpart);
 }
@@ -688,22 +940,6 @@ __global__ void k_copy_u32(const uint32_t *a, uint32_t *b, long long n) {
     if (i < n) b[i] = a[i];
 }
 
-// Block-level exclusive scan helpers (blockDim.x == 256, 4 items per thread).
-__device__ int32_t block_excl_scan256(int32_t v, int32_t *lds, int32_t &total) {
-    const int t = threadIdx.x;
-    lds[t] = v;
-    __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
-        const int32_t add = t >= d ? lds[t - d] : 0;
-        __syncthreads();
-        lds[t] += add;
-        __syncthreads();
-    }
-    total = lds[255];
-    const int32_t incl = lds[t];
-    __syncthreads();
-    return incl - v;
-}
 
 __global__ void k_scan_top(int32_t *bsum, long long nb) {
     __shared__ int32_t lds[256];
@@ -743,6 +979,13 @@ __device__ __forceinline__ unsigned wave_incl_scan(unsigned v) {
 // wave own the entries [start, start + total) in row order; this lane's row
 // owns [lo, hi) relative to start.  pos holds every row's start and, at
 // index N, the total entry count, so no scan is needed.
+// Where the weight of an incoming edge is read: from the list of entry
+// weights beside the entries (3D: a gather from the source's slot plane
+// would touch another plane of the grid) or from the source's own weights
+// (2D: those lines are in cache from the own part of nearby rows, and the
+// gather costs less than streaming a second list).
+template <int DIM> constexpr bool kInlineW = DIM == 3;
+
 struct WaveLists {
     int start;
     unsigned total, lo, hi;
@@ -807,10 +1050,12 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TU> s
 constexpr int kPre = 4;
 
 // Chunk [e0, e0 + 64) of a wave's entries: this lane's edge value
-// w_slot(y) (u(row) - u(y)), 0 past the end.  All 64 lanes must call it.
-template <typename TS, typename TA, typename TU>
+// w_slot(y) (u(row) - u(y)), 0 past the end; the weight is wv (INLINE_W,
+// loaded from the entry weights with the entry) or gathered from w.  All 64
+// lanes must call it.
+template <bool INLINE_W, typename TS, typename TA, typename TU>
 __device__ __forceinline__ TA incoming_edge(const WaveLists &L, long long z0, long long N, TA uz,
-                                            int32_t v, unsigned e0, const TU *__restrict__ u,
+                                            int32_t v, TS wv, unsigned e0, const TU *__restrict__ u,
                                             const TS *__restrict__ w) {
     const int lane = (int)(threadIdx.x & 63u);
     const bool ok = e0 + lane < L.total;
@@ -818,7 +1063,7 @@ __device__ __forceinline__ TA incoming_edge(const WaveLists &L, long long z0, lo
     TA wy = (TA)0, uy = (TA)0;
     if (ok) {  // N < 2^28 points, S N < 2^31: 32-bit indices
         const int y = (int)z0 + (v & 63) + (v >> 9);
-        wy = Conv<TS, TA>::ld(w[(unsigned)(((v >> 6) & 7) * (int)N + y)]);
+        wy = Conv<TS, TA>::ld(INLINE_W ? wv : w[(unsigned)(((v >> 6) & 7) * (int)N + y)]);
         uy = Conv<TU, TA>::ld(u[(unsigned)y]);
     }
     return ok ? wy * (ur - uy) : (TA)0;
@@ -877,24 +1122,28 @@ __device__ __forceinline__ TA incoming_reduce(const WaveLists &L, int32_t v, TA 
 // Up to kPre chunks are loaded before any is reduced, so their memory
 // latencies overlap.  The order of additions is fixed, so the result is
 // deterministic.  All 64 lanes must call this.
-template <typename TS, typename TA, typename TU>
+template <bool INLINE_W, typename TS, typename TA, typename TU>
 __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, long long N, TA uz,
                                             const TU *__restrict__ u, const TS *__restrict__ w,
-                                            const int32_t *__restrict__ ent) {
+                                            const int32_t *__restrict__ ent,
+                                            const TS *__restrict__ went) {
     const int lane = (int)(threadIdx.x & 63u);
     const long long z0 = z & ~63ll;
     TA acc = (TA)0;
     for (unsigned eb = 0; eb < L.total; eb += 64 * kPre) {
         int32_t v[kPre];
+        TS wv[kPre];
         TA val[kPre];
 #pragma unroll
         for (int j = 0; j < kPre; ++j) {
             const unsigned e = eb + 64 * j + lane;
             v[j] = e < L.total ? ent[L.start + e] : -1;
+            wv[j] = INLINE_W && e < L.total ? went[L.start + e] : TS{};
         }
 #pragma unroll
         for (int j = 0; j < kPre; ++j)
-            val[j] = incoming_edge<TS, TA, TU>(L, z0, N, uz, v[j], eb + 64 * j, u, w);
+            val[j] = incoming_edge<INLINE_W, TS, TA, TU>(L, z0, N, uz, v[j], wv[j], eb + 64 * j, u,
+                                                         w);
 #pragma unroll
         for (int j = 0; j < kPre; ++j) acc += incoming_reduce<TA>(L, v[j], val[j], eb + 64 * j);
     }
@@ -913,7 +1162,7 @@ __device__ __forceinline__ void apply_block(
     const GridInfo &g, long long blk, const TS *__restrict__ u, TS *__restrict__ out,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, TA h) {
+    const int32_t *__restrict__ ent, const TS *__restrict__ went, TA h) {
     constexpr int P = kApplyPPT;
     const long long N = g.N;
     const int lane = (int)(threadIdx.x & 63u);
@@ -937,6 +1186,7 @@ __device__ __forceinline__ void apply_block(
     }
     for (unsigned eb = 0; eb < tmax; eb += 64 * kPre) {
         int32_t v[P][kPre];
+        TS wv[P][kPre];
         TA val[P][kPre];
 #pragma unroll
         for (int k = 0; k < P; ++k)
@@ -944,13 +1194,14 @@ __device__ __forceinline__ void apply_block(
             for (int j = 0; j < kPre; ++j) {
                 const unsigned e = eb + 64 * j + lane;
                 v[k][j] = e < L[k].total ? ent[L[k].start + e] : -1;
+                wv[k][j] = kInlineW<DIM> && e < L[k].total ? went[L[k].start + e] : TS{};
             }
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
             for (int j = 0; j < kPre; ++j)
-                val[k][j] = incoming_edge<TS, TA, TS>(L[k], zw + 64 * k, N, uz[k], v[k][j],
-                                                      eb + 64 * j, u, w);
+                val[k][j] = incoming_edge<kInlineW<DIM>, TS, TA, TS>(
+                    L[k], zw + 64 * k, N, uz[k], v[k][j], wv[k][j], eb + 64 * j, u, w);
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
@@ -971,10 +1222,12 @@ __global__ __launch_bounds__(kBS) void k_apply(
     GridInfo g, const TS *__restrict__ u, TS *__restrict__ out,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, double dt, const double *__restrict__ dtcfl, int dt_mode) {
+    const int32_t *__restrict__ ent, const TS *__restrict__ went, double dt,
+    const double *__restrict__ dtcfl, int dt_mode) {
     const TA h = (TA)(dt_mode == ADLBR_DT_CFL ? dt * dtcfl[0] : dt);
-    apply_block<DIM, WIDE, PER, STEP, TS, TA>(g, xcd_block(blockIdx.x, gridDim.x), u, out, sb, w,
-                                              cnt, pos, ent, h);
+    apply_block<DIM, WIDE, PER, STEP, TS, TA>(
+        g, strip_block(xcd_block(blockIdx.x, gridDim.x), g, kApplyPoints), u, out, sb, w, cnt,
+        pos, ent, went, h);
 }
 
 // The problem that block b belongs to (first_block ascending): the lanes of
@@ -1007,8 +1260,9 @@ __global__ __launch_bounds__(kBS) void k_apply_batch(const BatchProb *__restrict
     const GridInfo g = P.g;
     const TA h = (TA)(P.dt_mode == ADLBR_DT_CFL ? P.dt * P.dtcfl[0] : P.dt);
     apply_block<DIM, WIDE, PER, true, TS, TA>(
-        g, b - P.first_block, (const TS *)P.u[parity], (TS *)P.u[parity ^ 1],
-        (const typename Slots<DIM, WIDE>::store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent, h);
+        g, strip_block(b - P.first_block, g, kApplyPoints), (const TS *)P.u[parity], (TS *)P.u[parity ^ 1],
+        (const typename Slots<DIM, WIDE>::store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent,
+        (const TS *)P.went, h);
 }
 
 // dst = src for every problem (u[1] -> u[0] after an odd number of steps).
@@ -1032,7 +1286,8 @@ __global__ __launch_bounds__(kBS) void k_cg_direction(
     GridInfo g, const T *__restrict__ zv, T *__restrict__ q, T *__restrict__ p,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const T *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, const CgState *st, double *partial, int first) {
+    const int32_t *__restrict__ ent, const T *__restrict__ went, const CgState *st,
+    double *partial, int first) {
     const long long N = g.N;
     const long long blk = xcd_block(blockIdx.x, gridDim.x);
     const long long z = blk * kBS + threadIdx.x;
@@ -1043,7 +1298,7 @@ __global__ __launch_bounds__(kBS) void k_cg_direction(
     const T zz = live ? zv[z] : (T)0;
     OwnPart<DIM, WIDE, PER, T, T, T> own;
     own.issue(g, z, live && !skip, zz, zv, sb, w);
-    T acc = skip ? (T)0 : wave_incoming<T, T, T>(L, z, N, zz, zv, w, ent);
+    T acc = skip ? (T)0 : wave_incoming<kInlineW<DIM>, T, T, T>(L, z, N, zz, zv, w, ent, went);
     if (live && !skip) {
         acc += own.sum(zz);
         const T dt = (T)st->dt;
@@ -1080,7 +1335,8 @@ __global__ __launch_bounds__(kBS) void k_residual(
     GridInfo g, const T *__restrict__ b, const double *__restrict__ x,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const T *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, double dt, double *partial, T *__restrict__ rout) {
+    const int32_t *__restrict__ ent, const T *__restrict__ went, double dt, double *partial,
+    T *__restrict__ rout) {
     const long long N = g.N;
     const long long z = (long long)blockIdx.x * kBS + threadIdx.x;
     const bool live = z < N;
@@ -1089,7 +1345,7 @@ __global__ __launch_bounds__(kBS) void k_residual(
     const double xz = live ? x[z] : 0.0;
     OwnPart<DIM, WIDE, PER, T, double, double> own;
     own.issue(g, z, live, xz, x, sb, w);
-    double ax = wave_incoming<T, double, double>(L, z, N, xz, x, w, ent);
+    double ax = wave_incoming<kInlineW<DIM>, T, double, double>(L, z, N, xz, x, w, ent, went);
     if (live) {
         ax += own.sum(xz);
         const double r = (double)b[z] - (xz + dt * ax);
@@ -1123,40 +1379,46 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
     }
     if (win_f64)
         hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, double, TS, TA, BINS>), dim3(nb), dim3(kBS), 0,
-                           s, g, off, (const double *)win, sb, w, op->mask, op->part, op->bincnt,
+                           s, g, off, (const double *)win, sb, w, op->mask, op->bincnt,
                            status);
     else
         hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, float, TS, TA, BINS>), dim3(nb), dim3(kBS), 0,
-                           s, g, off, (const float *)win, sb, w, op->mask, op->part, op->bincnt,
+                           s, g, off, (const float *)win, sb, w, op->mask, op->bincnt,
                            status);
-    hipLaunchKernelGGL(k_rmax_fin, dim3(1), dim3(256), 0, s, (const double *)op->part,
-                       (long long)nb, op->rmax);
     long long nparts;
     if (DIM == 2) {
         const int ntx = (g.nx + kTile - 1) / kTile, nty = (g.ny + kTile - 1) / kTile;
         const unsigned ntiles = (unsigned)(ntx * nty);
         const unsigned nchunk = (unsigned)nbins;  // 1024-point chunks
+        hipLaunchKernelGGL((k_tile_rmax<WIDE>), dim3(ntiles), dim3(256), 0, s, g,
+                           (const typename Slots<2, WIDE>::store_t *)op->sb,
+                           (const uint8_t *)op->mask, op->trmax, op->brmax);
+        hipLaunchKernelGGL(k_rmax_tiles, dim3(1), dim3(256), 0, s, (const int32_t *)op->trmax,
+                           (long long)ntiles, op->rmax);
         hipLaunchKernelGGL((k_tile_count<WIDE, PER>), dim3(ntiles), dim3(256), 0, s, g,
                            (const typename Slots<2, WIDE>::store_t *)op->sb, (const uint8_t *)op->mask,
-                           (const int32_t *)op->rmax, op->cnt, status);
+                           (const int32_t *)op->rmax, (const int32_t *)op->trmax,
+                           (const int32_t *)op->brmax, op->cnt, op->rank, status);
         hipLaunchKernelGGL(k_chunk_sum, dim3(nchunk), dim3(256), 0, s, (const uint8_t *)op->cnt, N,
                            (int32_t *)op->bincnt);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, (int32_t *)op->bincnt, nbins);
         hipLaunchKernelGGL(k_chunk_pos, dim3(nchunk), dim3(256), 0, s, (const uint8_t *)op->cnt, N,
                            (const int32_t *)op->bincnt, op->pos);
+        hipLaunchKernelGGL((k_place2d<WIDE, PER>), dim3(nb), dim3(256), 0, s, g,
+                           (const typename Slots<2, WIDE>::store_t *)op->sb,
+                           (const uint8_t *)op->mask, (const uint8_t *)op->rank,
+                           (const int32_t *)op->pos, op->ent);
         if (op->storage == ADLBR_F64)
-            hipLaunchKernelGGL((k_tile_fill<WIDE, PER, TS, TA, double>), dim3(ntiles), dim3(256), 0,
-                               s, g, (const typename Slots<2, WIDE>::store_t *)op->sb,
-                               (const uint8_t *)op->mask, (const TS *)w, (const int32_t *)op->rmax,
-                               (const uint8_t *)op->cnt, (const int32_t *)op->pos, op->ent,
-                               (double *)op->diag, op->part);
+            hipLaunchKernelGGL((k_rows<DIM, WIDE, PER, TS, TA, double>), dim3(nb), dim3(256), 0, s,
+                               g, (const store_t *)op->sb, (const TS *)w, (const uint8_t *)op->cnt,
+                               (const int32_t *)op->pos, op->ent, (TS *)op->went, (double *)op->diag,
+                               op->part);
         else
-            hipLaunchKernelGGL((k_tile_fill<WIDE, PER, TS, TA, float>), dim3(ntiles), dim3(256), 0,
-                               s, g, (const typename Slots<2, WIDE>::store_t *)op->sb,
-                               (const uint8_t *)op->mask, (const TS *)w, (const int32_t *)op->rmax,
-                               (const uint8_t *)op->cnt, (const int32_t *)op->pos, op->ent,
-                               (float *)op->diag, op->part);
-        nparts = ntiles;
+            hipLaunchKernelGGL((k_rows<DIM, WIDE, PER, TS, TA, float>), dim3(nb), dim3(256), 0, s,
+                               g, (const store_t *)op->sb, (const TS *)w, (const uint8_t *)op->cnt,
+                               (const int32_t *)op->pos, op->ent, (TS *)op->went, (float *)op->diag,
+                               op->part);
+        nparts = nb;
     } else {
         hipLaunchKernelGGL(k_copy_u32, dim3(nbb), dim3(kBS), 0, s, op->bincnt, op->binoff, nbins);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, (int32_t *)op->binoff, nbins);
@@ -1169,11 +1431,13 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
         if (op->storage == ADLBR_F64)
             hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, double>), dim3((unsigned)nbins),
                                dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w,
-                               op->pos, op->cnt, op->ent, (double *)op->diag, op->part, status);
+                               op->pos, op->cnt, op->ent, (TS *)op->went, (double *)op->diag, op->part,
+                               status);
         else
             hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, float>), dim3((unsigned)nbins),
                                dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w,
-                               op->pos, op->cnt, op->ent, (float *)op->diag, op->part, status);
+                               op->pos, op->cnt, op->ent, (TS *)op->went, (float *)op->diag, op->part,
+                               status);
         nparts = nbins;
     }
     hipLaunchKernelGGL(k_cfl, dim3(1), dim3(256), 0, s, (const double *)op->part, nparts,
@@ -1191,11 +1455,11 @@ int apply_impl(const adlbr_operator *op, const void *u, void *out, bool step, do
     if (step)
         hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, true, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)u, (TS *)out, (const store_t *)op->sb, (const TS *)op->w,
-                           op->cnt, op->pos, op->ent, dt, op->dtcfl, dt_mode);
+                           op->cnt, op->pos, op->ent, (const TS *)op->went, dt, op->dtcfl, dt_mode);
     else
         hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, false, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)u, (TS *)out, (const store_t *)op->sb, (const TS *)op->w,
-                           op->cnt, op->pos, op->ent, dt, op->dtcfl, dt_mode);
+                           op->cnt, op->pos, op->ent, (const TS *)op->went, dt, op->dtcfl, dt_mode);
     return ADLBR_OK;
 }
 
@@ -1253,7 +1517,7 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct BatchF 
                 const unsigned nb = (unsigned)((P.g.N + kApplyPoints - 1) / kApplyPoints);
                 hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, true, TS, TA>), dim3(nb), dim3(kBS), 0, s,
                                    P.g, (const TS *)P.u[parity], (TS *)P.u[parity ^ 1],
-                                   (const store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent, P.dt,
+                                   (const store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent, (const TS *)P.went, P.dt,
                                    P.dtcfl, P.dt_mode);
             }
             return ADLBR_OK;
@@ -1281,7 +1545,8 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct CgDirF 
         if (op->storage != ADLBR_F32 && op->storage != ADLBR_F64) return ADLBR_E_UNSUPPORTED;
         hipLaunchKernelGGL((k_cg_direction<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)z, (TS *)q, (TS *)p, (const store_t *)op->sb,
-                           (const TS *)op->w, op->cnt, op->pos, op->ent, (const CgState *)st,
+                           (const TS *)op->w, op->cnt, op->pos, op->ent, (const TS *)op->went,
+                           (const CgState *)st,
                            partial, first);
         hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kBS), 0, s, st, (const double *)partial,
                            (long long)nb);
@@ -1309,7 +1574,7 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct Residua
         const unsigned nb = (unsigned)((g.N + kBS - 1) / kBS);
         hipLaunchKernelGGL((k_residual<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)b, x, (const store_t *)op->sb, (const TS *)op->w, op->cnt,
-                           op->pos, op->ent, dt, partial, (TS *)rout);
+                           op->pos, op->ent, (const TS *)op->went, dt, partial, (TS *)rout);
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBS), 0, s, (const double *)partial,
                            (long long)nb, out);
         return ADLBR_OK;
@@ -1329,7 +1594,7 @@ template <int DIM, bool WIDE, bool PER> struct ResidualF<DIM, WIDE, PER, _Float1
 };
 
 struct Layout {
-    size_t sb, w, cnt, pos, ent, diag, scal, mask, part, bincnt, bincur, binoff, binbuf, total;
+    size_t sb, w, cnt, pos, ent, went, diag, scal, mask, part, trmax, brmax, rank, bincnt, bincur, binoff, binbuf, total;
 };
 
 Layout layout(const GridInfo &g, int storage, int wide) {
@@ -1344,11 +1609,17 @@ Layout layout(const GridInfo &g, int storage, int wide) {
     L.cnt = o;  o += align_up((size_t)N + 64);
     L.pos = o;  o += align_up(4 * (size_t)N + 256);
     L.ent = o;  o += align_up(4 * (size_t)(2 * S) * N);
+    L.went = o; o += g.dim == 3 ? align_up(dtype_size(storage) * (size_t)(2 * S) * N) : 0;
     L.diag = o; o += align_up((storage == ADLBR_F64 ? 8 : 4) * (size_t)N);
     L.scal = o; o += 256;
     L.mask = o; o += align_up((size_t)N + 64);
-    // partials: one per 256-point block, per 2D tile or per 3D bin
-    L.part = o; o += align_up(8 * ((size_t)N / 256 + 64));
+    // partials: one per 256-point block or per 3D bin
+    const size_t ntiles = g.dim == 2 ? (size_t)((g.nx + kTile - 1) / kTile) * ((g.ny + kTile - 1) / kTile) : 0;
+    L.part = o; o += align_up(8 * (std::max((size_t)N / 256, nbins) + 64));
+    L.trmax = o; o += ntiles ? align_up(4 * ntiles) : 0;
+    const size_t nbricks = g.dim == 2 ? (size_t)((g.nx + kBrick - 1) / kBrick) * ((g.ny + kBrick - 1) / kBrick) : 0;
+    L.brmax = o; o += nbricks ? align_up(4 * nbricks) : 0;
+    L.rank = o; o += g.dim == 2 ? align_up(6 * (size_t)N) : 0;
     L.bincnt = o; o += align_up(4 * nbins + 4);
     const bool bins = g.dim == 3;  // the 2D tile assembly needs no bins
     L.bincur = o; o += bins ? align_up(4 * nbins + 4) : 0;
@@ -1371,6 +1642,7 @@ void batch_describe(const adlbr_operator *op, BatchProb *d) {
     d->cnt = op->cnt;
     d->pos = op->pos;
     d->ent = op->ent;
+    d->went = op->went;
     d->dtcfl = op->dtcfl;
 }
 
@@ -1379,9 +1651,10 @@ size_t batch_footprint(const adlbr_operator *op) {
     size_t sbs;
     if (op->gi.dim == 2) sbs = op->wide ? sizeof(Slots<2, true>::store_t) : sizeof(Slots<2, false>::store_t);
     else sbs = op->wide ? sizeof(Slots<3, true>::store_t) : sizeof(Slots<3, false>::store_t);
-    // u and its successor, offsets, weights, count, row start, about one
-    // incoming entry per slot
-    return (size_t)op->gi.N * (2 * ts + sbs + (size_t)op->slots * (ts + 4) + 1 + 4);
+    // u and its successor, offsets, own weights, count, row start, and about
+    // two incoming entries (each with its weight) per slot
+    return (size_t)op->gi.N *
+           (2 * ts + sbs + (size_t)op->slots * ts + 2 * (size_t)op->slots * (4 + ts) + 1 + 4);
 }
 
 int batch_launch(const adlbr_operator *rep, const BatchProb *probs, const BatchProb *hprobs,
@@ -1445,6 +1718,10 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
         set_error("adlbr_operator_create: weights must be F64/F32, storage F64/F32/BF16/F16");
         return ADLBR_E_INVALID;
     }
+    if (flags & ~ADLBR_OP_WIDE) {
+        set_error("adlbr_operator_create: unknown flags 0x%x", flags);
+        return ADLBR_E_INVALID;
+    }
     const int wide = flags & ADLBR_OP_WIDE ? 1 : 0;
     if ((long long)(gi.dim == 2 ? 6 : 12) * gi.N >= (1ll << 31)) {
         set_error("adlbr_operator_create: too many edges for 32-bit list positions");
@@ -1474,12 +1751,16 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
     op->cnt = (uint8_t *)(b + L.cnt);
     op->pos = (int32_t *)(b + L.pos);
     op->ent = (int32_t *)(b + L.ent);
+    op->went = gi.dim == 3 ? b + L.went : nullptr;
     op->diag = b + L.diag;
     op->maxdiag = (double *)(b + L.scal);
     op->dtcfl = (double *)(b + L.scal + 8);
     op->rmax = (int32_t *)(b + L.scal + 16);
     op->mask = (uint8_t *)(b + L.mask);
     op->part = (double *)(b + L.part);
+    op->trmax = (int32_t *)(b + L.trmax);
+    op->brmax = (int32_t *)(b + L.brmax);
+    op->rank = (uint8_t *)(b + L.rank);
     op->bincnt = (uint32_t *)(b + L.bincnt);
     op->bincur = (uint32_t *)(b + L.bincur);
     op->binoff = (uint32_t *)(b + L.binoff);

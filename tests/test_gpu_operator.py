@@ -39,8 +39,16 @@ CASES = [
     ("2d-c1", (64, 64), lambda: synth.tensor2d_field(1301, 64, 64, 10.0), False),
     ("2d-ragged", (97, 61), lambda: synth.tensor2d_field(11, 97, 61, 50.0), False),
     ("2d-periodic", (48, 40), lambda: synth.tensor2d_field(12, 48, 40, 10.0), True),
+    # thin grid: more assembly tiles than 256-point blocks
+    ("2d-thin", (2, 3000), lambda: synth.tensor2d_field(17, 2, 3000, 20.0), False),
+    # large anisotropy: long offsets reach across several 64 x 64 tiles
+    ("2d-reach", (200, 150), lambda: synth.tensor2d_field(18, 200, 150, 250.0), False),
     ("3d", (20, 17, 13), lambda: synth.tensor3d_field(13, (20, 17, 13), 50.0), False),
     ("3d-periodic", (12, 10, 9), lambda: synth.tensor3d_field(14, (12, 10, 9), 10.0), True),
+    # planes of whole 256-point blocks: the strip traversal, with a short last strip
+    ("3d-strips", (32, 16, 13), lambda: synth.tensor3d_field(15, (32, 16, 13), 50.0), False),
+    ("3d-strips-periodic", (16, 16, 11), lambda: synth.tensor3d_field(16, (16, 16, 11), 20.0),
+     True),
 ]
 
 
@@ -74,6 +82,19 @@ def test_wide_offsets_same_result(lib):
     op2 = lib.Operator((80, 70), off, w, storage=torch.float64, wide=True)
     u = torch.from_numpy(synth.uniform(1, op1.N)).cuda()
     assert torch.equal(op1.apply(u), op2.apply(u))
+
+
+def test_wide_long_offsets_fp64(lib):
+    """Offsets beyond int8 (anisotropy 1000: up to 500 points) with int16
+    compact storage, reaching across many 64 x 64 tiles."""
+    import torch
+    dims = (200, 150)
+    D = synth.tensor2d_field(18, *dims, 1000.0)
+    op, A, _, _ = _setup(lib, D, dims, torch.float64, wide=True)
+    u0 = synth.uniform(3, op.N)
+    got = op.apply(torch.from_numpy(u0).cuda()).cpu().numpy()
+    ref = A @ u0
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-12
 
 
 def test_c1_explicit_100_steps_fp64(lib):
