@@ -112,7 +112,7 @@ __global__ void k_features(GridInfo g, const TD *diag, const float *w, const voi
     F[i] = (float)(1.0 / kd);
     double wq[S];
     for (int q = 0; q < S; ++q) {
-        wq[q] = (double)w[q * N + i];
+        wq[q] = (double)w[widx<S>(q, i, N)];
         F[(1 + q) * N + i] = (float)(dt * wq[q] / kd);
     }
     // slots from the compact superbase form

@@ -135,7 +135,7 @@ __device__ inline long long xcd_block(long long b, long long nb) {
 // the other, so blocks one plane apart run close together in time.  The
 // map is a bijection of [0, nblocks).
 #ifndef ADLBR_STRIP_Z
-#define ADLBR_STRIP_Z 8
+#define ADLBR_STRIP_Z 32
 #endif
 constexpr int kStripZ = ADLBR_STRIP_Z;
 
@@ -151,6 +151,18 @@ __device__ inline long long strip_block(long long L, const GridInfo &g, int poin
     const unsigned i = (unsigned)L - s * strip;
     const unsigned j = i / tz, z = z0 + i % tz;
     return (long long)z * bp + j;
+}
+
+// Index of weight q of point z in an operator's weights.  2D (S = 3):
+// point-major [N][3], so that the gather of an incoming edge's weight from
+// its source finds the source's three weights on one line.  3D (S = 6):
+// slot-major planes [6][N], read coalesced by the own part only (the 3D
+// incoming weights sit beside the entries).
+template <int S> __host__ __device__ __forceinline__ long long widx(int q, long long z, long long N) {
+    return S == 3 ? z * S + q : (long long)q * N + z;
+}
+template <int S> __host__ __device__ __forceinline__ unsigned widx32(int q, int z, int N) {
+    return S == 3 ? (unsigned)(z * S + q) : (unsigned)(q * N + z);
 }
 
 // Device-resident scalars of a (flexible) conjugate-gradient iteration.
@@ -295,6 +307,7 @@ __device__ inline double reduce_partials(const double *partial, long long n, boo
 const GridInfo &operator_grid(const adlbr_operator *op);
 int operator_storage(const adlbr_operator *op);
 const void *operator_diag(const adlbr_operator *op);
+// The operator's weights, in the storage dtype, at widx<S>(q, z, N).
 const void *operator_weights(const adlbr_operator *op);
 const void *operator_slots(const adlbr_operator *op);
 int operator_wide(const adlbr_operator *op);

@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void k_compact(
         unsigned m = 0;
         for (int q = 0; q < S; ++q) {
             wq[q] = (double)win[q * N + z];
-            w[q * N + z] = Conv<TS, TA>::st((TA)wq[q]);
+            w[widx<S>(q, z, N)] = Conv<TS, TA>::st((TA)wq[q]);
             if (wq[q] > 0.0) m |= 1u << q;
         }
         mask[z] = (uint8_t)m;
@@ -376,7 +376,7 @@ __device__ inline double row_diag(const GridInfo &g, long long z, const int32_t 
     sl.load(sb, z);
     const Coord p = coords(z, g);
     for (int q = 0; q < S; ++q) {
-        const double wv = (double)Conv<TS, TA>::ld(w[q * N + z]);
+        const double wv = (double)Conv<TS, TA>::ld(w[widx<S>(q, z, N)]);
         for (int sg = -1; sg <= 1; sg += 2) {
             long long t;
             if (edge_target<DIM, PER>(p, z, sl.o[q], sg, g, t)) d += wv;
@@ -384,7 +384,7 @@ __device__ inline double row_diag(const GridInfo &g, long long z, const int32_t 
     }
     for (int i = 0; i < c; ++i) {
         const int32_t v = e[i];
-        d += (double)Conv<TS, TA>::ld(w[(long long)((v >> 6) & 7) * N + z + (v >> 9)]);
+        d += (double)Conv<TS, TA>::ld(w[widx<S>((v >> 6) & 7, z + (v >> 9), N)]);
     }
     return d;
 }
@@ -397,7 +397,7 @@ __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *
     if (c > 16) {
         sort_row(e, c);
         if (we)
-            for (int i = 0; i < c; ++i) we[i] = w[(long long)((e[i] >> 6) & 7) * N + z + (e[i] >> 9)];
+            for (int i = 0; i < c; ++i) we[i] = w[widx<DIM == 2 ? 3 : 6>((e[i] >> 6) & 7, z + (e[i] >> 9), N)];
         return row_diag<DIM, WIDE, PER, TS, TA>(g, z, e, c, sb, w);
     }
     constexpr int S = DIM == 2 ? 3 : 6;
@@ -418,7 +418,7 @@ __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *
     for (int i = 0; i < 16; ++i) {
         if (i < c) {
             e[i] = r[i];
-            const TS wr = w[(long long)((r[i] >> 6) & 7) * N + z + (r[i] >> 9)];
+            const TS wr = w[widx<S>((r[i] >> 6) & 7, z + (r[i] >> 9), N)];
             if (we) we[i] = wr;
             wi[i] = Conv<TS, TA>::ld(wr);
         }
@@ -428,7 +428,7 @@ __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *
     sl.load(sb, z);
     const Coord p = coords(z, g);
     for (int q = 0; q < S; ++q) {
-        const double wv = (double)Conv<TS, TA>::ld(w[q * N + z]);
+        const double wv = (double)Conv<TS, TA>::ld(w[widx<S>(q, z, N)]);
         for (int sg = -1; sg <= 1; sg += 2) {
             long long t;
             if (edge_target<DIM, PER>(p, z, sl.o[q], sg, g, t)) d += wv;
@@ -914,7 +914,9 @@ __global__ __launch_bounds__(256) void k_place2d(GridInfo g,
 
 // Pass 3: sort every row, store the weight of each entry beside it (went,
 // where not null), take the diagonal A_zz and the block's largest diagonal
-// (dpart), one thread per target.
+// (dpart), one thread per target.  The rows of a block's 256 consecutive
+// targets are one run of ent; when it fits, it is staged in LDS with
+// coalesced loads and stores around the per-thread sort.
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TD>
 __global__ __launch_bounds__(256) void k_rows(GridInfo g,
                                               const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
@@ -923,14 +925,28 @@ __global__ __launch_bounds__(256) void k_rows(GridInfo g,
                                               const int32_t *__restrict__ pos,
                                               int32_t *__restrict__ ent, TS *__restrict__ went,
                                               TD *__restrict__ diag, double *__restrict__ dpart) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int kCap = 16 * 256;
+    __shared__ int32_t rows[kCap];
+    const long long N = g.N;
+    const long long t0 = (long long)blockIdx.x * blockDim.x, t = t0 + threadIdx.x;
+    const int p0 = pos[t0], p1 = pos[t0 + 256 < N ? t0 + 256 : N];
+    const bool staged = p1 - p0 <= kCap;  // block-uniform
+    if (staged) {
+        for (int i = threadIdx.x; i < p1 - p0; i += blockDim.x) rows[i] = ent[p0 + i];
+        __syncthreads();
+    }
     double dmax = 0.0;
-    if (t < g.N) {
+    if (t < N) {
         const int p = pos[t];
-        const double d = sort_row_diag<DIM, WIDE, PER, TS, TA>(g, t, ent + p, (int)cnt[t], sb, w,
+        int32_t *e = staged ? rows + (p - p0) : ent + p;
+        const double d = sort_row_diag<DIM, WIDE, PER, TS, TA>(g, t, e, (int)cnt[t], sb, w,
                                                                went ? went + p : nullptr);
         diag[t] = (TD)d;
         dmax = d;
+    }
+    if (staged) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < p1 - p0; i += blockDim.x) ent[p0 + i] = rows[i];
     }
     block_partial_max(dmax, dpart);
 }
@@ -1025,7 +1041,7 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TU> s
         const Coord p = coords(zi, g);
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            wq[q] = live ? Conv<TS, TA>::ld(w[(unsigned)(q * N + zi)]) : (TA)0;
+            wq[q] = live ? Conv<TS, TA>::ld(w[widx32<S>(q, zi, N)]) : (TA)0;
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 int t = 0;
@@ -1063,7 +1079,7 @@ __device__ __forceinline__ TA incoming_edge(const WaveLists &L, long long z0, lo
     TA wy = (TA)0, uy = (TA)0;
     if (ok) {  // N < 2^28 points, S N < 2^31: 32-bit indices
         const int y = (int)z0 + (v & 63) + (v >> 9);
-        wy = Conv<TS, TA>::ld(INLINE_W ? wv : w[(unsigned)(((v >> 6) & 7) * (int)N + y)]);
+        wy = Conv<TS, TA>::ld(INLINE_W ? wv : w[widx32<INLINE_W ? 6 : 3>((v >> 6) & 7, y, (int)N)]);
         uy = Conv<TU, TA>::ld(u[(unsigned)y]);
     }
     return ok ? wy * (ur - uy) : (TA)0;
