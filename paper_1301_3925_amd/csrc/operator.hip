@@ -1063,7 +1063,10 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TU> s
     }
 };
 
-constexpr int kPre = 4;
+#ifndef ADLBR_KPRE
+#define ADLBR_KPRE 4
+#endif
+constexpr int kPre = ADLBR_KPRE;
 
 // Chunk [e0, e0 + 64) of a wave's entries: this lane's edge value
 // w_slot(y) (u(row) - u(y)), 0 past the end; the weight is wv (INLINE_W,
@@ -1195,15 +1198,9 @@ __device__ __forceinline__ void apply_block(
         acc[k] = (TA)0;
         tmax = L[k].total > tmax ? L[k].total : tmax;
     }
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const long long z = zw + 64 * k + lane;
-        own[k].issue(g, z, z < N, uz[k], u, sb, w);
-    }
-    for (unsigned eb = 0; eb < tmax; eb += 64 * kPre) {
-        int32_t v[P][kPre];
-        TS wv[P][kPre];
-        TA val[P][kPre];
+    int32_t v[P][kPre];
+    TS wv[P][kPre];
+    auto load_chunks = [&](unsigned eb) {
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
@@ -1212,6 +1209,15 @@ __device__ __forceinline__ void apply_block(
                 v[k][j] = e < L[k].total ? ent[L[k].start + e] : -1;
                 wv[k][j] = kInlineW<DIM> && e < L[k].total ? went[L[k].start + e] : TS{};
             }
+    };
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const long long z = zw + 64 * k + lane;
+        own[k].issue(g, z, z < N, uz[k], u, sb, w);
+    }
+    for (unsigned eb = 0; eb < tmax; eb += 64 * kPre) {
+        load_chunks(eb);
+        TA val[P][kPre];
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
