@@ -277,12 +277,18 @@ __global__ __launch_bounds__(256) void k_st_grad_tiled(int nx, int ny, const T *
 }
 
 // Kernel 2: J -> K_rho * J (x then y, mirrored tile) -> eigen map -> D.
+// Both passes slide a window along the filter direction in registers: a
+// thread takes 8 consecutive outputs of a row (x pass) or 4 of a column (y
+// pass), reading 8 + 2 RR (4 + 2 RR) values instead of 25 per output.
+// Every output still sums its taps in the order j = 0 .. 2 RR.
 template <typename T, int RR>
 __global__ __launch_bounds__(256) void k_st_smooth_map_tiled(int nx, int ny,
                                                              const T *__restrict__ J,
                                                              T *__restrict__ D, Taps tr, T alpha,
                                                              T C, int map) {
     constexpr int E = kTile + 2 * RR;
+    constexpr int XO = 8, YO = 4;  // outputs per thread in the x and y passes
+    static_assert(kTile % XO == 0 && (kTile / YO) * kTile == 256, "pass shapes");
     __shared__ T sj[3][E * E];
     __shared__ T sx[3][E * kTile];
     const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
@@ -295,35 +301,44 @@ __global__ __launch_bounds__(256) void k_st_smooth_map_tiled(int nx, int ny,
         sj[2][k] = J[2 * N + i];
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < E * kTile; k += 256) {
-        const int yy = k / kTile, xx = k % kTile;
-        T a0 = (T)0, a1 = (T)0, a2 = (T)0;
+    for (int it = threadIdx.x; it < E * (kTile / XO); it += 256) {
+        const int yy = it / (kTile / XO), xs = (it % (kTile / XO)) * XO;
 #pragma unroll
-        for (int j = 0; j <= 2 * RR; ++j) {
-            const T w = tap<T>(tr, j);
-            const int q = yy * E + xx + j;
-            a0 += w * sj[0][q];
-            a1 += w * sj[1][q];
-            a2 += w * sj[2][q];
+        for (int c = 0; c < 3; ++c) {
+            T win[XO + 2 * RR];
+#pragma unroll
+            for (int j = 0; j < XO + 2 * RR; ++j) win[j] = sj[c][yy * E + xs + j];
+#pragma unroll
+            for (int o = 0; o < XO; ++o) {
+                T a = (T)0;
+#pragma unroll
+                for (int j = 0; j <= 2 * RR; ++j) a += tap<T>(tr, j) * win[o + j];
+                sx[c][yy * kTile + xs + o] = a;
+            }
         }
-        sx[0][k] = a0;
-        sx[1][k] = a1;
-        sx[2][k] = a2;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < kTile * kTile; k += 256) {
-        const int ty = k / kTile, tx = k % kTile;
+    const int tx = threadIdx.x % kTile, ys = (threadIdx.x / kTile) * YO;
+    T acc[3][YO];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T win[YO + 2 * RR];
+#pragma unroll
+        for (int j = 0; j < YO + 2 * RR; ++j) win[j] = sx[c][(ys + j) * kTile + tx];
+#pragma unroll
+        for (int o = 0; o < YO; ++o) {
+            T a = (T)0;
+#pragma unroll
+            for (int j = 0; j <= 2 * RR; ++j) a += tap<T>(tr, j) * win[o + j];
+            acc[c][o] = a;
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < YO; ++o) {
+        const int ty = ys + o;
         const int gx = x0 + tx, gy = y0 + ty;
         if (gx >= nx || gy >= ny) continue;
-        T a = (T)0, b = (T)0, c = (T)0;
-#pragma unroll
-        for (int j = 0; j <= 2 * RR; ++j) {
-            const T w = tap<T>(tr, j);
-            const int q = (ty + j) * kTile + tx;
-            a += w * sx[0][q];
-            b += w * sx[1][q];
-            c += w * sx[2][q];
-        }
+        const T a = acc[0][o], b = acc[1][o], c = acc[2][o];
         const T hd = (T)0.5 * (a - c);
         const T disc = sqrt(hd * hd + b * b);
         const T mid = (T)0.5 * (a + c);
