@@ -957,15 +957,28 @@ __global__ void k_copy_u32(const uint32_t *a, uint32_t *b, long long n) {
 }
 
 
-__global__ void k_scan_top(int32_t *bsum, long long nb) {
+// In-place exclusive scan of bsum[0 .. nb) by one block of 256 threads:
+// 4096 values a round, 16 consecutive ones per thread (one round covers the
+// chunk sums of a 2048^2 grid).
+__global__ __launch_bounds__(256) void k_scan_top(int32_t *bsum, long long nb) {
+    constexpr int V = 16;
     __shared__ int32_t lds[256];
     int32_t carry = 0;
-    for (long long b0 = 0; b0 < nb; b0 += 256) {
-        const long long i = b0 + threadIdx.x;
-        const int32_t v = i < nb ? bsum[i] : 0;
+    for (long long b0 = 0; b0 < nb; b0 += 256 * V) {
+        const long long i0 = b0 + (long long)threadIdx.x * V;
+        int32_t v[V], sum = 0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            v[k] = i0 + k < nb ? bsum[i0 + k] : 0;
+            sum += v[k];
+        }
         int32_t total;
-        const int32_t ex = block_excl_scan256(v, lds, total);
-        if (i < nb) bsum[i] = carry + ex;
+        int32_t run = carry + block_excl_scan256(sum, lds, total);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (i0 + k < nb) bsum[i0 + k] = run;
+            run += v[k];
+        }
         carry += total;
     }
 }
@@ -1169,20 +1182,6 @@ __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, lon
     return acc;
 }
 
-// First point of the calling wave's P consecutive 64-point groups in block
-// blk.  Blocks cover 256 P consecutive points, except on a 2D grid whose
-// rows are whole groups and whose row count is a multiple of 4 (with
-// P = 1): there a block takes a 64 x 4 patch, its four waves one row apart,
-// so that their neighbour gathers share the CU's L1 (2D apply on 2048^2:
-// 124 -> 109 us).  Same block count either way.
-__device__ __forceinline__ long long wave_group(const GridInfo &g, long long blk, int P) {
-    const long long wv = threadIdx.x >> 6;
-    if (P == 1 && g.dim == 2 && g.nx % 64 == 0 && g.ny % 4 == 0) {
-        const long long gpr = g.nx / 64;
-        return ((blk / gpr) * 4 + wv) * g.nx + (blk % gpr) * 64;
-    }
-    return blk * kApplyPoints + wv * 64 * P;
-}
 
 // One block of out = A u (STEP = false) or u - h A u (STEP = true): every
 // wave takes kApplyPPT consecutive groups of 64 rows (a block kApplyPoints
