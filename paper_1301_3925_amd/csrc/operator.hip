@@ -40,7 +40,7 @@ struct adlbr_operator {
     uint8_t *cnt;
     int32_t *pos;
     int32_t *ent;
-    void *went;        // [entries] weight of every incoming entry (storage dtype)
+    void *went;        // 3D: [entries] every incoming entry with its weight (EntW)
     void *diag;
     double *maxdiag;
     double *dtcfl;
@@ -355,14 +355,21 @@ __device__ inline void sort_row(int32_t *e, int c) {
     }
 }
 
-// Sort row z (entries e[0..c)), store the weight of each of its entries
-// beside it (we[i], in the storage dtype; not when we is null) and return
+// An incoming entry with its weight, as the 3D lists keep them: the apply
+// takes both with one vector load per lane.
+template <typename TS> struct alignas(sizeof(TS) > 4 ? 16 : 8) EntW {
+    int32_t e;
+    TS w;
+};
+
+// Sort row z (entries e[0..c)), store every entry again with its weight
+// (we[i], the weight in the storage dtype; not when we is null) and return
 // A_zz, summed as row_diag does.  A row of up to 16 entries is sorted in registers and its
 // incoming weights are all requested before any is added.
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
 __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *e, int c,
                                        const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
-                                       const TS *__restrict__ w, TS *__restrict__ we);
+                                       const TS *__restrict__ w, EntW<TS> *__restrict__ we);
 
 // A_zz = own in-grid weights (both signs) + weights of the incoming edges.
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
@@ -392,12 +399,13 @@ __device__ inline double row_diag(const GridInfo &g, long long z, const int32_t 
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
 __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *e, int c,
                                        const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
-                                       const TS *__restrict__ w, TS *__restrict__ we) {
+                                       const TS *__restrict__ w, EntW<TS> *__restrict__ we) {
     const long long N = g.N;
     if (c > 16) {
         sort_row(e, c);
         if (we)
-            for (int i = 0; i < c; ++i) we[i] = w[widx<DIM == 2 ? 3 : 6>((e[i] >> 6) & 7, z + (e[i] >> 9), N)];
+            for (int i = 0; i < c; ++i)
+                we[i] = EntW<TS>{e[i], w[widx<DIM == 2 ? 3 : 6>((e[i] >> 6) & 7, z + (e[i] >> 9), N)]};
         return row_diag<DIM, WIDE, PER, TS, TA>(g, z, e, c, sb, w);
     }
     constexpr int S = DIM == 2 ? 3 : 6;
@@ -419,7 +427,7 @@ __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *
         if (i < c) {
             e[i] = r[i];
             const TS wr = w[widx<S>((r[i] >> 6) & 7, z + (r[i] >> 9), N)];
-            if (we) we[i] = wr;
+            if (we) we[i] = EntW<TS>{r[i], wr};
             wi[i] = Conv<TS, TA>::ld(wr);
         }
     }
@@ -482,7 +490,7 @@ __global__ __launch_bounds__(256) void k_bin_build(
     GridInfo g, const uint32_t *__restrict__ bincnt, const uint32_t *__restrict__ binoff,
     const int2 *__restrict__ binbuf, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
     const TS *__restrict__ w, int32_t *__restrict__ pos, uint8_t *__restrict__ cnt,
-    int32_t *__restrict__ ent, TS *__restrict__ went, TD *__restrict__ diag,
+    int32_t *__restrict__ ent, EntW<TS> *__restrict__ went, TD *__restrict__ diag,
     double *__restrict__ dpart, int32_t *status) {
     __shared__ int32_t lcnt[kBin];
     __shared__ int32_t loff[kBin];
@@ -923,7 +931,7 @@ __global__ __launch_bounds__(256) void k_rows(GridInfo g,
                                               const TS *__restrict__ w,
                                               const uint8_t *__restrict__ cnt,
                                               const int32_t *__restrict__ pos,
-                                              int32_t *__restrict__ ent, TS *__restrict__ went,
+                                              int32_t *__restrict__ ent, EntW<TS> *__restrict__ went,
                                               TD *__restrict__ diag, double *__restrict__ dpart) {
     constexpr int kCap = 16 * 256;
     __shared__ int32_t rows[kCap];
@@ -1020,18 +1028,29 @@ struct WaveLists {
     unsigned total, lo, hi;
 };
 
-__device__ __forceinline__ WaveLists wave_lists(const uint8_t *__restrict__ cnt,
-                                                const int32_t *__restrict__ pos, long long z,
+__device__ __forceinline__ WaveLists wave_lists(const int32_t *__restrict__ pos, long long z,
                                                 long long N) {
+    // All 64 lanes call this; the wave's rows are 64 consecutive points from
+    // a multiple of 64.  A row's end is the next row's start (the next
+    // lane's pos), so the counts are not read; the wave's end is one
+    // scalar load.
     WaveLists L;
-    const long long z0 = z & ~63ll;
-    const long long zend = z0 + 64 < N ? z0 + 64 : N;
-    const unsigned c = z < N ? cnt[z] : 0u;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int z0 = __builtin_amdgcn_readfirstlane((int)(z - lane));  // N < 2^28
+    if ((long long)z0 >= N) {
+        L.start = 0;
+        L.total = L.lo = L.hi = 0u;
+        return L;
+    }
+    const int zend = z0 + 64 < N ? z0 + 64 : (int)N;
     const int pz = z < N ? pos[z] : 0;
-    L.start = z0 < N ? pos[z0] : 0;
-    L.total = z0 < N ? (unsigned)(pos[zend] - L.start) : 0u;
+    const int pend = pos[zend];
+    L.start = __builtin_amdgcn_readfirstlane(pz);
+    const int pnext = __shfl_down(pz, 1, 64);
+    const int phi = lane == 63 || z + 1 >= N ? pend : pnext;
+    L.total = (unsigned)(pend - L.start);
     L.lo = z < N ? (unsigned)(pz - L.start) : 0u;
-    L.hi = L.lo + c;
+    L.hi = z < N ? (unsigned)(phi - L.start) : 0u;
     return L;
 }
 
@@ -1040,6 +1059,10 @@ __device__ __forceinline__ WaveLists wave_lists(const uint8_t *__restrict__ cnt,
 // these loads before the dependent loads of the incoming part: issue()
 // loads the weights and the neighbour values (u(z) where an edge is
 // missing, so its term is exactly 0), sum() adds them up.
+template <typename TS> struct W3 {
+    TS v[3];
+};
+
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TU> struct OwnPart {
     static constexpr int S = DIM == 2 ? 3 : 6;
     TA wq[S];
@@ -1052,9 +1075,12 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TU> s
         Slots<DIM, WIDE> sl;
         if (live) sl.load(sb, zi);
         const Coord p = coords(zi, g);
+        W3<TS> w3{};  // 2D: the three point-major weights in one load
+        if (S == 3 && live) w3 = ((const W3<TS> *)w)[zi];
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            wq[q] = live ? Conv<TS, TA>::ld(w[widx32<S>(q, zi, N)]) : (TA)0;
+            wq[q] = !live ? (TA)0
+                          : Conv<TS, TA>::ld(S == 3 ? w3.v[q < 3 ? q : 0] : w[widx32<S>(q, zi, N)]);
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 int t = 0;
@@ -1158,7 +1184,7 @@ template <bool INLINE_W, typename TS, typename TA, typename TU>
 __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, long long N, TA uz,
                                             const TU *__restrict__ u, const TS *__restrict__ w,
                                             const int32_t *__restrict__ ent,
-                                            const TS *__restrict__ went) {
+                                            const EntW<TS> *__restrict__ went) {
     const int lane = (int)(threadIdx.x & 63u);
     const long long z0 = z & ~63ll;
     TA acc = (TA)0;
@@ -1169,8 +1195,14 @@ __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, lon
 #pragma unroll
         for (int j = 0; j < kPre; ++j) {
             const unsigned e = eb + 64 * j + lane;
-            v[j] = e < L.total ? ent[L.start + e] : -1;
-            wv[j] = INLINE_W && e < L.total ? went[L.start + e] : TS{};
+            if (INLINE_W) {
+                const EntW<TS> r = e < L.total ? went[L.start + e] : EntW<TS>{-1, TS{}};
+                v[j] = r.e;
+                wv[j] = r.w;
+            } else {
+                v[j] = e < L.total ? ent[L.start + e] : -1;
+                wv[j] = TS{};
+            }
         }
 #pragma unroll
         for (int j = 0; j < kPre; ++j)
@@ -1195,7 +1227,7 @@ __device__ __forceinline__ void apply_block(
     const GridInfo &g, long long blk, const TS *__restrict__ u, TS *__restrict__ out,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, const TS *__restrict__ went, TA h) {
+    const int32_t *__restrict__ ent, const EntW<TS> *__restrict__ went, TA h) {
     constexpr int P = kApplyPPT;
     const long long N = g.N;
     const int lane = (int)(threadIdx.x & 63u);
@@ -1207,7 +1239,7 @@ __device__ __forceinline__ void apply_block(
 #pragma unroll
     for (int k = 0; k < P; ++k) {
         const long long z = zw + 64 * k + lane;
-        L[k] = wave_lists(cnt, pos, z, N);
+        L[k] = wave_lists(pos, z, N);
         uz[k] = z < N ? Conv<TS, TA>::ld(u[z]) : (TA)0;
         acc[k] = (TA)0;
         tmax = L[k].total > tmax ? L[k].total : tmax;
@@ -1220,8 +1252,14 @@ __device__ __forceinline__ void apply_block(
 #pragma unroll
             for (int j = 0; j < kPre; ++j) {
                 const unsigned e = eb + 64 * j + lane;
-                v[k][j] = e < L[k].total ? ent[L[k].start + e] : -1;
-                wv[k][j] = kInlineW<DIM> && e < L[k].total ? went[L[k].start + e] : TS{};
+                if (kInlineW<DIM>) {
+                    const EntW<TS> r = e < L[k].total ? went[L[k].start + e] : EntW<TS>{-1, TS{}};
+                    v[k][j] = r.e;
+                    wv[k][j] = r.w;
+                } else {
+                    v[k][j] = e < L[k].total ? ent[L[k].start + e] : -1;
+                    wv[k][j] = TS{};
+                }
             }
     };
 #pragma unroll
@@ -1258,7 +1296,7 @@ __global__ __launch_bounds__(kBS) void k_apply(
     GridInfo g, const TS *__restrict__ u, TS *__restrict__ out,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, const TS *__restrict__ went, double dt,
+    const int32_t *__restrict__ ent, const EntW<TS> *__restrict__ went, double dt,
     const double *__restrict__ dtcfl, int dt_mode) {
     const TA h = (TA)(dt_mode == ADLBR_DT_CFL ? dt * dtcfl[0] : dt);
     apply_block<DIM, WIDE, PER, STEP, TS, TA>(
@@ -1298,7 +1336,7 @@ __global__ __launch_bounds__(kBS) void k_apply_batch(const BatchProb *__restrict
     apply_block<DIM, WIDE, PER, true, TS, TA>(
         g, strip_block(b - P.first_block, g, kApplyPoints), (const TS *)P.u[parity], (TS *)P.u[parity ^ 1],
         (const typename Slots<DIM, WIDE>::store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent,
-        (const TS *)P.went, h);
+        (const EntW<TS> *)P.went, h);
 }
 
 // dst = src for every problem (u[1] -> u[0] after an odd number of steps).
@@ -1322,7 +1360,7 @@ __global__ __launch_bounds__(kBS) void k_cg_direction(
     GridInfo g, const T *__restrict__ zv, T *__restrict__ q, T *__restrict__ p,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const T *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, const T *__restrict__ went, const CgState *st,
+    const int32_t *__restrict__ ent, const EntW<T> *__restrict__ went, const CgState *st,
     double *partial, int first) {
     const long long N = g.N;
     const long long blk = xcd_block(blockIdx.x, gridDim.x);
@@ -1330,7 +1368,7 @@ __global__ __launch_bounds__(kBS) void k_cg_direction(
     const bool live = z < N;
     double pqz = 0.0;
     const bool skip = st->bad || st->done;
-    const WaveLists L = wave_lists(cnt, pos, z, N);
+    const WaveLists L = wave_lists(pos, z, N);
     const T zz = live ? zv[z] : (T)0;
     OwnPart<DIM, WIDE, PER, T, T, T> own;
     own.issue(g, z, live && !skip, zz, zv, sb, w);
@@ -1371,13 +1409,13 @@ __global__ __launch_bounds__(kBS) void k_residual(
     GridInfo g, const T *__restrict__ b, const double *__restrict__ x,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const T *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, const T *__restrict__ went, double dt, double *partial,
+    const int32_t *__restrict__ ent, const EntW<T> *__restrict__ went, double dt, double *partial,
     T *__restrict__ rout) {
     const long long N = g.N;
     const long long z = wave_group(g, blockIdx.x, 1) + (threadIdx.x & 63);
     const bool live = z < N;
     double r2 = 0.0;
-    const WaveLists L = wave_lists(cnt, pos, z, N);
+    const WaveLists L = wave_lists(pos, z, N);
     const double xz = live ? x[z] : 0.0;
     OwnPart<DIM, WIDE, PER, T, double, double> own;
     own.issue(g, z, live, xz, x, sb, w);
@@ -1447,12 +1485,12 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
         if (op->storage == ADLBR_F64)
             hipLaunchKernelGGL((k_rows<DIM, WIDE, PER, TS, TA, double>), dim3(nb), dim3(256), 0, s,
                                g, (const store_t *)op->sb, (const TS *)w, (const uint8_t *)op->cnt,
-                               (const int32_t *)op->pos, op->ent, (TS *)op->went, (double *)op->diag,
+                               (const int32_t *)op->pos, op->ent, (EntW<TS> *)op->went, (double *)op->diag,
                                op->part);
         else
             hipLaunchKernelGGL((k_rows<DIM, WIDE, PER, TS, TA, float>), dim3(nb), dim3(256), 0, s,
                                g, (const store_t *)op->sb, (const TS *)w, (const uint8_t *)op->cnt,
-                               (const int32_t *)op->pos, op->ent, (TS *)op->went, (float *)op->diag,
+                               (const int32_t *)op->pos, op->ent, (EntW<TS> *)op->went, (float *)op->diag,
                                op->part);
         nparts = nb;
     } else {
@@ -1467,12 +1505,12 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
         if (op->storage == ADLBR_F64)
             hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, double>), dim3((unsigned)nbins),
                                dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w,
-                               op->pos, op->cnt, op->ent, (TS *)op->went, (double *)op->diag, op->part,
+                               op->pos, op->cnt, op->ent, (EntW<TS> *)op->went, (double *)op->diag, op->part,
                                status);
         else
             hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, float>), dim3((unsigned)nbins),
                                dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w,
-                               op->pos, op->cnt, op->ent, (TS *)op->went, (float *)op->diag, op->part,
+                               op->pos, op->cnt, op->ent, (EntW<TS> *)op->went, (float *)op->diag, op->part,
                                status);
         nparts = nbins;
     }
@@ -1491,11 +1529,11 @@ int apply_impl(const adlbr_operator *op, const void *u, void *out, bool step, do
     if (step)
         hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, true, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)u, (TS *)out, (const store_t *)op->sb, (const TS *)op->w,
-                           op->cnt, op->pos, op->ent, (const TS *)op->went, dt, op->dtcfl, dt_mode);
+                           op->cnt, op->pos, op->ent, (const EntW<TS> *)op->went, dt, op->dtcfl, dt_mode);
     else
         hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, false, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)u, (TS *)out, (const store_t *)op->sb, (const TS *)op->w,
-                           op->cnt, op->pos, op->ent, (const TS *)op->went, dt, op->dtcfl, dt_mode);
+                           op->cnt, op->pos, op->ent, (const EntW<TS> *)op->went, dt, op->dtcfl, dt_mode);
     return ADLBR_OK;
 }
 
@@ -1553,7 +1591,7 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct BatchF 
                 const unsigned nb = (unsigned)((P.g.N + kApplyPoints - 1) / kApplyPoints);
                 hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, true, TS, TA>), dim3(nb), dim3(kBS), 0, s,
                                    P.g, (const TS *)P.u[parity], (TS *)P.u[parity ^ 1],
-                                   (const store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent, (const TS *)P.went, P.dt,
+                                   (const store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent, (const EntW<TS> *)P.went, P.dt,
                                    P.dtcfl, P.dt_mode);
             }
             return ADLBR_OK;
@@ -1581,7 +1619,7 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct CgDirF 
         if (op->storage != ADLBR_F32 && op->storage != ADLBR_F64) return ADLBR_E_UNSUPPORTED;
         hipLaunchKernelGGL((k_cg_direction<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)z, (TS *)q, (TS *)p, (const store_t *)op->sb,
-                           (const TS *)op->w, op->cnt, op->pos, op->ent, (const TS *)op->went,
+                           (const TS *)op->w, op->cnt, op->pos, op->ent, (const EntW<TS> *)op->went,
                            (const CgState *)st,
                            partial, first);
         hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kBS), 0, s, st, (const double *)partial,
@@ -1610,7 +1648,7 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct Residua
         const unsigned nb = (unsigned)((g.N + kBS - 1) / kBS);
         hipLaunchKernelGGL((k_residual<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)b, x, (const store_t *)op->sb, (const TS *)op->w, op->cnt,
-                           op->pos, op->ent, (const TS *)op->went, dt, partial, (TS *)rout);
+                           op->pos, op->ent, (const EntW<TS> *)op->went, dt, partial, (TS *)rout);
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBS), 0, s, (const double *)partial,
                            (long long)nb, out);
         return ADLBR_OK;
@@ -1645,7 +1683,7 @@ Layout layout(const GridInfo &g, int storage, int wide) {
     L.cnt = o;  o += align_up((size_t)N + 64);
     L.pos = o;  o += align_up(4 * (size_t)N + 256);
     L.ent = o;  o += align_up(4 * (size_t)(2 * S) * N);
-    L.went = o; o += g.dim == 3 ? align_up(dtype_size(storage) * (size_t)(2 * S) * N) : 0;
+    L.went = o; o += g.dim == 3 ? align_up((dtype_size(storage) > 4 ? 16 : 8) * (size_t)(2 * S) * N) : 0;
     L.diag = o; o += align_up((storage == ADLBR_F64 ? 8 : 4) * (size_t)N);
     L.scal = o; o += 256;
     L.mask = o; o += align_up((size_t)N + 64);
