@@ -946,9 +946,14 @@ __global__ __launch_bounds__(256) void k_rows(GridInfo g,
     double dmax = 0.0;
     if (t < N) {
         const int p = pos[t];
-        int32_t *e = staged ? rows + (p - p0) : ent + p;
-        const double d = sort_row_diag<DIM, WIDE, PER, TS, TA>(g, t, e, (int)cnt[t], sb, w,
-                                                               went ? went + p : nullptr);
+        // two calls, so that the staged one addresses LDS directly (not
+        // through flat addressing)
+        const double d = staged ? sort_row_diag<DIM, WIDE, PER, TS, TA>(g, t, rows + (p - p0),
+                                                                        (int)cnt[t], sb, w,
+                                                                        went ? went + p : nullptr)
+                                : sort_row_diag<DIM, WIDE, PER, TS, TA>(g, t, ent + p, (int)cnt[t],
+                                                                        sb, w,
+                                                                        went ? went + p : nullptr);
         diag[t] = (TD)d;
         dmax = d;
     }
