@@ -22,7 +22,7 @@ namespace adlbr {
 
 int apply_K(const adlbr_operator *op, const void *u, void *out, double dt, hipStream_t s);
 int net_apply_mfma(const adlbr_net *net, const adlbr_operator *op, const float *r, float *z,
-                   const float *rp, double *part, hipStream_t s);
+                   const float *rp, double *part, const CgState *st, hipStream_t s);
 int net_mfma_blocks(int nx, int ny);
 int net_pack_mfma(const adlbr_net *net, hipStream_t s);
 
@@ -703,7 +703,7 @@ int net_apply(const adlbr_net *net, const adlbr_operator *op, double dt, const v
         return ADLBR_E_UNSUPPORTED;
     }
     if (d.dim == 2 && net->gates8)
-        return net_apply_mfma(net, op, (const float *)r, (float *)z, nullptr, nullptr, s);
+        return net_apply_mfma(net, op, (const float *)r, (float *)z, nullptr, nullptr, nullptr, s);
     if (!net->scratch) {
         set_error("net: the FP32 inference path needs net->scratch ([2W][N] FP32)");
         return ADLBR_E_INVALID;
@@ -732,14 +732,15 @@ __global__ __launch_bounds__(kBS) void k_dots2(long long N, const float *__restr
 }  // namespace
 
 int net_apply_dots(const adlbr_net *net, const adlbr_operator *op, const float *r,
-                   const float *rp, float *z, double *part, long long *nparts, hipStream_t s) {
+                   const float *rp, float *z, double *part, long long *nparts,
+                   const CgState *st, hipStream_t s) {
     NetDims d;
     int rc = check_net(op, net, &d);
     if (rc) return rc;
     const GridInfo &g = operator_grid(op);
     if (d.dim == 2 && net->gates8 && operator_storage(op) == ADLBR_F32) {
         *nparts = net_mfma_blocks(g.nx, g.ny);
-        return net_apply_mfma(net, op, r, z, rp, part, s);
+        return net_apply_mfma(net, op, r, z, rp, part, st, s);
     }
     rc = net_apply(net, op, 0.0, r, z, s);
     if (rc) return rc;

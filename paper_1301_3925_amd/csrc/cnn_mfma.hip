@@ -256,7 +256,9 @@ __global__ __launch_bounds__(256) void k_net2d_fused(int nx, int ny, const float
                                                      const bf16x4 *__restrict__ wpack,
                                                      float *__restrict__ z,
                                                      const float *__restrict__ rp,
-                                                     double *__restrict__ part) {
+                                                     double *__restrict__ part,
+                                                     const CgState *__restrict__ st) {
+    if (st && (st->done || st->bad)) return;  // the solve has stopped: nothing reads z
     __shared__ __attribute__((aligned(16))) float sr[kR0 * kR0];
     __shared__ __attribute__((aligned(16))) uint8_t sg1[kR1 * kR1 * 16];
     __shared__ __attribute__((aligned(16))) uint8_t sg2[kR2 * kR2 * 16];
@@ -362,11 +364,11 @@ int net_mfma_blocks(int nx, int ny) {
 }
 
 int net_apply_mfma(const adlbr_net *net, const adlbr_operator *op, const float *r, float *z,
-                   const float *rp, double *part, hipStream_t s) {
+                   const float *rp, double *part, const CgState *st, hipStream_t s) {
     const GridInfo &g = operator_grid(op);
     hipLaunchKernelGGL(k_net2d_fused, dim3(net_mfma_blocks(g.nx, g.ny)), dim3(256), 0, s, g.nx,
                        g.ny, r, net->features, (const uint8_t *)net->gates8,
-                       (const bf16x4 *)(net->layers + kPackOffset), z, rp, part);
+                       (const bf16x4 *)(net->layers + kPackOffset), z, rp, part, st);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }

@@ -202,9 +202,12 @@ int net_apply(const adlbr_net *net, const adlbr_operator *op, double dt, const v
               hipStream_t s);
 // z = preconditioned r (FP32) and the per-block FP64 partials of <z, r> in
 // part[0 .. nparts) and of <z, rp> in part[nparts .. 2 nparts) (rp may be
-// null); nparts (host out) depends on the inference path taken.
+// null); nparts (host out) depends on the inference path taken.  st (may be
+// null): a solver state whose done or bad flag turns the fused inference
+// into a no-op (the solver's later kernels ignore z and the partials then).
 int net_apply_dots(const adlbr_net *net, const adlbr_operator *op, const float *r,
-                   const float *rp, float *z, double *part, long long *nparts, hipStream_t s);
+                   const float *rp, float *z, double *part, long long *nparts,
+                   const CgState *st, hipStream_t s);
 
 // Rows per block of the explicit-step kernels: every wave of a 256-thread
 // block takes kApplyPPT groups of 64 consecutive rows.

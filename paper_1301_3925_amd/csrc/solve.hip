@@ -298,7 +298,8 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
             // z = N(r) with the dots <z, r>, <z, r_prev> fused where possible
             long long np = 0;
             int e = net_apply_dots(p->net, op, (const float *)rc_,
-                                   first ? nullptr : (const float *)ro, (float *)z, part, &np, s);
+                                   first ? nullptr : (const float *)ro, (float *)z, part, &np, cg,
+                                   s);
             if (e) return e;
             hipLaunchKernelGGL(k_fcg_scalars, dim3(1), dim3(kBS), 0, s, st, (const double *)part,
                                np, (const double *)prr, (long long)nb, hist, kMaxHist, first);
