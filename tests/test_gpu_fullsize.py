@@ -1,0 +1,240 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times.
+
+The oracle cannot run these workloads end to end, so every test compares
+outputs the oracle can compute one by one at sampled points, and checks
+properties that hold at any size:
+
+- 2048^2 coherence-enhancing diffusion, FP32: the diffusion tensor at
+  sampled points against the oracle's tensor of the whole image; offsets
+  (bit-exact) and weights at those points against the oracle's stencils of
+  the GPU's own tensor; the diagonal and one explicit step at the sampled
+  rows against the oracle's operator on a crop around each row; mass and
+  the maximum principle over ten steps of the whole grid.
+- 256^3, kappa <= 50, FP32 storage: stencils, diagonal and one step the
+  same way.
+- 1024^2 implicit step (kappa = 200, dt = 50 x CFL), FP32: Jacobi-PCG to
+  1e-6, with the residual of the returned x recomputed by the oracle's
+  operator on the whole grid.
+
+A row of A involves only points within the largest offset component R of
+it (its own edges reach at most R, and a source whose edge lands on it lies
+within that source's offset), so the oracle's operator on the crop of
+half-width R around the row, with the GPU's exported offsets and weights,
+holds the whole row (crops at the grid border end where the grid ends, as
+the Neumann rule drops edges there).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_3925_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+NSAMPLE = 256
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_1301_3925_amd as adlbr
+    assert torch.cuda.is_available()
+    return adlbr
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _samples(seed, dims, k=NSAMPLE):
+    """k distinct linear indices: a few corners and edge points, the rest random."""
+    n = int(np.prod(dims))
+    corners = [0, dims[0] - 1, n - 1, n - dims[0]]
+    rnd = np.random.default_rng(seed).choice(n, k - len(corners), replace=False)
+    return np.unique(np.concatenate([np.array(corners), rnd]))
+
+
+def _crop_row(dims, off, w, u, z, R):
+    """(A u)(z) and A_zz by the oracle's operator on the crop of half-width R
+    around z (off: int16 [S][d][N], w: [S][N], u: [N], all full-grid, x
+    fastest)."""
+    d = len(dims)
+    coords, rest = [], int(z)
+    for n in dims:
+        coords.append(rest % n)
+        rest //= n
+    lo = [max(0, c - R) for c in coords]
+    hi = [min(n, c + R + 1) for c, n in zip(coords, dims)]
+    cdims = tuple(h - l for l, h in zip(lo, hi))
+    ax = [np.arange(l, h, dtype=np.int64) for l, h in zip(lo, hi)]
+    if d == 2:
+        lin = (ax[1][:, None] * dims[0] + ax[0][None, :]).reshape(-1)
+        c = (coords[0] - lo[0]) + cdims[0] * (coords[1] - lo[1])
+    else:
+        lin = (ax[2][:, None, None] * (dims[0] * dims[1]) + ax[1][None, :, None] * dims[0]
+               + ax[0][None, None, :]).reshape(-1)
+        c = (coords[0] - lo[0]) + cdims[0] * ((coords[1] - lo[1]) + cdims[1] * (coords[2] - lo[2]))
+    A = oracle.operator_matrix(cdims, off[:, :, lin], w[:, lin].astype(np.float64)).tocsr()
+    row = A.getrow(c)
+    return float(row @ u[lin].astype(np.float64)), float(A[c, c])
+
+
+@pytest.fixture(scope="module")
+def ced2048(lib):
+    import torch
+    n = 2048
+    dims = (n, n)
+    u0 = torch.from_numpy(synth.ced_image2d(1302, n, n)).float().cuda()
+    D = lib.structure_tensor(u0, dims, 1.0, 4.0, 1e-4, 1e-5)
+    off, w, st = lib.build_stencils(D, dims)
+    assert st.cpu().numpy()[0] == -1
+    op = lib.Operator(dims, off, w, storage=torch.float32)
+    return dims, u0, D, off, w, op
+
+
+def test_c2_full_size_tensor_sampled(lib, ced2048):
+    dims, u0, D, _, _, _ = ced2048
+    ref = oracle.structure_tensor_d(u0.double().cpu().numpy(), dims, 1.0, 4.0, 1e-4, 1e-5)
+    idx = _samples(1, dims)
+    got = D.double().cpu().numpy()[:, idx]
+    assert _rel(got, ref[:, idx]) <= 1e-5
+
+
+def test_c2_full_size_stencils_sampled(lib, ced2048):
+    dims, _, D, off, w, _ = ced2048
+    idx = _samples(2, dims)
+    Dref = D.double().cpu().numpy()[:, idx]  # the oracle sees the GPU's own tensor
+    ro, rw, _ = oracle.stencil(Dref)
+    assert np.array_equal(off.cpu().numpy()[:, :, idx], ro)
+    got = w.double().cpu().numpy()[:, idx]
+    assert np.allclose(got, rw.astype(np.float32).astype(np.float64), rtol=1e-6, atol=0)
+
+
+def test_c2_full_size_step_sampled(lib, ced2048):
+    """One explicit step at dt = 0.9 / max A_zz, and the diagonal, at the
+    sampled rows; ten steps keep the mass and the bounds of u0."""
+    import torch
+    dims, u0, _, off, w, op = ced2048
+    offn, wn = off.cpu().numpy(), w.double().cpu().numpy()
+    R = int(np.abs(offn).max())
+    diag = op.diagonal().double().cpu().numpy()
+    assert op.dt_cfl() == pytest.approx(1.0 / diag.max(), rel=1e-6)
+    dt = 0.9 * op.dt_cfl()
+    u = u0.clone()
+    op.step(u, 0.9, 1, cfl_fraction=True)
+    un, u1 = u0.double().cpu().numpy(), u.double().cpu().numpy()
+    idx = _samples(3, dims, 96)
+    ref = np.empty(idx.size)
+    dref = np.empty(idx.size)
+    for k, z in enumerate(idx):
+        au, dz = _crop_row(dims, offn, wn, un, int(z), R)
+        ref[k] = un[z] - dt * au
+        dref[k] = dz
+    assert _rel(diag[idx], dref) <= 1e-6
+    assert _rel(u1[idx], ref) <= 1e-5
+    op.step(u, 0.9, 9, cfl_fraction=True)
+    u10 = u.double().cpu().numpy()
+    assert abs(u10.sum() - un.sum()) <= 1e-6 * abs(un.sum())
+    assert u10.min() >= un.min() - 1e-6 and u10.max() <= un.max() + 1e-6
+
+
+def test_c3_full_size_sampled(lib):
+    """256^3, kappa <= 50: stencils bit-exact and the diagonal and one FP32
+    step at sampled rows."""
+    import torch
+    dims = (256, 256, 256)
+    D = synth.tensor3d_field(1303, dims, 50.0)
+    off, w, st = lib.build_stencils(torch.from_numpy(D).cuda(), dims)
+    assert st.cpu().numpy()[0] == -1
+    idx = _samples(4, dims)
+    ro, rw, _ = oracle.stencil(np.ascontiguousarray(D[:, idx]))
+    offn = off.cpu().numpy()
+    assert np.array_equal(offn[:, :, idx], ro)
+    wn = w.cpu().numpy()
+    r2 = (ro.astype(np.float64) ** 2).sum(1).max(0)
+    scale = np.abs(D[:, idx]).max(0) * np.maximum(1.0, r2)
+    assert np.all(np.abs(wn[:, idx] - rw) <= 1e-14 * scale)
+    del D
+    op = lib.Operator(dims, off, w, storage=torch.float32)
+    u0 = torch.from_numpy(synth.uniform(1304, int(np.prod(dims)))).float().cuda()
+    u = u0.clone()
+    op.step(u, 0.9, 1, cfl_fraction=True)
+    dt = 0.9 * op.dt_cfl()
+    # the FP32 operator's weights are the FP32 roundings of the exported ones
+    w32 = w.float().double().cpu().numpy()
+    un, u1 = u0.double().cpu().numpy(), u.double().cpu().numpy()
+    diag = op.diagonal().double().cpu().numpy()
+    R = int(np.abs(offn).max())
+    sidx = idx[:48]
+    ref = np.empty(sidx.size)
+    dref = np.empty(sidx.size)
+    for k, z in enumerate(sidx):
+        au, dz = _crop_row(dims, offn, w32, un, int(z), R)
+        ref[k] = un[z] - dt * au
+        dref[k] = dz
+    assert _rel(diag[sidx], dref) <= 1e-6
+    assert _rel(u1[sidx], ref) <= 1e-5
+
+
+def test_c5_full_size_jacobi_residual_by_oracle(lib):
+    """1024^2, kappa = 200, dt = 50 x CFL: Jacobi-PCG to 1e-6; the residual
+    of the returned x, recomputed in FP64 by the oracle's operator (with the
+    FP32 weights the GPU uses), is within the tolerance."""
+    import torch
+    dims = (1024, 1024)
+    D = synth.tensor2d_field(1305, 1024, 1024, 200.0)
+    off, w, st = lib.build_stencils(torch.from_numpy(D).cuda(), dims)
+    op = lib.Operator(dims, off, w, storage=torch.float32)
+    dt = 50.0 * op.dt_cfl()
+    N = int(np.prod(dims))
+    b = torch.from_numpy(synth.uniform(1305, N)).float().cuda()
+    x, rep = op.solve(b, dt, method="jacobi", tol=1e-6, check_every=10)
+    assert rep["converged"]
+    A = oracle.operator_matrix(dims, off.cpu().numpy(), w.float().double().cpu().numpy())
+    xn, bn = x.double().cpu().numpy(), b.double().cpu().numpy()
+    r = bn - (xn + dt * (A @ xn))
+    # x is returned in FP32: its rounding adds about |K| 6e-8 |x| to the FP64 residual
+    assert np.linalg.norm(r) / np.linalg.norm(bn) <= 1.2e-6
+
+
+def test_c4_full_batch_autotuned_bitwise(lib):
+    """The whole uneven batch (64 images 256^2..1536^2, 8 volumes
+    64^3..192^3, FP32), autotuned and run through the captured graph as
+    bench.py runs it: every problem bit-identical to stepping it alone, and
+    a sampled row of one image against the oracle's operator."""
+    import torch
+    probs = synth.batch_problems(1304)
+    ops, us, refs, offs = [], [], [], []
+    for p in probs:
+        D = (synth.tensor2d_field(p["seed"], *p["n"], p["kappa"]) if p["dim"] == 2
+             else synth.tensor3d_field(p["seed"], p["n"], p["kappa"]))
+        off, w, st = lib.build_stencils(torch.from_numpy(D).float().cuda(), p["n"])
+        assert st.cpu().numpy()[0] == -1
+        ops.append(lib.Operator(p["n"], off, w, storage=torch.float32))
+        offs.append((off, w))
+        u0 = torch.from_numpy(synth.uniform(p["seed"] + 7, int(np.prod(p["n"])))).float().cuda()
+        us.append(u0)
+        refs.append(u0.clone())
+    nsteps = 3
+    b = lib.Batch(ops, us, dt=0.9, dt_mode="cfl")
+    b.tune(steps=3, use_cache=False)
+    b.run(nsteps)
+    for op, r in zip(ops, refs):
+        op.step(r, 0.9, nsteps, cfl_fraction=True)
+    torch.cuda.synchronize()
+    for k, (u, r) in enumerate(zip(us, refs)):
+        assert torch.equal(u, r), k
+    # one explicit step of the first image at sampled rows, by the oracle
+    k = 0
+    dims = tuple(probs[k]["n"])
+    off, w = offs[k]
+    u0 = torch.from_numpy(synth.uniform(probs[k]["seed"] + 7, int(np.prod(dims)))).float().cuda()
+    u1 = u0.clone()
+    ops[k].step(u1, 0.9, 1, cfl_fraction=True)
+    offn, wn = off.cpu().numpy(), w.double().cpu().numpy()
+    un, u1n = u0.double().cpu().numpy(), u1.double().cpu().numpy()
+    dt = 0.9 * ops[k].dt_cfl()
+    R = int(np.abs(offn).max())
+    idx = _samples(5, dims, 32)
+    ref = np.array([un[z] - dt * _crop_row(dims, offn, wn, un, int(z), R)[0] for z in idx])
+    assert _rel(u1n[idx], ref) <= 1e-5
