@@ -302,10 +302,11 @@ int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
  *   gates8   [N][2W] uint8     g1, g2 per point as round(255 g) for the
  *                              inference kernel
  *   scratch  [2W][N] FP32      working planes of the FP32 forward path
- *   layers   [2W(W+1)T + 3584] FP32  weights of the four-layer stack, [W1,
- *                              W2, flip(W2)^T, flip(W1)^T], then (2D) the
- *                              BF16 MFMA operands of its four layers packed
- *                              per lane (adlbr_net_gates)
+ *   layers   [2W(W+1)T + 7168] FP32  weights of the four-layer stack, [W1,
+ *                              W2, flip(W2)^T, flip(W1)^T], then the BF16
+ *                              MFMA operands packed per lane (2D: all four
+ *                              layers; 3D: the two W -> W layers)
+ *                              (adlbr_net_gates)
  * adlbr_net_gates must run again after params change.
  * ------------------------------------------------------------------ */
 typedef struct adlbr_net {
@@ -334,9 +335,11 @@ int adlbr_net_gates(adlbr_operator *op, adlbr_net *net, void *stream);
  * for adlbr_net_backward. */
 int adlbr_net_forward(adlbr_operator *op, const adlbr_net *net, const float *r, float *z,
                       float *saved, void *stream);
-/* The inference path flexible CG uses: in 2D with net->gates8 set, the
- * fused MFMA kernel (BF16 operands, FP32 accumulation, 8-bit gates);
- * otherwise the FP32 path of adlbr_net_forward. */
+/* The inference path flexible CG uses, with net->gates8 set: in 2D the
+ * fused MFMA kernel (BF16 operands, FP32 accumulation, 8-bit gates); in 3D
+ * (also net->scratch) the W -> W layers on MFMA and the thin layers in
+ * FP32, BF16 activations between layers; otherwise the FP32 path of
+ * adlbr_net_forward. */
 int adlbr_net_precondition(adlbr_operator *op, const adlbr_net *net, const float *r, float *z,
                            void *stream);
 /* Backward of sum(gz * z) for one sample: adds the r-path weight

@@ -329,7 +329,7 @@ class Net:
         self.gates8 = torch.empty((N, 32), dtype=torch.uint8, device=dev)
         self.scratch = torch.empty((32, N), dtype=torch.float32, device=dev)
         T = 3 ** self.dim
-        self.layers = torch.empty(2 * 16 * 17 * T + 3584, dtype=torch.float32, device=dev)
+        self.layers = torch.empty(2 * 16 * 17 * T + 7168, dtype=torch.float32, device=dev)
         self._s = capi.NetStruct(self.dim, 16, 16, nf, self.params.data_ptr(),
                                  self.features.data_ptr(), self.hidden_act.data_ptr(),
                                  self.gates.data_ptr(), self.gates8.data_ptr(),

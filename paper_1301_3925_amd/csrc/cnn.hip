@@ -25,6 +25,9 @@ int net_apply_mfma(const adlbr_net *net, const adlbr_operator *op, const float *
                    const float *rp, double *part, const CgState *st, hipStream_t s);
 int net_mfma_blocks(int nx, int ny);
 int net_pack_mfma(const adlbr_net *net, hipStream_t s);
+int net_pack_mfma3d(const adlbr_net *net, hipStream_t s);
+int net_apply_mfma3d(const adlbr_net *net, const adlbr_operator *op, const float *r, float *z,
+                     const float *rp, double *part, const CgState *st, hipStream_t s);
 
 namespace {
 
@@ -704,6 +707,9 @@ int net_apply(const adlbr_net *net, const adlbr_operator *op, double dt, const v
     }
     if (d.dim == 2 && net->gates8)
         return net_apply_mfma(net, op, (const float *)r, (float *)z, nullptr, nullptr, nullptr, s);
+    if (d.dim == 3 && net->gates8 && net->scratch)
+        return net_apply_mfma3d(net, op, (const float *)r, (float *)z, nullptr, nullptr, nullptr,
+                                s);
     if (!net->scratch) {
         set_error("net: the FP32 inference path needs net->scratch ([2W][N] FP32)");
         return ADLBR_E_INVALID;
@@ -741,6 +747,10 @@ int net_apply_dots(const adlbr_net *net, const adlbr_operator *op, const float *
     if (d.dim == 2 && net->gates8 && operator_storage(op) == ADLBR_F32) {
         *nparts = net_mfma_blocks(g.nx, g.ny);
         return net_apply_mfma(net, op, r, z, rp, part, st, s);
+    }
+    if (d.dim == 3 && net->gates8 && net->scratch && operator_storage(op) == ADLBR_F32) {
+        *nparts = nblk(g.N);
+        return net_apply_mfma3d(net, op, r, z, rp, part, st, s);
     }
     rc = net_apply(net, op, 0.0, r, z, s);
     if (rc) return rc;
@@ -824,10 +834,8 @@ extern "C" int adlbr_net_gates(adlbr_operator *op, adlbr_net *net, void *stream)
                        net->gates8);
     hipLaunchKernelGGL(k_expand_weights, dim3(16), dim3(kBS), 0, s, P + d.oW1, P + d.oW2,
                        net->layers, d.W, d.T, d.l2, d.l3, d.l4);
-    if (g.dim == 2) {
-        rc = net_pack_mfma(net, s);
-        if (rc) return rc;
-    }
+    rc = g.dim == 2 ? net_pack_mfma(net, s) : net_pack_mfma3d(net, s);
+    if (rc) return rc;
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }

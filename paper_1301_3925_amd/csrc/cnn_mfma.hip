@@ -342,6 +342,180 @@ __global__ void k_pack_mfma(const float *__restrict__ L1, const float *__restric
     out[e] = v;
 }
 
+
+// ------------------------------------------------------------------ 3D --
+// The 3D inference runs layer by layer: the thin layers (1 -> 16, 16 -> 1)
+// on the vector units, one thread per point; the two 16 -> 16 layers on the
+// matrix cores as implicit GEMMs over 8 x 8 x 4 tiles (27 taps x one
+// v_mfma_f32_16x16x16_bf16 per 16-pixel group, the tile plus a one-point
+// halo staged in LDS).  Activations cross HBM between layers as BF16
+// [N][16] (32 bytes a point), gates as the 8-bit g1, g2 of every point.
+constexpr int k3X = 8, k3Y = 8, k3Z = 4;                 // output tile
+constexpr int k3HX = k3X + 2, k3HY = k3Y + 2, k3HZ = k3Z + 2;
+constexpr int k3Halo = k3HX * k3HY * k3HZ;               // 600 staged points
+constexpr int k3T = 27;
+
+__device__ __forceinline__ bool in_grid3(int x, int y, int z, int nx, int ny, int nz) {
+    return x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz;
+}
+
+// Layer 1: a1[p][co] = g1[p][co] sum_t W1[co][t] r(p + off_t), r = 0 outside
+// the grid (tap t = (dz + 1) 9 + (dy + 1) 3 + (dx + 1)).
+__global__ __launch_bounds__(256) void k_net3d_l1(GridInfo g, const float *__restrict__ r,
+                                                  const float *__restrict__ W1,
+                                                  const uint8_t *__restrict__ G8,
+                                                  uint4 *__restrict__ a1,
+                                                  const CgState *__restrict__ st) {
+    if (st && (st->done || st->bad)) return;
+    __shared__ float sw[16 * k3T];
+    for (int k = threadIdx.x; k < 16 * k3T; k += blockDim.x) sw[k] = W1[k];
+    __syncthreads();
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.N) return;
+    const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
+    float rv[k3T];
+#pragma unroll
+    for (int t = 0; t < k3T; ++t) {
+        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+        rv[t] = in_grid3(x + dx, y + dy, z + dz, g.nx, g.ny, g.nz)
+                    ? r[i + dx + (long long)g.nx * (dy + (long long)g.ny * dz)]
+                    : 0.f;
+    }
+    const uint4 gq = ((const uint4 *)G8)[2 * i];  // g1: bytes 0 .. 15
+    const uint32_t gw[4] = {gq.x, gq.y, gq.z, gq.w};
+    uint32_t outw[8];
+#pragma unroll
+    for (int co = 0; co < 16; co += 2) {
+        float a0 = 0.f, b0 = 0.f;
+#pragma unroll
+        for (int t = 0; t < k3T; ++t) {
+            a0 += sw[co * k3T + t] * rv[t];
+            b0 += sw[(co + 1) * k3T + t] * rv[t];
+        }
+        a0 *= q8((gw[co >> 2] >> (8 * (co & 3))) & 0xffu);
+        b0 *= q8((gw[(co + 1) >> 2] >> (8 * ((co + 1) & 3))) & 0xffu);
+        outw[co >> 1] = (uint32_t)(uint16_t)bfbits(a0) | ((uint32_t)(uint16_t)bfbits(b0) << 16);
+    }
+    a1[2 * i] = make_uint4(outw[0], outw[1], outw[2], outw[3]);
+    a1[2 * i + 1] = make_uint4(outw[4], outw[5], outw[6], outw[7]);
+}
+
+// Layers 2 and 3 (16 -> 16): out[p][co] = g[p][co] sum_t sum_ci W_t[co][ci]
+// in(p + off_t)[ci], as D = W_t X_t on the matrix cores.  wpack: the layer's
+// 27 A operands, per lane (row co = lane & 15, ci = 4 (lane >> 4) + c);
+// goff: byte offset of the gate in each point's 32 gate bytes (0: g1,
+// 16: g2).
+__global__ __launch_bounds__(256) void k_net3d_mfma(GridInfo g, const uint2 *__restrict__ in,
+                                                    const bf16x4 *__restrict__ wpack,
+                                                    const uint8_t *__restrict__ G8, int goff,
+                                                    uint2 *__restrict__ out,
+                                                    const CgState *__restrict__ st) {
+    if (st && (st->done || st->bad)) return;
+    __shared__ __attribute__((aligned(16))) short sx[k3Halo * kStride];
+    const int ntx = (g.nx + k3X - 1) / k3X, nty = (g.ny + k3Y - 1) / k3Y;
+    const int bx = (int)(blockIdx.x % ntx), by = (int)((blockIdx.x / ntx) % nty),
+              bz = (int)(blockIdx.x / ((long long)ntx * nty));
+    const int x0 = bx * k3X - 1, y0 = by * k3Y - 1, z0 = bz * k3Z - 1;  // halo origin
+    // stage the tile and its halo: 4 channels (8 bytes) per item, 0 outside
+    for (int k = threadIdx.x; k < k3Halo * 4; k += blockDim.x) {
+        const int h = k >> 2, q = k & 3;
+        const int hx = h % k3HX, hy = (h / k3HX) % k3HY, hz = h / (k3HX * k3HY);
+        const int x = x0 + hx, y = y0 + hy, z = z0 + hz;
+        uint2 v = make_uint2(0u, 0u);
+        if (in_grid3(x, y, z, g.nx, g.ny, g.nz))
+            v = in[4 * (x + (long long)g.nx * (y + (long long)g.ny * z)) + q];
+        *(uint2 *)(sx + h * kStride + 4 * q) = v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bf16x4 wb[k3T];
+#pragma unroll
+    for (int t = 0; t < k3T; ++t) wb[t] = wpack[t * 64 + lane];
+    __syncthreads();
+    const int n = lane & 15, kq = (lane >> 4) * 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int p = (wave * 4 + j) * 16 + n;  // this lane's output point in the tile
+        const int px = p % k3X, py = (p / k3X) % k3Y, pz = p / (k3X * k3Y);
+        const short *base = sx + ((pz + 1) * (k3HX * k3HY) + (py + 1) * k3HX + (px + 1)) * kStride + kq;
+        f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < k3T; ++t) {
+            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+            const bf16x4 b = *(const bf16x4 *)(base + (dz * (k3HX * k3HY) + dy * k3HX + dx) * kStride);
+            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wb[t], b, d, 0, 0, 0);
+        }
+        const int x = x0 + 1 + px, y = y0 + 1 + py, z = z0 + 1 + pz;
+        if (!in_grid3(x, y, z, g.nx, g.ny, g.nz)) continue;
+        const long long i = x + (long long)g.nx * (y + (long long)g.ny * z);
+        const uint32_t g4 = *(const uint32_t *)(G8 + 32 * i + goff + kq);
+        float v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = d[c] * q8((g4 >> (8 * c)) & 0xffu);
+        out[4 * i + (kq >> 2)] =
+            make_uint2((uint16_t)bfbits(v[0]) | ((uint32_t)(uint16_t)bfbits(v[1]) << 16),
+                       (uint16_t)bfbits(v[2]) | ((uint32_t)(uint16_t)bfbits(v[3]) << 16));
+    }
+}
+
+// Layer 4 (16 -> 1) and the output: z = F0 r + sum_t sum_ci W4[ci][t]
+// a3(p + off_t)[ci]; with part, the per-block FP64 partials of <z, r> in
+// part[0 .. gridDim) and of <z, rp> in part[gridDim .. 2 gridDim).
+__global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint4 *__restrict__ a3,
+                                                  const float *__restrict__ W4,
+                                                  const float *__restrict__ r,
+                                                  const float *__restrict__ F0,
+                                                  float *__restrict__ zout,
+                                                  const float *__restrict__ rp,
+                                                  double *__restrict__ part,
+                                                  const CgState *__restrict__ st) {
+    if (st && (st->done || st->bad)) return;
+    __shared__ float sw[16 * k3T];
+    for (int k = threadIdx.x; k < 16 * k3T; k += blockDim.x) sw[k] = W4[k];
+    __syncthreads();
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double zr = 0.0, zrp = 0.0;
+    if (i < g.N) {
+        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny),
+                  z = (int)(i / ((long long)g.nx * g.ny));
+        float acc = 0.f;
+        for (int t = 0; t < k3T; ++t) {
+            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+            if (!in_grid3(x + dx, y + dy, z + dz, g.nx, g.ny, g.nz)) continue;
+            const long long q = i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
+            const uint4 lo = a3[2 * q], hi = a3[2 * q + 1];
+            const uint32_t wds[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+            for (int ci = 0; ci < 16; ++ci) {
+                const uint32_t bits = (wds[ci >> 1] >> (16 * (ci & 1))) << 16;
+                acc += sw[ci * k3T + t] * __uint_as_float(bits);
+            }
+        }
+        const float ri = r[i];
+        const float zi = F0[i] * ri + acc;
+        zout[i] = zi;
+        zr = (double)zi * (double)ri;
+        if (rp) zrp = (double)zi * (double)rp[i];
+    }
+    if (part) {
+        block_partial_sum(zr, part);
+        block_partial_sum(zrp, part + gridDim.x);
+    }
+}
+
+// The A operands of layers 2 and 3 (3D), per lane: [layer][tap][lane].
+__global__ void k_pack_mfma3d(const float *__restrict__ L2, const float *__restrict__ L3,
+                              bf16x4 *__restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * k3T * 64) return;
+    const int lane = e % 64, t = (e / 64) % k3T;
+    const float *W = e >= k3T * 64 ? L3 : L2;
+    const int co = lane & 15, k0 = (lane >> 4) * 4;
+    bf16x4 v;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = bfbits(W[(co * 16 + k0 + c) * k3T + t]);
+    out[e] = v;
+}
+
 }  // namespace
 
 // Offset (in floats) of the packed MFMA operands inside net->layers (2D).
@@ -352,6 +526,41 @@ int net_pack_mfma(const adlbr_net *net, hipStream_t s) {
     const size_t l2 = 16 * 9, l3 = l2 + 16 * 16 * 9, l4 = l3 + 16 * 16 * 9;
     hipLaunchKernelGGL(k_pack_mfma, dim3((kPackEntries + 255) / 256), dim3(256), 0, s, L, L + l2,
                        L + l3, L + l4, (bf16x4 *)(net->layers + kPackOffset));
+    ADLBR_LAUNCH_CHECK();
+    return ADLBR_OK;
+}
+
+// Packed 3D operands sit after the expanded 3D weights (T = 27).
+constexpr size_t kPackOffset3 = 2 * 16 * 17 * 27;
+
+int net_pack_mfma3d(const adlbr_net *net, hipStream_t s) {
+    const float *L = net->layers;
+    const size_t l2 = 16 * 27, l3 = l2 + 16 * 16 * 27;
+    hipLaunchKernelGGL(k_pack_mfma3d, dim3((2 * k3T * 64 + 255) / 256), dim3(256), 0, s, L + l2,
+                       L + l3, (bf16x4 *)(net->layers + kPackOffset3));
+    ADLBR_LAUNCH_CHECK();
+    return ADLBR_OK;
+}
+
+int net_apply_mfma3d(const adlbr_net *net, const adlbr_operator *op, const float *r, float *z,
+                     const float *rp, double *part, const CgState *st, hipStream_t s) {
+    const GridInfo &g = operator_grid(op);
+    const long long N = g.N;
+    const float *L = net->layers;
+    const size_t l2 = 16 * 27, l3 = l2 + 16 * 16 * 27, l4 = l3 + 16 * 16 * 27;
+    const bf16x4 *pk = (const bf16x4 *)(net->layers + kPackOffset3);
+    // activations as BF16 [N][16] in the two halves of the FP32 scratch
+    uint4 *A = (uint4 *)net->scratch, *B = (uint4 *)(net->scratch + 8 * N);
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    const unsigned nt = (unsigned)(((g.nx + k3X - 1) / k3X) * (long long)((g.ny + k3Y - 1) / k3Y) *
+                                   ((g.nz + k3Z - 1) / k3Z));
+    hipLaunchKernelGGL(k_net3d_l1, dim3(nb), dim3(256), 0, s, g, r, L, net->gates8, A, st);
+    hipLaunchKernelGGL(k_net3d_mfma, dim3(nt), dim3(256), 0, s, g, (const uint2 *)A, pk,
+                       net->gates8, 16, (uint2 *)B, st);
+    hipLaunchKernelGGL(k_net3d_mfma, dim3(nt), dim3(256), 0, s, g, (const uint2 *)B, pk + k3T * 64,
+                       net->gates8, 0, (uint2 *)A, st);
+    hipLaunchKernelGGL(k_net3d_l4, dim3(nb), dim3(256), 0, s, g, (const uint4 *)A, L + l4, r,
+                       net->features, z, rp, part, st);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }

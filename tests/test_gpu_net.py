@@ -130,12 +130,14 @@ def test_residual(lib):
     assert _rel(r.double().cpu().numpy(), b - K @ x) <= 1e-5
 
 
-def test_mfma_inference_matches_fp32_forward(lib):
-    """The fused BF16 MFMA kernel agrees with the FP32 forward to BF16
-    accuracy on a ragged grid (tiles cut by both edges)."""
+@pytest.mark.parametrize("dims", [(100, 75), (21, 18, 13)])
+def test_mfma_inference_matches_fp32_forward(lib, dims):
+    """The MFMA inference (2D: the fused kernel; 3D: the layer kernels)
+    agrees with the FP32 forward to BF16 accuracy on a ragged grid (tiles
+    cut by every edge)."""
     import torch
-    dims = (100, 75)
-    D = synth.tensor2d_field(9, *dims, 100.0)
+    D = (synth.tensor2d_field(9, *dims, 100.0) if len(dims) == 2
+         else synth.tensor3d_field(9, dims, 50.0))
     off, w, _ = lib.build_stencils(torch.from_numpy(D).cuda(), dims)
     op = lib.Operator(dims, off, w, storage=torch.float32)
     A = oracle.operator_matrix(dims, off.cpu().numpy(), w.cpu().numpy())
