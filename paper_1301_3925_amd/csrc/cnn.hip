@@ -28,6 +28,7 @@ int net_pack_mfma(const adlbr_net *net, hipStream_t s);
 int net_pack_mfma3d(const adlbr_net *net, hipStream_t s);
 int net_apply_mfma3d(const adlbr_net *net, const adlbr_operator *op, const float *r, float *z,
                      const float *rp, double *part, const CgState *st, hipStream_t s);
+long long net3d_tiles(const GridInfo &g);
 
 namespace {
 
@@ -749,7 +750,7 @@ int net_apply_dots(const adlbr_net *net, const adlbr_operator *op, const float *
         return net_apply_mfma(net, op, r, z, rp, part, st, s);
     }
     if (d.dim == 3 && net->gates8 && net->scratch && operator_storage(op) == ADLBR_F32) {
-        *nparts = nblk(g.N);
+        *nparts = net3d_tiles(g);
         return net_apply_mfma3d(net, op, r, z, rp, part, st, s);
     }
     rc = net_apply(net, op, 0.0, r, z, s);

@@ -359,28 +359,50 @@ __device__ __forceinline__ bool in_grid3(int x, int y, int z, int nx, int ny, in
     return x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz;
 }
 
+// The tile of block b (8 x 8 x 4 points) and the origin of its halo.
+struct Tile3 {
+    int x0, y0, z0;  // halo origin = tile origin - 1
+};
+__device__ __forceinline__ Tile3 tile3(const GridInfo &g, long long b) {
+    const int ntx = (g.nx + k3X - 1) / k3X, nty = (g.ny + k3Y - 1) / k3Y;
+    Tile3 t;
+    t.x0 = (int)(b % ntx) * k3X - 1;
+    t.y0 = (int)((b / ntx) % nty) * k3Y - 1;
+    t.z0 = (int)(b / ((long long)ntx * nty)) * k3Z - 1;
+    return t;
+}
+// LDS index of tile point p's neighbour at tap t in the halo region.
+__device__ __forceinline__ int halo_idx(int p, int t) {
+    const int px = p % k3X, py = (p / k3X) % k3Y, pz = p / (k3X * k3Y);
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    return (pz + 1 + dz) * (k3HX * k3HY) + (py + 1 + dy) * k3HX + (px + 1 + dx);
+}
+
 // Layer 1: a1[p][co] = g1[p][co] sum_t W1[co][t] r(p + off_t), r = 0 outside
-// the grid (tap t = (dz + 1) 9 + (dy + 1) 3 + (dx + 1)).
+// the grid (tap t = (dz + 1) 9 + (dy + 1) 3 + (dx + 1)); one thread per
+// point of an 8 x 8 x 4 tile, r of the tile and its halo staged in LDS.
 __global__ __launch_bounds__(256) void k_net3d_l1(GridInfo g, const float *__restrict__ r,
                                                   const float *__restrict__ W1,
                                                   const uint8_t *__restrict__ G8,
                                                   uint4 *__restrict__ a1,
                                                   const CgState *__restrict__ st) {
     if (st && (st->done || st->bad)) return;
-    __shared__ float sw[16 * k3T];
-    for (int k = threadIdx.x; k < 16 * k3T; k += blockDim.x) sw[k] = W1[k];
-    __syncthreads();
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.N) return;
-    const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((long long)g.nx * g.ny));
-    float rv[k3T];
-#pragma unroll
-    for (int t = 0; t < k3T; ++t) {
-        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-        rv[t] = in_grid3(x + dx, y + dy, z + dz, g.nx, g.ny, g.nz)
-                    ? r[i + dx + (long long)g.nx * (dy + (long long)g.ny * dz)]
+    __shared__ float sr[k3Halo];
+    const Tile3 T = tile3(g, blockIdx.x);
+    for (int h = threadIdx.x; h < k3Halo; h += blockDim.x) {
+        const int x = T.x0 + h % k3HX, y = T.y0 + (h / k3HX) % k3HY, z = T.z0 + h / (k3HX * k3HY);
+        sr[h] = in_grid3(x, y, z, g.nx, g.ny, g.nz)
+                    ? r[x + (long long)g.nx * (y + (long long)g.ny * z)]
                     : 0.f;
     }
+    __syncthreads();
+    const int p = threadIdx.x;
+    const int x = T.x0 + 1 + p % k3X, y = T.y0 + 1 + (p / k3X) % k3Y, z = T.z0 + 1 + p / (k3X * k3Y);
+    if (!in_grid3(x, y, z, g.nx, g.ny, g.nz)) return;
+    const long long i = x + (long long)g.nx * (y + (long long)g.ny * z);
+    float rv[k3T];
+#pragma unroll
+    for (int t = 0; t < k3T; ++t) rv[t] = sr[halo_idx(p, t)];
     const uint4 gq = ((const uint4 *)G8)[2 * i];  // g1: bytes 0 .. 15
     const uint32_t gw[4] = {gq.x, gq.y, gq.z, gq.w};
     uint32_t outw[8];
@@ -388,9 +410,9 @@ __global__ __launch_bounds__(256) void k_net3d_l1(GridInfo g, const float *__res
     for (int co = 0; co < 16; co += 2) {
         float a0 = 0.f, b0 = 0.f;
 #pragma unroll
-        for (int t = 0; t < k3T; ++t) {
-            a0 += sw[co * k3T + t] * rv[t];
-            b0 += sw[(co + 1) * k3T + t] * rv[t];
+        for (int t = 0; t < k3T; ++t) {  // uniform weights: scalar loads, SGPR operands
+            a0 += W1[co * k3T + t] * rv[t];
+            b0 += W1[(co + 1) * k3T + t] * rv[t];
         }
         a0 *= q8((gw[co >> 2] >> (8 * (co & 3))) & 0xffu);
         b0 *= q8((gw[(co + 1) >> 2] >> (8 * ((co + 1) & 3))) & 0xffu);
@@ -412,10 +434,8 @@ __global__ __launch_bounds__(256) void k_net3d_mfma(GridInfo g, const uint2 *__r
                                                     const CgState *__restrict__ st) {
     if (st && (st->done || st->bad)) return;
     __shared__ __attribute__((aligned(16))) short sx[k3Halo * kStride];
-    const int ntx = (g.nx + k3X - 1) / k3X, nty = (g.ny + k3Y - 1) / k3Y;
-    const int bx = (int)(blockIdx.x % ntx), by = (int)((blockIdx.x / ntx) % nty),
-              bz = (int)(blockIdx.x / ((long long)ntx * nty));
-    const int x0 = bx * k3X - 1, y0 = by * k3Y - 1, z0 = bz * k3Z - 1;  // halo origin
+    const Tile3 T = tile3(g, blockIdx.x);
+    const int x0 = T.x0, y0 = T.y0, z0 = T.z0;
     // stage the tile and its halo: 4 channels (8 bytes) per item, 0 outside
     for (int k = threadIdx.x; k < k3Halo * 4; k += blockDim.x) {
         const int h = k >> 2, q = k & 3;
@@ -458,9 +478,11 @@ __global__ __launch_bounds__(256) void k_net3d_mfma(GridInfo g, const uint2 *__r
 }
 
 // Layer 4 (16 -> 1) and the output: z = F0 r + sum_t sum_ci W4[ci][t]
-// a3(p + off_t)[ci]; with part, the per-block FP64 partials of <z, r> in
-// part[0 .. gridDim) and of <z, rp> in part[gridDim .. 2 gridDim).
-__global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint4 *__restrict__ a3,
+// a3(p + off_t)[ci], on the matrix cores like layers 2 and 3 with only row
+// co = 0 of the A operand non-zero (lanes 0 .. 15 then hold the outputs of
+// their group's 16 points); with part, the block's FP64 partials of <z, r>
+// in part[blockIdx] and of <z, rp> in part[gridDim + blockIdx].
+__global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint2 *__restrict__ a3,
                                                   const float *__restrict__ W4,
                                                   const float *__restrict__ r,
                                                   const float *__restrict__ F0,
@@ -469,32 +491,47 @@ __global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint4 *__res
                                                   double *__restrict__ part,
                                                   const CgState *__restrict__ st) {
     if (st && (st->done || st->bad)) return;
+    __shared__ __attribute__((aligned(16))) short sx[k3Halo * kStride];
     __shared__ float sw[16 * k3T];
+    const Tile3 T = tile3(g, blockIdx.x);
     for (int k = threadIdx.x; k < 16 * k3T; k += blockDim.x) sw[k] = W4[k];
+    for (int k = threadIdx.x; k < k3Halo * 4; k += blockDim.x) {
+        const int h = k >> 2, q = k & 3;
+        const int x = T.x0 + h % k3HX, y = T.y0 + (h / k3HX) % k3HY, z = T.z0 + h / (k3HX * k3HY);
+        uint2 v = make_uint2(0u, 0u);
+        if (in_grid3(x, y, z, g.nx, g.ny, g.nz))
+            v = a3[4 * (x + (long long)g.nx * (y + (long long)g.ny * z)) + q];
+        *(uint2 *)(sx + h * kStride + 4 * q) = v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 15, kq = (lane >> 4) * 4;
     __syncthreads();
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    bf16x4 wb[k3T];  // A: row co = n, ci = kq + c; only row 0 is W4
+#pragma unroll
+    for (int t = 0; t < k3T; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) wb[t][c] = n == 0 ? bfbits(sw[(kq + c) * k3T + t]) : (short)0;
     double zr = 0.0, zrp = 0.0;
-    if (i < g.N) {
-        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny),
-                  z = (int)(i / ((long long)g.nx * g.ny));
-        float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int p = (wave * 4 + j) * 16 + n;
+        const short *base = sx + halo_idx(p, 13) * kStride + kq;  // tap 13: the point itself
+        f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
         for (int t = 0; t < k3T; ++t) {
             const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-            if (!in_grid3(x + dx, y + dy, z + dz, g.nx, g.ny, g.nz)) continue;
-            const long long q = i + dx + (long long)g.nx * (dy + (long long)g.ny * dz);
-            const uint4 lo = a3[2 * q], hi = a3[2 * q + 1];
-            const uint32_t wds[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-#pragma unroll
-            for (int ci = 0; ci < 16; ++ci) {
-                const uint32_t bits = (wds[ci >> 1] >> (16 * (ci & 1))) << 16;
-                acc += sw[ci * k3T + t] * __uint_as_float(bits);
-            }
+            const bf16x4 b = *(const bf16x4 *)(base + (dz * (k3HX * k3HY) + dy * k3HX + dx) * kStride);
+            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wb[t], b, d, 0, 0, 0);
         }
+        const int x = T.x0 + 1 + p % k3X, y = T.y0 + 1 + (p / k3X) % k3Y,
+                  z = T.z0 + 1 + p / (k3X * k3Y);
+        if (kq != 0 || !in_grid3(x, y, z, g.nx, g.ny, g.nz)) continue;
+        const long long i = x + (long long)g.nx * (y + (long long)g.ny * z);
         const float ri = r[i];
-        const float zi = F0[i] * ri + acc;
+        const float zi = F0[i] * ri + d[0];
         zout[i] = zi;
-        zr = (double)zi * (double)ri;
-        if (rp) zrp = (double)zi * (double)rp[i];
+        zr += (double)zi * (double)ri;
+        if (rp) zrp += (double)zi * (double)rp[i];
     }
     if (part) {
         block_partial_sum(zr, part);
@@ -530,6 +567,10 @@ int net_pack_mfma(const adlbr_net *net, hipStream_t s) {
     return ADLBR_OK;
 }
 
+long long net3d_tiles(const GridInfo &g) {
+    return (long long)((g.nx + k3X - 1) / k3X) * ((g.ny + k3Y - 1) / k3Y) * ((g.nz + k3Z - 1) / k3Z);
+}
+
 // Packed 3D operands sit after the expanded 3D weights (T = 27).
 constexpr size_t kPackOffset3 = 2 * 16 * 17 * 27;
 
@@ -551,15 +592,13 @@ int net_apply_mfma3d(const adlbr_net *net, const adlbr_operator *op, const float
     const bf16x4 *pk = (const bf16x4 *)(net->layers + kPackOffset3);
     // activations as BF16 [N][16] in the two halves of the FP32 scratch
     uint4 *A = (uint4 *)net->scratch, *B = (uint4 *)(net->scratch + 8 * N);
-    const unsigned nb = (unsigned)((N + 255) / 256);
-    const unsigned nt = (unsigned)(((g.nx + k3X - 1) / k3X) * (long long)((g.ny + k3Y - 1) / k3Y) *
-                                   ((g.nz + k3Z - 1) / k3Z));
-    hipLaunchKernelGGL(k_net3d_l1, dim3(nb), dim3(256), 0, s, g, r, L, net->gates8, A, st);
+    const unsigned nt = (unsigned)net3d_tiles(g);
+    hipLaunchKernelGGL(k_net3d_l1, dim3(nt), dim3(256), 0, s, g, r, L, net->gates8, A, st);
     hipLaunchKernelGGL(k_net3d_mfma, dim3(nt), dim3(256), 0, s, g, (const uint2 *)A, pk,
                        net->gates8, 16, (uint2 *)B, st);
     hipLaunchKernelGGL(k_net3d_mfma, dim3(nt), dim3(256), 0, s, g, (const uint2 *)B, pk + k3T * 64,
                        net->gates8, 0, (uint2 *)A, st);
-    hipLaunchKernelGGL(k_net3d_l4, dim3(nb), dim3(256), 0, s, g, (const uint4 *)A, L + l4, r,
+    hipLaunchKernelGGL(k_net3d_l4, dim3(nt), dim3(256), 0, s, g, (const uint2 *)A, L + l4, r,
                        net->features, z, rp, part, st);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;

@@ -222,22 +222,32 @@ template <typename TA, typename TB> __global__ void k_convert(long long N, const
     if (i < N) b[i] = (TB)a[i];
 }
 
-// Most dot partials the fused inference kernel leaves (its persistent grid
-// has at most 3 blocks per CU on 256 CUs).
+// Most dot partials the inference leaves: the 2D fused kernel's persistent
+// grid has at most 3 blocks per CU on 256 CUs; the 3D path leaves one per
+// 8 x 8 x 4 tile.
 constexpr size_t kDotParts = 768;
+
+size_t dot_parts(const GridInfo &g) {
+    const size_t nb = (size_t)((g.N + kBS - 1) / kBS);
+    size_t m = std::max(nb, kDotParts);
+    if (g.dim == 3)
+        m = std::max(m, (size_t)((g.nx + 7) / 8) * ((g.ny + 7) / 8) * ((g.nz + 3) / 4));
+    return m;
+}
 
 struct SolveLayout {
     size_t st, hist, part, x64, vec[6], total;
 };
 
-SolveLayout solve_layout(long long N, size_t esz, int max_hist) {
+SolveLayout solve_layout(const GridInfo &g, size_t esz, int max_hist) {
     SolveLayout L;
     size_t o = 0;
+    const long long N = g.N;
     const size_t nb = (size_t)((N + kBS - 1) / kBS);
     L.st = o;   o += align_up(sizeof(SolveState));
     L.hist = o; o += align_up(8 * (size_t)max_hist);
-    // two regions of dot partials (up to max(nb, kDotParts) each), then |r|^2
-    L.part = o; o += align_up(8 * (2 * std::max(nb, kDotParts) + nb) + 64);
+    // two regions of dot partials (up to dot_parts each), then |r|^2
+    L.part = o; o += align_up(8 * (2 * dot_parts(g) + nb) + 64);
     L.x64 = o;  o += align_up(8 * (size_t)N);
     for (int k = 0; k < 6; ++k) {
         L.vec[k] = o;
@@ -255,12 +265,12 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     const GridInfo &g = operator_grid(op);
     const long long N = g.N;
     const unsigned nb = (unsigned)((N + kBS - 1) / kBS);
-    const SolveLayout L = solve_layout(N, sizeof(T), kMaxHist);
+    const SolveLayout L = solve_layout(g, sizeof(T), kMaxHist);
     SolveState *st = (SolveState *)(ws + L.st);
     double *hist = (double *)(ws + L.hist);
     double *part = (double *)(ws + L.part);
     // partials of |r|^2 of the flexible-CG update, after the dot partials
-    double *prr = part + 2 * (long long)std::max((size_t)nb, kDotParts);
+    double *prr = part + 2 * (long long)dot_parts(g);
     T *r = (T *)(ws + L.vec[0]);
     T *r2 = (T *)(ws + L.vec[1]);
     T *z = (T *)(ws + L.vec[2]);
@@ -454,7 +464,7 @@ extern "C" int adlbr_solve_workspace(adlbr_operator *op, int method, size_t *byt
         set_error("adlbr_solve_workspace: the operator's storage must be ADLBR_F32 or ADLBR_F64");
         return ADLBR_E_UNSUPPORTED;
     }
-    *bytes = solve_layout(operator_grid(op).N, dtype_size(sto), kMaxHist).total;
+    *bytes = solve_layout(operator_grid(op), dtype_size(sto), kMaxHist).total;
     return ADLBR_OK;
 }
 
