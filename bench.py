@@ -47,10 +47,10 @@ ALGO_BYTES = {(2, 8): 16 + 3 * 8 + 4, (2, 4): 8 + 3 * 4 + 4, (2, 2): 4 + 3 * 2 +
 # x 1.0), with the SHA-256 of the kernel sources they were taken on.  A
 # change to those sources makes the figure stale: traffic is then null.
 TRAFFIC = {
-    "c2": {"sha256": "d93bf47da040fd0c587b42730d2169e4ca301cb6512553b60124c787ce0e8f9c",
-           "bytes_per_launch": 221940564},
-    "c3": {"sha256": "d93bf47da040fd0c587b42730d2169e4ca301cb6512553b60124c787ce0e8f9c",
-           "bytes_per_launch": 2459000469},
+    "c2": {"sha256": "2bd40b289b7e844bcbb7f74a13c3e5bf6f65e461a430aed9298b7f5f48062671",
+           "bytes_per_launch": 221592559},
+    "c3": {"sha256": "2bd40b289b7e844bcbb7f74a13c3e5bf6f65e461a430aed9298b7f5f48062671",
+           "bytes_per_launch": 2443947619},
 }
 TRAFFIC_SOURCES = ("paper_1301_3925_amd/csrc/operator.hip", "paper_1301_3925_amd/csrc/common.h")
 
@@ -78,14 +78,18 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2",
                     choices=["c1", "c2", "c3", "c3-precision", "c4", "c5", "c5-3d", "copy"])
-    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-steps", type=int, default=None,
+                    help="c5: training steps (default 3000 in 2D, 300 in 3D)")
     ap.add_argument("--off-policy", action="store_true",
                     help="c5: train on Jacobi-PCG residuals only (no flexible-CG residuals)")
     ap.add_argument("--refresh", type=int, default=4,
                     help="c5: how many times flexible-CG residuals join the training pool")
     ap.add_argument("--dtype", default=None, help="storage dtype for c3: f64|f32|bf16|f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.train_steps is None:
+        args.train_steps = 300 if args.workload == "c5-3d" else 3000
+    return args
 
 
 def cpu_baseline_c2(u0_np, n_full):
