@@ -40,7 +40,7 @@ struct adlbr_operator {
     uint8_t *cnt;
     int32_t *pos;
     int32_t *ent;
-    void *went;        // 3D: [entries] every incoming entry with its weight (EntW)
+    void *went;        // 3D: [entries] the weight of every incoming entry (EntRec)
     void *diag;
     double *maxdiag;
     double *dtcfl;
@@ -355,12 +355,41 @@ __device__ inline void sort_row(int32_t *e, int c) {
     }
 }
 
-// An incoming entry with its weight, as the 3D lists keep them: the apply
-// takes both with one vector load per lane.
-template <typename TS> struct alignas(sizeof(TS) > 4 ? 16 : 8) EntW {
+// The weights of the 3D incoming entries, one EntRec per entry.  FP32: the
+// entry again with its weight in one 8-byte record, so that one vector load
+// brings both; other dtypes: the weight alone, beside ent (a record would
+// need padding: 16 bytes for FP64, 8 for 16-bit weights).
+template <typename TS> struct alignas(8) EntW {
     int32_t e;
     TS w;
 };
+template <typename TS> constexpr bool kPackedEW = sizeof(TS) == 4;
+template <typename TS, bool PACKED = kPackedEW<TS>> struct EntRecT {
+    typedef TS type;
+};
+template <typename TS> struct EntRecT<TS, true> {
+    typedef EntW<TS> type;
+};
+template <typename TS> using EntRec = typename EntRecT<TS>::type;
+
+template <typename TS> __device__ __forceinline__ EntRec<TS> make_rec(int32_t e, TS w) {
+    if constexpr (kPackedEW<TS>) return EntRec<TS>{e, w};
+    else return w;
+}
+// Entry i and its weight (-1 and 0 when !ok).
+template <typename TS>
+__device__ __forceinline__ void load_rec(const EntRec<TS> *__restrict__ went,
+                                         const int32_t *__restrict__ ent, long long i, bool ok,
+                                         int32_t &v, TS &w) {
+    if constexpr (kPackedEW<TS>) {
+        const EntRec<TS> r = ok ? went[i] : EntRec<TS>{-1, TS{}};
+        v = r.e;
+        w = r.w;
+    } else {
+        v = ok ? ent[i] : -1;
+        w = ok ? went[i] : TS{};
+    }
+}
 
 // Sort row z (entries e[0..c)), store every entry again with its weight
 // (we[i], the weight in the storage dtype; not when we is null) and return
@@ -369,7 +398,7 @@ template <typename TS> struct alignas(sizeof(TS) > 4 ? 16 : 8) EntW {
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
 __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *e, int c,
                                        const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
-                                       const TS *__restrict__ w, EntW<TS> *__restrict__ we);
+                                       const TS *__restrict__ w, EntRec<TS> *__restrict__ we);
 
 // A_zz = own in-grid weights (both signs) + weights of the incoming edges.
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
@@ -399,13 +428,13 @@ __device__ inline double row_diag(const GridInfo &g, long long z, const int32_t 
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
 __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *e, int c,
                                        const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
-                                       const TS *__restrict__ w, EntW<TS> *__restrict__ we) {
+                                       const TS *__restrict__ w, EntRec<TS> *__restrict__ we) {
     const long long N = g.N;
     if (c > 16) {
         sort_row(e, c);
         if (we)
             for (int i = 0; i < c; ++i)
-                we[i] = EntW<TS>{e[i], w[widx<DIM == 2 ? 3 : 6>((e[i] >> 6) & 7, z + (e[i] >> 9), N)]};
+                we[i] = make_rec<TS>(e[i], w[widx<DIM == 2 ? 3 : 6>((e[i] >> 6) & 7, z + (e[i] >> 9), N)]);
         return row_diag<DIM, WIDE, PER, TS, TA>(g, z, e, c, sb, w);
     }
     constexpr int S = DIM == 2 ? 3 : 6;
@@ -427,7 +456,7 @@ __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *
         if (i < c) {
             e[i] = r[i];
             const TS wr = w[widx<S>((r[i] >> 6) & 7, z + (r[i] >> 9), N)];
-            if (we) we[i] = EntW<TS>{r[i], wr};
+            if (we) we[i] = make_rec<TS>(r[i], wr);
             wi[i] = Conv<TS, TA>::ld(wr);
         }
     }
@@ -490,7 +519,7 @@ __global__ __launch_bounds__(256) void k_bin_build(
     GridInfo g, const uint32_t *__restrict__ bincnt, const uint32_t *__restrict__ binoff,
     const int2 *__restrict__ binbuf, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
     const TS *__restrict__ w, int32_t *__restrict__ pos, uint8_t *__restrict__ cnt,
-    int32_t *__restrict__ ent, EntW<TS> *__restrict__ went, TD *__restrict__ diag,
+    int32_t *__restrict__ ent, EntRec<TS> *__restrict__ went, TD *__restrict__ diag,
     double *__restrict__ dpart, int32_t *status) {
     __shared__ int32_t lcnt[kBin];
     __shared__ int32_t loff[kBin];
@@ -931,7 +960,7 @@ __global__ __launch_bounds__(256) void k_rows(GridInfo g,
                                               const TS *__restrict__ w,
                                               const uint8_t *__restrict__ cnt,
                                               const int32_t *__restrict__ pos,
-                                              int32_t *__restrict__ ent, EntW<TS> *__restrict__ went,
+                                              int32_t *__restrict__ ent, EntRec<TS> *__restrict__ went,
                                               TD *__restrict__ diag, double *__restrict__ dpart) {
     constexpr int kCap = 16 * 256;
     __shared__ int32_t rows[kCap];
@@ -1189,7 +1218,7 @@ template <bool INLINE_W, typename TS, typename TA, typename TU>
 __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, long long N, TA uz,
                                             const TU *__restrict__ u, const TS *__restrict__ w,
                                             const int32_t *__restrict__ ent,
-                                            const EntW<TS> *__restrict__ went) {
+                                            const EntRec<TS> *__restrict__ went) {
     const int lane = (int)(threadIdx.x & 63u);
     const long long z0 = z & ~63ll;
     TA acc = (TA)0;
@@ -1201,9 +1230,7 @@ __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, lon
         for (int j = 0; j < kPre; ++j) {
             const unsigned e = eb + 64 * j + lane;
             if (INLINE_W) {
-                const EntW<TS> r = e < L.total ? went[L.start + e] : EntW<TS>{-1, TS{}};
-                v[j] = r.e;
-                wv[j] = r.w;
+                load_rec<TS>(went, ent, L.start + e, e < L.total, v[j], wv[j]);
             } else {
                 v[j] = e < L.total ? ent[L.start + e] : -1;
                 wv[j] = TS{};
@@ -1232,7 +1259,7 @@ __device__ __forceinline__ void apply_block(
     const GridInfo &g, long long blk, const TS *__restrict__ u, TS *__restrict__ out,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, const EntW<TS> *__restrict__ went, TA h) {
+    const int32_t *__restrict__ ent, const EntRec<TS> *__restrict__ went, TA h) {
     constexpr int P = kApplyPPT;
     const long long N = g.N;
     const int lane = (int)(threadIdx.x & 63u);
@@ -1258,9 +1285,7 @@ __device__ __forceinline__ void apply_block(
             for (int j = 0; j < kPre; ++j) {
                 const unsigned e = eb + 64 * j + lane;
                 if (kInlineW<DIM>) {
-                    const EntW<TS> r = e < L[k].total ? went[L[k].start + e] : EntW<TS>{-1, TS{}};
-                    v[k][j] = r.e;
-                    wv[k][j] = r.w;
+                    load_rec<TS>(went, ent, L[k].start + e, e < L[k].total, v[k][j], wv[k][j]);
                 } else {
                     v[k][j] = e < L[k].total ? ent[L[k].start + e] : -1;
                     wv[k][j] = TS{};
@@ -1301,7 +1326,7 @@ __global__ __launch_bounds__(kBS) void k_apply(
     GridInfo g, const TS *__restrict__ u, TS *__restrict__ out,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, const EntW<TS> *__restrict__ went, double dt,
+    const int32_t *__restrict__ ent, const EntRec<TS> *__restrict__ went, double dt,
     const double *__restrict__ dtcfl, int dt_mode) {
     const TA h = (TA)(dt_mode == ADLBR_DT_CFL ? dt * dtcfl[0] : dt);
     apply_block<DIM, WIDE, PER, STEP, TS, TA>(
@@ -1341,7 +1366,7 @@ __global__ __launch_bounds__(kBS) void k_apply_batch(const BatchProb *__restrict
     apply_block<DIM, WIDE, PER, true, TS, TA>(
         g, strip_block(b - P.first_block, g, kApplyPoints), (const TS *)P.u[parity], (TS *)P.u[parity ^ 1],
         (const typename Slots<DIM, WIDE>::store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent,
-        (const EntW<TS> *)P.went, h);
+        (const EntRec<TS> *)P.went, h);
 }
 
 // dst = src for every problem (u[1] -> u[0] after an odd number of steps).
@@ -1365,7 +1390,7 @@ __global__ __launch_bounds__(kBS) void k_cg_direction(
     GridInfo g, const T *__restrict__ zv, T *__restrict__ q, T *__restrict__ p,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const T *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, const EntW<T> *__restrict__ went, const CgState *st,
+    const int32_t *__restrict__ ent, const EntRec<T> *__restrict__ went, const CgState *st,
     double *partial, int first) {
     const long long N = g.N;
     const long long blk = xcd_block(blockIdx.x, gridDim.x);
@@ -1414,7 +1439,7 @@ __global__ __launch_bounds__(kBS) void k_residual(
     GridInfo g, const T *__restrict__ b, const double *__restrict__ x,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const T *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
-    const int32_t *__restrict__ ent, const EntW<T> *__restrict__ went, double dt, double *partial,
+    const int32_t *__restrict__ ent, const EntRec<T> *__restrict__ went, double dt, double *partial,
     T *__restrict__ rout) {
     const long long N = g.N;
     const long long z = wave_group(g, blockIdx.x, 1) + (threadIdx.x & 63);
@@ -1490,12 +1515,12 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
         if (op->storage == ADLBR_F64)
             hipLaunchKernelGGL((k_rows<DIM, WIDE, PER, TS, TA, double>), dim3(nb), dim3(256), 0, s,
                                g, (const store_t *)op->sb, (const TS *)w, (const uint8_t *)op->cnt,
-                               (const int32_t *)op->pos, op->ent, (EntW<TS> *)op->went, (double *)op->diag,
+                               (const int32_t *)op->pos, op->ent, (EntRec<TS> *)op->went, (double *)op->diag,
                                op->part);
         else
             hipLaunchKernelGGL((k_rows<DIM, WIDE, PER, TS, TA, float>), dim3(nb), dim3(256), 0, s,
                                g, (const store_t *)op->sb, (const TS *)w, (const uint8_t *)op->cnt,
-                               (const int32_t *)op->pos, op->ent, (EntW<TS> *)op->went, (float *)op->diag,
+                               (const int32_t *)op->pos, op->ent, (EntRec<TS> *)op->went, (float *)op->diag,
                                op->part);
         nparts = nb;
     } else {
@@ -1510,12 +1535,12 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
         if (op->storage == ADLBR_F64)
             hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, double>), dim3((unsigned)nbins),
                                dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w,
-                               op->pos, op->cnt, op->ent, (EntW<TS> *)op->went, (double *)op->diag, op->part,
+                               op->pos, op->cnt, op->ent, (EntRec<TS> *)op->went, (double *)op->diag, op->part,
                                status);
         else
             hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, float>), dim3((unsigned)nbins),
                                dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w,
-                               op->pos, op->cnt, op->ent, (EntW<TS> *)op->went, (float *)op->diag, op->part,
+                               op->pos, op->cnt, op->ent, (EntRec<TS> *)op->went, (float *)op->diag, op->part,
                                status);
         nparts = nbins;
     }
@@ -1534,11 +1559,11 @@ int apply_impl(const adlbr_operator *op, const void *u, void *out, bool step, do
     if (step)
         hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, true, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)u, (TS *)out, (const store_t *)op->sb, (const TS *)op->w,
-                           op->cnt, op->pos, op->ent, (const EntW<TS> *)op->went, dt, op->dtcfl, dt_mode);
+                           op->cnt, op->pos, op->ent, (const EntRec<TS> *)op->went, dt, op->dtcfl, dt_mode);
     else
         hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, false, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)u, (TS *)out, (const store_t *)op->sb, (const TS *)op->w,
-                           op->cnt, op->pos, op->ent, (const EntW<TS> *)op->went, dt, op->dtcfl, dt_mode);
+                           op->cnt, op->pos, op->ent, (const EntRec<TS> *)op->went, dt, op->dtcfl, dt_mode);
     return ADLBR_OK;
 }
 
@@ -1596,7 +1621,7 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct BatchF 
                 const unsigned nb = (unsigned)((P.g.N + kApplyPoints - 1) / kApplyPoints);
                 hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, true, TS, TA>), dim3(nb), dim3(kBS), 0, s,
                                    P.g, (const TS *)P.u[parity], (TS *)P.u[parity ^ 1],
-                                   (const store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent, (const EntW<TS> *)P.went, P.dt,
+                                   (const store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent, (const EntRec<TS> *)P.went, P.dt,
                                    P.dtcfl, P.dt_mode);
             }
             return ADLBR_OK;
@@ -1624,7 +1649,7 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct CgDirF 
         if (op->storage != ADLBR_F32 && op->storage != ADLBR_F64) return ADLBR_E_UNSUPPORTED;
         hipLaunchKernelGGL((k_cg_direction<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)z, (TS *)q, (TS *)p, (const store_t *)op->sb,
-                           (const TS *)op->w, op->cnt, op->pos, op->ent, (const EntW<TS> *)op->went,
+                           (const TS *)op->w, op->cnt, op->pos, op->ent, (const EntRec<TS> *)op->went,
                            (const CgState *)st,
                            partial, first);
         hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kBS), 0, s, st, (const double *)partial,
@@ -1653,7 +1678,7 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct Residua
         const unsigned nb = (unsigned)((g.N + kBS - 1) / kBS);
         hipLaunchKernelGGL((k_residual<DIM, WIDE, PER, TS>), dim3(nb), dim3(kBS), 0, s, g,
                            (const TS *)b, x, (const store_t *)op->sb, (const TS *)op->w, op->cnt,
-                           op->pos, op->ent, (const EntW<TS> *)op->went, dt, partial, (TS *)rout);
+                           op->pos, op->ent, (const EntRec<TS> *)op->went, dt, partial, (TS *)rout);
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBS), 0, s, (const double *)partial,
                            (long long)nb, out);
         return ADLBR_OK;
@@ -1688,7 +1713,7 @@ Layout layout(const GridInfo &g, int storage, int wide) {
     L.cnt = o;  o += align_up((size_t)N + 64);
     L.pos = o;  o += align_up(4 * (size_t)N + 256);
     L.ent = o;  o += align_up(4 * (size_t)(2 * S) * N);
-    L.went = o; o += g.dim == 3 ? align_up((dtype_size(storage) > 4 ? 16 : 8) * (size_t)(2 * S) * N) : 0;
+    L.went = o; o += g.dim == 3 ? align_up((dtype_size(storage) == 4 ? 8 : dtype_size(storage)) * (size_t)(2 * S) * N) : 0;
     L.diag = o; o += align_up((storage == ADLBR_F64 ? 8 : 4) * (size_t)N);
     L.scal = o; o += 256;
     L.mask = o; o += align_up((size_t)N + 64);
