@@ -483,7 +483,7 @@ __global__ __launch_bounds__(256) void k_net3d_mfma(GridInfo g, const uint2 *__r
 // their group's 16 points); with part, the block's FP64 partials of <z, r>
 // in part[blockIdx] and of <z, rp> in part[gridDim + blockIdx].
 __global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint2 *__restrict__ a3,
-                                                  const float *__restrict__ W4,
+                                                  const bf16x4 *__restrict__ w4pack,
                                                   const float *__restrict__ r,
                                                   const float *__restrict__ F0,
                                                   float *__restrict__ zout,
@@ -492,9 +492,7 @@ __global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint2 *__res
                                                   const CgState *__restrict__ st) {
     if (st && (st->done || st->bad)) return;
     __shared__ __attribute__((aligned(16))) short sx[k3Halo * kStride];
-    __shared__ float sw[16 * k3T];
     const Tile3 T = tile3(g, blockIdx.x);
-    for (int k = threadIdx.x; k < 16 * k3T; k += blockDim.x) sw[k] = W4[k];
     for (int k = threadIdx.x; k < k3Halo * 4; k += blockDim.x) {
         const int h = k >> 2, q = k & 3;
         const int x = T.x0 + h % k3HX, y = T.y0 + (h / k3HX) % k3HY, z = T.z0 + h / (k3HX * k3HY);
@@ -505,12 +503,25 @@ __global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint2 *__res
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, kq = (lane >> 4) * 4;
+    // the output's inputs for this lane's four points (lanes 0 .. 15 write
+    // them), requested before the matrix work
+    float rv[4], fv[4], pv[4];
+    int iv[4];  // N < 2^28
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int p = (wave * 4 + j) * 16 + n;
+        const int x = T.x0 + 1 + p % k3X, y = T.y0 + 1 + (p / k3X) % k3Y,
+                  z = T.z0 + 1 + p / (k3X * k3Y);
+        const bool live = kq == 0 && in_grid3(x, y, z, g.nx, g.ny, g.nz);
+        iv[j] = live ? (int)(x + (long long)g.nx * (y + (long long)g.ny * z)) : -1;
+        rv[j] = live ? r[iv[j]] : 0.f;
+        fv[j] = live ? F0[iv[j]] : 0.f;
+        pv[j] = live && rp ? rp[iv[j]] : 0.f;
+    }
+    bf16x4 wb[k3T];  // A: row co = n, ci = kq + c; only row 0 is W4 (packed [t][kq / 4])
+#pragma unroll
+    for (int t = 0; t < k3T; ++t) wb[t] = n == 0 ? w4pack[t * 4 + (kq >> 2)] : bf16x4{0, 0, 0, 0};
     __syncthreads();
-    bf16x4 wb[k3T];  // A: row co = n, ci = kq + c; only row 0 is W4
-#pragma unroll
-    for (int t = 0; t < k3T; ++t)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) wb[t][c] = n == 0 ? bfbits(sw[(kq + c) * k3T + t]) : (short)0;
     double zr = 0.0, zrp = 0.0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -523,27 +534,30 @@ __global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint2 *__res
             const bf16x4 b = *(const bf16x4 *)(base + (dz * (k3HX * k3HY) + dy * k3HX + dx) * kStride);
             d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wb[t], b, d, 0, 0, 0);
         }
-        const int x = T.x0 + 1 + p % k3X, y = T.y0 + 1 + (p / k3X) % k3Y,
-                  z = T.z0 + 1 + p / (k3X * k3Y);
-        if (kq != 0 || !in_grid3(x, y, z, g.nx, g.ny, g.nz)) continue;
-        const long long i = x + (long long)g.nx * (y + (long long)g.ny * z);
-        const float ri = r[i];
-        const float zi = F0[i] * ri + d[0];
-        zout[i] = zi;
-        zr += (double)zi * (double)ri;
-        if (rp) zrp += (double)zi * (double)rp[i];
+        if (iv[j] < 0) continue;
+        const float zi = fv[j] * rv[j] + d[0];
+        zout[iv[j]] = zi;
+        zr += (double)zi * (double)rv[j];
+        zrp += (double)zi * (double)pv[j];
     }
-    if (part) {
-        block_partial_sum(zr, part);
-        block_partial_sum(zrp, part + gridDim.x);
-    }
+    if (part) block_partial_sum2(zr, zrp, part, part + gridDim.x);
 }
 
-// The A operands of layers 2 and 3 (3D), per lane: [layer][tap][lane].
+// The A operands of layers 2 and 3 (3D), per lane: [layer][tap][lane];
+// then row 0 of layer 4's, [tap][ci / 4] (the only non-zero row).
+constexpr int k3Pack4 = 2 * k3T * 64, k3PackEntries = k3Pack4 + k3T * 4;
 __global__ void k_pack_mfma3d(const float *__restrict__ L2, const float *__restrict__ L3,
-                              bf16x4 *__restrict__ out) {
+                              const float *__restrict__ L4, bf16x4 *__restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 2 * k3T * 64) return;
+    if (e >= k3PackEntries) return;
+    if (e >= k3Pack4) {
+        const int t = (e - k3Pack4) / 4, q = (e - k3Pack4) % 4;
+        bf16x4 v;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = bfbits(L4[(4 * q + c) * k3T + t]);
+        out[e] = v;
+        return;
+    }
     const int lane = e % 64, t = (e / 64) % k3T;
     const float *W = e >= k3T * 64 ? L3 : L2;
     const int co = lane & 15, k0 = (lane >> 4) * 4;
@@ -576,9 +590,10 @@ constexpr size_t kPackOffset3 = 2 * 16 * 17 * 27;
 
 int net_pack_mfma3d(const adlbr_net *net, hipStream_t s) {
     const float *L = net->layers;
-    const size_t l2 = 16 * 27, l3 = l2 + 16 * 16 * 27;
-    hipLaunchKernelGGL(k_pack_mfma3d, dim3((2 * k3T * 64 + 255) / 256), dim3(256), 0, s, L + l2,
-                       L + l3, (bf16x4 *)(net->layers + kPackOffset3));
+    const size_t l2 = 16 * 27, l3 = l2 + 16 * 16 * 27, l4 = l3 + 16 * 16 * 27;
+    static_assert(k3PackEntries * 2 <= 7168, "the packed operands fit the layers' reserve");
+    hipLaunchKernelGGL(k_pack_mfma3d, dim3((k3PackEntries + 255) / 256), dim3(256), 0, s, L + l2,
+                       L + l3, L + l4, (bf16x4 *)(net->layers + kPackOffset3));
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }
@@ -598,7 +613,7 @@ int net_apply_mfma3d(const adlbr_net *net, const adlbr_operator *op, const float
                        net->gates8, 16, (uint2 *)B, st);
     hipLaunchKernelGGL(k_net3d_mfma, dim3(nt), dim3(256), 0, s, g, (const uint2 *)B, pk + k3T * 64,
                        net->gates8, 0, (uint2 *)A, st);
-    hipLaunchKernelGGL(k_net3d_l4, dim3(nt), dim3(256), 0, s, g, (const uint2 *)A, L + l4, r,
+    hipLaunchKernelGGL(k_net3d_l4, dim3(nt), dim3(256), 0, s, g, (const uint2 *)A, pk + k3Pack4, r,
                        net->features, z, rp, part, st);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;

@@ -280,6 +280,27 @@ __device__ inline void block_partial_sum(double v, double *partial) {
     __syncthreads();  // red[] may be reused by a second call
 }
 
+// Block sums of a and b into pa[blockIdx.x] and pb[blockIdx.x] in one pass
+// (blockDim.x == 256): butterfly sums within each wave, then the four wave
+// sums in wave order; fixed order, so deterministic.
+__device__ inline void block_partial_sum2(double a, double b, double *pa, double *pb) {
+    __shared__ double red2[2][4];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        a += __shfl_xor(a, d, 64);
+        b += __shfl_xor(b, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red2[0][threadIdx.x >> 6] = a;
+        red2[1][threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pa[blockIdx.x] = ((red2[0][0] + red2[0][1]) + red2[0][2]) + red2[0][3];
+        pb[blockIdx.x] = ((red2[1][0] + red2[1][1]) + red2[1][2]) + red2[1][3];
+    }
+}
+
 // Block maximum of v into partial[blockIdx.x] (blockDim.x == 256).
 __device__ inline void block_partial_max(double v, double *partial) {
     __shared__ double red[256];
