@@ -502,7 +502,9 @@ def run_c5(args, dev, stream):
     t0 = time.perf_counter()
     net, hist = adlbr.train_net(op, dt, rhs_seeds=range(2001, 2017), steps=args.train_steps,
                                 batch=4, lr=3e-3, seed=0, log_every=100,
-                                on_policy=not args.off_policy, refresh=args.refresh)
+                                on_policy=not args.off_policy, refresh=args.refresh,
+                                log=lambda it, l: print(f"training step {it}: loss {l:.4f}",
+                                                        file=sys.stderr, flush=True))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     _, rt, tt = timed("fcg", net)

@@ -428,7 +428,7 @@ def adam(params, grads, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=
 
 def train_net(op: "Operator", dt: float, rhs_seeds, steps: int = 400, batch: int = 4,
               lr: float = 2e-3, seed: int = 0, snapshot_iters=(1, 2, 4, 8, 16, 32),
-              log_every: int = 0, on_policy: bool = False, refresh: int = 1):
+              log_every: int = 0, on_policy: bool = False, refresh: int = 1, log=None):
     """Train the preconditioner on residuals the solver itself generates:
     for each right-hand side, Jacobi-PCG stopped after k iterations leaves a
     residual r_k = b - K x_k (adlbr_residual); each Adam step takes `batch`
@@ -436,7 +436,8 @@ def train_net(op: "Operator", dt: float, rhs_seeds, steps: int = 400, batch: int
     network's own backward kernels and updates with adlbr_net_adam.  With
     on_policy, the residuals of flexible CG with the network as it stands
     (stopped after the same k) join the pool `refresh` times, evenly spaced
-    after the first half of the steps.
+    after the first half of the steps.  log(step, loss), if given, is called
+    with every logged loss (every log_every steps).
     Returns (net, history of losses)."""
     import numpy as np
     from . import synth
@@ -486,4 +487,6 @@ def train_net(op: "Operator", dt: float, rhs_seeds, steps: int = 400, batch: int
         net.refresh_gates()
         if log_every and (it % log_every == 0 or it == 1):
             hist.append((it, float(loss.item()) / batch))
+            if log is not None:
+                log(it, hist[-1][1])
     return net, hist
