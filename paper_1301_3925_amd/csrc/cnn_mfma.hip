@@ -378,6 +378,30 @@ __device__ __forceinline__ int halo_idx(int p, int t) {
     return (pz + 1 + dz) * (k3HX * k3HY) + (py + 1 + dy) * k3HX + (px + 1 + dx);
 }
 
+// Stage a BF16 [N][16] field over the tile's halo into LDS (kStride shorts
+// per point, 0 outside the grid), 8 bytes per item: every load of a thread is
+// issued before its first LDS store, so the block waits for one round trip to
+// memory instead of one per item.  Needs blockDim.x == 256.
+constexpr int k3StageItems = k3Halo * 4, k3StageIters = (k3StageItems + 255) / 256;
+__device__ __forceinline__ void stage3d(const GridInfo &g, const Tile3 &T, const uint2 *__restrict__ in,
+                                        short *sx) {
+    uint2 v[k3StageIters];
+#pragma unroll
+    for (int it = 0; it < k3StageIters; ++it) {
+        const int k = (int)threadIdx.x + 256 * it;
+        const int h = k >> 2, q = k & 3;
+        const int x = T.x0 + h % k3HX, y = T.y0 + (h / k3HX) % k3HY, z = T.z0 + h / (k3HX * k3HY);
+        v[it] = make_uint2(0u, 0u);
+        if (k < k3StageItems && in_grid3(x, y, z, g.nx, g.ny, g.nz))
+            v[it] = in[4 * (x + (long long)g.nx * (y + (long long)g.ny * z)) + q];
+    }
+#pragma unroll
+    for (int it = 0; it < k3StageIters; ++it) {
+        const int k = (int)threadIdx.x + 256 * it;
+        if (k < k3StageItems) *(uint2 *)(sx + (k >> 2) * kStride + 4 * (k & 3)) = v[it];
+    }
+}
+
 // Layer 1: a1[p][co] = g1[p][co] sum_t W1[co][t] r(p + off_t), r = 0 outside
 // the grid (tap t = (dz + 1) 9 + (dy + 1) 3 + (dx + 1)); one thread per
 // point of an 8 x 8 x 4 tile, r of the tile and its halo staged in LDS.
@@ -389,11 +413,20 @@ __global__ __launch_bounds__(256) void k_net3d_l1(GridInfo g, const float *__res
     if (st && (st->done || st->bad)) return;
     __shared__ float sr[k3Halo];
     const Tile3 T = tile3(g, blockIdx.x);
-    for (int h = threadIdx.x; h < k3Halo; h += blockDim.x) {
-        const int x = T.x0 + h % k3HX, y = T.y0 + (h / k3HX) % k3HY, z = T.z0 + h / (k3HX * k3HY);
-        sr[h] = in_grid3(x, y, z, g.nx, g.ny, g.nz)
-                    ? r[x + (long long)g.nx * (y + (long long)g.ny * z)]
-                    : 0.f;
+    {
+        constexpr int kIters = (k3Halo + 255) / 256;
+        float v[kIters];  // all loads first, then the LDS stores
+#pragma unroll
+        for (int it = 0; it < kIters; ++it) {
+            const int h = (int)threadIdx.x + 256 * it;
+            const int x = T.x0 + h % k3HX, y = T.y0 + (h / k3HX) % k3HY, z = T.z0 + h / (k3HX * k3HY);
+            const bool ok = h < k3Halo && in_grid3(x, y, z, g.nx, g.ny, g.nz);
+            const float rv = r[ok ? x + (long long)g.nx * (y + (long long)g.ny * z) : 0];
+            v[it] = ok ? rv : 0.f;  // a load from point 0 and a select: no branch per item
+        }
+#pragma unroll
+        for (int it = 0; it < kIters; ++it)
+            if ((int)threadIdx.x + 256 * it < k3Halo) sr[threadIdx.x + 256 * it] = v[it];
     }
     __syncthreads();
     const int p = threadIdx.x;
@@ -436,22 +469,21 @@ __global__ __launch_bounds__(256) void k_net3d_mfma(GridInfo g, const uint2 *__r
     __shared__ __attribute__((aligned(16))) short sx[k3Halo * kStride];
     const Tile3 T = tile3(g, blockIdx.x);
     const int x0 = T.x0, y0 = T.y0, z0 = T.z0;
-    // stage the tile and its halo: 4 channels (8 bytes) per item, 0 outside
-    for (int k = threadIdx.x; k < k3Halo * 4; k += blockDim.x) {
-        const int h = k >> 2, q = k & 3;
-        const int hx = h % k3HX, hy = (h / k3HX) % k3HY, hz = h / (k3HX * k3HY);
-        const int x = x0 + hx, y = y0 + hy, z = z0 + hz;
-        uint2 v = make_uint2(0u, 0u);
-        if (in_grid3(x, y, z, g.nx, g.ny, g.nz))
-            v = in[4 * (x + (long long)g.nx * (y + (long long)g.ny * z)) + q];
-        *(uint2 *)(sx + h * kStride + 4 * q) = v;
-    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     bf16x4 wb[k3T];
 #pragma unroll
     for (int t = 0; t < k3T; ++t) wb[t] = wpack[t * 64 + lane];
-    __syncthreads();
     const int n = lane & 15, kq = (lane >> 4) * 4;
+    uint32_t gv[4];  // the gates of this lane's four output points, requested before the matrix work
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int p = (wave * 4 + j) * 16 + n;
+        const int x = x0 + 1 + p % k3X, y = y0 + 1 + (p / k3X) % k3Y, z = z0 + 1 + p / (k3X * k3Y);
+        const long long i = in_grid3(x, y, z, g.nx, g.ny, g.nz) ? x + (long long)g.nx * (y + (long long)g.ny * z) : 0;
+        gv[j] = *(const uint32_t *)(G8 + 32 * i + goff + kq);
+    }
+    stage3d(g, T, in, sx);
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int p = (wave * 4 + j) * 16 + n;  // this lane's output point in the tile
@@ -467,7 +499,7 @@ __global__ __launch_bounds__(256) void k_net3d_mfma(GridInfo g, const uint2 *__r
         const int x = x0 + 1 + px, y = y0 + 1 + py, z = z0 + 1 + pz;
         if (!in_grid3(x, y, z, g.nx, g.ny, g.nz)) continue;
         const long long i = x + (long long)g.nx * (y + (long long)g.ny * z);
-        const uint32_t g4 = *(const uint32_t *)(G8 + 32 * i + goff + kq);
+        const uint32_t g4 = gv[j];
         float v[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[c] = d[c] * q8((g4 >> (8 * c)) & 0xffu);
@@ -493,14 +525,6 @@ __global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint2 *__res
     if (st && (st->done || st->bad)) return;
     __shared__ __attribute__((aligned(16))) short sx[k3Halo * kStride];
     const Tile3 T = tile3(g, blockIdx.x);
-    for (int k = threadIdx.x; k < k3Halo * 4; k += blockDim.x) {
-        const int h = k >> 2, q = k & 3;
-        const int x = T.x0 + h % k3HX, y = T.y0 + (h / k3HX) % k3HY, z = T.z0 + h / (k3HX * k3HY);
-        uint2 v = make_uint2(0u, 0u);
-        if (in_grid3(x, y, z, g.nx, g.ny, g.nz))
-            v = a3[4 * (x + (long long)g.nx * (y + (long long)g.ny * z)) + q];
-        *(uint2 *)(sx + h * kStride + 4 * q) = v;
-    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, kq = (lane >> 4) * 4;
     // the output's inputs for this lane's four points (lanes 0 .. 15 write
@@ -514,13 +538,16 @@ __global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint2 *__res
                   z = T.z0 + 1 + p / (k3X * k3Y);
         const bool live = kq == 0 && in_grid3(x, y, z, g.nx, g.ny, g.nz);
         iv[j] = live ? (int)(x + (long long)g.nx * (y + (long long)g.ny * z)) : -1;
-        rv[j] = live ? r[iv[j]] : 0.f;
-        fv[j] = live ? F0[iv[j]] : 0.f;
-        pv[j] = live && rp ? rp[iv[j]] : 0.f;
+        const int ii = live ? iv[j] : 0;  // loads from point 0 and selects: no branches
+        const float r0 = r[ii], f0 = F0[ii], p0 = (rp ? rp : r)[ii];
+        rv[j] = live ? r0 : 0.f;
+        fv[j] = live ? f0 : 0.f;
+        pv[j] = live && rp ? p0 : 0.f;
     }
     bf16x4 wb[k3T];  // A: row co = n, ci = kq + c; only row 0 is W4 (packed [t][kq / 4])
 #pragma unroll
     for (int t = 0; t < k3T; ++t) wb[t] = n == 0 ? w4pack[t * 4 + (kq >> 2)] : bf16x4{0, 0, 0, 0};
+    stage3d(g, T, a3, sx);
     __syncthreads();
     double zr = 0.0, zrp = 0.0;
 #pragma unroll
