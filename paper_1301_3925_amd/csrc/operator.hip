@@ -1105,22 +1105,35 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TU> s
                                           const TU *__restrict__ u,
                                           const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
                                           const TS *__restrict__ w) {
+        // Every load reads an address in the grid (point 0 for a dead lane,
+        // the point itself for a missing edge) and the values that do not
+        // count are dropped afterwards, so there is no per-lane branch around
+        // a load and the wave issues them all before it waits.
         const int N = (int)g.N, zi = live ? (int)z : 0;  // N < 2^28, S N < 2^31
         Slots<DIM, WIDE> sl;
-        if (live) sl.load(sb, zi);
+        sl.load(sb, zi);
         const Coord p = coords(zi, g);
         W3<TS> w3{};  // 2D: the three point-major weights in one load
-        if (S == 3 && live) w3 = ((const W3<TS> *)w)[zi];
+        TS wr[S];
+        if (S == 3) w3 = ((const W3<TS> *)w)[zi];
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
-            wq[q] = !live ? (TA)0
-                          : Conv<TS, TA>::ld(S == 3 ? w3.v[q < 3 ? q : 0] : w[widx32<S>(q, zi, N)]);
+        for (int q = 0; q < S; ++q) wr[q] = S == 3 ? w3.v[q < 3 ? q : 0] : w[widx32<S>(q, zi, N)];
+        bool okq[2 * S];
+        TU ur[2 * S];
+#pragma unroll
+        for (int q = 0; q < S; ++q)
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 int t = 0;
-                const bool ok = live && edge_target32<DIM, PER>(p, zi, sl.o[q], k ? 1 : -1, g, t);
-                un[2 * q + k] = ok ? Conv<TU, TA>::ld(u[(unsigned)t]) : uz;
+                okq[2 * q + k] = live && edge_target32<DIM, PER>(p, zi, sl.o[q], k ? 1 : -1, g, t);
+                ur[2 * q + k] = u[(unsigned)(okq[2 * q + k] ? t : zi)];
             }
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            wq[q] = live ? Conv<TS, TA>::ld(wr[q]) : (TA)0;
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                un[2 * q + k] = okq[2 * q + k] ? Conv<TU, TA>::ld(ur[2 * q + k]) : uz;
         }
     }
     __device__ __forceinline__ TA sum(TA uz) const {
@@ -1143,23 +1156,35 @@ constexpr int kPre = ADLBR_KPRE;
 
 // Chunk [e0, e0 + 64) of a wave's entries: this lane's edge value
 // w_slot(y) (u(row) - u(y)), 0 past the end; the weight is wv (INLINE_W,
-// loaded from the entry weights with the entry) or gathered from w.  All 64
-// lanes must call it.
-template <bool INLINE_W, typename TS, typename TA, typename TU>
-__device__ __forceinline__ TA incoming_edge(const WaveLists &L, long long z0, long long N, TA uz,
-                                            int32_t v, TS wv, unsigned e0, const TU *__restrict__ u,
-                                            const TS *__restrict__ w) {
-    const int lane = (int)(threadIdx.x & 63u);
-    const bool ok = e0 + lane < L.total;
-    const TA ur = __shfl(uz, ok ? (v & 63) : 0, 64);  // all lanes take part
-    TA wy = (TA)0, uy = (TA)0;
-    if (ok) {  // N < 2^28 points, S N < 2^31: 32-bit indices
-        const int y = (int)z0 + (v & 63) + (v >> 9);
-        wy = Conv<TS, TA>::ld(INLINE_W ? wv : w[widx32<INLINE_W ? 6 : 3>((v >> 6) & 7, y, (int)N)]);
-        uy = Conv<TU, TA>::ld(u[(unsigned)y]);
+// loaded from the entry weights with the entry) or gathered from w.  Split in
+// two so that a wave can issue the gathers of several chunks before it waits
+// for any: issue() loads from addresses that are always in the grid (point
+// z0 for lanes past the end, whose values are then dropped), with no per-lane
+// branch around the loads; value() forms the product.  All 64 lanes must call
+// issue().
+template <bool INLINE_W, typename TS, typename TA, typename TU> struct InEdge {
+    TA ur;
+    TS wy;
+    TU uy;
+    bool ok;
+    __device__ __forceinline__ void issue(const WaveLists &L, long long z0, long long N, TA uz,
+                                          int32_t v, TS wv, unsigned e0, const TU *__restrict__ u,
+                                          const TS *__restrict__ w) {
+        const int lane = (int)(threadIdx.x & 63u);
+        ok = e0 + lane < L.total;
+        ur = __shfl(uz, ok ? (v & 63) : 0, 64);  // all lanes take part
+        wy = INLINE_W ? wv : TS{};
+        uy = TU{};
+        if (e0 < L.total) {  // wave-uniform; then z0 < N.  N < 2^28 points, S N < 2^31
+            const int y = ok ? (int)z0 + (v & 63) + (v >> 9) : (int)z0;
+            if (!INLINE_W) wy = w[widx32<INLINE_W ? 6 : 3>(ok ? (v >> 6) & 7 : 0, y, (int)N)];
+            uy = u[(unsigned)y];
+        }
     }
-    return ok ? wy * (ur - uy) : (TA)0;
-}
+    __device__ __forceinline__ TA value() const {
+        return ok ? Conv<TS, TA>::ld(wy) * (ur - Conv<TU, TA>::ld(uy)) : (TA)0;
+    }
+};
 
 // Cross-lane moves within a wavefront by DPP (no LDS traffic): CTRL is a
 // row_shr:n (0x110 + n) or row_bcast:15 / row_bcast:31 (0x142 / 0x143)
@@ -1236,10 +1261,11 @@ __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, lon
                 wv[j] = TS{};
             }
         }
+        InEdge<INLINE_W, TS, TA, TU> ie[kPre];
 #pragma unroll
-        for (int j = 0; j < kPre; ++j)
-            val[j] = incoming_edge<INLINE_W, TS, TA, TU>(L, z0, N, uz, v[j], wv[j], eb + 64 * j, u,
-                                                         w);
+        for (int j = 0; j < kPre; ++j) ie[j].issue(L, z0, N, uz, v[j], wv[j], eb + 64 * j, u, w);
+#pragma unroll
+        for (int j = 0; j < kPre; ++j) val[j] = ie[j].value();
 #pragma unroll
         for (int j = 0; j < kPre; ++j) acc += incoming_reduce<TA>(L, v[j], val[j], eb + 64 * j);
     }
@@ -1300,12 +1326,16 @@ __device__ __forceinline__ void apply_block(
     for (unsigned eb = 0; eb < tmax; eb += 64 * kPre) {
         load_chunks(eb);
         TA val[P][kPre];
+        InEdge<kInlineW<DIM>, TS, TA, TS> ie[P][kPre];
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
             for (int j = 0; j < kPre; ++j)
-                val[k][j] = incoming_edge<kInlineW<DIM>, TS, TA, TS>(
-                    L[k], zw + 64 * k, N, uz[k], v[k][j], wv[k][j], eb + 64 * j, u, w);
+                ie[k][j].issue(L[k], zw + 64 * k, N, uz[k], v[k][j], wv[k][j], eb + 64 * j, u, w);
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int j = 0; j < kPre; ++j) val[k][j] = ie[k][j].value();
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
