@@ -1149,10 +1149,10 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TU> s
     }
 };
 
-#ifndef ADLBR_KPRE
-#define ADLBR_KPRE 4
-#endif
-constexpr int kPre = ADLBR_KPRE;
+// Chunks of 64 entries whose loads a wave has in flight at once: 8 with
+// 32-bit arithmetic; 4 with FP64, whose wider values would otherwise cost
+// occupancy (109 instead of 81 registers in the 3D step).
+template <typename TA> constexpr int kPreOf = sizeof(TA) == 8 ? 4 : 8;
 
 // Chunk [e0, e0 + 64) of a wave's entries: this lane's edge value
 // w_slot(y) (u(row) - u(y)), 0 past the end; the weight is wv (INLINE_W,
@@ -1244,6 +1244,7 @@ __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, lon
                                             const TU *__restrict__ u, const TS *__restrict__ w,
                                             const int32_t *__restrict__ ent,
                                             const EntRec<TS> *__restrict__ went) {
+    constexpr int kPre = kPreOf<TA>;
     const int lane = (int)(threadIdx.x & 63u);
     const long long z0 = z & ~63ll;
     TA acc = (TA)0;
@@ -1286,7 +1287,7 @@ __device__ __forceinline__ void apply_block(
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
     const uint8_t *__restrict__ cnt, const int32_t *__restrict__ pos,
     const int32_t *__restrict__ ent, const EntRec<TS> *__restrict__ went, TA h) {
-    constexpr int P = kApplyPPT;
+    constexpr int P = kApplyPPT, kPre = kPreOf<TA>;
     const long long N = g.N;
     const int lane = (int)(threadIdx.x & 63u);
     const long long zw = wave_group(g, blk, P);
