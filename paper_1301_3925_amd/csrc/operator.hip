@@ -393,10 +393,13 @@ __device__ __forceinline__ void load_rec(const EntRec<TS> *__restrict__ went,
 
 // Sort row z (entries e[0..c)), store every entry again with its weight
 // (we[i], the weight in the storage dtype; not when we is null) and return
-// A_zz, summed as row_diag does.  A row of up to 16 entries is sorted in registers and its
-// incoming weights are all requested before any is added.
+// A_zz, summed as row_diag does.  A row of up to 16 entries is sorted in
+// registers and its incoming weights are all requested before any is added.
+// cw: a wave-uniform bound on c over the lanes that call this together (16
+// when unknown); with cw <= 8 the sort takes 8 rounds instead of 16 and only
+// cw weights are requested.
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
-__device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *e, int c,
+__device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *e, int c, int cw,
                                        const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
                                        const TS *__restrict__ w, EntRec<TS> *__restrict__ we);
 
@@ -426,7 +429,7 @@ __device__ inline double row_diag(const GridInfo &g, long long z, const int32_t 
 }
 
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
-__device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *e, int c,
+__device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *e, int c, int cw,
                                        const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
                                        const TS *__restrict__ w, EntRec<TS> *__restrict__ we) {
     const long long N = g.N;
@@ -441,24 +444,47 @@ __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *
     int32_t r[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) r[i] = i < c ? e[i] : 0x7fffffff;
+    // odd-even transposition sort: n rounds sort n keys (keys are distinct;
+    // the padding sorts last)
+    if (cw <= 8) {
 #pragma unroll
-    for (int round = 0; round < 16; ++round) {
+        for (int round = 0; round < 8; ++round) {
 #pragma unroll
-        for (int i = round & 1; i + 1 < 16; i += 2) {
-            const int32_t a = r[i], bb = r[i + 1];
-            r[i] = min(a, bb);
-            r[i + 1] = max(a, bb);
+            for (int i = round & 1; i + 1 < 8; i += 2) {
+                const int32_t a = r[i], bb = r[i + 1];
+                r[i] = min(a, bb);
+                r[i + 1] = max(a, bb);
+            }
         }
+    } else {
+#pragma unroll
+        for (int round = 0; round < 16; ++round) {
+#pragma unroll
+            for (int i = round & 1; i + 1 < 16; i += 2) {
+                const int32_t a = r[i], bb = r[i + 1];
+                r[i] = min(a, bb);
+                r[i + 1] = max(a, bb);
+            }
+        }
+    }
+    // the weights: up to the wave's bound, from in-grid addresses (the
+    // row's own first weight past c) with no per-lane branch, so they are
+    // all in flight at once
+    TS wr[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        wr[i] = TS{};
+        if (i < cw)
+            wr[i] = w[i < c ? widx<S>((r[i] >> 6) & 7, z + (r[i] >> 9), N) : widx<S>(0, z, N)];
     }
     TA wi[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         if (i < c) {
             e[i] = r[i];
-            const TS wr = w[widx<S>((r[i] >> 6) & 7, z + (r[i] >> 9), N)];
-            if (we) we[i] = make_rec<TS>(r[i], wr);
-            wi[i] = Conv<TS, TA>::ld(wr);
+            if (we) we[i] = make_rec<TS>(r[i], wr[i]);
         }
+        wi[i] = i < c ? Conv<TS, TA>::ld(wr[i]) : (TA)0;
     }
     double d = 0.0;
     Slots<DIM, WIDE> sl;
@@ -576,8 +602,8 @@ __global__ __launch_bounds__(256) void k_bin_build(
         const long long z = t0 + tl;
         if (z >= N) continue;
         const int c = min(lcnt[tl], 255);
-        const double d = sort_row_diag<DIM, WIDE, PER, TS, TA>(g, z, ent + base + loff[tl], c, sb,
-                                                               w, went + base + loff[tl]);
+        const double d = sort_row_diag<DIM, WIDE, PER, TS, TA>(g, z, ent + base + loff[tl], c, 16,
+                                                               sb, w, went + base + loff[tl]);
         diag[z] = (TD)d;
         dmax = fmax(dmax, d);
     }
@@ -934,19 +960,38 @@ __global__ __launch_bounds__(256) void k_place2d(GridInfo g,
 #pragma unroll
     for (int k = 0; k < 6; ++k) rk[k] = rank[k * N + z];
     const Coord p = coords(z, g);
+    // the six targets first, then their row starts from in-grid addresses
+    // (z itself for an edge that is not placed) with no branch around the
+    // loads, so all six are in flight at once, then the stores
+    long long tt[6];
+    bool ok[6];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        if (!(m & (1u << q))) continue;
+    for (int q = 0; q < 3; ++q)
 #pragma unroll
-        for (int sg = -1; sg <= 1; sg += 2) {
-            long long t;
-            if (!edge_target<2, PER>(p, z, sl.o[q], sg, g, t)) continue;
-            if (z - t >= (1ll << 22) || z - t <= -(1ll << 22)) continue;  // flagged earlier
-            const int r = rk[2 * q + (sg > 0)];
-            if (r == 255) continue;
-            ent[(long long)pos[t] + r] = (int32_t)(((z - t) << 9) | (q << 6) | (t & 63));
+        for (int k = 0; k < 2; ++k) {
+            long long t = z;
+            bool v = (m >> q) & 1u;
+            v = v && edge_target<2, PER>(p, z, sl.o[q], k ? 1 : -1, g, t);
+            v = v && z - t < (1ll << 22) && z - t > -(1ll << 22);  // else flagged earlier
+            v = v && rk[2 * q + k] != 255;
+            ok[2 * q + k] = v;
+            tt[2 * q + k] = v ? t : z;
         }
-    }
+    int32_t pt[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) pt[e] = pos[tt[e]];
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+        if (ok[e])
+            ent[(long long)pt[e] + rk[e]] =
+                (int32_t)(((z - tt[e]) << 9) | ((e >> 1) << 6) | (tt[e] & 63));
+}
+
+// Maximum of v over the wavefront, in every lane (all 64 lanes must call it).
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    return __builtin_amdgcn_readfirstlane(v);
 }
 
 // Pass 3: sort every row, store the weight of each entry beside it (went,
@@ -968,20 +1013,34 @@ __global__ __launch_bounds__(256) void k_rows(GridInfo g,
     const long long t0 = (long long)blockIdx.x * blockDim.x, t = t0 + threadIdx.x;
     const int p0 = pos[t0], p1 = pos[t0 + 256 < N ? t0 + 256 : N];
     const bool staged = p1 - p0 <= kCap;  // block-uniform
-    if (staged) {
-        for (int i = threadIdx.x; i < p1 - p0; i += blockDim.x) rows[i] = ent[p0 + i];
+    if (staged) {  // all of a thread's loads first, then its LDS stores
+        const int n = p1 - p0;
+        int32_t v[kCap / 256];
+#pragma unroll
+        for (int it = 0; it < kCap / 256; ++it) {
+            const int i = (int)threadIdx.x + 256 * it;
+            v[it] = 0;
+            if (256 * it < n) v[it] = ent[p0 + (i < n ? i : 0)];  // block-uniform test
+        }
+#pragma unroll
+        for (int it = 0; it < kCap / 256; ++it) {
+            const int i = (int)threadIdx.x + 256 * it;
+            if (i < n) rows[i] = v[it];
+        }
         __syncthreads();
     }
+    const int c = t < N ? (int)cnt[t] : 0;
+    const int cw = wave_max_i(c);  // all lanes
     double dmax = 0.0;
     if (t < N) {
         const int p = pos[t];
         // two calls, so that the staged one addresses LDS directly (not
         // through flat addressing)
-        const double d = staged ? sort_row_diag<DIM, WIDE, PER, TS, TA>(g, t, rows + (p - p0),
-                                                                        (int)cnt[t], sb, w,
+        const double d = staged ? sort_row_diag<DIM, WIDE, PER, TS, TA>(g, t, rows + (p - p0), c,
+                                                                        cw, sb, w,
                                                                         went ? went + p : nullptr)
-                                : sort_row_diag<DIM, WIDE, PER, TS, TA>(g, t, ent + p, (int)cnt[t],
-                                                                        sb, w,
+                                : sort_row_diag<DIM, WIDE, PER, TS, TA>(g, t, ent + p, c, cw, sb,
+                                                                        w,
                                                                         went ? went + p : nullptr);
         diag[t] = (TD)d;
         dmax = d;
