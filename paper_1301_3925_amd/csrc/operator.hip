@@ -699,6 +699,11 @@ __device__ inline void tile_edges(const GridInfo &g, int x0, int y0, int tw, int
     }
 }
 
+template <bool WIDE, typename F>
+__device__ inline void source_edges_of(const GridInfo &g, int x, int y, const Slots<2, WIDE> &sl,
+                                       unsigned m, int x0, int y0, int tw, int th, int stride,
+                                       F f);
+
 // The edges of positive weight from source (x, y) into the rectangle
 // [x0, x0 + tw) x [y0, y0 + th) (Neumann grid): f(local index, target,
 // entry, source, edge index 2q + (sign > 0)).
@@ -712,6 +717,15 @@ __device__ inline void source_edges(const GridInfo &g, int x, int y, int x0, int
     sl.load(sb, z);  // issued with the mask load, not after it
     const unsigned m = mask[z];
     if (!m) return;
+    source_edges_of<WIDE>(g, x, y, sl, m, x0, y0, tw, th, stride, f);
+}
+
+// source_edges with the source's slots and mask already loaded.
+template <bool WIDE, typename F>
+__device__ inline void source_edges_of(const GridInfo &g, int x, int y, const Slots<2, WIDE> &sl,
+                                       unsigned m, int x0, int y0, int tw, int th, int stride,
+                                       F f) {
+    const long long z = x + (long long)g.nx * y;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         if (!(m & (1u << q))) continue;
@@ -750,11 +764,35 @@ __device__ inline void brick_pass(const GridInfo &g, int x0, int y0, int tw, int
     }
     __syncthreads();
     const int n = *nlist;
-    constexpr int BB = kBrick * kBrick;
-    for (int k = threadIdx.x; k < n * BB; k += blockDim.x) {
-        const int br = list[k / BB], p = k % BB;
-        const int x = (br % nbx) * kBrick + p % kBrick, y = (br / nbx) * kBrick + p / kBrick;
-        if (x < g.nx && y < g.ny) source_edges<WIDE>(g, x, y, x0, y0, tw, th, stride, sb, mask, f);
+    constexpr int BB = kBrick * kBrick, G = 4;
+    // G sources per thread at a time: their slots and masks are requested
+    // together (from point 0 for a lane with no source, whose mask is then
+    // taken as 0), then their edges are visited
+    for (int kb = 0; kb < n * BB; kb += G * (int)blockDim.x) {  // block-uniform
+        Slots<2, WIDE> sl[G];
+        unsigned m[G];
+        int xs[G], ys[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int k = kb + j * (int)blockDim.x + (int)threadIdx.x;
+            int x = 0, y = 0;
+            bool ok = false;
+            if (k < n * BB) {
+                const int br = list[k / BB], p = k % BB;
+                x = (br % nbx) * kBrick + p % kBrick;
+                y = (br / nbx) * kBrick + p / kBrick;
+                ok = x < g.nx && y < g.ny;
+            }
+            const long long z = ok ? x + (long long)g.nx * y : 0;
+            sl[j].load(sb, z);
+            const unsigned mm = mask[z];
+            m[j] = ok ? mm : 0u;
+            xs[j] = x;
+            ys[j] = y;
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (m[j]) source_edges_of<WIDE>(g, xs[j], ys[j], sl[j], m[j], x0, y0, tw, th, stride, f);
     }
     __syncthreads();
 }
