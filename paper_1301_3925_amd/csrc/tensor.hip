@@ -293,12 +293,29 @@ __global__ __launch_bounds__(256) void k_st_smooth_map_tiled(int nx, int ny,
     __shared__ T sx[3][E * kTile];
     const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
     const long long N = (long long)nx * ny;
-    for (int k = threadIdx.x; k < E * E; k += 256) {
-        const int gx = mirror(x0 - RR + k % E, nx), gy = mirror(y0 - RR + k / E, ny);
-        const long long i = (long long)gy * nx + gx;
-        sj[0][k] = J[i];
-        sj[1][k] = J[N + i];
-        sj[2][k] = J[2 * N + i];
+    // staged B items per thread at a time: all their loads, then their LDS
+    // stores (a lane past the end reloads the tile's first point)
+    constexpr int B = 7;
+    for (int kb = 0; kb < E * E; kb += B * 256) {
+        T v[B][3];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int k0 = kb + b * 256 + (int)threadIdx.x, k = k0 < E * E ? k0 : 0;
+            const int gx = mirror(x0 - RR + k % E, nx), gy = mirror(y0 - RR + k / E, ny);
+            const long long i = (long long)gy * nx + gx;
+            v[b][0] = J[i];
+            v[b][1] = J[N + i];
+            v[b][2] = J[2 * N + i];
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int k = kb + b * 256 + (int)threadIdx.x;
+            if (k < E * E) {
+                sj[0][k] = v[b][0];
+                sj[1][k] = v[b][1];
+                sj[2][k] = v[b][2];
+            }
+        }
     }
     __syncthreads();
     for (int it = threadIdx.x; it < E * (kTile / XO); it += 256) {
