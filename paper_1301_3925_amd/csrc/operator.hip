@@ -396,8 +396,8 @@ __device__ __forceinline__ void load_rec(const EntRec<TS> *__restrict__ went,
 // A_zz, summed as row_diag does.  A row of up to 16 entries is sorted in
 // registers and its incoming weights are all requested before any is added.
 // cw: a wave-uniform bound on c over the lanes that call this together (16
-// when unknown); with cw <= 8 the sort takes 8 rounds instead of 16 and only
-// cw weights are requested.
+// when unknown); with cw <= 8 (12) the sort takes 8 (12) rounds instead of
+// 16, and only cw weights are requested.
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
 __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *e, int c, int cw,
                                        const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
@@ -428,6 +428,19 @@ __device__ inline double row_diag(const GridInfo &g, long long z, const int32_t 
     return d;
 }
 
+// Odd-even transposition sort of r[0 .. n) in registers.
+template <int n> __device__ __forceinline__ void oe_sort(int32_t *r) {
+#pragma unroll
+    for (int round = 0; round < n; ++round) {
+#pragma unroll
+        for (int i = round & 1; i + 1 < n; i += 2) {
+            const int32_t a = r[i], bb = r[i + 1];
+            r[i] = min(a, bb);
+            r[i + 1] = max(a, bb);
+        }
+    }
+}
+
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
 __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *e, int c, int cw,
                                        const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
@@ -444,29 +457,14 @@ __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *
     int32_t r[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) r[i] = i < c ? e[i] : 0x7fffffff;
-    // odd-even transposition sort: n rounds sort n keys (keys are distinct;
-    // the padding sorts last)
-    if (cw <= 8) {
-#pragma unroll
-        for (int round = 0; round < 8; ++round) {
-#pragma unroll
-            for (int i = round & 1; i + 1 < 8; i += 2) {
-                const int32_t a = r[i], bb = r[i + 1];
-                r[i] = min(a, bb);
-                r[i + 1] = max(a, bb);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int round = 0; round < 16; ++round) {
-#pragma unroll
-            for (int i = round & 1; i + 1 < 16; i += 2) {
-                const int32_t a = r[i], bb = r[i + 1];
-                r[i] = min(a, bb);
-                r[i + 1] = max(a, bb);
-            }
-        }
-    }
+    // odd-even transposition sort of the first 8, 12 or 16 keys (n rounds
+    // sort n keys; keys are distinct and the padding sorts last)
+    if (cw <= 8)
+        oe_sort<8>(r);
+    else if (cw <= 12)
+        oe_sort<12>(r);
+    else
+        oe_sort<16>(r);
     // the weights: up to the wave's bound, from in-grid addresses (the
     // row's own first weight past c) with no per-lane branch, so they are
     // all in flight at once

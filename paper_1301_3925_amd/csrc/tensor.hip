@@ -239,9 +239,18 @@ __global__ __launch_bounds__(256) void k_st_grad_tiled(int nx, int ny, const T *
     __shared__ T sx[E * EU];                // blurred along x
     __shared__ T ss[EU * EU];               // u_sigma
     const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
-    for (int k = threadIdx.x; k < E * E; k += 256) {
-        const int gx = mirror(x0 - 1 - RS + k % E, nx), gy = mirror(y0 - 1 - RS + k / E, ny);
-        su[k] = u[(long long)gy * nx + gx];
+    {  // all of a thread's loads, then its LDS stores
+        constexpr int B = (E * E + 255) / 256;
+        T v[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int k0 = b * 256 + (int)threadIdx.x, k = k0 < E * E ? k0 : 0;
+            const int gx = mirror(x0 - 1 - RS + k % E, nx), gy = mirror(y0 - 1 - RS + k / E, ny);
+            v[b] = u[(long long)gy * nx + gx];
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if (b * 256 + (int)threadIdx.x < E * E) su[b * 256 + threadIdx.x] = v[b];
     }
     __syncthreads();
     for (int k = threadIdx.x; k < E * EU; k += 256) {
