@@ -141,9 +141,9 @@ constexpr int kStripZ = ADLBR_STRIP_Z;
 
 __device__ inline long long strip_block(long long L, const GridInfo &g, int points_per_block) {
     if (g.dim != 3 || kStripZ <= 1) return L;
-    const long long plane = (long long)g.nx * g.ny;
-    if (plane % points_per_block) return L;
-    const unsigned bp = (unsigned)(plane / points_per_block);
+    const unsigned plane = (unsigned)g.nx * (unsigned)g.ny;  // N < 2^28
+    if (plane % (unsigned)points_per_block) return L;
+    const unsigned bp = plane / (unsigned)points_per_block;
     const unsigned strip = (unsigned)kStripZ * bp;
     const unsigned s = (unsigned)L / strip;
     const unsigned z0 = s * (unsigned)kStripZ;
@@ -174,8 +174,11 @@ template <int S> __host__ __device__ __forceinline__ unsigned widx32(int q, int 
 __device__ __forceinline__ long long wave_group(const GridInfo &g, long long blk, int P) {
     const long long wv = threadIdx.x >> 6;
     if (P == 1 && g.dim == 2 && g.nx % 64 == 0 && g.ny % 4 == 0) {
-        const long long gpr = g.nx / 64;
-        return ((blk / gpr) * 4 + wv) * g.nx + (blk % gpr) * 64;
+        // 32-bit division (blocks < 2^22 for N < 2^28): a 64-bit one by a
+        // runtime divisor costs a long scalar sequence in every wave
+        const unsigned gpr = (unsigned)g.nx / 64u, b = (unsigned)blk;
+        const unsigned by = b / gpr, bx = b - by * gpr;
+        return (long long)(by * 4u + (unsigned)wv) * g.nx + (long long)bx * 64;
     }
     return blk * 256 * P + wv * 64 * P;
 }
