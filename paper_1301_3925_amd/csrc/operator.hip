@@ -1519,7 +1519,8 @@ __global__ __launch_bounds__(kBS) void k_cg_direction(
     const int32_t *__restrict__ ent, const EntRec<T> *__restrict__ went, const CgState *st,
     double *partial, int first) {
     const long long N = g.N;
-    const long long blk = xcd_block(blockIdx.x, gridDim.x);
+    // the apply's block order (XCD bands; 3D strips of planes)
+    const long long blk = strip_block(xcd_block(blockIdx.x, gridDim.x), g, kApplyPoints);
     const long long z = wave_group(g, blk, 1) + (threadIdx.x & 63);
     const bool live = z < N;
     double pqz = 0.0;
@@ -1568,7 +1569,10 @@ __global__ __launch_bounds__(kBS) void k_residual(
     const int32_t *__restrict__ ent, const EntRec<T> *__restrict__ went, double dt, double *partial,
     T *__restrict__ rout) {
     const long long N = g.N;
-    const long long z = wave_group(g, blockIdx.x, 1) + (threadIdx.x & 63);
+    // the apply's block order (XCD bands; 3D strips of planes); the partial
+    // stays at blockIdx.x
+    const long long blk = strip_block(xcd_block(blockIdx.x, gridDim.x), g, kApplyPoints);
+    const long long z = wave_group(g, blk, 1) + (threadIdx.x & 63);
     const bool live = z < N;
     double r2 = 0.0;
     const WaveLists L = wave_lists(pos, z, N);
