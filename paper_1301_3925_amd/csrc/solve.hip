@@ -414,11 +414,14 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
             ++restarts;
         }
     }
-    // final report
+    // final report (a confirmed convergence has just computed the true
+    // residual of this x)
     int32_t iters = 0;
     double bb = 0.0;
-    rc = true_residual(op, dt, b, x64, &st->rr_true, part, nullptr, s);
-    if (rc) return rc;
+    if (!converged) {
+        rc = true_residual(op, dt, b, x64, &st->rr_true, part, nullptr, s);
+        if (rc) return rc;
+    }
     hipLaunchKernelGGL((k_convert<double, T>), dim3(nb), dim3(kBS), 0, s, N, (const double *)x64, x);
     double rt = 0.0;
     ADLBR_CHECK_HIP(hipMemcpyAsync(&iters, &cg->iter, 4, hipMemcpyDeviceToHost, s));
