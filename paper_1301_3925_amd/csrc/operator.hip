@@ -454,6 +454,13 @@ __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *
         return row_diag<DIM, WIDE, PER, TS, TA>(g, z, e, c, sb, w);
     }
     constexpr int S = DIM == 2 ? 3 : 6;
+    // the row's own slots and weights do not depend on the sort: requested
+    // first, so they arrive while it runs
+    Slots<DIM, WIDE> sl;
+    sl.load(sb, z);
+    TS wown[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) wown[q] = w[widx<S>(q, z, N)];
     int32_t r[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) r[i] = i < c ? e[i] : 0x7fffffff;
@@ -485,11 +492,9 @@ __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *
         wi[i] = i < c ? Conv<TS, TA>::ld(wr[i]) : (TA)0;
     }
     double d = 0.0;
-    Slots<DIM, WIDE> sl;
-    sl.load(sb, z);
     const Coord p = coords(z, g);
     for (int q = 0; q < S; ++q) {
-        const double wv = (double)Conv<TS, TA>::ld(w[widx<S>(q, z, N)]);
+        const double wv = (double)Conv<TS, TA>::ld(wown[q]);
         for (int sg = -1; sg <= 1; sg += 2) {
             long long t;
             if (edge_target<DIM, PER>(p, z, sl.o[q], sg, g, t)) d += wv;
@@ -1048,6 +1053,7 @@ __global__ __launch_bounds__(256) void k_rows(GridInfo g,
     const long long N = g.N;
     const long long t0 = (long long)blockIdx.x * blockDim.x, t = t0 + threadIdx.x;
     const int p0 = pos[t0], p1 = pos[t0 + 256 < N ? t0 + 256 : N];
+    const int c = t < N ? (int)cnt[t] : 0, p = t < N ? pos[t] : 0;  // requested with the staging
     const bool staged = p1 - p0 <= kCap;  // block-uniform
     if (staged) {  // all of a thread's loads first, then its LDS stores
         const int n = p1 - p0;
@@ -1065,11 +1071,9 @@ __global__ __launch_bounds__(256) void k_rows(GridInfo g,
         }
         __syncthreads();
     }
-    const int c = t < N ? (int)cnt[t] : 0;
     const int cw = wave_max_i(c);  // all lanes
     double dmax = 0.0;
     if (t < N) {
-        const int p = pos[t];
         // two calls, so that the staged one addresses LDS directly (not
         // through flat addressing)
         const double d = staged ? sort_row_diag<DIM, WIDE, PER, TS, TA>(g, t, rows + (p - p0), c,
