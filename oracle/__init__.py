@@ -229,54 +229,3 @@ def structure_tensor_d(u, dims, sigma, rho, alpha, C, eig_map: int = CED):
     _load().or_structure_tensor_d(dim, _p(nd), _p(u), float(sigma), float(rho),
                                   float(alpha), float(C), int(eig_map), _p(D))
     return D
-
-
-def operator_rows(dims, off, w, rows, periodic: bool = False):
-    """Selected rows of A = 1/2 grad E_h, computed literally for large grids:
-    for each row z, every point y within the largest stencil radius is
-    scanned and each directed edge touching z (z's own edges, and edges of
-    y that land on z) adds its weight (eq. (def:E*) with h = 1, Neumann
-    truncation V(z; h)).  Returns a scipy CSR matrix of shape
-    (len(rows), N)."""
-    import scipy.sparse as sp
-    dims = tuple(int(d) for d in dims)
-    dim = len(dims)
-    off = np.asarray(off)
-    w = np.asarray(w, dtype=np.float64)
-    n = int(np.prod(dims))
-    K = w.shape[0]
-    R = int(np.abs(off).max()) if off.size else 0
-    strides = [1, dims[0], dims[0] * (dims[1] if dim > 1 else 1)][:dim]
-    ri, ci, vv = [], [], []
-    rng = np.arange(-R, R + 1)
-    box = np.stack(np.meshgrid(*([rng] * dim), indexing="ij")).reshape(dim, -1)
-    for r_i, z in enumerate(np.asarray(rows, dtype=np.int64)):
-        pz = [(z // strides[c]) % dims[c] for c in range(dim)]
-        q = np.array(pz)[:, None] + box
-        if periodic:
-            q = q % np.array(dims)[:, None]
-        else:
-            ok = np.all([(q[c] >= 0) & (q[c] < dims[c]) for c in range(dim)], axis=0)
-            q = q[:, ok]
-        ys = sum(q[c] * strides[c] for c in range(dim))
-        ys = np.unique(ys)
-        qy = np.stack([(ys // strides[c]) % dims[c] for c in range(dim)])
-        for i in range(K):
-            wi = w[i, ys]
-            for s in (-1, 1):
-                t = qy + s * off[i][:, ys].astype(np.int64)
-                if periodic:
-                    t = t % np.array(dims)[:, None]
-                    inside = np.ones(ys.size, bool)
-                else:
-                    inside = np.all([(t[c] >= 0) & (t[c] < dims[c]) for c in range(dim)], axis=0)
-                tl = sum(t[c] * strides[c] for c in range(dim))
-                live = inside & (wi != 0.0) & (tl != ys)
-                own = live & (ys == z)        # edges of z itself
-                inc = live & (tl == z)        # edges of y landing on z
-                for mask, other in ((own, tl), (inc, ys)):
-                    if mask.any():
-                        ri += [r_i] * (2 * int(mask.sum()))
-                        ci += [z] * int(mask.sum()) + list(other[mask])
-                        vv += list(wi[mask]) + list(-wi[mask])
-    return sp.csr_matrix((vv, (ri, ci)), shape=(len(rows), n))

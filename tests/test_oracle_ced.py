@@ -1,12 +1,15 @@
 """Pins of the oracle's structure-tensor diffusion tensor (CED / EED).
 
 The paper's only CED number (the largest eigenvalue at t = 0, Table on the
-fingerprint) needs an image that is not available, so the values of the CED
-tensor itself are "parity unpinned" by the paper.  What the paper and the
-mathematics fix is pinned here: SPD with eigenvalues in [alpha, 1] and
-anisotropy <= alpha^-1/2, D = alpha Id on a flat image, the coherence
-direction along straight stripes, and exact invariance properties of the
-Gaussian smoothing.
+fingerprint) needs an image that is not available.  What the paper and the
+mathematics fix is pinned here instead:
+- properties: SPD with eigenvalues in [alpha, 1] and anisotropy
+  <= alpha^-1/2, D = alpha Id on a flat image, the coherence direction along
+  straight stripes, transpose covariance;
+- values: the whole pipeline against scipy's mirrored Gaussian filter and
+  numpy's eigensolver (2D and 3D), and against closed forms on cosine
+  images for which every stage is exact, with three distinct eigenvalues in
+  3D so that the eigenvalue assignment is checked.
 """
 import math
 
@@ -95,3 +98,173 @@ def test_ced_rotation_covariance():
     assert np.allclose(DT[0], sw(D[2]), atol=1e-12)
     assert np.allclose(DT[1], sw(D[1]), atol=1e-12)
     assert np.allclose(DT[2], sw(D[0]), atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Value pins of the whole pipeline (Section 5: u_sigma = K_sigma * u,
+# J = K_rho * (grad u_sigma grad u_sigma^T), eigenvalue map).  Two
+# independent routes: a library one (scipy's Gaussian filter with mirror
+# extension, numpy's symmetric eigensolver) on a generic image, and a closed
+# form on images for which every stage is exact.
+
+def _taps(s):
+    r = math.ceil(3.0 * s)
+    j = np.arange(-r, r + 1, dtype=np.float64)
+    g = np.exp(-j * j / (2.0 * s * s))
+    return j, g / g.sum(), r
+
+
+def _eigmap(J, alpha, C, eig_map):
+    """D from J (..., d, d) by the eigenvalue map of Section 5 (CED) or the
+    edge-enhancing map, eigenvalues taken in descending order."""
+    mu, V = np.linalg.eigh(J)          # ascending
+    mu, V = mu[..., ::-1], V[..., :, ::-1]
+    d = J.shape[-1]
+    lam = np.empty_like(mu)
+    if eig_map == oracle.CED:
+        lam[..., 0] = alpha
+        for k in range(1, d):
+            dm = mu[..., 0] - mu[..., k]
+            with np.errstate(divide="ignore"):
+                e = np.where(dm == 0, 0.0, np.exp(-C / np.where(dm == 0, 1.0, dm) ** 2))
+            lam[..., k] = alpha + (1 - alpha) * e
+    else:
+        for k in range(d - 1):
+            m = mu[..., k]
+            lam[..., k] = np.where(m == 0, 1.0, 1 - np.exp(-C / np.where(m == 0, 1.0, m) ** 2))
+        lam[..., d - 1] = 1.0
+    return np.einsum("...ik,...k,...jk->...ij", V, lam, V)
+
+
+def _planes(Dm, dim):
+    idx = [(0, 0), (0, 1), (1, 1)] if dim == 2 else \
+        [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    return np.stack([Dm[..., a, b].reshape(-1) for a, b in idx])
+
+
+def _scipy_pipeline(u, dims, sigma, rho, alpha, C, eig_map):
+    from scipy import ndimage
+    dim = len(dims)
+    a = u.reshape(dims[::-1])            # axes (z,) y, x
+    blur = lambda f, s: ndimage.gaussian_filter(f, s, mode="reflect",
+                                                radius=math.ceil(3 * s))
+    us = blur(a, sigma)
+    pad = np.pad(us, 1, mode="symmetric")  # half-sample mirror
+    g = []
+    for c in range(dim):                   # c = 0 is x, the last array axis
+        ax = dim - 1 - c
+        hi = [slice(1, -1)] * dim
+        lo = [slice(1, -1)] * dim
+        hi[ax], lo[ax] = slice(2, None), slice(None, -2)
+        g.append(0.5 * (pad[tuple(hi)] - pad[tuple(lo)]))
+    J = np.empty(a.shape + (dim, dim))
+    for i in range(dim):
+        for j in range(i, dim):
+            J[..., i, j] = J[..., j, i] = blur(g[i] * g[j], rho)
+    return _planes(_eigmap(J, alpha, C, eig_map), dim)
+
+
+def test_ced2d_matches_scipy_gaussian_pipeline():
+    """2D CED tensor of a generic image = the same definition evaluated by
+    scipy.ndimage.gaussian_filter (mode 'reflect' is the half-sample mirror,
+    radius ceil(3 s)) + mirrored central differences + numpy's eigh.  sigma
+    = 1.5 and rho = 2.5 separate the readings: a variance instead of a
+    standard deviation, unnormalized taps or another truncation radius each
+    move D by far more than the tolerance."""
+    dims = (41, 37)
+    u = synth.ced_image2d(77, *dims, ndiscs=3)
+    sig, rho, C = 1.5, 2.5, 1e-6
+    D = oracle.structure_tensor_d(u, dims, sig, rho, ALPHA, C)
+    R = _scipy_pipeline(u, dims, sig, rho, ALPHA, C, oracle.CED)
+    assert np.abs(D - R).max() <= 1e-12
+
+
+def test_ced3d_matches_scipy_gaussian_pipeline():
+    """The same library cross-check in 3D, CED and edge-enhancing maps, on
+    a volume of 3D synthetic type (Section 5, 3D experiments)."""
+    dims = (15, 13, 12)
+    rng = np.random.default_rng(9)
+    u = synth.ced_image3d(4, 15)[: np.prod(dims)] + 0.1 * rng.standard_normal(np.prod(dims))
+    sig, rho = 1.5, 2.5
+    for eig_map, C in ((oracle.CED, 1e-7), (oracle.EED, 1e-6)):
+        D = oracle.structure_tensor_d(u, dims, sig, rho, ALPHA, C, eig_map)
+        R = _scipy_pipeline(u, dims, sig, rho, ALPHA, C, eig_map)
+        assert np.abs(D - R).max() <= 1e-12, eig_map
+
+
+def _closed_form_J(dims, a, b, m, sigma, rho):
+    """Closed-form J for u = a cos(kx x') + b cos(ky y') (x' = x + 1/2,
+    k = pi m / n): these cosines are even about both mirror points, so the
+    mirrored Gaussian acts on them as the discrete transfer function
+    G_s(k) = sum_j g_j cos(k j), and the central difference of cos(k x') is
+    -sin(k) sin(k x').  J_xy is exact only where the rho-kernel stays in the
+    grid.  Returns J (..., 3, 3) on the grid and the interior mask."""
+    nx, ny = dims[0], dims[1]
+    kx, ky = math.pi * m[0] / nx, math.pi * m[1] / ny
+    G = lambda s, k: float(np.dot(_taps(s)[1], np.cos(k * _taps(s)[0])))
+    Ax = a * G(sigma, kx) * math.sin(kx)
+    Ay = b * G(sigma, ky) * math.sin(ky)
+    shape = dims[::-1]
+    idx = np.indices(shape)
+    xp, yp = idx[-1] + 0.5, idx[-2] + 0.5
+    J = np.zeros(shape + (3, 3))
+    J[..., 0, 0] = 0.5 * Ax * Ax * (1 - G(rho, 2 * kx) * np.cos(2 * kx * xp))
+    J[..., 1, 1] = 0.5 * Ay * Ay * (1 - G(rho, 2 * ky) * np.cos(2 * ky * yp))
+    J[..., 0, 1] = J[..., 1, 0] = (Ax * Ay * G(rho, kx) * G(rho, ky)
+                                   * np.sin(kx * xp) * np.sin(ky * yp))
+    r = _taps(rho)[2]
+    inner = ((idx[-1] >= r) & (idx[-1] < nx - r) & (idx[-2] >= r) & (idx[-2] < ny - r))
+    return J, inner
+
+
+def test_ced3d_closed_form_three_distinct_eigenvalues():
+    """3D eigenvalue assignment (Section 5, 3D CED; edge-enhancing map).
+    For u = a cos(kx x') + b cos(ky y'), constant in z, J is known in closed
+    form: mu_3 = 0 on e_z, and mu_1 > mu_2 > 0 in the x-y plane.  C is set
+    so that the three CED eigenvalues alpha, lambda_2, lambda_3 are far
+    apart; an ascending sort, or lambda_2 and lambda_3 exchanged, moves D by
+    O(1).  Expected D = sum lambda_k v_k v_k^T from the closed-form J."""
+    dims = (40, 36, 6)
+    a, b, m = 1.0, 0.6, (5, 4)
+    sig, rho = 1.0, 2.0
+    x = np.arange(dims[0]) + 0.5
+    y = np.arange(dims[1]) + 0.5
+    ux = a * np.cos(math.pi * m[0] / dims[0] * x)
+    uy = b * np.cos(math.pi * m[1] / dims[1] * y)
+    u = np.broadcast_to(ux[None, None, :] + uy[None, :, None], dims[::-1]).reshape(-1).copy()
+    J, inner = _closed_form_J(dims, a, b, m, sig, rho)
+    mu = np.linalg.eigvalsh(J[inner])[:, ::-1]
+    assert np.all(mu[:, 2] == 0) and np.all(mu[:, 1] > 0.05 * mu[:, 0])
+    C = float(np.median((mu[:, 0] - mu[:, 1]) ** 2))
+    for eig_map in (oracle.CED, oracle.EED):
+        Cm = C if eig_map == oracle.CED else float(np.median(mu[:, 1] ** 2))
+        D = oracle.structure_tensor_d(u, dims, sig, rho, ALPHA, Cm, eig_map)
+        E = _planes(_eigmap(J, ALPHA, Cm, eig_map), 3)
+        sel = inner.reshape(-1)
+        assert np.abs(D[:, sel] - E[:, sel]).max() <= 1e-10, eig_map
+        # the assignment matters: at a good share of these points the three
+        # eigenvalues of D are 0.1 apart, so any other assignment moves D by
+        # at least that much there
+        lam = np.linalg.eigvalsh(_eigmap(J[inner], ALPHA, Cm, eig_map))
+        assert np.mean(np.min(np.diff(lam, axis=-1), axis=-1) > 0.1) > 0.3, eig_map
+
+
+def test_ced2d_closed_form():
+    """2D counterpart of the closed form (Section 5, CED): distinct mu_1 >
+    mu_2 at interior points, lambda_1 = alpha across the structure."""
+    dims = (44, 38)
+    a, b, m = 1.0, 0.7, (6, 5)
+    sig, rho = 1.5, 2.5
+    x = np.arange(dims[0]) + 0.5
+    y = np.arange(dims[1]) + 0.5
+    u = (a * np.cos(math.pi * m[0] / dims[0] * x)[None, :]
+         + b * np.cos(math.pi * m[1] / dims[1] * y)[:, None]).reshape(-1)
+    J3, inner = _closed_form_J(dims + (1,), a, b, m, sig, rho)
+    J = J3[0, :, :, :2, :2]
+    inner = inner[0]
+    mu = np.linalg.eigvalsh(J[inner])
+    C = float(np.median((mu[:, 1] - mu[:, 0]) ** 2))
+    D = oracle.structure_tensor_d(u, dims, sig, rho, ALPHA, C)
+    E = _planes(_eigmap(J, ALPHA, C, oracle.CED), 2)
+    sel = inner.reshape(-1)
+    assert np.abs(D[:, sel] - E[:, sel]).max() <= 1e-10
