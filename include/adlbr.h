@@ -122,7 +122,11 @@ int adlbr_build_stencils(const adlbr_grid *g, const void *D, int D_dtype,
  * (2D: o2 = -o0-o1; 3D: o3 = -(o0+o1), o4 = o0-o2, o5 = o1+o2); otherwise
  * status gets ADLBR_ST_STENCIL.  Compact offsets are stored as int8 unless
  * flags has ADLBR_OP_WIDE (int16); an offset that does not fit sets
- * ADLBR_ST_RANGE.
+ * ADLBR_ST_RANGE and that point keeps no edge (its weights are stored as 0,
+ * so A stays symmetric).  A point reached by more than 255 stencils sets
+ * ADLBR_ST_INCOMING; its row keeps 255 of them.  In both cases every
+ * later call still reads only memory inside the workspace and the grid,
+ * but A is not the operator of the input: the caller must check status.
  *
  * adlbr_operator_workspace: bytes of device workspace for this grid,
  *   storage dtype and flags (an upper bound, independent of the data).
@@ -360,11 +364,13 @@ int adlbr_net_workspace(adlbr_operator *op, const adlbr_net *net, size_t *bytes)
 int adlbr_net_loss_grad(adlbr_operator *op, double dt, const float *r, const float *z,
                         float *gz, double *loss, void *workspace, size_t ws_bytes,
                         void *stream);
-/* Adam step (step counts from 1): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+/* Adam step (step counts from 1) on the scaled gradient g = grad_scale *
+ * grads (grad_scale > 0, e.g. 1/batch to average summed per-sample
+ * gradients): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
  * p -= lr mhat / (sqrt(vhat) + eps).  All device FP32 [n]. */
 int adlbr_net_adam(float *params, const float *grads, float *m, float *v, int64_t n,
-                   int32_t step, double lr, double beta1, double beta2, double eps,
-                   void *stream);
+                   int32_t step, double grad_scale, double lr, double beta1, double beta2,
+                   double eps, void *stream);
 /* r = b - (I + dt A) x (device, the operator's storage dtype). */
 int adlbr_residual(adlbr_operator *op, double dt, const void *b, const void *x, void *r,
                    void *stream);

@@ -10,9 +10,10 @@ from __future__ import annotations
 import ctypes
 
 from . import capi
-from .capi import AdlbrError  # noqa: F401
+from .capi import AdlbrError
 
-__all__ = ["build_stencils", "Operator", "structure_tensor", "grid", "AdlbrError"]
+__all__ = ["build_stencils", "Operator", "structure_tensor", "grid", "AdlbrError",
+           "status_flags"]
 
 
 def _torch():
@@ -94,13 +95,46 @@ def build_stencils(D, dims, w_dtype=None, periodic: bool = False, stream=None, o
     return off, w, st
 
 
+_OP_ERRORS = {capi.ST_RANGE: "an offset does not fit the operator's storage",
+              capi.ST_STENCIL: "slots are not built from a superbase",
+              capi.ST_INCOMING: "more than 255 stencils reach one point"}
+
+
+def status_flags(status) -> int:
+    """The OR of ADLBR_ST_* flags of a device status word (synchronizes)."""
+    return int(status[1].item())
+
+
 class Operator:
     """The assembled operator A = 1/2 grad E_h (adlbr_operator_create).
 
-    Holds its device workspace (a torch uint8 tensor) for its lifetime."""
+    Holds its device workspace (a torch uint8 tensor) for its lifetime.
+    With check=True (the default) the constructor synchronizes and raises
+    AdlbrError when the device status word reports a bad operator (an
+    offset out of range, slots that are not a superbase, a point reached by
+    more than 255 stencils).  wide=None picks int8 compact offsets and falls
+    back to int16 when an offset does not fit (needs check=True); with
+    check=False the caller reads self.status itself."""
 
     def __init__(self, dims, offsets, weights, storage=None, periodic: bool = False,
-                 wide: bool = False, stream=None, workspace=None):
+                 wide=None, stream=None, workspace=None, check: bool = True):
+        self._h = ctypes.c_void_p()
+        self._create(dims, offsets, weights, storage, periodic, bool(wide), stream, workspace)
+        if not check:
+            return
+        flags = status_flags(self.status)
+        if wide is None and flags & capi.ST_RANGE:
+            self.close()
+            self._create(dims, offsets, weights, storage, periodic, True, stream, workspace)
+            flags = status_flags(self.status)
+        bad = [msg for f, msg in _OP_ERRORS.items() if flags & f]
+        if bad:
+            first = int(self.status[0].item())
+            self.close()
+            raise AdlbrError(capi.E_RANGE, "operator_create: " + "; ".join(bad) +
+                             f" (first point {first})")
+
+    def _create(self, dims, offsets, weights, storage, periodic, wide, stream, workspace):
         torch = _torch()
         lib = capi.load()
         _require_cuda(offsets, weights)
@@ -108,6 +142,7 @@ class Operator:
         self.N = _npoints(self.dims)
         self.storage = storage or torch.float32
         self.device = weights.device
+        self.wide = wide
         self._grid = grid(self.dims, periodic)
         flags = capi.OP_WIDE if wide else 0
         nbytes = ctypes.c_size_t()
@@ -420,10 +455,12 @@ def residual(op: "Operator", b, x, dt: float, out=None, stream=None):
 
 
 def adam(params, grads, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
-         stream=None):
+         grad_scale: float = 1.0, stream=None):
+    """Adam step on grad_scale * grads (adlbr_net_adam)."""
     capi.check(capi.load().adlbr_net_adam(_ptr(params), _ptr(grads), _ptr(m), _ptr(v),
-                                          params.numel(), int(step), float(lr), float(beta1),
-                                          float(beta2), float(eps), _stream(stream)))
+                                          params.numel(), int(step), float(grad_scale),
+                                          float(lr), float(beta1), float(beta2), float(eps),
+                                          _stream(stream)))
 
 
 def train_net(op: "Operator", dt: float, rhs_seeds, steps: int = 400, batch: int = 4,
@@ -482,8 +519,7 @@ def train_net(op: "Operator", dt: float, rhs_seeds, steps: int = 400, batch: int
             net.loss_grad(dt, r, z[j], gz[j], loss)
             net.backward(r, gz[j], saved[j], gparams, ggates)
         net.gates_backward(ggates, gparams)
-        gparams.mul_(1.0 / batch)
-        adam(net.params, gparams, m, v, it, lr)
+        adam(net.params, gparams, m, v, it, lr, grad_scale=1.0 / batch)
         net.refresh_gates()
         if log_every and (it % log_every == 0 or it == 1):
             hist.append((it, float(loss.item()) / batch))

@@ -109,7 +109,7 @@ SIGNATURES = {
     "adlbr_net_gates_backward": ([_P, _P, _P, _P, _P, _SZ, _P], _I),
     "adlbr_net_workspace": ([_P, _P, ctypes.POINTER(_SZ)], _I),
     "adlbr_net_loss_grad": ([_P, _D, _P, _P, _P, _P, _P, _SZ, _P], _I),
-    "adlbr_net_adam": ([_P, _P, _P, _P, _I64, ctypes.c_int32, _D, _D, _D, _D, _P], _I),
+    "adlbr_net_adam": ([_P, _P, _P, _P, _I64, ctypes.c_int32, _D, _D, _D, _D, _D, _P], _I),
     "adlbr_residual": ([_P, _D, _P, _P, _P, _P], _I),
 }
 

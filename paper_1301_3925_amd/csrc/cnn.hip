@@ -562,11 +562,11 @@ __global__ __launch_bounds__(kBS) void k_loss_fin(const double *part, long long 
     if (threadIdx.x == 0) *loss += t;
 }
 
-__global__ void k_adam(float *p, const float *g, float *m, float *v, long long n, float lr,
-                       float b1, float b2, float eps, float c1, float c2) {
+__global__ void k_adam(float *p, const float *g, float *m, float *v, long long n, float gscale,
+                       float lr, float b1, float b2, float eps, float c1, float c2) {
     const long long i = (long long)blockIdx.x * kBS + threadIdx.x;
     if (i >= n) return;
-    const float gi = g[i];
+    const float gi = gscale * g[i];
     const float mi = b1 * m[i] + (1.f - b1) * gi;
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
@@ -1004,16 +1004,16 @@ extern "C" int adlbr_net_loss_grad(adlbr_operator *op, double dt, const float *r
 }
 
 extern "C" int adlbr_net_adam(float *params, const float *grads, float *m, float *v, int64_t n,
-                              int32_t step, double lr, double beta1, double beta2, double eps,
-                              void *stream) {
+                              int32_t step, double grad_scale, double lr, double beta1,
+                              double beta2, double eps, void *stream) {
     clear_error();
-    if (!params || !grads || !m || !v || n < 1 || step < 1) {
+    if (!params || !grads || !m || !v || n < 1 || step < 1 || !(grad_scale > 0.0)) {
         set_error("adlbr_net_adam: bad argument");
         return ADLBR_E_INVALID;
     }
     const float c1 = (float)(1.0 - pow(beta1, step)), c2 = (float)(1.0 - pow(beta2, step));
     hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(kBS), 0, as_stream(stream), params, grads, m, v,
-                       (long long)n, (float)lr, (float)beta1, (float)beta2, (float)eps, c1, c2);
+                       (long long)n, (float)grad_scale, (float)lr, (float)beta1, (float)beta2, (float)eps, c1, c2);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }

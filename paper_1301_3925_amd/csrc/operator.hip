@@ -304,11 +304,15 @@ __global__ __launch_bounds__(256) void k_compact(
                       s[5][c] == s[1][c] + s[2][c];
         }
         if (!rel) st |= ADLBR_ST_STENCIL;
-        if (!Slots<DIM, WIDE>::pack(s, sb, z)) st |= ADLBR_ST_RANGE;
+        // a point whose slots do not fit the compact format keeps no edge
+        // (zero weights, empty mask), so the operator stays symmetric and
+        // its diagonal is not inflated by self-edges; the flag reports it
+        const bool packed = Slots<DIM, WIDE>::pack(s, sb, z);
+        if (!packed) st |= ADLBR_ST_RANGE;
         p = coords(z, g);
         unsigned m = 0;
         for (int q = 0; q < S; ++q) {
-            wq[q] = (double)win[q * N + z];
+            wq[q] = packed ? (double)win[q * N + z] : 0.0;
             w[widx<S>(q, z, N)] = Conv<TS, TA>::st((TA)wq[q]);
             if (wq[q] > 0.0) m |= 1u << q;
         }
@@ -597,6 +601,16 @@ __global__ __launch_bounds__(256) void k_bin_build(
         const int tl = v.x - (int)t0;
         const int k = atomicAdd(&lcnt[tl], 1);
         if (k < 255) ent[base + loff[tl] + k] = v.y;
+    }
+    // Rows clamped at 255 entries (flagged above) leave the bin's region
+    // [base + clamped total, base + E) unwritten, and the apply reads it as
+    // the tail of the bin's last row (the next bin starts at base + E).  It
+    // is filled with entries that contribute exactly 0: offset 0 on the last
+    // row's lane (kBin is a multiple of 64, so that lane is 63), weight 0.
+    const int32_t clamped_total = scan[255];
+    for (unsigned e = (unsigned)clamped_total + threadIdx.x; e < E; e += 256) {
+        ent[base + e] = 63;
+        went[base + e] = make_rec<TS>(63, TS{});
     }
     __syncthreads();
     double dmax = 0.0;

@@ -281,9 +281,17 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     const bool net = p->method == ADLBR_SOLVE_FCG_NET;
     CgState *cg = &st->cg;
 
-    hipEvent_t e0, e1;
-    ADLBR_CHECK_HIP(hipEventCreate(&e0));
-    ADLBR_CHECK_HIP(hipEventCreate(&e1));
+    // the two timing events are destroyed on every exit path
+    struct Events {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    ADLBR_CHECK_HIP(hipEventCreate(&ev.e[0]));
+    ADLBR_CHECK_HIP(hipEventCreate(&ev.e[1]));
+    const hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
     ADLBR_CHECK_HIP(hipEventRecord(e0, s));
     // clear the state, set dt
     hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, st, dt);
@@ -431,8 +439,6 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     ADLBR_CHECK_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rep) {
         rep->iters = fell_back ? net_iters + iters : iters;
         rep->converged = converged;

@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "smooth_field", "tensor2d_from_angle", "tensor2d_const", "tensor2d_field",
     "tensor3d_from_rotvec", "tensor3d_field", "uniform", "ced_image2d",
-    "ced_image3d", "batch_problems", "random_spd2", "random_spd3",
+    "ced_image3d", "batch_problems", "random_spd2", "random_spd3", "overflow_field3d",
 ]
 
 
@@ -221,3 +221,25 @@ def batch_problems(seed: int, n2d: int = 64, n3d: int = 8,
         probs.append({"dim": 3, "n": (s, s, s), "seed": seed * 1000 + 500 + j,
                       "kappa": kappa_max})
     return probs
+
+
+def overflow_field3d():
+    """A 17^3 tensor field whose stencils nearly all reach the centre c: at
+    every y with v = c - y primitive, D(y) = v v^T / |v|^2 + 1e-3 Id, a
+    needle along v; elsewhere D = Id.  Returns (dims, D (6, N), index of c).
+    It exercises the limit of 255 incoming edges per point."""
+    n = (17, 17, 17)
+    c = np.array([8, 8, 8])
+    N = int(np.prod(n))
+    idx = np.arange(N)
+    P = np.stack([idx % n[0], (idx // n[0]) % n[1], idx // (n[0] * n[1])])
+    D = np.zeros((6, N))
+    for i in range(N):
+        v = c - P[:, i]
+        if math.gcd(math.gcd(int(abs(v[0])), int(abs(v[1]))), int(abs(v[2]))) != 1:
+            M = np.eye(3)
+        else:
+            vh = v / np.linalg.norm(v)
+            M = np.outer(vh, vh) + 1e-3 * np.eye(3)
+        D[:, i] = [M[0, 0], M[0, 1], M[0, 2], M[1, 1], M[1, 2], M[2, 2]]
+    return n, D, int(c[0] + n[0] * (c[1] + n[1] * c[2]))

@@ -126,3 +126,15 @@ def test_explicit_euler_mass_max_principle_energy():
             e_prev = e
         assert lo - 1e-12 <= u.min() and u.max() <= hi + 1e-12
         assert abs(u.sum() - m0) <= 1e-10 * abs(m0)
+
+
+def test_overflow_field_reaches_centre_more_than_255_times():
+    """The crafted field of the operator's incoming-list limit test: the
+    oracle's stencils of synth.overflow_field3d() put more than 255
+    positive-weight edges on the centre (each needle stencil holds the
+    primitive vector towards it, Section 2: the stencil of a near
+    rank-one tensor contains the lattice direction it is aligned with)."""
+    dims, D, c = synth.overflow_field3d()
+    off, w, st = oracle.stencil3d(D)
+    A = oracle.operator_matrix(dims, off, w)
+    assert (A.getrow(c).toarray() != 0).sum() - 1 > 255
