@@ -1,32 +1,37 @@
 #!/usr/bin/env python3
 """AD-LBR hot-path benchmark on one MI355X.
 
-Default workload: coherence-enhancing diffusion on a 2048x2048 FP32 image
-(synthetic oriented stripes with noise and interrupted lines).  Every 10
-explicit steps the diffusion tensor is recomputed from the structure tensor
-of u (sigma = 1, rho = 4, alpha = 1e-4, C = 1e-5), the AD-LBR stencils are
-rebuilt and the operator re-assembled; 1000 explicit steps in all.
+Default workload ("c4"): the uneven batch -- 64 square images (sides
+256..1536, smooth orientation fields, kappa uniform in 1..50) and 8 cubic
+volumes (sides 64..192, needle / plate / isotropic fields, kappa <= 50),
+FP32.  One benchmark step is one pass of the hot path over the whole batch:
+the AD-LBR stencils of all 72 tensor fields, the assembly of all 72
+operators (in place, so the captured graph stays valid), then 100 explicit
+Euler steps of every problem at 0.9 x its own CFL bound, replayed from one
+captured HIP graph with the autotuned launch variants.  The value is
+whole-job throughput in Mpoint-steps/s (grid points x explicit steps /
+wall time), with every input resident in HBM before the timed region.
 
-One benchmark "step" is one such period: structure tensor -> stencils ->
-operator assembly -> 10 explicit Euler steps at 0.9 x the CFL bound.  The
-value is whole-job throughput in Mpoint-steps/s (grid points x explicit
-steps / wall time), inputs resident in HBM before the timed region.
+The same JSON line carries the roofline of the dominant kernel (the batched
+step, k_apply_batch: algorithmic bytes of one step of every problem over
+its measured duration), the CPU baseline (the FP64 oracle on a bounded
+sample of the same batch, one thread and all cores), and the implicit-step
+comparison of the metric's second half: time to 1e-6 relative residual for
+flexible CG with the learned preconditioner against Jacobi-PCG on 1024^2
+(kappa = 200) and 128^3, dt = 50 x the explicit CFL bound.
 
-Other workloads (--workload): "c3" is the 256^3 3D field stepped in FP32
-without rebuilds (kappa <= 50), "c1" the 64^2 FP64 run, "c5" the implicit
-step (I + dt A) x = b on 1024^2 (kappa = 200, dt = 50 x the explicit CFL
-bound): time to 1e-6 relative residual for Jacobi-PCG and for flexible CG
-with the learned preconditioner (trained first, on the GPU, on residuals of
-other right-hand sides; training time reported separately), "c5-3d" the
-same on 128^3.
+Other workloads (--workload): "c2" the 2048^2 coherence-enhancing
+diffusion run (structure tensor, stencils and assembly every 10 steps),
+"c3" the 256^3 volume stepped without rebuilds, "c3-precision" the same in
+FP64/FP32/BF16/FP16 storage, "c1" the 64^2 FP64 run, "c5" / "c5-3d" the
+implicit step alone, "copy" a 1 GiB device copy (the HBM anchor).
 
-Prints ONE JSON line.
+Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -41,11 +46,12 @@ ALGO_BYTES = {(2, 8): 16 + 3 * 8 + 4, (2, 4): 8 + 3 * 4 + 4, (2, 2): 4 + 3 * 2 +
               (3, 8): 16 + 6 * 8 + 12, (3, 4): 8 + 6 * 4 + 12, (3, 2): 4 + 6 * 2 + 12}
 
 
-# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
-# (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by what the same
-# counters read for the 1 GiB copy of --workload copy (FETCH x 2.0, WRITE
-# x 1.0), with the SHA-256 of the kernel sources they were taken on.  A
-# change to those sources makes the figure stale: traffic is then null.
+# HBM bytes per unit of the dominant kernel (c2, c3: one launch; c4: every
+# launch of one batch step), from two rocprofv3 --pmc runs (FETCH_SIZE,
+# WRITE_SIZE; KiB per dispatch) scaled by what the same counters read for
+# the 1 GiB copy of --workload copy (FETCH x 2.0, WRITE x 1.0), with the
+# SHA-256 of the kernel sources they were taken on.  A change to those
+# sources makes the figure stale: traffic is then null.
 TRAFFIC = {
     "c2": {"sha256": "b038c868729927a94f3ef5669159a50a3d9c643d99e6c7c56622462292268f31",
            "bytes_per_launch": 221488231},
@@ -53,6 +59,10 @@ TRAFFIC = {
            "bytes_per_launch": 2435736144},
 }
 TRAFFIC_SOURCES = ("paper_1301_3925_amd/csrc/operator.hip", "paper_1301_3925_amd/csrc/common.h")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def source_digest():
@@ -76,20 +86,116 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2",
+    ap.add_argument("--workload", default="c4",
                     choices=["c1", "c2", "c3", "c3-precision", "c4", "c5", "c5-3d", "copy"])
     ap.add_argument("--train-steps", type=int, default=None,
                     help="c5: training steps (default 3000 in 2D, 300 in 3D)")
+    ap.add_argument("--train-steps-3d", type=int, default=300,
+                    help="c4: training steps of the 3D implicit-step comparison")
     ap.add_argument("--off-policy", action="store_true",
                     help="c5: train on Jacobi-PCG residuals only (no flexible-CG residuals)")
     ap.add_argument("--refresh", type=int, default=4,
                     help="c5: how many times flexible-CG residuals join the training pool")
     ap.add_argument("--dtype", default=None, help="storage dtype for c3: f64|f32|bf16|f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-implicit", action="store_true",
+                    help="c4: leave out the implicit-step comparison")
+    ap.add_argument("--workers", type=int, default=None,
+                    help="host worker processes (default min(16, cpu count))")
     args = ap.parse_args()
     if args.train_steps is None:
         args.train_steps = 300 if args.workload == "c5-3d" else 3000
+    if args.workers is None:
+        args.workers = max(1, min(16, os.cpu_count() or 1))
     return args
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ------------------------------------------------------------------ fields --
+
+def _field(p):
+    import numpy as np
+    from paper_1301_3925_amd import synth
+    D = (synth.tensor2d_field(p["seed"], *p["n"], p["kappa"]) if p["dim"] == 2
+         else synth.tensor3d_field(p["seed"], p["n"], p["kappa"]))
+    return D.astype(np.float32)
+
+
+def batch_fields(probs, workers):
+    """The batch's tensor fields (FP32, host), drawn in worker processes.
+    Runs before anything touches the GPU (fork after HIP init is unsafe)."""
+    import multiprocessing as mp
+    import numpy as np
+    if workers <= 1:
+        return [_field(p) for p in probs]
+    order = sorted(range(len(probs)), key=lambda i: -int(np.prod(probs[i]["n"])))
+    with mp.get_context("fork").Pool(workers) as pool:
+        out = pool.map(_field, [probs[i] for i in order], chunksize=1)
+    res = [None] * len(probs)
+    for i, D in zip(order, out):
+        res[i] = D
+    return res
+
+
+# ---------------------------------------------------------- CPU baseline --
+
+def _oracle_job(p, nsteps=100):
+    """The FP64 oracle as it stands on one problem of the batch: stencils,
+    operator assembly, nsteps explicit steps at 0.9 x its CFL bound."""
+    import numpy as np
+    import oracle
+    from paper_1301_3925_amd import synth
+    D = (synth.tensor2d_field(p["seed"], *p["n"], p["kappa"]) if p["dim"] == 2
+         else synth.tensor3d_field(p["seed"], p["n"], p["kappa"]))
+    u0 = synth.uniform(p["seed"] + 7, D.shape[1])
+    t0 = time.perf_counter()
+    off, w, _ = oracle.stencil(D)
+    A = oracle.operator_matrix(p["n"], off, w)
+    oracle.explicit_steps(A, u0, 0.9 * oracle.cfl(A), nsteps)
+    return time.perf_counter() - t0, int(np.prod(p["n"])) * nsteps
+
+
+def cpu_baseline_c4(probs, workers):
+    """The oracle on a bounded sample of the batch: its 16 smallest images
+    and 2 smallest volumes, each taken through stencils, assembly and 100
+    explicit steps -- first one problem after another on one thread, then
+    spread over `workers` processes (the oracle is single-threaded C plus
+    scipy; independent problems are its natural parallelism)."""
+    import multiprocessing as mp
+    import numpy as np
+    p2 = sorted([p for p in probs if p["dim"] == 2], key=lambda p: p["n"][0])[:16]
+    p3 = sorted([p for p in probs if p["dim"] == 3], key=lambda p: p["n"][0])[:2]
+    sample = p3 + p2
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    work1 = sum(_oracle_job(p)[1] for p in sample)
+    t1 = time.perf_counter() - t0
+    log(f"oracle sample single-thread: {t1:.1f} s")
+    with mp.get_context("fork").Pool(workers) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_job, sample, chunksize=1)
+        tp = time.perf_counter() - t0
+    workp = sum(r[1] for r in res)
+    log(f"oracle sample on {workers} processes: {tp:.1f} s")
+    desc = ("the batch's 16 smallest images and 2 smallest volumes "
+            f"({sum(int(np.prod(p['n'])) for p in sample)} points), each through "
+            "stencils, assembly and 100 explicit steps in FP64")
+    return {"value": round(workp / tp / 1e6, 3), "unit": "Mpoint-steps/s", "cores": workers,
+            "kind": "oracle", "sample": desc + f", {workers} worker processes",
+            "seconds": round(tp, 3), "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "single_thread": {"value": round(work1 / t1 / 1e6, 3), "unit": "Mpoint-steps/s",
+                              "cores": 1, "seconds": round(t1, 3)}}
 
 
 def cpu_baseline_c2(u0_np, n_full, periods=3):
@@ -112,7 +218,7 @@ def cpu_baseline_c2(u0_np, n_full, periods=3):
             "kind": "oracle",
             "sample": f"the first {periods} rebuild periods (structure tensor, stencils, assembly, "
                       f"10 explicit steps each) of the whole {n}x{n} image, FP64, single thread",
-            "seconds": round(t, 3)}
+            "seconds": round(t, 3), "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def cpu_baseline_steps(dims, D_np, u0_np, nsteps):
@@ -127,8 +233,11 @@ def cpu_baseline_steps(dims, D_np, u0_np, nsteps):
     return {"value": n * nsteps / t / 1e6, "unit": "Mpoint-steps/s", "cores": 1,
             "kind": "oracle",
             "sample": f"stencils + assembly + {nsteps} explicit steps on {'x'.join(map(str, dims))}"
-                      ", FP64, single thread", "seconds": round(t, 3)}
+                      ", FP64, single thread", "seconds": round(t, 3),
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
+
+# ---------------------------------------------------------------- main --
 
 def main():
     args = parse()
@@ -136,119 +245,253 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): nothing in this "
               "library uses a second GPU", file=sys.stderr)
         sys.exit(2)
+    fields = cpu = None
+    if args.workload == "c4":
+        # host-side work in worker processes first: forking after the GPU
+        # is initialized is not safe
+        from paper_1301_3925_amd import synth
+        probs = synth.batch_problems(1304)
+        if not args.no_cpu_baseline:
+            cpu = cpu_baseline_c4(probs, args.workers)
+        t0 = time.perf_counter()
+        fields = batch_fields(probs, args.workers)
+        log(f"drew {len(fields)} tensor fields in {time.perf_counter() - t0:.1f} s "
+            f"({args.workers} processes)")
+    import torch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    if args.workload == "c4":
+        return run_c4(args, dev, stream, probs, fields, cpu)
+    if args.workload == "c2":
+        return run_c2(args, dev, stream)
+    if args.workload == "copy":
+        return run_copy(args, dev, stream)
+    if args.workload == "c3-precision":
+        return run_precision(args, dev, stream)
+    if args.workload in ("c5", "c5-3d"):
+        print(json.dumps(implicit_line(args, dev, args.workload == "c5-3d", args.train_steps)),
+              flush=True)
+        return
+    return run_fixed(args, dev, stream)
+
+
+def run_c4(args, dev, stream, probs, fields, cpu):
+    import numpy as np
+    import torch
+    import paper_1301_3925_amd as adlbr
+    nsteps = 100
+    K = args.steps if args.steps is not None else 10
+    Ds, outs, ops, us = [], [], [], []
+    for p, D in zip(probs, fields):
+        N = int(np.prod(p["n"]))
+        S = 3 if p["dim"] == 2 else 6
+        Dg = torch.from_numpy(D).to(dev)
+        out = (torch.empty((S, p["dim"], N), dtype=torch.int16, device=dev),
+               torch.empty((S, N), dtype=torch.float32, device=dev),
+               torch.empty(2, dtype=torch.int32, device=dev))
+        adlbr.build_stencils(Dg, p["n"], out=out)
+        ops.append(adlbr.Operator(p["n"], out[0], out[1], storage=torch.float32))
+        us.append(torch.from_numpy(synth_u0(p, N)).float().to(dev))
+        Ds.append(Dg)
+        outs.append(out)
+    del fields
+    torch.cuda.synchronize()
+    log("built 72 operators")
+    b = adlbr.Batch(ops, us, dt=0.9, dt_mode="cfl")
+    variants = b.tune(steps=10)
+    log(f"tuned: {variants}")
+
+    def one_pass(ev=None):
+        # the whole hot path over the batch: stencils, in-place assembly,
+        # 100 explicit steps of every problem from the captured graph
+        if ev is not None:
+            ev[0].record(stream)
+        for p, Dg, out, op in zip(probs, Ds, outs, ops):
+            adlbr.build_stencils(Dg, p["n"], out=out)
+            op.rebuild(out[0], out[1])
+        if ev is not None:
+            ev[1].record(stream)
+        b.run(nsteps)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for _ in range(max(1, args.warmup)):
+        one_pass()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    t0 = time.perf_counter()
+    for k in range(K):
+        one_pass(evs[k])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / K
+    build_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / K
+    steps_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / K
+    flags = 0
+    for out, op in zip(outs, ops):
+        flags |= adlbr.status_flags(out[2]) | adlbr.status_flags(op.status)
+    if flags & ~adlbr.capi.ST_CLAMPED:
+        print(f"status error: flags {flags:#x}", file=sys.stderr)
+        sys.exit(1)
+    log(f"timed {K} passes: {wall * 1e3:.2f} ms each (build {build_ms:.2f}, steps {steps_ms:.2f})")
+    # the same 100 steps launched per problem, one problem after another
+    tmps = [torch.empty_like(u) for u in us]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for op, u, t in zip(ops, us, tmps):
+        op.step(u, 0.9, nsteps, cfl_fraction=True, u_tmp=t)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    n2 = sum(int(np.prod(p["n"])) for p in probs if p["dim"] == 2)
+    n3 = sum(int(np.prod(p["n"])) for p in probs if p["dim"] == 3)
+    pts = n2 + n3
+    abytes = ALGO_BYTES[(2, 4)] * n2 + ALGO_BYTES[(3, 4)] * n3
+    step_s = steps_ms / 1e3 / nsteps
+    achieved = abytes / step_s / 1e9
+    launches = sum(v["chunks"] * (v["problems"] if v["variant"] & 4 else 1) for v in variants)
+    res = {
+        "metric": "Mpoint-steps/s", "value": round(pts * nsteps / wall / 1e6, 2),
+        "unit": "Mpoint-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch-64x2d-256..1536-8x3d-64..192-f32",
+                   "problems": len(probs), "points_2d": n2, "points_3d": n3,
+                   "explicit_steps_per_pass": nsteps, "seed": 1304, "kappa": "U[1,50] (2D), <=50 (3D)",
+                   "dt": "0.9/max A_zz per problem",
+                   "pass": "stencils + assembly of all problems, then 100 explicit steps of "
+                           "every problem in one graph replay"},
+        "phases_ms_per_pass": {"stencils_and_assembly": round(build_ms, 3),
+                               "explicit_steps_x100": round(steps_ms, 3)},
+        "per_problem_launches": {"value": round(pts * nsteps / seq / 1e6, 2),
+                                 "unit": "Mpoint-steps/s", "seconds": round(seq, 4),
+                                 "what": "the 100 steps alone, adlbr_step per problem"},
+        "autotuned_variants": variants,
+        "roofline": {"bound": "hbm", "kernel": "k_apply_batch (batched explicit step, FP32)",
+                     "unit_of_work": "one explicit step of every problem "
+                                     f"({launches} launches)",
+                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for("c4"),
+                     "algo_bytes": abytes, "avg_step_us": round(step_s * 1e6, 2)},
+    }
+    del b
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
+    if not args.no_implicit:
+        del ops, us, tmps, Ds, outs
+        torch.cuda.empty_cache()
+        res["implicit_2d"] = implicit_line(args, dev, False, 3000)
+        res["implicit_3d"] = implicit_line(args, dev, True, args.train_steps_3d)
+    print(json.dumps(res), flush=True)
+
+
+def synth_u0(p, N):
+    from paper_1301_3925_amd import synth
+    return synth.uniform(p["seed"] + 7, N)
+
+
+def run_c2(args, dev, stream):
+    """2048^2 coherence-enhancing diffusion: one step is one rebuild period
+    (structure tensor -> stencils -> in-place assembly -> 10 explicit
+    steps at 0.9 x the CFL bound)."""
     import numpy as np
     import torch
     import paper_1301_3925_amd as adlbr
     from paper_1301_3925_amd import synth
+    n = 2048
+    dims = (n, n)
+    N = n * n
+    K = args.steps if args.steps is not None else 100
+    sub = 10
+    u0 = synth.ced_image2d(1302, n, n)
+    u = torch.from_numpy(u0).float().to(dev)
+    tmp = torch.empty_like(u)
+    Dbuf = torch.empty((3, N), dtype=torch.float32, device=dev)
+    outs = (torch.empty((3, 2, N), dtype=torch.int16, device=dev),
+            torch.empty((3, N), dtype=torch.float32, device=dev),
+            torch.empty(2, dtype=torch.int32, device=dev))
+    adlbr.structure_tensor(u, dims, 1.0, 4.0, 1e-4, 1e-5, out=Dbuf)
+    adlbr.build_stencils(Dbuf, dims, out=outs)
+    op = adlbr.Operator(dims, outs[0], outs[1], storage=torch.float32)
+    import ctypes
+    sz = ctypes.c_size_t()
+    g = adlbr.grid(dims)
+    adlbr.capi.check(adlbr.capi.load().adlbr_tensor_workspace(ctypes.byref(g), adlbr.capi.F32,
+                                                              ctypes.byref(sz)))
+    tws = torch.empty(sz.value, dtype=torch.uint8, device=dev)
+    flags = torch.zeros(2, dtype=torch.int32, device=dev)
+    ev = []
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
+    def period(record):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if record else None
+        if record:
+            e[0].record(stream)
+        adlbr.structure_tensor(u, dims, 1.0, 4.0, 1e-4, 1e-5, out=Dbuf, workspace=tws)
+        if record:
+            e[1].record(stream)
+        adlbr.build_stencils(Dbuf, dims, out=outs)
+        if record:
+            e[2].record(stream)
+        op.rebuild(outs[0], outs[1])
+        if record:
+            e[3].record(stream)
+        op.step(u, 0.9, sub, cfl_fraction=True, u_tmp=tmp)
+        if record:
+            e[4].record(stream)
+            ev.append(e)
+        flags.bitwise_or_(outs[2]).bitwise_or_(op.status)  # bookkeeping of the status words
 
-    if args.workload == "c2":
-        n = 2048
-        dims = (n, n)
-        N = n * n
-        K = args.steps if args.steps is not None else 100
-        sub = 10
-        u0 = synth.ced_image2d(1302, n, n)
-        u = torch.from_numpy(u0).float().to(dev)
-        tmp = torch.empty_like(u)
-        Dbuf = torch.empty((3, N), dtype=torch.float32, device=dev)
-        tws = torch.empty(1, dtype=torch.uint8, device=dev)
-        outs = (torch.empty((3, 2, N), dtype=torch.int16, device=dev),
-                torch.empty((3, N), dtype=torch.float32, device=dev),
-                torch.empty(2, dtype=torch.int32, device=dev))
-        opws = [None]
-        # size the workspaces once
-        nb = adlbr.capi.Grid()
-        import ctypes
-        sz = ctypes.c_size_t()
-        g = adlbr.grid(dims)
-        adlbr.capi.check(adlbr.capi.load().adlbr_tensor_workspace(ctypes.byref(g), adlbr.capi.F32,
-                                                                  ctypes.byref(sz)))
-        tws = torch.empty(sz.value, dtype=torch.uint8, device=dev)
-        adlbr.capi.check(adlbr.capi.load().adlbr_operator_workspace(
-            ctypes.byref(g), adlbr.capi.F32, 0, ctypes.byref(sz)))
-        opws = torch.empty(sz.value, dtype=torch.uint8, device=dev)
-        ev = []
+    for _ in range(args.warmup):
+        period(False)
+    u.copy_(torch.from_numpy(u0).float().to(dev))
+    flags.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        period(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fl = int(flags[1].item())
+    if fl & ~adlbr.capi.ST_CLAMPED:
+        print(f"status error: flags {fl:#x}", file=sys.stderr)
+        sys.exit(1)
+    phase = np.zeros(4)
+    for e in ev:
+        for k in range(4):
+            phase[k] += e[k].elapsed_time(e[k + 1])
+    phase /= K
+    step_kernel_s = phase[3] / 1e3 / sub
+    abytes = ALGO_BYTES[(2, 4)] * N
+    achieved = abytes / step_kernel_s / 1e9
+    value = N * sub * K / wall / 1e6
+    res = {
+        "metric": "Mpoint-steps/s", "value": round(value, 2), "unit": "Mpoint-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(wall / K * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "ced2d-2048x2048-f32", "n": [n, n], "explicit_steps": K * sub,
+                   "rebuild_every": sub, "sigma": 1.0, "rho": 4.0, "alpha": 1e-4,
+                   "C": 1e-5, "dt": "0.9/max A_zz", "seed": 1302},
+        "phases_ms_per_period": {"structure_tensor": round(phase[0], 4),
+                                 "stencils": round(phase[1], 4),
+                                 "assembly": round(phase[2], 4),
+                                 "explicit_steps_x10": round(phase[3], 4)},
+        "roofline": {"bound": "hbm", "kernel": "k_apply (explicit step, 2D FP32)",
+                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for("c2"),
+                     "algo_bytes_per_point": ALGO_BYTES[(2, 4)],
+                     "avg_launch_us": round(step_kernel_s * 1e6, 3)},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_c2(u0, n)
+    print(json.dumps(res), flush=True)
 
-        def period(record):
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if record else None
-            if record:
-                e[0].record(stream)
-            adlbr.structure_tensor(u, dims, 1.0, 4.0, 1e-4, 1e-5, out=Dbuf, workspace=tws)
-            if record:
-                e[1].record(stream)
-            off, w, st = adlbr.build_stencils(Dbuf, dims, out=outs)
-            if record:
-                e[2].record(stream)
-            op = adlbr.Operator(dims, off, w, storage=torch.float32, workspace=opws)
-            if record:
-                e[3].record(stream)
-            op.step(u, 0.9, sub, cfl_fraction=True, u_tmp=tmp)
-            if record:
-                e[4].record(stream)
-                ev.append(e)
-            return op
 
-        for _ in range(args.warmup):
-            period(False)
-        u.copy_(torch.from_numpy(u0).float().to(dev))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(K):
-            op = period(True)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        st = outs[2].cpu().numpy()
-        ost = op.status.cpu().numpy()
-        if st[0] != -1 or ost[0] != -1:
-            print(f"status error: stencils {st.tolist()} operator {ost.tolist()}", file=sys.stderr)
-            sys.exit(1)
-        phase = np.zeros(4)
-        for e in ev:
-            for k in range(4):
-                phase[k] += e[k].elapsed_time(e[k + 1])
-        phase /= K
-        step_kernel_s = phase[3] / 1e3 / sub
-        abytes = ALGO_BYTES[(2, 4)] * N
-        achieved = abytes / step_kernel_s / 1e9
-        value = N * sub * K / wall / 1e6
-        res = {
-            "metric": "Mpoint-steps/s", "value": round(value, 2), "unit": "Mpoint-steps/s",
-            "n_gpus": 1, "steps": K, "warmup": args.warmup,
-            "ms_per_step": round(wall / K * 1e3, 4), "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "ced2d-2048x2048-f32", "n": [n, n], "explicit_steps": K * sub,
-                       "rebuild_every": sub, "sigma": 1.0, "rho": 4.0, "alpha": 1e-4,
-                       "C": 1e-5, "dt": "0.9/max A_zz", "seed": 1302},
-            "phases_ms_per_period": {"structure_tensor": round(phase[0], 4),
-                                     "stencils": round(phase[1], 4),
-                                     "assembly": round(phase[2], 4),
-                                     "explicit_steps_x10": round(phase[3], 4)},
-            "roofline": {"bound": "hbm", "kernel": "k_apply (explicit step, 2D FP32)",
-                         "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for("c2"),
-                         "algo_bytes_per_point": ALGO_BYTES[(2, 4)],
-                         "avg_launch_us": round(step_kernel_s * 1e6, 3)},
-        }
-        if not args.no_cpu_baseline:
-            res["cpu_baseline"] = cpu_baseline_c2(u0, n)
-        print(json.dumps(res), flush=True)
-        return
-
-    if args.workload == "copy":
-        return run_copy(args, dev, stream)
-    if args.workload == "c4":
-        return run_c4(args, dev, stream)
-    if args.workload == "c3-precision":
-        return run_precision(args, dev, stream)
-    if args.workload in ("c5", "c5-3d"):
-        run_c5(args, dev, stream)
-        return
-
-    # c1 / c3: fixed operator, explicit steps only
+def run_fixed(args, dev, stream):
+    """c1 / c3: a fixed operator, explicit steps only."""
+    import numpy as np
+    import torch
+    import paper_1301_3925_amd as adlbr
+    from paper_1301_3925_amd import synth
     if args.workload == "c1":
         dims, kappa, seed, sdt = (64, 64), 10.0, 1301, args.dtype or "f64"
         D = synth.tensor2d_field(seed, 64, 64, kappa)
@@ -291,7 +534,8 @@ def main():
                    "n": list(dims), "kappa": kappa, "explicit_steps": K, "seed": seed},
         "roofline": {"bound": "hbm", "kernel": f"k_apply (explicit step, {dim}D {sdt})",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for("c3") if (dim == 3 and sdt == "f32") else None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic_for("c3") if (dim == 3 and sdt == "f32") else None,
                      "algo_bytes_per_point": ALGO_BYTES[(dim, esz)],
                      "avg_launch_us": round(step_s * 1e6, 3)},
     }
@@ -310,8 +554,10 @@ def run_precision(args, dev, stream):
     explicit steps with u and the weights stored in FP64, FP32, BF16 and
     FP16 (arithmetic in FP64 for FP64 storage, FP32 otherwise; offsets and
     the stencil build always FP64).  Reports each variant's step rate and its
-    relative L2 difference to the FP64 run (the FP64 GPU path itself matches
-    the FP64 oracle to 1e-12 in the parity tests)."""
+    relative L2 difference to the FP64 run after 50, 100, 150 and 200 steps
+    (the FP64 GPU path itself matches the FP64 oracle to 1e-12 in the parity
+    tests, which also bound the variants' errors against the oracle on a
+    64^3 volume of the same recipe)."""
     import numpy as np
     import torch
     import paper_1301_3925_amd as adlbr
@@ -323,6 +569,7 @@ def run_precision(args, dev, stream):
     off, w, st = adlbr.build_stencils(torch.from_numpy(D).to(dev), dims)
     del D
     u0 = synth.uniform(seed + 1, N)
+    marks = [K // 4 * (j + 1) for j in range(4)]
     out, ref = {}, None
     for sdt, tdt in (("f64", torch.float64), ("f32", torch.float32), ("bf16", torch.bfloat16),
                      ("f16", torch.float16)):
@@ -338,15 +585,22 @@ def run_precision(args, dev, stream):
         e1.record(stream)
         torch.cuda.synchronize()
         step_s = e0.elapsed_time(e1) / 1e3 / K
-        res = u.double()
+        # errors at the marks: the same steps again, stopping at each mark
+        u.copy_(torch.from_numpy(u0).to(tdt).to(dev))
+        snaps, done = [], 0
+        for m in marks:
+            op.step(u, 0.9, m - done, cfl_fraction=True, u_tmp=tmp)
+            done = m
+            snaps.append(u.double().clone())
         if ref is None:
-            ref = res
-        err = float((res - ref).norm() / ref.norm())
+            ref = snaps
+        errs = [float((s - r).norm() / r.norm()) for s, r in zip(snaps, ref)]
         esz = torch.tensor([], dtype=tdt).element_size()
         out[sdt] = {"Mpoint_steps_per_s": round(N / step_s / 1e6, 1),
                     "us_per_step": round(step_s * 1e6, 1),
-                    "rel_l2_vs_f64": err,
+                    "rel_l2_vs_f64_at": dict(zip(map(str, marks), errs)),
                     "hbm_frac": round(ALGO_BYTES[(3, esz)] * N / step_s / 1e9 / PEAK_HBM_GBS, 4)}
+        log(f"{sdt}: {out[sdt]}")
         del op, u, tmp
         torch.cuda.empty_cache()
     print(json.dumps({
@@ -357,78 +611,6 @@ def run_precision(args, dev, stream):
         "config": {"workload": "explicit3d-256^3-precision-variants", "n": list(dims),
                    "kappa": kappa, "explicit_steps": K, "seed": seed},
         "precision": out}), flush=True)
-
-
-def run_c4(args, dev, stream):
-    """Uneven batch: 64 square images (sides 256..1536, kappa 1..50, smooth
-    orientation fields) and 8 cubic volumes (sides 64..192, needle / plate /
-    isotropic fields, kappa <= 50), each stepped 100 times at 0.9 x its own
-    CFL bound in FP32.  Timed: one replay of the captured graph of the whole
-    100-step batch (after autotuning and a warm-up run); beside it, the same
-    100 steps launched per problem (adlbr_step one problem after another)."""
-    import numpy as np
-    import torch
-    import paper_1301_3925_amd as adlbr
-    from paper_1301_3925_amd import synth
-    probs = synth.batch_problems(1304)
-    ops, us, u0s = [], [], []
-    for p in probs:
-        D = (synth.tensor2d_field(p["seed"], *p["n"], p["kappa"]) if p["dim"] == 2
-             else synth.tensor3d_field(p["seed"], p["n"], p["kappa"]))
-        off, w, st = adlbr.build_stencils(torch.from_numpy(D).float().to(dev), p["n"])
-        ops.append(adlbr.Operator(p["n"], off, w, storage=torch.float32))
-        N = int(np.prod(p["n"]))
-        u0 = torch.from_numpy(synth.uniform(p["seed"] + 7, N)).float().to(dev)
-        u0s.append(u0)
-        us.append(u0.clone())
-        del D, off, w
-    torch.cuda.synchronize()
-    nsteps = 100
-    K = args.steps if args.steps is not None else 3
-    b = adlbr.Batch(ops, us, dt=0.9, dt_mode="cfl")
-    variants = b.tune(steps=10)
-    for _ in range(max(1, args.warmup)):
-        b.run(nsteps)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(K):
-        b.run(nsteps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / K
-    gpu_ms = e0.elapsed_time(e1) / K
-    # per-problem launches of the same work
-    tmps = [torch.empty_like(u) for u in us]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for op, u, t in zip(ops, us, tmps):
-        op.step(u, 0.9, nsteps, cfl_fraction=True, u_tmp=t)
-    torch.cuda.synchronize()
-    seq = time.perf_counter() - t1
-    n2 = sum(int(np.prod(p["n"])) for p in probs if p["dim"] == 2)
-    n3 = sum(int(np.prod(p["n"])) for p in probs if p["dim"] == 3)
-    pts = n2 + n3
-    abytes = ALGO_BYTES[(2, 4)] * n2 + ALGO_BYTES[(3, 4)] * n3
-    step_s = gpu_ms / 1e3 / nsteps
-    achieved = abytes / step_s / 1e9
-    print(json.dumps({
-        "metric": "Mpoint-steps/s", "value": round(pts * nsteps / wall / 1e6, 2),
-        "unit": "Mpoint-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batch-64x2d-256..1536-8x3d-64..192-f32", "problems": len(probs),
-                   "points_2d": n2, "points_3d": n3, "explicit_steps": nsteps, "seed": 1304,
-                   "dt": "0.9/max A_zz per problem"},
-        "per_problem_launches": {"value": round(pts * nsteps / seq / 1e6, 2),
-                                 "unit": "Mpoint-steps/s", "seconds": round(seq, 4)},
-        "autotuned_variants": variants,
-        "roofline": {"bound": "hbm", "kernel": "k_apply_batch or k_apply (tuned batch step, FP32)",
-                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                     "algo_bytes": abytes, "avg_step_us": round(step_s * 1e6, 2)},
-    }), flush=True)
 
 
 def run_copy(args, dev, stream):
@@ -463,12 +645,17 @@ def run_copy(args, dev, stream):
           flush=True)
 
 
-def run_c5(args, dev, stream):
+def implicit_line(args, dev, three, train_steps):
+    """The implicit step (I + dt A) x = b, dt = 50 x the explicit CFL bound,
+    kappa = 200, FP32, x0 = 0, to a true relative residual of 1e-6: Jacobi-
+    PCG, flexible CG with the untrained network, and flexible CG with the
+    network trained first on the GPU on residuals of other right-hand sides
+    (seeds 2001-2016; training time reported separately).  Best of `reps`
+    timed solves after `warmup` untimed ones."""
     import numpy as np
     import torch
     import paper_1301_3925_amd as adlbr
     from paper_1301_3925_amd import synth
-    three = args.workload == "c5-3d"
     if three:
         dims = (128, 128, 128)
         D = synth.tensor3d_field(1305, dims, 200.0)
@@ -480,12 +667,12 @@ def run_c5(args, dev, stream):
     op = adlbr.Operator(dims, off, w, storage=torch.float32)
     dt = 50.0 * op.dt_cfl()
     b = torch.from_numpy(synth.uniform(1305, N)).float().to(dev)
-    reps = max(1, args.steps if args.steps is not None else 3)
+    reps = 3
+    warm = max(1, min(args.warmup, 2))
 
     def timed(method, net=None):
-        ws = None
         best = None
-        for _ in range(args.warmup + reps):
+        for _ in range(warm + reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             x, rep = op.solve(b, dt, method=method, net=net, tol=1e-6, check_every=10)
@@ -500,17 +687,16 @@ def run_c5(args, dev, stream):
     _, ru, tu = timed("fcg", untrained)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    net, hist = adlbr.train_net(op, dt, rhs_seeds=range(2001, 2017), steps=args.train_steps,
+    net, hist = adlbr.train_net(op, dt, rhs_seeds=range(2001, 2017), steps=train_steps,
                                 batch=4, lr=3e-3, seed=0, log_every=100,
                                 on_policy=not args.off_policy, refresh=args.refresh,
-                                log=lambda it, l: print(f"training step {it}: loss {l:.4f}",
-                                                        file=sys.stderr, flush=True))
+                                log=lambda it, l: log(f"training step {it}: loss {l:.4f}"))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     _, rt, tt = timed("fcg", net)
     res = {
         "metric": "time to 1e-6 relative residual", "value": round(tt * 1e3, 3), "unit": "ms",
-        "n_gpus": 1, "steps": reps, "warmup": args.warmup, "ms_per_step": round(tt * 1e3, 3),
+        "n_gpus": 1, "steps": reps, "warmup": warm, "ms_per_step": round(tt * 1e3, 3),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": ("implicit3d-128^3" if three else "implicit2d-1024x1024") +
@@ -521,12 +707,14 @@ def run_c5(args, dev, stream):
                           "fell_back": ru["fell_back"], "rel_res": ru["rel_res"]},
         "fcg_trained": {"iters": rt["iters"], "ms": round(tt * 1e3, 3),
                         "fell_back": rt["fell_back"], "rel_res": rt["rel_res"]},
-        "training": {"seconds": round(t_train, 2), "steps": args.train_steps, "batch": 4,
+        "training": {"seconds": round(t_train, 2), "steps": train_steps, "batch": 4,
                      "on_policy": not args.off_policy, "refresh": args.refresh,
                      "loss": hist},
         "speedup_vs_jacobi": round(tj / tt, 3),
     }
-    print(json.dumps(res), flush=True)
+    log(f"implicit {'3D' if three else '2D'}: jacobi {tj * 1e3:.2f} ms ({rj['iters']} it), "
+        f"fcg trained {tt * 1e3:.2f} ms ({rt['iters']} it)")
+    return res
 
 
 if __name__ == "__main__":

@@ -151,6 +151,14 @@ int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets,
                           int flags, void *workspace, size_t ws_bytes,
                           int32_t *status, void *stream, adlbr_operator **op);
 int adlbr_operator_destroy(adlbr_operator *op);
+/* Rebuild op in place from new stencils of the same grid (offsets and
+ * weights as for adlbr_operator_create; the storage dtype and flags stay):
+ * the stencils change when D does, e.g. every few steps of coherence-
+ * enhancing diffusion (Section 5).  The operator keeps its workspace and
+ * every device address in it, so batches and captured graphs that use op
+ * stay valid.  Asynchronous on `stream`; status as for create. */
+int adlbr_operator_rebuild(adlbr_operator *op, const int16_t *offsets, const void *weights,
+                           int w_dtype, int32_t *status, void *stream);
 
 /* Largest explicit-Euler step keeping I - dt A entrywise non-negative
  * (discrete maximum principle): 1 / max_z A_zz.  Host out; synchronizes. */

@@ -165,6 +165,21 @@ class Operator:
     def handle(self):
         return self._h
 
+    def rebuild(self, offsets, weights, stream=None, check: bool = False):
+        """Re-assemble in place from new stencils of the same grid
+        (adlbr_operator_rebuild): device addresses stay, so a Batch over
+        this operator stays valid.  Asynchronous unless check=True."""
+        _require_cuda(offsets, weights)
+        capi.check(capi.load().adlbr_operator_rebuild(
+            self._h, _ptr(offsets), _ptr(weights), _dtype_code(weights.dtype),
+            _ptr(self.status), _stream(stream)))
+        if check:
+            flags = status_flags(self.status)
+            bad = [msg for f, msg in _OP_ERRORS.items() if flags & f]
+            if bad:
+                raise AdlbrError(capi.E_RANGE, "operator_rebuild: " + "; ".join(bad))
+        return self
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             capi.load().adlbr_operator_destroy(self._h)

@@ -83,6 +83,7 @@ SIGNATURES = {
     "adlbr_operator_create": ([_GP, _P, _P, _I, _I, _I, _P, _SZ, _P, _P,
                                ctypes.POINTER(_P)], _I),
     "adlbr_operator_destroy": ([_P], _I),
+    "adlbr_operator_rebuild": ([_P, _P, _P, _I, _P, _P], _I),
     "adlbr_operator_dt_cfl": ([_P, ctypes.POINTER(_D), _P], _I),
     "adlbr_operator_diagonal": ([_P, _P, _I, _P], _I),
     "adlbr_apply": ([_P, _P, _P, _P], _I),

@@ -264,9 +264,9 @@ extern "C" int adlbr_batch_tune(adlbr_batch *b, int steps, int use_cache, void *
         return ADLBR_E_INVALID;
     }
     hipStream_t s = as_stream(stream);
-    hipEvent_t e0, e1;
-    ADLBR_CHECK_HIP(hipEventCreate(&e0));
-    ADLBR_CHECK_HIP(hipEventCreate(&e1));
+    EventPair ev;
+    ADLBR_CHECK_HIP(ev.create());
+    const hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
     int rc = ADLBR_OK;
     for (auto &c : b->classes) {
         const long long key = cache_key(c);
@@ -316,8 +316,6 @@ extern "C" int adlbr_batch_tune(adlbr_batch *b, int steps, int use_cache, void *
         std::lock_guard<std::mutex> lk(g_cache_mu);
         g_cache[key] = std::make_pair(best, best_budget);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     drop_graph(b);  // the variants are baked into a captured graph
     if (!rc) ADLBR_LAUNCH_CHECK();
     return rc;

@@ -38,6 +38,20 @@ void clear_error();
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Two timing events, destroyed on every exit path of the function that
+// holds them.
+struct EventPair {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    hipError_t create() {
+        hipError_t r = hipEventCreate(&e[0]);
+        return r == hipSuccess ? hipEventCreate(&e[1]) : r;
+    }
+    ~EventPair() {
+        for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
 // ------------------------------------------------------------------ grid --
 struct GridInfo {
     int dim;

@@ -2030,6 +2030,27 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
     return ADLBR_OK;
 }
 
+extern "C" int adlbr_operator_rebuild(adlbr_operator *op, const int16_t *offsets,
+                                      const void *weights, int w_dtype, int32_t *status,
+                                      void *stream) {
+    clear_error();
+    if (!op || !offsets || !weights || !status) {
+        set_error("adlbr_operator_rebuild: null pointer argument");
+        return ADLBR_E_INVALID;
+    }
+    if (w_dtype != ADLBR_F64 && w_dtype != ADLBR_F32) {
+        set_error("adlbr_operator_rebuild: weights must be F64/F32");
+        return ADLBR_E_INVALID;
+    }
+    hipStream_t s = as_stream(stream);
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(1), 0, s, status);
+    const int rc = dispatch<BuildF>(op, offsets, weights, (int)(w_dtype == ADLBR_F64), status, s);
+    hipLaunchKernelGGL(k_status_final, dim3(1), dim3(1), 0, s, status);
+    if (rc) return rc;
+    ADLBR_LAUNCH_CHECK();
+    return ADLBR_OK;
+}
+
 extern "C" int adlbr_operator_destroy(adlbr_operator *op) {
     delete op;
     return ADLBR_OK;

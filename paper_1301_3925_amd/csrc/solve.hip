@@ -281,16 +281,8 @@ int solve_impl(adlbr_operator *op, double dt, const T *b, T *x, const adlbr_solv
     const bool net = p->method == ADLBR_SOLVE_FCG_NET;
     CgState *cg = &st->cg;
 
-    // the two timing events are destroyed on every exit path
-    struct Events {
-        hipEvent_t e[2] = {nullptr, nullptr};
-        ~Events() {
-            for (hipEvent_t x : e)
-                if (x) (void)hipEventDestroy(x);
-        }
-    } ev;
-    ADLBR_CHECK_HIP(hipEventCreate(&ev.e[0]));
-    ADLBR_CHECK_HIP(hipEventCreate(&ev.e[1]));
+    EventPair ev;
+    ADLBR_CHECK_HIP(ev.create());
     const hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
     ADLBR_CHECK_HIP(hipEventRecord(e0, s));
     // clear the state, set dt

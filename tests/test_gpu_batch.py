@@ -121,3 +121,32 @@ def test_batch_rejects_bad_arguments(lib):
         lib.Batch(ops, us[:-1])
     with pytest.raises(Exception):
         lib.Batch(ops[:1], us[:1], tmps=us[:1])  # u aliased with its scratch
+
+
+def test_rebuild_in_place_keeps_the_batch_graph_valid(lib):
+    """adlbr_operator_rebuild re-assembles an operator from new stencils
+    into the same workspace: a batch whose graph was captured before the
+    rebuild steps the new operators, bit-identical to operators created
+    from scratch on the new stencils (2D and 3D, FP32)."""
+    import torch
+    ops, us = _problems(lib, torch.float32)
+    b = lib.Batch(ops, us, dt=0.9, dt_mode="cfl")
+    b.run(4)  # captures the graph for 4 steps
+    torch.cuda.synchronize()
+    fresh = []
+    for k, op in enumerate(ops):
+        dims = op.dims
+        D = (synth.tensor2d_field(300 + k, *dims, 40.0) if len(dims) == 2
+             else synth.tensor3d_field(300 + k, dims, 40.0))
+        off, w, _ = lib.build_stencils(torch.from_numpy(D).cuda(), dims)
+        op.rebuild(off, w, check=True)
+        fresh.append(lib.Operator(dims, off, w, storage=torch.float32))
+    ref = [u.clone() for u in us]
+    for op, u in zip(fresh, ref):
+        op.step(u, 0.9, 4, cfl_fraction=True)
+    b.run(4)  # the same graph, replayed
+    torch.cuda.synchronize()
+    for k, (u, r) in enumerate(zip(us, ref)):
+        assert torch.equal(u, r), k
+    for op, f in zip(ops, fresh):
+        assert op.dt_cfl() == f.dt_cfl()
