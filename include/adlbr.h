@@ -257,6 +257,19 @@ int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
                            const adlbr_tensor_params *p, void *D,
                            void *workspace, size_t ws_bytes, void *stream);
 
+/* adlbr_structure_tensor without a workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc).  The scratch is a device array
+ * of 128 MiB that the library holds on every GPU it runs on until the
+ * process ends; the call itself allocates nothing.  Same arguments and
+ * results as adlbr_structure_tensor (bit-identical output); ADLBR_E_NOMEM
+ * when adlbr_tensor_workspace() for this grid and dtype exceeds 128 MiB
+ * (e.g. 2D FP32 up to 5.59e6 points, 3D FP32 up to 2.79e6).  All calls on
+ * one GPU share that array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be serialized by the caller. */
+int adlbr_structure_tensor_noalloc(const adlbr_grid *g, const void *u, int dtype,
+                                   const adlbr_tensor_params *p, void *D, void *stream);
+
 /* ------------------------------------------------------------------ *
  * Implicit step: solve K x = b with K = I + dt A by conjugate gradients.
  * This is the linear system of the restoration problem

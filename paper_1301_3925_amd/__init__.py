@@ -352,6 +352,25 @@ def structure_tensor(u, dims, sigma: float, rho: float, alpha: float, C: float,
     return out
 
 
+def structure_tensor_noalloc(u, dims, sigma: float, rho: float, alpha: float, C: float,
+                             eig_map: str = "ced", out=None, stream=None):
+    """adlbr_structure_tensor_noalloc: the same tensor with the library's
+    static device scratch instead of a workspace (nothing is allocated when
+    `out` is given).  Calls that overlap on one GPU race."""
+    torch = _torch()
+    lib = capi.load()
+    _require_cuda(u)
+    dims = tuple(int(d) for d in dims)
+    g = grid(dims)
+    nj = 3 if len(dims) == 2 else 6
+    out = torch.empty((nj, u.numel()), dtype=u.dtype, device=u.device) if out is None else out
+    p = capi.TensorParams(float(sigma), float(rho), float(alpha), float(C),
+                          capi.MAP_CED if eig_map == "ced" else capi.MAP_EED)
+    capi.check(lib.adlbr_structure_tensor_noalloc(ctypes.byref(g), _ptr(u), _dtype_code(u.dtype),
+                                                  ctypes.byref(p), _ptr(out), _stream(stream)))
+    return out
+
+
 class Net:
     """Learned preconditioner z = r / diag(K) + N(r) of an FP32 operator
     (adlbr_net_*).  Holds the parameters and the per-operator buffers."""

@@ -101,6 +101,7 @@ SIGNATURES = {
     "adlbr_solve": ([_P, _D, _P, _P, ctypes.POINTER(SolveParams), _P, _SZ,
                      ctypes.POINTER(SolveReport), _P], _I),
     "adlbr_structure_tensor": ([_GP, _P, _I, ctypes.POINTER(TensorParams), _P, _P, _SZ, _P], _I),
+    "adlbr_structure_tensor_noalloc": ([_GP, _P, _I, ctypes.POINTER(TensorParams), _P, _P], _I),
     "adlbr_net_param_count": ([_I, _I, _I, ctypes.POINTER(_SZ)], _I),
     "adlbr_net_features": ([_P, _D, _P, _P], _I),
     "adlbr_net_gates": ([_P, _P, _P], _I),

@@ -7,7 +7,16 @@
 // central differences, then a per-point eigen map.  All passes stream the
 // planes through HBM with coalesced x-fastest accesses; the Gaussian taps
 // (truncated at ceil(3 s), normalized) are computed on the host in FP64.
+#include <mutex>
+
 #include "common.h"
+
+// Scratch of adlbr_structure_tensor_noalloc: the two working halves that
+// adlbr_structure_tensor takes from its workspace, in device memory the
+// library holds from load to process exit (one copy per GPU).  Host code
+// uses only the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace adlbr {
 namespace {
@@ -475,39 +484,106 @@ extern "C" int adlbr_tensor_workspace(const adlbr_grid *g, int dtype, size_t *by
     return ADLBR_OK;
 }
 
-extern "C" int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
-                                      const adlbr_tensor_params *p, void *D, void *workspace,
-                                      size_t ws_bytes, void *stream) {
-    clear_error();
-    GridInfo gi;
-    int rc = check_grid(g, &gi);
+namespace {
+// Arguments shared by both tensor entry points; on success gi is the grid
+// and need the scratch bytes (two halves of `half` bytes).
+int tensor_args(const char *who, const adlbr_grid *g, const void *u, int dtype,
+                const adlbr_tensor_params *p, const void *D, GridInfo *gi, size_t *half) {
+    int rc = check_grid(g, gi);
     if (rc) return rc;
-    if (!u || !p || !D || !workspace) {
-        set_error("adlbr_structure_tensor: null pointer argument");
+    if (!u || !p || !D) {
+        set_error("%s: null pointer argument", who);
         return ADLBR_E_INVALID;
     }
     if (dtype != ADLBR_F32 && dtype != ADLBR_F64) {
-        set_error("adlbr_structure_tensor: dtype must be ADLBR_F32 or ADLBR_F64");
+        set_error("%s: dtype must be ADLBR_F32 or ADLBR_F64", who);
         return ADLBR_E_INVALID;
     }
     if (!(p->sigma > 0.0) || !(p->rho > 0.0) || p->sigma > 10.0 || p->rho > 10.0 ||
         !(p->alpha > 0.0) || !(p->alpha <= 1.0) || !(p->C >= 0.0) ||
         (p->eig_map != ADLBR_MAP_CED && p->eig_map != ADLBR_MAP_EED)) {
-        set_error("adlbr_structure_tensor: need 0 < sigma, rho <= 10, 0 < alpha <= 1, C >= 0");
+        set_error("%s: need 0 < sigma, rho <= 10, 0 < alpha <= 1, C >= 0", who);
         return ADLBR_E_INVALID;
     }
-    size_t need;
-    adlbr_tensor_workspace(g, dtype, &need);
-    if (ws_bytes < need) {
-        set_error("adlbr_structure_tensor: workspace has %zu bytes, %zu needed", ws_bytes, need);
-        return ADLBR_E_NOMEM;
-    }
-    const int nj = gi.dim == 2 ? 3 : 6;
-    const size_t half = align_up(dtype_size(dtype) * nj * (size_t)gi.N);
-    char *b = (char *)workspace;
-    hipStream_t s = as_stream(stream);
+    const int nj = gi->dim == 2 ? 3 : 6;
+    *half = align_up(dtype_size(dtype) * nj * (size_t)gi->N);
+    return ADLBR_OK;
+}
+
+int tensor_run(const GridInfo &gi, const void *u, int dtype, const adlbr_tensor_params *p,
+               void *D, char *b, size_t half, hipStream_t s) {
     if (dtype == ADLBR_F32)
-        return run_tensor<float>(gi, (const float *)u, p, (float *)D, (float *)b, (float *)(b + half), s);
+        return run_tensor<float>(gi, (const float *)u, p, (float *)D, (float *)b,
+                                 (float *)(b + half), s);
     return run_tensor<double>(gi, (const double *)u, p, (double *)D, (double *)b,
                               (double *)(b + half), s);
+}
+
+// Device address of `scratch` on each GPU, looked up once per device with
+// that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(char **out) {
+    int dev = -1;
+    ADLBR_CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("adlbr_structure_tensor_noalloc: device %d beyond the supported %d", dev,
+                  kMaxDevices);
+        return ADLBR_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("adlbr_structure_tensor_noalloc: hipGetSymbolAddress failed: %s",
+                      hipGetErrorString(e));
+            return ADLBR_E_HIP;
+        }
+        g_scratch_ptr[dev] = (char *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return ADLBR_OK;
+}
+}  // namespace
+
+extern "C" int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
+                                      const adlbr_tensor_params *p, void *D, void *workspace,
+                                      size_t ws_bytes, void *stream) {
+    clear_error();
+    GridInfo gi;
+    size_t half = 0;
+    int rc = tensor_args("adlbr_structure_tensor", g, u, dtype, p, D, &gi, &half);
+    if (rc) return rc;
+    if (!workspace) {
+        set_error("adlbr_structure_tensor: null workspace");
+        return ADLBR_E_INVALID;
+    }
+    if (ws_bytes < 2 * half) {
+        set_error("adlbr_structure_tensor: workspace has %zu bytes, %zu needed", ws_bytes,
+                  2 * half);
+        return ADLBR_E_NOMEM;
+    }
+    return tensor_run(gi, u, dtype, p, D, (char *)workspace, half, as_stream(stream));
+}
+
+extern "C" int adlbr_structure_tensor_noalloc(const adlbr_grid *g, const void *u, int dtype,
+                                              const adlbr_tensor_params *p, void *D,
+                                              void *stream) {
+    clear_error();
+    GridInfo gi;
+    size_t half = 0;
+    int rc = tensor_args("adlbr_structure_tensor_noalloc", g, u, dtype, p, D, &gi, &half);
+    if (rc) return rc;
+    if (2 * half > kNoAllocScratchBytes) {
+        set_error("adlbr_structure_tensor_noalloc: needs %zu bytes of scratch, the static "
+                  "scratch holds %zu", 2 * half, kNoAllocScratchBytes);
+        return ADLBR_E_NOMEM;
+    }
+    char *b = nullptr;
+    rc = scratch_address(&b);
+    if (rc) return rc;
+    return tensor_run(gi, u, dtype, p, D, b, half, as_stream(stream));
 }
