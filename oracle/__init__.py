@@ -229,3 +229,39 @@ def structure_tensor_d(u, dims, sigma, rho, alpha, C, eig_map: int = CED):
     _load().or_structure_tensor_d(dim, _p(nd), _p(u), float(sigma), float(rho),
                                   float(alpha), float(C), int(eig_map), _p(D))
     return D
+
+
+# ------------------------------------------------------------ restoration --
+
+def restoration_exact(n: int, kappa: float, lam: float, alpha: float = 1.0 / 3.0):
+    """Exact solution of the restoration test (Section 5, eq. (elliptic),
+    -lambda div(D grad u) + u = v on the whole plane) at the n x n cell
+    centres of the unit square: u = u0 o f with f(x, y) = (x, y +
+    alpha cos(2 pi x)), where u0 solves the one-dimensional problem
+    -lambda kappa^-2 u0'' + u0 = 1_{y < 1/2}:
+        u0(y) = 1 - exp(-(1/2 - y)/l) / 2   (y < 1/2)
+        u0(y) = exp(-(y - 1/2)/l) / 2       (y >= 1/2),   l = sqrt(lambda)/kappa.
+    (The paper states the Fourier multiplier 1/(1 + <xi, D0 xi>) without
+    the factors lambda and 4 pi^2; the elliptic equation fixes them.)"""
+    c = (np.arange(n, dtype=np.float64) + 0.5) / n
+    return restoration_exact_at(np.tile(c, n), np.repeat(c, n), kappa, lam, alpha)
+
+
+def restoration_exact_at(x, y, kappa: float, lam: float, alpha: float = 1.0 / 3.0):
+    """restoration_exact at arbitrary points (x, y) of the plane."""
+    t = np.asarray(y, dtype=np.float64) + alpha * np.cos(2.0 * np.pi * np.asarray(x))
+    ell = np.sqrt(lam) / kappa
+    return np.where(t < 0.5, 1.0 - 0.5 * np.exp(-np.abs(0.5 - t) / ell),
+                    0.5 * np.exp(-np.abs(t - 0.5) / ell))
+
+
+def restoration_errors(u_h, u, n: int):
+    """Relative errors of a discrete solution against the exact one: the
+    L2 norm over the grid points, and the H1 semi-norm with forward
+    differences along x and y (the measures of the restoration test)."""
+    e = (np.asarray(u_h, dtype=np.float64) - u).reshape(n, n)
+    U = np.asarray(u, dtype=np.float64).reshape(n, n)
+    l2 = np.linalg.norm(e) / np.linalg.norm(U)
+    ge = np.concatenate([np.diff(e, axis=0).ravel(), np.diff(e, axis=1).ravel()])
+    gu = np.concatenate([np.diff(U, axis=0).ravel(), np.diff(U, axis=1).ravel()])
+    return float(l2), float(np.linalg.norm(ge) / np.linalg.norm(gu))

@@ -23,6 +23,7 @@ __all__ = [
     "smooth_field", "tensor2d_from_angle", "tensor2d_const", "tensor2d_field",
     "tensor3d_from_rotvec", "tensor3d_field", "uniform", "ced_image2d",
     "ced_image3d", "batch_problems", "random_spd2", "random_spd3", "overflow_field3d",
+    "restoration_problem",
 ]
 
 
@@ -243,3 +244,24 @@ def overflow_field3d():
             M = np.outer(vh, vh) + 1e-3 * np.eye(3)
         D[:, i] = [M[0, 0], M[0, 1], M[0, 2], M[1, 1], M[1, 2], M[2, 2]]
     return n, D, int(c[0] + n[0] * (c[1] + n[1] * c[2]))
+
+
+def restoration_problem(n: int, kappa: float, alpha: float = 1.0 / 3.0, sub: int = 32):
+    """Inputs of the restoration experiment on the unit square, n x n pixels
+    with centres z = ((i + 1/2)/n, (j + 1/2)/n): the tensor
+    D = [[1, s], [s, s^2 + kappa^-2]], s = 2 pi alpha sin(2 pi x), at the
+    centres, and the image v = v0 o f with v0 = 1_{y < 1/2} and
+    f(x, y) = (x, y + alpha cos(2 pi x)), averaged over each pixel (the
+    area fraction below the stripe's edge y = 1/2 - alpha cos(2 pi x),
+    exact in y, `sub` samples per pixel in x).
+    Returns (D (3, n*n), v (n*n,)) in the library's layout."""
+    c = (np.arange(n, dtype=np.float64) + 0.5) / n
+    x = np.tile(c, n)
+    s = 2.0 * math.pi * alpha * np.sin(2.0 * math.pi * x)
+    D = np.stack([np.ones_like(x), s, s * s + kappa ** -2.0])
+    xs = (np.arange(n * sub, dtype=np.float64) + 0.5) / (n * sub)
+    edge = 0.5 - alpha * np.cos(2.0 * math.pi * xs)
+    lo = np.arange(n, dtype=np.float64) / n
+    frac = np.clip((edge[None, :] - lo[:, None]) * n, 0.0, 1.0)
+    v = frac.reshape(n, n, sub).mean(axis=2).reshape(-1)
+    return D, v
