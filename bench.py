@@ -100,6 +100,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-implicit", action="store_true",
                     help="c4: leave out the implicit-step comparison")
+    ap.add_argument("--layout", default="tiled", choices=["tiled", "lists"],
+                    help="operator layout for explicit steps (FP64 storage always uses lists)")
     ap.add_argument("--workers", type=int, default=None,
                     help="host worker processes (default min(16, cpu count))")
     args = ap.parse_args()
@@ -291,7 +293,8 @@ def run_c4(args, dev, stream, probs, fields, cpu):
                torch.empty((S, N), dtype=torch.float32, device=dev),
                torch.empty(2, dtype=torch.int32, device=dev))
         adlbr.build_stencils(Dg, p["n"], out=out)
-        ops.append(adlbr.Operator(p["n"], out[0], out[1], storage=torch.float32))
+        ops.append(adlbr.Operator(p["n"], out[0], out[1], storage=torch.float32,
+                                  tiled=args.layout == "tiled"))
         us.append(torch.from_numpy(synth_u0(p, N)).float().to(dev))
         Ds.append(Dg)
         outs.append(out)
@@ -357,6 +360,7 @@ def run_c4(args, dev, stream, probs, fields, cpu):
         "config": {"workload": "batch-64x2d-256..1536-8x3d-64..192-f32",
                    "problems": len(probs), "points_2d": n2, "points_3d": n3,
                    "explicit_steps_per_pass": nsteps, "seed": 1304, "kappa": "U[1,50] (2D), <=50 (3D)",
+                   "layout": args.layout,
                    "dt": "0.9/max A_zz per problem",
                    "pass": "stencils + assembly of all problems, then 100 explicit steps of "
                            "every problem in one graph replay"},
@@ -366,7 +370,9 @@ def run_c4(args, dev, stream, probs, fields, cpu):
                                  "unit": "Mpoint-steps/s", "seconds": round(seq, 4),
                                  "what": "the 100 steps alone, adlbr_step per problem"},
         "autotuned_variants": variants,
-        "roofline": {"bound": "hbm", "kernel": "k_apply_batch (batched explicit step, FP32)",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_apply_tiled_batch" if args.layout == "tiled" else "k_apply_batch") +
+                               " (batched explicit step, FP32)",
                      "unit_of_work": "one explicit step of every problem "
                                      f"({launches} launches)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -411,7 +417,8 @@ def run_c2(args, dev, stream):
             torch.empty(2, dtype=torch.int32, device=dev))
     adlbr.structure_tensor(u, dims, 1.0, 4.0, 1e-4, 1e-5, out=Dbuf)
     adlbr.build_stencils(Dbuf, dims, out=outs)
-    op = adlbr.Operator(dims, outs[0], outs[1], storage=torch.float32)
+    op = adlbr.Operator(dims, outs[0], outs[1], storage=torch.float32,
+                        tiled=args.layout == "tiled")
     import ctypes
     sz = ctypes.c_size_t()
     g = adlbr.grid(dims)
@@ -470,12 +477,14 @@ def run_c2(args, dev, stream):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "ced2d-2048x2048-f32", "n": [n, n], "explicit_steps": K * sub,
                    "rebuild_every": sub, "sigma": 1.0, "rho": 4.0, "alpha": 1e-4,
-                   "C": 1e-5, "dt": "0.9/max A_zz", "seed": 1302},
+                   "C": 1e-5, "dt": "0.9/max A_zz", "seed": 1302, "layout": args.layout},
         "phases_ms_per_period": {"structure_tensor": round(phase[0], 4),
                                  "stencils": round(phase[1], 4),
                                  "assembly": round(phase[2], 4),
                                  "explicit_steps_x10": round(phase[3], 4)},
-        "roofline": {"bound": "hbm", "kernel": "k_apply (explicit step, 2D FP32)",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_apply_tiled" if args.layout == "tiled" else "k_apply") +
+                               " (explicit step, 2D FP32)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for("c2"),
                      "algo_bytes_per_point": ALGO_BYTES[(2, 4)],
@@ -506,7 +515,8 @@ def run_fixed(args, dev, stream):
     dim = len(dims)
     Dg = torch.from_numpy(D).to(dev)
     off, w, st = adlbr.build_stencils(Dg, dims)
-    op = adlbr.Operator(dims, off, w, storage=tdt)
+    layout = "lists" if sdt == "f64" else args.layout
+    op = adlbr.Operator(dims, off, w, storage=tdt, tiled=layout == "tiled")
     u0 = synth.uniform(seed + 1, N)
     u = torch.from_numpy(u0).to(tdt).to(dev)
     tmp = torch.empty_like(u)
@@ -531,8 +541,9 @@ def run_fixed(args, dev, stream):
         "ms_per_step": round(wall / K * 1e3, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": sdt, "data": "synthetic",
         "config": {"workload": ("explicit2d-64x64" if dim == 2 else "explicit3d-256^3") + "-" + sdt,
-                   "n": list(dims), "kappa": kappa, "explicit_steps": K, "seed": seed},
-        "roofline": {"bound": "hbm", "kernel": f"k_apply (explicit step, {dim}D {sdt})",
+                   "n": list(dims), "kappa": kappa, "explicit_steps": K, "seed": seed,
+                   "layout": layout},
+        "roofline": {"bound": "hbm", "kernel": f"{'k_apply_tiled' if layout == 'tiled' else 'k_apply'} (explicit step, {dim}D {sdt})",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic_for("c3") if (dim == 3 and sdt == "f32") else None,
@@ -573,7 +584,8 @@ def run_precision(args, dev, stream):
     out, ref = {}, None
     for sdt, tdt in (("f64", torch.float64), ("f32", torch.float32), ("bf16", torch.bfloat16),
                      ("f16", torch.float16)):
-        op = adlbr.Operator(dims, off, w, storage=tdt)
+        layout = "lists" if sdt == "f64" else args.layout
+        op = adlbr.Operator(dims, off, w, storage=tdt, tiled=layout == "tiled")
         u = torch.from_numpy(u0).to(tdt).to(dev)
         tmp = torch.empty_like(u)
         op.step(u, 0.9, 1, cfl_fraction=True, u_tmp=tmp)  # warm-up
@@ -596,7 +608,7 @@ def run_precision(args, dev, stream):
             ref = snaps
         errs = [float((s - r).norm() / r.norm()) for s, r in zip(snaps, ref)]
         esz = torch.tensor([], dtype=tdt).element_size()
-        out[sdt] = {"Mpoint_steps_per_s": round(N / step_s / 1e6, 1),
+        out[sdt] = {"layout": layout, "Mpoint_steps_per_s": round(N / step_s / 1e6, 1),
                     "us_per_step": round(step_s * 1e6, 1),
                     "rel_l2_vs_f64_at": dict(zip(map(str, marks), errs)),
                     "hbm_frac": round(ALGO_BYTES[(3, esz)] * N / step_s / 1e9 / PEAK_HBM_GBS, 4)}

@@ -143,6 +143,15 @@ int adlbr_build_stencils(const adlbr_grid *g, const void *D, int D_dtype,
  *   op                host out, the new plan; free with adlbr_operator_destroy
  * ------------------------------------------------------------------ */
 #define ADLBR_OP_WIDE 1
+/* Tiled layout (Neumann grids, storage F32, BF16 or F16): the explicit step
+ * stages u over a tile of targets and its halo h in LDS; edges whose offset
+ * components are all within h (h = the operator's largest offset
+ * component, capped at 8 in 2D and 2 in 3D) are found from the staged
+ * sources instead of being listed, and only the longer edges keep incoming
+ * lists.  Apply, step, batches, dt_cfl and the diagonal work as with the
+ * list layout (results equal to rounding; each layout is deterministic);
+ * adlbr_solve and the residual need the list layout (ADLBR_E_UNSUPPORTED). */
+#define ADLBR_OP_TILED 2
 
 int adlbr_operator_workspace(const adlbr_grid *g, int storage, int flags,
                              size_t *bytes);
@@ -220,7 +229,7 @@ int adlbr_batch_tune(adlbr_batch *batch, int steps, int use_cache, void *stream)
 int adlbr_batch_set_variant(adlbr_batch *batch, int cls, int variant, size_t chunk_bytes,
                             void *stream);
 /* Class cls (0-based, in order of first appearance): its class key
- * (dim*1000 + wide*100 + periodic*10 + storage), launch variant, number of
+ * (tiled*10000 + dim*1000 + wide*100 + periodic*10 + storage), launch variant, number of
  * problems and, where the pointers are not NULL, number of chunks and chunk
  * budget in bytes.  ADLBR_E_INVALID past the last class. */
 int adlbr_batch_variant(const adlbr_batch *batch, int cls, int *key, int *variant, int *nprob,

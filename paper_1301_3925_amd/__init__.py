@@ -108,6 +108,10 @@ def status_flags(status) -> int:
 class Operator:
     """The assembled operator A = 1/2 grad E_h (adlbr_operator_create).
 
+    tiled=True asks for the tiled layout (ADLBR_OP_TILED: explicit steps
+    with tile + halo staged in LDS, near edges unlisted; Neumann grids,
+    F32/BF16/F16 storage; not for solve).
+
     Holds its device workspace (a torch uint8 tensor) for its lifetime.
     With check=True (the default) the constructor synchronizes and raises
     AdlbrError when the device status word reports a bad operator (an
@@ -117,8 +121,10 @@ class Operator:
     check=False the caller reads self.status itself."""
 
     def __init__(self, dims, offsets, weights, storage=None, periodic: bool = False,
-                 wide=None, stream=None, workspace=None, check: bool = True):
+                 wide=None, stream=None, workspace=None, check: bool = True,
+                 tiled: bool = False):
         self._h = ctypes.c_void_p()
+        self.tiled = bool(tiled)
         self._create(dims, offsets, weights, storage, periodic, bool(wide), stream, workspace)
         if not check:
             return
@@ -144,7 +150,7 @@ class Operator:
         self.device = weights.device
         self.wide = wide
         self._grid = grid(self.dims, periodic)
-        flags = capi.OP_WIDE if wide else 0
+        flags = (capi.OP_WIDE if wide else 0) | (capi.OP_TILED if self.tiled else 0)
         nbytes = ctypes.c_size_t()
         capi.check(lib.adlbr_operator_workspace(ctypes.byref(self._grid),
                                                 _dtype_code(self.storage), flags,

@@ -19,6 +19,7 @@ ST_NOT_SPD, ST_RANGE, ST_ITER, ST_CLAMPED, ST_STENCIL, ST_INCOMING = 1, 2, 4, 8,
 F64, F32, BF16, F16 = 0, 1, 2, 3
 NEUMANN, PERIODIC = 0, 1
 OP_WIDE = 1
+OP_TILED = 2
 DT_ABS, DT_CFL = 0, 1
 MAP_CED, MAP_EED = 0, 1
 

@@ -90,7 +90,7 @@ int upload(adlbr_batch::Class &c, int variant, size_t budget, hipStream_t s) {
         }
         BatchProb p = c.host[i];
         p.first_block = fb;
-        fb += (p.g.N + kApplyPoints - 1) / kApplyPoints;
+        fb += p.nblocks;
         used += c.bytes[i];
         d.push_back(p);
         c.chunks.back().count++;
@@ -175,7 +175,8 @@ extern "C" int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *c
             set_error("adlbr_batch_create: problem %d: null or aliased buffer, or dt < 0", i);
             return ADLBR_E_INVALID;
         }
-        if ((operator_grid(ops[i]).N + kApplyPoints - 1) / kApplyPoints >= (1ll << 31)) {
+        int bp = 0;
+        if (batch_blocks(ops[i], &bp) >= (1ll << 31)) {
             set_error("adlbr_batch_create: problem %d too large", i);
             return ADLBR_E_RANGE;
         }
@@ -221,7 +222,7 @@ extern "C" int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *c
     for (auto &c : b->classes) {
         c.dev = (BatchProb *)(base + o);
         o += sizeof(BatchProb) * c.host.size();
-        for (const BatchProb &p : c.host) total_blocks += (p.g.N + kApplyPoints - 1) / kApplyPoints;
+        for (const BatchProb &p : c.host) total_blocks += p.nblocks;
     }
     if (total_blocks >= (1ll << 31)) {
         delete b;

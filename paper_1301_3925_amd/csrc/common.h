@@ -232,8 +232,10 @@ constexpr int kApplyPPT = 1;
 constexpr int kApplyPoints = 256 * kApplyPPT;
 
 // Device descriptor of one problem of a batch (one operator and its two
-// state buffers); first_block is the problem's first 256-point block in
-// the batch's grid (blocks of kApplyPoints rows).
+// state buffers); first_block is the problem's first block in the batch's
+// grid, nblocks its number of blocks and block_points the points a block
+// covers in linear order (kApplyPoints rows for the list layout, one tile
+// for the tiled layout).
 struct BatchProb {
     GridInfo g;
     const void *sb;
@@ -246,9 +248,14 @@ struct BatchProb {
     void *u[2];
     double dt;
     int32_t dt_mode;
-    int32_t pad;
+    int32_t block_points;
     long long first_block;
+    long long nblocks;
+    const int32_t *hnear;    // tiled layout: halo of the near edges
+    const double *maxdiag;   // tiled layout: max A_zz (fixed-point scale)
 };
+// Blocks of one explicit step of op, and the points each covers.
+long long batch_blocks(const adlbr_operator *op, int *block_points);
 // Class of an operator for batching (dim, offset width, boundary, storage):
 // problems of one class share a kernel instance.
 int batch_class(const adlbr_operator *op);
@@ -367,5 +374,6 @@ const void *operator_diag(const adlbr_operator *op);
 const void *operator_weights(const adlbr_operator *op);
 const void *operator_slots(const adlbr_operator *op);
 int operator_wide(const adlbr_operator *op);
+int operator_tiled(const adlbr_operator *op);
 
 }  // namespace adlbr

@@ -35,6 +35,7 @@ struct adlbr_operator {
     int slots;    // 3 or 6
     int storage;  // adlbr_dtype
     int wide;     // int16 compact offsets
+    int tiled;    // tiled layout: near edges from LDS tiles, far edges listed
     void *sb;
     void *w;
     uint8_t *cnt;
@@ -45,6 +46,9 @@ struct adlbr_operator {
     double *maxdiag;
     double *dtcfl;
     int32_t *rmax;     // 2D: largest tile reach
+    int32_t *hnear;    // edges with every offset component <= hnear are not listed (tiled)
+    double *wmax;      // largest weight (tiled: scale of the diagonal pass)
+    double *rpart;     // per-block reach partials (tiled)
     uint8_t *mask;     // bit q: slot q has a positive weight
     double *part;      // per-block partials of the assembly
     int32_t *trmax;    // 2D: reach of every 64 x 64 tile
@@ -240,9 +244,12 @@ constexpr int kBin = 1 << kBinShift;
 // k-th candidate edge or -1.
 template <int DIM, bool PER>
 __device__ __forceinline__ long long edge_k(const Coord &p, long long z, const int s[6][3],
-                                           const double *wq, int k, const GridInfo &g) {
+                                           const double *wq, int k, const GridInfo &g,
+                                           int hnear = 0) {
     const int q = k >> 1, sg = (k & 1) ? 1 : -1;
     if (!(wq[q] > 0.0)) return -1;
+    if (hnear > 0 && max(max(abs(s[q][0]), abs(s[q][1])), abs(s[q][2])) <= hnear)
+        return -1;  // a near edge of the tiled layout: not listed
     long long t;
     if (!edge_target<DIM, PER>(p, z, s[q], sg, g, t)) return -1;
     // entries store z - t in 23 bits; such an edge is flagged and left out
@@ -272,14 +279,13 @@ __device__ __forceinline__ unsigned bin_append(int bin, uint32_t *counter, bool 
     return slot;
 }
 
-// Pack the slots, convert the weights, record which slots carry a positive
-// weight (mask bit q) and, for the binned assembly (BINS), count the edges
-// landing in each bin.
-template <int DIM, bool WIDE, bool PER, typename TWin, typename TS, typename TA, bool BINS>
+// Pack the slots, convert the weights and record which slots carry a
+// positive weight (mask bit q).
+template <int DIM, bool WIDE, bool PER, typename TWin, typename TS, typename TA>
 __global__ __launch_bounds__(256) void k_compact(
     GridInfo g, const int16_t *__restrict__ off, const TWin *__restrict__ win,
     typename Slots<DIM, WIDE>::store_t *__restrict__ sb, TS *__restrict__ w,
-    uint8_t *__restrict__ mask, uint32_t *__restrict__ bincnt, int32_t *status) {
+    uint8_t *__restrict__ mask, int32_t *status) {
     const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = z < g.N;  // every lane takes part in the ballots
     constexpr int S = DIM == 2 ? 3 : 6;
@@ -318,12 +324,51 @@ __global__ __launch_bounds__(256) void k_compact(
         }
         mask[z] = (uint8_t)m;
     }
-    for (int k = 0; k < 2 * S; ++k) {
-        const long long t = live ? edge_k<DIM, PER>(p, z, s, wq, k, g) : -1;
-        if (t == -2) st |= ADLBR_ST_RANGE;
-        if (BINS) bin_append(t >= 0 ? (int)(t >> kBinShift) : -1, bincnt, true);
-    }
+    for (int k = 0; k < 2 * S; ++k)
+        if (live && edge_k<DIM, PER>(p, z, s, wq, k, g) == -2) st |= ADLBR_ST_RANGE;
     if (live) report(status, z, st);
+}
+
+// The listed edges of point z, k = 2q + (sign > 0) in order: f(k, target)
+// with target -1 for an edge that is not listed (zero weight, leaves a
+// Neumann grid, beyond the 22-bit entry range, or near in the tiled layout).
+template <int DIM, bool WIDE, bool PER, typename F>
+__device__ __forceinline__ void listed_edges(const GridInfo &g, long long z, bool live,
+                                             const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                                             const uint8_t *__restrict__ mask, int hnear, F f) {
+    constexpr int S = DIM == 2 ? 3 : 6;
+    int s[6][3];
+    double wq[6];
+    for (int q = 0; q < 6; ++q) {
+        wq[q] = 0.0;
+        for (int c = 0; c < 3; ++c) s[q][c] = 0;
+    }
+    Coord p{0, 0, 0};
+    if (live) {
+        Slots<DIM, WIDE> sl;
+        sl.load(sb, z);
+        const unsigned m = mask[z];
+        for (int q = 0; q < S; ++q) {
+            for (int c = 0; c < DIM; ++c) s[q][c] = sl.o[q][c];
+            wq[q] = (m >> q) & 1u ? 1.0 : 0.0;
+        }
+        p = coords(z, g);
+    }
+    for (int k = 0; k < 2 * S; ++k) f(k, live ? edge_k<DIM, PER>(p, z, s, wq, k, g, hnear) : -1ll);
+}
+
+// Count the listed edges landing in each bin of targets (wave-aggregated
+// atomics, one per distinct bin per wavefront).
+template <int DIM, bool WIDE, bool PER>
+__global__ __launch_bounds__(256) void k_bin_count(GridInfo g,
+                                                   const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                                                   const uint8_t *__restrict__ mask,
+                                                   const int32_t *__restrict__ hnear,
+                                                   uint32_t *__restrict__ bincnt) {
+    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    listed_edges<DIM, WIDE, PER>(g, z, z < g.N, sb, mask, *hnear, [&](int, long long t) {
+        bin_append(t >= 0 ? (int)(t >> kBinShift) : -1, bincnt, true);  // every lane
+    });
 }
 
 // Sort one row's entries ascending (the order is then independent of the
@@ -510,38 +555,22 @@ __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *
     return d;
 }
 
-// Place every edge (target, entry) in its bin's region of binbuf.
-template <int DIM, bool WIDE, bool PER, typename TWin>
-__global__ void k_bin_fill(GridInfo g, const int16_t *__restrict__ off, const TWin *__restrict__ win,
+// Place every listed edge (target, entry) in its bin's region of binbuf
+// (the same edges as k_bin_count).
+template <int DIM, bool WIDE, bool PER>
+__global__ void k_bin_fill(GridInfo g, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                           const uint8_t *__restrict__ mask, const int32_t *__restrict__ hnear,
                            const uint32_t *__restrict__ binoff, uint32_t *__restrict__ bincur,
                            int2 *__restrict__ binbuf) {
     const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = z < g.N;
-    constexpr int S = DIM == 2 ? 3 : 6;
-    const long long N = g.N;
-    int s[6][3];
-    double wq[6];
-    for (int q = 0; q < 6; ++q) {
-        wq[q] = 0.0;
-        for (int c = 0; c < 3; ++c) s[q][c] = 0;
-    }
-    Coord p{0, 0, 0};
-    if (live) {
-        for (int q = 0; q < S; ++q) {
-            for (int c = 0; c < 3; ++c) s[q][c] = c < DIM ? (int)off[(DIM * q + c) * N + z] : 0;
-            wq[q] = (double)win[q * N + z];
-        }
-        p = coords(z, g);
-    }
-    for (int k = 0; k < 2 * S; ++k) {
-        const long long t = live ? edge_k<DIM, PER>(p, z, s, wq, k, g) : -1;
+    listed_edges<DIM, WIDE, PER>(g, z, z < g.N, sb, mask, *hnear, [&](int k, long long t) {
         const int bin = t >= 0 ? (int)(t >> kBinShift) : -1;
-        const unsigned slot = bin_append(bin, bincur, false);
+        const unsigned slot = bin_append(bin, bincur, false);  // every lane
         if (bin >= 0) {
             const int32_t e = (int32_t)(((z - t) << 9) | ((k >> 1) << 6) | (t & 63));
             binbuf[(long long)binoff[bin] + slot] = make_int2((int)t, e);
         }
-    }
+    });
 }
 
 // One block per bin: per-target counts and offsets in LDS, entries placed at
@@ -679,7 +708,7 @@ template <bool PER> __device__ inline Window window_axis(int t0, int tw, int R, 
 template <bool WIDE, bool PER, typename F>
 __device__ inline void tile_edges(const GridInfo &g, int x0, int y0, int tw, int th, int stride,
                                   int R, const typename Slots<2, WIDE>::store_t *__restrict__ sb,
-                                  const uint8_t *__restrict__ mask, F f) {
+                                  const uint8_t *__restrict__ mask, int hnear, F f) {
     const Window wx = window_axis<PER>(x0, tw, R, g.nx);
     const Window wy = window_axis<PER>(y0, th, R, g.ny);
     const long long W = (long long)wx.len * wy.len;
@@ -698,6 +727,7 @@ __device__ inline void tile_edges(const GridInfo &g, int x0, int y0, int tw, int
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             if (!(m & (1u << q))) continue;
+            if (max(abs(sl.o[q][0]), abs(sl.o[q][1])) <= hnear) continue;  // near (tiled)
 #pragma unroll
             for (int sg = -1; sg <= 1; sg += 2) {
                 int tx = x + sg * sl.o[q][0], ty = y + sg * sl.o[q][1];
@@ -719,7 +749,7 @@ __device__ inline void tile_edges(const GridInfo &g, int x0, int y0, int tw, int
 template <bool WIDE, typename F>
 __device__ inline void source_edges_of(const GridInfo &g, int x, int y, const Slots<2, WIDE> &sl,
                                        unsigned m, int x0, int y0, int tw, int th, int stride,
-                                       F f);
+                                       int hnear, F f);
 
 // The edges of positive weight from source (x, y) into the rectangle
 // [x0, x0 + tw) x [y0, y0 + th) (Neumann grid): f(local index, target,
@@ -734,18 +764,21 @@ __device__ inline void source_edges(const GridInfo &g, int x, int y, int x0, int
     sl.load(sb, z);  // issued with the mask load, not after it
     const unsigned m = mask[z];
     if (!m) return;
-    source_edges_of<WIDE>(g, x, y, sl, m, x0, y0, tw, th, stride, f);
+    source_edges_of<WIDE>(g, x, y, sl, m, x0, y0, tw, th, stride, 0, f);
 }
 
-// source_edges with the source's slots and mask already loaded.
+// source_edges with the source's slots and mask already loaded; edges
+// whose offset components are all <= hnear (near edges of the tiled
+// layout) are left out.
 template <bool WIDE, typename F>
 __device__ inline void source_edges_of(const GridInfo &g, int x, int y, const Slots<2, WIDE> &sl,
                                        unsigned m, int x0, int y0, int tw, int th, int stride,
-                                       F f) {
+                                       int hnear, F f) {
     const long long z = x + (long long)g.nx * y;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         if (!(m & (1u << q))) continue;
+        if (max(abs(sl.o[q][0]), abs(sl.o[q][1])) <= hnear) continue;
 #pragma unroll
         for (int sg = -1; sg <= 1; sg += 2) {
             const int tx = x + sg * sl.o[q][0], ty = y + sg * sl.o[q][1];
@@ -768,7 +801,7 @@ __device__ inline void brick_pass(const GridInfo &g, int x0, int y0, int tw, int
                                   const int32_t *__restrict__ brmax,
                                   const typename Slots<2, WIDE>::store_t *__restrict__ sb,
                                   const uint8_t *__restrict__ mask, int32_t *list, int32_t *nlist,
-                                  F f) {
+                                  int hnear, F f) {
     const int nbx = (g.nx + kBrick - 1) / kBrick;
     if (threadIdx.x == 0) *nlist = 0;
     __syncthreads();
@@ -809,7 +842,8 @@ __device__ inline void brick_pass(const GridInfo &g, int x0, int y0, int tw, int
         }
 #pragma unroll
         for (int j = 0; j < G; ++j)
-            if (m[j]) source_edges_of<WIDE>(g, xs[j], ys[j], sl[j], m[j], x0, y0, tw, th, stride, f);
+            if (m[j])
+                source_edges_of<WIDE>(g, xs[j], ys[j], sl[j], m[j], x0, y0, tw, th, stride, hnear, f);
     }
     __syncthreads();
 }
@@ -827,10 +861,11 @@ __device__ inline void tile_sources(const GridInfo &g, int x0, int y0, int tw, i
                                     int R, const int32_t *__restrict__ trmax,
                                     const int32_t *__restrict__ brmax,
                                     const typename Slots<2, WIDE>::store_t *__restrict__ sb,
-                                    const uint8_t *__restrict__ mask, int32_t *list, F f) {
+                                    const uint8_t *__restrict__ mask, int32_t *list, int hnear,
+                                    F f) {
     static_assert(CAP >= (kTile / kBrick) * (kTile / kBrick), "a tile's bricks fit the list");
     if (PER) {
-        tile_edges<WIDE, PER>(g, x0, y0, tw, th, stride, R, sb, mask, f);
+        tile_edges<WIDE, PER>(g, x0, y0, tw, th, stride, R, sb, mask, hnear, f);
         return;
     }
     int32_t *nlist = list + CAP;
@@ -840,7 +875,7 @@ __device__ inline void tile_sources(const GridInfo &g, int x0, int y0, int tw, i
         const long long nc = (long long)(bxb - bxa + 1) * (byb - bya + 1);
         if (nc <= CAP) {
             brick_pass<WIDE>(g, x0, y0, tw, th, stride, bxa, bya, bxb - bxa + 1, byb - bya + 1,
-                             brmax, sb, mask, list, nlist, f);
+                             brmax, sb, mask, list, nlist, hnear, f);
             return;
         }
     }
@@ -856,7 +891,7 @@ __device__ inline void tile_sources(const GridInfo &g, int x0, int y0, int tw, i
             if (ax >= bx || ay >= by) continue;
             const int bxa = ax / kBrick, bya = ay / kBrick;
             brick_pass<WIDE>(g, x0, y0, tw, th, stride, bxa, bya, (bx - 1) / kBrick - bxa + 1,
-                             (by - 1) / kBrick - bya + 1, brmax, sb, mask, list, nlist, f);
+                             (by - 1) / kBrick - bya + 1, brmax, sb, mask, list, nlist, hnear, f);
         }
 }
 
@@ -920,6 +955,7 @@ __global__ __launch_bounds__(256) void k_tile_count(GridInfo g,
                                                     const int32_t *__restrict__ Rp,
                                                     const int32_t *__restrict__ trmax,
                                                     const int32_t *__restrict__ brmax,
+                                                    const int32_t *__restrict__ hnear,
                                                     uint8_t *__restrict__ cnt,
                                                     uint8_t *__restrict__ rank, int32_t *status) {
     __shared__ int32_t lc[kTile * kTile];
@@ -932,7 +968,7 @@ __global__ __launch_bounds__(256) void k_tile_count(GridInfo g,
     __syncthreads();
     const long long N = g.N;
     tile_sources<WIDE, PER, CAP>(g, x0, y0, tw, th, kTile, *Rp, trmax, brmax, sb, mask, list,
-                                 [&](int tl, long long, int32_t, long long z, int k) {
+                                 *hnear, [&](int tl, long long, int32_t, long long z, int k) {
                                      const int r = atomicAdd(&lc[tl], 1);
                                      rank[k * N + z] = (uint8_t)min(r, 255);
                                  });
@@ -1003,8 +1039,10 @@ __global__ __launch_bounds__(256) void k_place2d(GridInfo g,
                                                  const uint8_t *__restrict__ mask,
                                                  const uint8_t *__restrict__ rank,
                                                  const int32_t *__restrict__ pos,
+                                                 const int32_t *__restrict__ hnear,
                                                  int32_t *__restrict__ ent) {
     const long long N = g.N;
+    const int h = *hnear;
     const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (z >= N) return;
     Slots<2, WIDE> sl;
@@ -1026,6 +1064,7 @@ __global__ __launch_bounds__(256) void k_place2d(GridInfo g,
         for (int k = 0; k < 2; ++k) {
             long long t = z;
             bool v = (m >> q) & 1u;
+            v = v && max(abs(sl.o[q][0]), abs(sl.o[q][1])) > h;  // near edges (tiled) unlisted
             v = v && edge_target<2, PER>(p, z, sl.o[q], k ? 1 : -1, g, t);
             v = v && z - t < (1ll << 22) && z - t > -(1ll << 22);  // else flagged earlier
             v = v && rk[2 * q + k] != 255;
@@ -1518,10 +1557,414 @@ template <typename TS>
 __global__ __launch_bounds__(kBS) void k_copy_batch(const BatchProb *__restrict__ probs, int nprob) {
     const long long b = blockIdx.x;
     const BatchProb &P = probs[find_prob(probs, nprob, b)];
-    for (int k = 0; k < kApplyPPT; ++k) {
-        const long long z = (b - P.first_block) * kApplyPoints + k * kBS + threadIdx.x;
+    for (int k = 0; k < P.block_points / kBS; ++k) {
+        const long long z = (b - P.first_block) * P.block_points + k * kBS + threadIdx.x;
         if (z < P.g.N) ((TS *)P.u[0])[z] = ((const TS *)P.u[1])[z];
     }
+}
+
+// ----------------------------------------------------------- tiled apply --
+// The explicit step with the u of a tile of targets and its halo staged in
+// LDS (the tiled layout, ADLBR_OP_TILED).  Edges whose offset has all
+// components within the halo h ("near" edges) never leave the staged
+// region: a block finds every near edge that lands in its tile by visiting
+// the sources of tile + halo, and sums them in LDS; only the "far" edges
+// (some component beyond h) are listed by the assembly.  h is the
+// operator's own reach, capped by the halo the LDS holds (2D 8, 3D 2), so a
+// near-isotropic operator has no list at all.
+//   own part       every edge of the target, in FP32 registers, neighbours
+//                  from LDS (near) or from HBM (far), in slot order;
+//   near incoming  scattered into a 64-bit fixed-point accumulator per
+//                  target with LDS integer atomics: integer sums do not
+//                  depend on the order of the additions, so the result is
+//                  deterministic.  Scale 2^s per block from max A_zz and
+//                  the range of u over the staged region: every term is at
+//                  most M = max A_zz * range (a weight is at most its
+//                  source's A_zz), s puts M below 2^50, and at most
+//                  (2h+1)^d - 1 <= 288 terms reach a target, so the sum
+//                  stays below 2^59; a term's rounding is at most
+//                  2^-49 M;
+//   far incoming   the target's list, in its sorted order, in FP32.
+// A u = own + near + far, added in that order.
+template <int DIM> struct TileCfg;
+template <> struct TileCfg<2> {
+    static constexpr int TX = 64, TY = 16, TZ = 1, HMAX = 8;
+};
+template <> struct TileCfg<3> {
+    static constexpr int TX = 32, TY = 8, TZ = 8, HMAX = 2;
+};
+template <int DIM> struct Tile {
+    using C = TileCfg<DIM>;
+    static constexpr int TX = C::TX, TY = C::TY, TZ = C::TZ, HMAX = C::HMAX;
+    static constexpr int T = TX * TY * TZ;                       // targets per block
+    static constexpr int HX = TX + 2 * HMAX, HY = TY + 2 * HMAX;
+    static constexpr int HZ = DIM == 3 ? TZ + 2 * HMAX : 1;
+    static constexpr int H = HX * HY * HZ;                       // staged points at most
+    static constexpr int PT = T / kBS;                           // targets per thread
+    static_assert(T % kBS == 0, "whole targets per thread");
+};
+
+template <int DIM> __host__ __device__ inline long long tiles_of(const GridInfo &g) {
+    using TL = Tile<DIM>;
+    const long long ntx = (g.nx + TL::TX - 1) / TL::TX, nty = (g.ny + TL::TY - 1) / TL::TY;
+    const long long ntz = DIM == 3 ? (g.nz + TL::TZ - 1) / TL::TZ : 1;
+    return ntx * nty * ntz;
+}
+
+// Fixed point with 2^50 > |x * scale| (the magic constant 1.5 * 2^52 puts
+// x * scale, rounded to nearest, in the low bits of a double).
+__device__ __forceinline__ long long to_fixed(float x, double scale) {
+    const double magic = 6755399441055744.0;
+    return __double_as_longlong(fma((double)x, scale, magic)) - __double_as_longlong(magic);
+}
+
+// Scale 2^s and its inverse for terms of magnitude at most `bound` (see
+// above); a zero bound has only zero terms, a non-finite one gives NaN
+// results.
+__device__ __forceinline__ void fixed_scale(double bound, double &scale, double &inv) {
+    if (!(bound > 0.0)) {
+        scale = inv = 1.0;
+    } else if (!isfinite(bound)) {
+        scale = 1.0;
+        inv = __longlong_as_double(0x7ff8000000000000ll);
+    } else {
+        const int e = ilogb(bound) + 1;  // bound < 2^e
+        scale = ldexp(1.0, 50 - e);
+        inv = ldexp(1.0, e - 50);
+    }
+}
+
+struct TileBox {
+    int x0, y0, z0, tw, th, td;   // tile origin and extent (clipped to the grid)
+    int hx0, hy0, hz0, sx, sy, sz; // staged region (tile + halo, clipped)
+};
+
+template <int DIM> __device__ __forceinline__ TileBox tile_box(const GridInfo &g, long long tile, int h) {
+    using TL = Tile<DIM>;
+    const int ntx = (g.nx + TL::TX - 1) / TL::TX, nty = (g.ny + TL::TY - 1) / TL::TY;
+    TileBox b;
+    const int t = (int)tile;
+    b.x0 = (t % ntx) * TL::TX;
+    b.y0 = ((t / ntx) % nty) * TL::TY;
+    b.z0 = DIM == 3 ? (t / (ntx * nty)) * TL::TZ : 0;
+    b.tw = min(TL::TX, g.nx - b.x0);
+    b.th = min(TL::TY, g.ny - b.y0);
+    b.td = DIM == 3 ? min(TL::TZ, g.nz - b.z0) : 1;
+    b.hx0 = max(0, b.x0 - h);
+    b.hy0 = max(0, b.y0 - h);
+    b.hz0 = DIM == 3 ? max(0, b.z0 - h) : 0;
+    b.sx = min(g.nx, b.x0 + b.tw + h) - b.hx0;
+    b.sy = min(g.ny, b.y0 + b.th + h) - b.hy0;
+    b.sz = DIM == 3 ? min(g.nz, b.z0 + b.td + h) - b.hz0 : 1;
+    return b;
+}
+
+// LDS index of grid point (x, y, z) in the staged region.
+template <int DIM> __device__ __forceinline__ int sidx(const TileBox &b, int x, int y, int z) {
+    using TL = Tile<DIM>;
+    return (x - b.hx0) + TL::HX * ((y - b.hy0) + (DIM == 3 ? TL::HY * (z - b.hz0) : 0));
+}
+
+template <int DIM> __device__ __forceinline__ bool in_tile(const TileBox &b, int x, int y, int z) {
+    return (unsigned)(x - b.x0) < (unsigned)b.tw && (unsigned)(y - b.y0) < (unsigned)b.th &&
+           (DIM == 2 || (unsigned)(z - b.z0) < (unsigned)b.td);
+}
+template <int DIM> __device__ __forceinline__ int tidx(const TileBox &b, int x, int y, int z) {
+    using TL = Tile<DIM>;
+    return (x - b.x0) + TL::TX * ((y - b.y0) + (DIM == 3 ? TL::TY * (z - b.z0) : 0));
+}
+
+// Weights of point z in the arithmetic type.
+template <int DIM, typename TS, typename TA>
+__device__ __forceinline__ void load_weights(const TS *__restrict__ w, int z, int N, TA *wq) {
+    constexpr int S = DIM == 2 ? 3 : 6;
+    if (S == 3) {
+        const W3<TS> w3 = ((const W3<TS> *)w)[z];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) wq[q] = Conv<TS, TA>::ld(w3.v[q < 3 ? q : 0]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < S; ++q) wq[q] = Conv<TS, TA>::ld(w[widx32<S>(q, z, N)]);
+    }
+}
+
+__device__ __forceinline__ int max_abs3(const int *o, int dim) {
+    int m = max(abs(o[0]), abs(o[1]));
+    return dim == 3 ? max(m, abs(o[2])) : m;
+}
+
+// Block-wide min and max (blockDim.x == kBS), in every thread.
+__device__ __forceinline__ void block_minmax(float &lo, float &hi, float *red) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, d, 64));
+        hi = fmaxf(hi, __shfl_xor(hi, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = lo;
+        red[4 + (threadIdx.x >> 6)] = hi;
+    }
+    __syncthreads();
+    lo = fminf(fminf(red[0], red[1]), fminf(red[2], red[3]));
+    hi = fmaxf(fmaxf(red[4], red[5]), fmaxf(red[6], red[7]));
+}
+
+// One block of the tiled step (MODE 0: out = u - hstep A u; 1: out = A u)
+// or of the diagonal pass (MODE 2: diag[z] += near incoming weights, and
+// dpart[tile] = the tile's largest diagonal).  Shared by the single-operator
+// and batched kernels, so both give bit-identical results.
+template <int DIM, bool WIDE, int MODE, typename TS, typename TD>
+__device__ __forceinline__ void tile_block(
+    const GridInfo &g, long long tile, const TS *__restrict__ u, TS *__restrict__ out,
+    const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
+    const int32_t *__restrict__ pos, const int32_t *__restrict__ ent,
+    const EntRec<TS> *__restrict__ went, int h, double bound_scale, float hstep,
+    TD *__restrict__ diag, double *__restrict__ dpart) {
+    using TL = Tile<DIM>;
+    constexpr int S = DIM == 2 ? 3 : 6;
+    constexpr bool DIAG = MODE == 2;
+    __shared__ float us[DIAG ? 1 : TL::H];
+    __shared__ unsigned long long acc[TL::T];
+    __shared__ float ownv[DIAG ? 1 : TL::T];
+    __shared__ float red[8];
+    const int N = (int)g.N;  // N < 2^28
+    h = min(max(h, 0), TL::HMAX);  // the staged region must fit the LDS arrays
+    const TileBox b = tile_box<DIM>(g, tile, h);
+    const int nst = b.sx * b.sy * b.sz;
+    // 1. stage u over tile + halo, with its range; clear the accumulators
+    float lo = INFINITY, hi = -INFINITY;
+    if (!DIAG) {
+        constexpr int G = 8;
+        for (int k0 = 0; k0 < nst; k0 += G * kBS) {  // block-uniform
+            float v[G];
+            int li[G];
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int k = k0 + j * kBS + (int)threadIdx.x;
+                const bool ok = k < nst;
+                const int kk = ok ? k : 0;
+                const int lx = kk % b.sx, r = kk / b.sx, ly = r % b.sy, lz = r / b.sy;
+                const int zg = (b.hx0 + lx) + g.nx * ((b.hy0 + ly) + g.ny * (b.hz0 + lz));
+                v[j] = Conv<TS, float>::ld(u[zg]);
+                li[j] = ok ? lx + TL::HX * (ly + TL::HY * lz) : -1;
+            }
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (li[j] >= 0) {
+                    us[li[j]] = v[j];
+                    lo = fminf(lo, v[j]);
+                    hi = fmaxf(hi, v[j]);
+                }
+        }
+    }
+    for (int k = threadIdx.x; k < TL::T; k += kBS) acc[k] = 0ull;
+    if (!DIAG) block_minmax(lo, hi, red);  // contains a barrier
+    __syncthreads();
+    double scale, inv;
+    fixed_scale(DIAG ? bound_scale : bound_scale * ((double)hi - (double)lo), scale, inv);
+    // 2. the tile's own points: own part in registers, near edges landing in
+    // the tile into the accumulators
+    for (int j = 0; j < TL::PT; ++j) {
+        const int k = (int)threadIdx.x + j * kBS;
+        const int lx = k % TL::TX, ly = (k / TL::TX) % TL::TY, lz = k / (TL::TX * TL::TY);
+        const int x = b.x0 + lx, y = b.y0 + ly, zz = b.z0 + lz;
+        if (lx >= b.tw || ly >= b.th || lz >= b.td) continue;
+        const int zi = x + g.nx * (y + g.ny * zz);
+        Slots<DIM, WIDE> sl;
+        sl.load(sb, zi);
+        float wq[S];
+        load_weights<DIM, TS, float>(w, zi, N, wq);
+        const float uz = DIAG ? 0.f : us[sidx<DIM>(b, x, y, zz)];
+        // far neighbours of the own part: requested together, from in-grid
+        // addresses (the point itself where none is needed)
+        float uf[2 * S];
+        bool anyfar = false;
+        if (!DIAG) {
+#pragma unroll
+            for (int q = 0; q < S; ++q) anyfar |= wq[q] > 0.f && max_abs3(sl.o[q], DIM) > h;
+        }
+        if (!DIAG && __any(anyfar)) {
+#pragma unroll
+            for (int q = 0; q < S; ++q)
+#pragma unroll
+                for (int sg = 0; sg < 2; ++sg) {
+                    const int s1 = sg ? 1 : -1;
+                    const int tx = x + s1 * sl.o[q][0], ty = y + s1 * sl.o[q][1];
+                    const int tz = DIM == 3 ? zz + s1 * sl.o[q][2] : 0;
+                    const bool ing = (unsigned)tx < (unsigned)g.nx && (unsigned)ty < (unsigned)g.ny &&
+                                     (DIM == 2 || (unsigned)tz < (unsigned)g.nz);
+                    const bool far = max_abs3(sl.o[q], DIM) > h;
+                    const int ti = ing && far && wq[q] > 0.f ? tx + g.nx * (ty + g.ny * tz) : zi;
+                    uf[2 * q + sg] = Conv<TS, float>::ld(u[ti]);
+                }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 2 * S; ++q) uf[q] = 0.f;
+        }
+        float a = 0.f;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            if (!(wq[q] > 0.f)) continue;
+            const bool near = max_abs3(sl.o[q], DIM) <= h;
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) {
+                const int s1 = sg ? 1 : -1;
+                const int tx = x + s1 * sl.o[q][0], ty = y + s1 * sl.o[q][1];
+                const int tz = DIM == 3 ? zz + s1 * sl.o[q][2] : 0;
+                if (!((unsigned)tx < (unsigned)g.nx && (unsigned)ty < (unsigned)g.ny &&
+                      (DIM == 2 || (unsigned)tz < (unsigned)g.nz)))
+                    continue;  // Neumann truncation
+                if (DIAG) {
+                    if (near && in_tile<DIM>(b, tx, ty, tz))
+                        atomicAdd(&acc[tidx<DIM>(b, tx, ty, tz)],
+                                  (unsigned long long)to_fixed(wq[q], scale));
+                    continue;
+                }
+                const float ut = near ? us[sidx<DIM>(b, tx, ty, tz)] : uf[2 * q + sg];
+                const float term = wq[q] * (uz - ut);
+                a += term;
+                if (near && in_tile<DIM>(b, tx, ty, tz))
+                    atomicAdd(&acc[tidx<DIM>(b, tx, ty, tz)],
+                              (unsigned long long)to_fixed(-term, scale));
+            }
+        }
+        if (!DIAG) ownv[k] = a;
+    }
+    // 3. the halo's sources: their near edges that land in the tile
+    for (int k = threadIdx.x; k < nst; k += kBS) {
+        const int lx = k % b.sx, r = k / b.sx, ly = r % b.sy, lz = r / b.sy;
+        const int x = b.hx0 + lx, y = b.hy0 + ly, zz = b.hz0 + lz;
+        if (in_tile<DIM>(b, x, y, zz)) continue;
+        const int yi = x + g.nx * (y + g.ny * zz);
+        Slots<DIM, WIDE> sl;
+        sl.load(sb, yi);
+        float wq[S];
+        load_weights<DIM, TS, float>(w, yi, N, wq);
+        const float uy = DIAG ? 0.f : us[sidx<DIM>(b, x, y, zz)];
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            if (!(wq[q] > 0.f) || max_abs3(sl.o[q], DIM) > h) continue;
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) {
+                const int s1 = sg ? 1 : -1;
+                const int tx = x + s1 * sl.o[q][0], ty = y + s1 * sl.o[q][1];
+                const int tz = DIM == 3 ? zz + s1 * sl.o[q][2] : 0;
+                if (!in_tile<DIM>(b, tx, ty, tz)) continue;
+                const float v = DIAG ? wq[q] : wq[q] * (us[sidx<DIM>(b, tx, ty, tz)] - uy);
+                atomicAdd(&acc[tidx<DIM>(b, tx, ty, tz)], (unsigned long long)to_fixed(v, scale));
+            }
+        }
+    }
+    __syncthreads();
+    // 4. far incoming from the lists, then the result
+    double dmax = 0.0;
+    for (int j = 0; j < TL::PT; ++j) {
+        const int k = (int)threadIdx.x + j * kBS;
+        const int lx = k % TL::TX, ly = (k / TL::TX) % TL::TY, lz = k / (TL::TX * TL::TY);
+        if (lx >= b.tw || ly >= b.th || lz >= b.td) continue;
+        const int x = b.x0 + lx, y = b.y0 + ly, zz = b.z0 + lz;
+        const int zi = x + g.nx * (y + g.ny * zz);
+        const double nearv = (double)(long long)acc[k] * inv;
+        if (DIAG) {
+            const double d = (double)diag[zi] + nearv;
+            diag[zi] = (TD)d;
+            dmax = fmax(dmax, d);
+            continue;
+        }
+        const float uz = us[sidx<DIM>(b, x, y, zz)];
+        const int p0 = pos[zi], p1 = pos[zi + 1];
+        float far = 0.f;
+        for (int p = p0; p < p1; ++p) {
+            int32_t v;
+            TS wv;
+            if (kInlineW<DIM>) {
+                load_rec<TS>(went, ent, p, true, v, wv);
+            } else {
+                v = ent[p];
+                wv = w[widx32<S>((v >> 6) & 7, zi + (v >> 9), N)];
+            }
+            far += Conv<TS, float>::ld(wv) * (uz - Conv<TS, float>::ld(u[zi + (v >> 9)]));
+        }
+        const float a = (ownv[k] + (float)nearv) + far;
+        out[zi] = Conv<TS, float>::st(MODE == 0 ? uz - hstep * a : a);
+    }
+    if (DIAG) block_partial_max(dmax, dpart);
+}
+
+template <int DIM, bool WIDE, int MODE, typename TS>
+__global__ __launch_bounds__(kBS) void k_apply_tiled(
+    GridInfo g, const TS *__restrict__ u, TS *__restrict__ out,
+    const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
+    const int32_t *__restrict__ pos, const int32_t *__restrict__ ent,
+    const EntRec<TS> *__restrict__ went, const int32_t *__restrict__ hnear,
+    const double *__restrict__ maxdiag, double dt, const double *__restrict__ dtcfl, int dt_mode) {
+    const float hstep = (float)(dt_mode == ADLBR_DT_CFL ? dt * dtcfl[0] : dt);
+    tile_block<DIM, WIDE, MODE, TS, float>(g, xcd_block(blockIdx.x, gridDim.x), u, out, sb, w,
+                                           pos, ent, went, *hnear, *maxdiag, hstep, nullptr,
+                                           nullptr);
+}
+
+// The diagonal's near incoming part (tiled layout): diag[z] += the weights
+// of the near edges landing on z; dpart[tile] = the tile's largest A_zz.
+template <int DIM, bool WIDE, typename TS, typename TD>
+__global__ __launch_bounds__(kBS) void k_tile_diag(
+    GridInfo g, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
+    const int32_t *__restrict__ hnear, const double *__restrict__ wmax, TD *__restrict__ diag,
+    double *__restrict__ dpart) {
+    tile_block<DIM, WIDE, 2, TS, TD>(g, blockIdx.x, (const TS *)nullptr, (TS *)nullptr, sb, w,
+                                     nullptr, nullptr, nullptr, *hnear, *wmax, 0.f, diag, dpart);
+}
+
+// Batched tiled step: blocks laid out problem after problem, one tile each.
+template <int DIM, bool WIDE, typename TS, bool XCD>
+__global__ __launch_bounds__(kBS) void k_apply_tiled_batch(const BatchProb *__restrict__ probs,
+                                                           int nprob, int parity) {
+    const long long bb = XCD ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
+    const BatchProb &P = probs[find_prob(probs, nprob, bb)];
+    const GridInfo g = P.g;
+    const float hstep = (float)(P.dt_mode == ADLBR_DT_CFL ? P.dt * P.dtcfl[0] : P.dt);
+    tile_block<DIM, WIDE, 0, TS, float>(
+        g, bb - P.first_block, (const TS *)P.u[parity], (TS *)P.u[parity ^ 1],
+        (const typename Slots<DIM, WIDE>::store_t *)P.sb, (const TS *)P.w, P.pos, P.ent,
+        (const EntRec<TS> *)P.went, *P.hnear, *P.maxdiag, hstep, (float *)nullptr, nullptr);
+}
+
+// Reach (largest offset component over the edges of positive weight) and
+// largest weight of each block of points, for the tiled layout's halo and
+// fixed-point scales; k_tile_params reduces them.
+template <int DIM, bool WIDE, typename TS>
+__global__ __launch_bounds__(256) void k_reach_wmax(GridInfo g,
+                                                    const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+                                                    const TS *__restrict__ w, double *__restrict__ rpart,
+                                                    double *__restrict__ wpart) {
+    constexpr int S = DIM == 2 ? 3 : 6;
+    const long long z = (long long)blockIdx.x * 256 + threadIdx.x;
+    double r = 0.0, wm = 0.0;
+    if (z < g.N) {
+        Slots<DIM, WIDE> sl;
+        sl.load(sb, z);
+        float wq[S];
+        load_weights<DIM, TS, float>(w, (int)z, (int)g.N, wq);
+        for (int q = 0; q < S; ++q)
+            if (wq[q] > 0.f) {
+                r = fmax(r, (double)max_abs3(sl.o[q], DIM));
+                wm = fmax(wm, (double)wq[q]);
+            }
+    }
+    block_partial_max(r, rpart);
+    block_partial_max(wm, wpart);
+}
+
+// hnear = min(hmax, reach) (0 for the list layout: every edge is listed)
+// and the largest weight.
+__global__ __launch_bounds__(256) void k_tile_params(const double *rpart, const double *wpart,
+                                                     long long nb, int hmax, int32_t *hnear,
+                                                     double *wmax) {
+    const double r = reduce_partials(rpart, nb, true);
+    const double wm = reduce_partials(wpart, nb, true);
+    if (threadIdx.x != 0) return;
+    *hnear = hmax > 0 ? (int32_t)fmin((double)hmax, r) : 0;
+    *wmax = wm;
 }
 
 // Conjugate-gradient direction with K = I + dt A (dt from the state):
@@ -1624,19 +2067,26 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
     const unsigned nbb = (unsigned)((nbins + kBS - 1) / kBS);
     TS *w = (TS *)op->w;
     store_t *sb = (store_t *)op->sb;
-    constexpr bool BINS = DIM == 3;
-    if (BINS) {
-        hipLaunchKernelGGL(k_fill_i32, dim3(nbb), dim3(kBS), 0, s, (int32_t *)op->bincnt, nbins, 0);
-        hipLaunchKernelGGL(k_fill_i32, dim3(nbb), dim3(kBS), 0, s, (int32_t *)op->bincur, nbins, 0);
-    }
     if (win_f64)
-        hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, double, TS, TA, BINS>), dim3(nb), dim3(kBS), 0,
-                           s, g, off, (const double *)win, sb, w, op->mask, op->bincnt,
-                           status);
+        hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, double, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
+                           off, (const double *)win, sb, w, op->mask, status);
     else
-        hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, float, TS, TA, BINS>), dim3(nb), dim3(kBS), 0,
-                           s, g, off, (const float *)win, sb, w, op->mask, op->bincnt,
-                           status);
+        hipLaunchKernelGGL((k_compact<DIM, WIDE, PER, float, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
+                           off, (const float *)win, sb, w, op->mask, status);
+    // the halo of the near edges (tiled layout) or 0 (every edge listed)
+    constexpr bool kTiledOk = !PER && sizeof(TS) <= 4;
+    bool tiled_params = false;
+    if constexpr (kTiledOk) {
+        if (op->tiled) {
+            hipLaunchKernelGGL((k_reach_wmax<DIM, WIDE, TS>), dim3(nb), dim3(256), 0, s, g,
+                               (const store_t *)sb, (const TS *)w, op->rpart, op->part);
+            hipLaunchKernelGGL(k_tile_params, dim3(1), dim3(256), 0, s, (const double *)op->rpart,
+                               (const double *)op->part, (long long)nb, Tile<DIM>::HMAX,
+                               op->hnear, op->wmax);
+            tiled_params = true;
+        }
+    }
+    if (!tiled_params) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, op->hnear, 1ll, 0);
     long long nparts;
     if (DIM == 2) {
         const int ntx = (g.nx + kTile - 1) / kTile, nty = (g.ny + kTile - 1) / kTile;
@@ -1650,7 +2100,8 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
         hipLaunchKernelGGL((k_tile_count<WIDE, PER>), dim3(ntiles), dim3(256), 0, s, g,
                            (const typename Slots<2, WIDE>::store_t *)op->sb, (const uint8_t *)op->mask,
                            (const int32_t *)op->rmax, (const int32_t *)op->trmax,
-                           (const int32_t *)op->brmax, op->cnt, op->rank, status);
+                           (const int32_t *)op->brmax, (const int32_t *)op->hnear, op->cnt, op->rank,
+                           status);
         hipLaunchKernelGGL(k_chunk_sum, dim3(nchunk), dim3(256), 0, s, (const uint8_t *)op->cnt, N,
                            (int32_t *)op->bincnt);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, (int32_t *)op->bincnt, nbins);
@@ -1659,7 +2110,7 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
         hipLaunchKernelGGL((k_place2d<WIDE, PER>), dim3(nb), dim3(256), 0, s, g,
                            (const typename Slots<2, WIDE>::store_t *)op->sb,
                            (const uint8_t *)op->mask, (const uint8_t *)op->rank,
-                           (const int32_t *)op->pos, op->ent);
+                           (const int32_t *)op->pos, (const int32_t *)op->hnear, op->ent);
         if (op->storage == ADLBR_F64)
             hipLaunchKernelGGL((k_rows<DIM, WIDE, PER, TS, TA, double>), dim3(nb), dim3(256), 0, s,
                                g, (const store_t *)op->sb, (const TS *)w, (const uint8_t *)op->cnt,
@@ -1672,14 +2123,16 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
                                op->part);
         nparts = nb;
     } else {
+        hipLaunchKernelGGL(k_fill_i32, dim3(nbb), dim3(kBS), 0, s, (int32_t *)op->bincnt, nbins, 0);
+        hipLaunchKernelGGL(k_fill_i32, dim3(nbb), dim3(kBS), 0, s, (int32_t *)op->bincur, nbins, 0);
+        hipLaunchKernelGGL((k_bin_count<DIM, WIDE, PER>), dim3(nb), dim3(kBS), 0, s, g,
+                           (const store_t *)sb, (const uint8_t *)op->mask, (const int32_t *)op->hnear,
+                           op->bincnt);
         hipLaunchKernelGGL(k_copy_u32, dim3(nbb), dim3(kBS), 0, s, op->bincnt, op->binoff, nbins);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, (int32_t *)op->binoff, nbins);
-        if (win_f64)
-            hipLaunchKernelGGL((k_bin_fill<DIM, WIDE, PER, double>), dim3(nb), dim3(kBS), 0, s, g,
-                               off, (const double *)win, op->binoff, op->bincur, op->binbuf);
-        else
-            hipLaunchKernelGGL((k_bin_fill<DIM, WIDE, PER, float>), dim3(nb), dim3(kBS), 0, s, g,
-                               off, (const float *)win, op->binoff, op->bincur, op->binbuf);
+        hipLaunchKernelGGL((k_bin_fill<DIM, WIDE, PER>), dim3(nb), dim3(kBS), 0, s, g,
+                           (const store_t *)sb, (const uint8_t *)op->mask, (const int32_t *)op->hnear,
+                           op->binoff, op->bincur, op->binbuf);
         if (op->storage == ADLBR_F64)
             hipLaunchKernelGGL((k_bin_build<DIM, WIDE, PER, TS, TA, double>), dim3((unsigned)nbins),
                                dim3(256), 0, s, g, op->bincnt, op->binoff, op->binbuf, sb, w,
@@ -1692,6 +2145,18 @@ int build_impl(adlbr_operator *op, const int16_t *off, const void *win, int win_
                                status);
         nparts = nbins;
     }
+    if constexpr (kTiledOk) {
+        if (op->tiled) {
+            // the rows above hold the own part and the far incoming edges;
+            // add the near incoming ones and take the largest A_zz per tile
+            const long long nt = tiles_of<DIM>(g);
+            hipLaunchKernelGGL((k_tile_diag<DIM, WIDE, TS, float>), dim3((unsigned)nt), dim3(kBS),
+                               0, s, g, (const store_t *)sb, (const TS *)w,
+                               (const int32_t *)op->hnear, (const double *)op->wmax,
+                               (float *)op->diag, op->part);
+            nparts = nt;
+        }
+    }
     hipLaunchKernelGGL(k_cfl, dim3(1), dim3(256), 0, s, (const double *)op->part, nparts,
                        op->maxdiag, op->dtcfl);
     ADLBR_LAUNCH_CHECK();
@@ -1703,6 +2168,24 @@ int apply_impl(const adlbr_operator *op, const void *u, void *out, bool step, do
                hipStream_t s) {
     typedef typename Slots<DIM, WIDE>::store_t store_t;
     const GridInfo g = op->gi;
+    if constexpr (!PER && sizeof(TS) <= 4) {
+        if (op->tiled) {
+            const unsigned nt = (unsigned)tiles_of<DIM>(g);
+            if (step)
+                hipLaunchKernelGGL((k_apply_tiled<DIM, WIDE, 0, TS>), dim3(nt), dim3(kBS), 0, s, g,
+                                   (const TS *)u, (TS *)out, (const store_t *)op->sb,
+                                   (const TS *)op->w, op->pos, op->ent,
+                                   (const EntRec<TS> *)op->went, (const int32_t *)op->hnear,
+                                   (const double *)op->maxdiag, dt, op->dtcfl, dt_mode);
+            else
+                hipLaunchKernelGGL((k_apply_tiled<DIM, WIDE, 1, TS>), dim3(nt), dim3(kBS), 0, s, g,
+                                   (const TS *)u, (TS *)out, (const store_t *)op->sb,
+                                   (const TS *)op->w, op->pos, op->ent,
+                                   (const EntRec<TS> *)op->went, (const int32_t *)op->hnear,
+                                   (const double *)op->maxdiag, dt, op->dtcfl, dt_mode);
+            return ADLBR_OK;
+        }
+    }
     const unsigned nb = (unsigned)((g.N + kApplyPoints - 1) / kApplyPoints);
     if (step)
         hipLaunchKernelGGL((k_apply<DIM, WIDE, PER, true, TS, TA>), dim3(nb), dim3(kBS), 0, s, g,
@@ -1754,10 +2237,31 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct ApplyF 
 };
 
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct BatchF {
-    static int run(const adlbr_operator *, const BatchProb *probs, const BatchProb *hprobs,
+    static int run(const adlbr_operator *rep, const BatchProb *probs, const BatchProb *hprobs,
                    int nprob, long long nblocks, int parity, int variant, int copy,
                    hipStream_t s) {
         typedef typename Slots<DIM, WIDE>::store_t store_t;
+        if constexpr (!PER && sizeof(TS) <= 4) {
+            if (rep->tiled && !copy) {
+                if (variant & 4) {  // one launch per problem (same kernel as adlbr_step)
+                    for (int i = 0; i < nprob; ++i) {
+                        const BatchProb &P = hprobs[i];
+                        hipLaunchKernelGGL((k_apply_tiled<DIM, WIDE, 0, TS>), dim3((unsigned)P.nblocks),
+                                           dim3(kBS), 0, s, P.g, (const TS *)P.u[parity],
+                                           (TS *)P.u[parity ^ 1], (const store_t *)P.sb,
+                                           (const TS *)P.w, P.pos, P.ent, (const EntRec<TS> *)P.went,
+                                           P.hnear, P.maxdiag, P.dt, P.dtcfl, P.dt_mode);
+                    }
+                } else if (variant & 1) {
+                    hipLaunchKernelGGL((k_apply_tiled_batch<DIM, WIDE, TS, true>),
+                                       dim3((unsigned)nblocks), dim3(kBS), 0, s, probs, nprob, parity);
+                } else {
+                    hipLaunchKernelGGL((k_apply_tiled_batch<DIM, WIDE, TS, false>),
+                                       dim3((unsigned)nblocks), dim3(kBS), 0, s, probs, nprob, parity);
+                }
+                return ADLBR_OK;
+            }
+        }
         if (variant & 4) {  // one launch per problem (same kernel as adlbr_step)
             for (int i = 0; i < nprob; ++i) {
                 const BatchProb &P = hprobs[i];
@@ -1846,7 +2350,8 @@ template <int DIM, bool WIDE, bool PER> struct ResidualF<DIM, WIDE, PER, _Float1
 };
 
 struct Layout {
-    size_t sb, w, cnt, pos, ent, went, diag, scal, mask, part, trmax, brmax, rank, bincnt, bincur, binoff, binbuf, total;
+    size_t sb, w, cnt, pos, ent, went, diag, scal, mask, part, rpart, trmax, brmax, rank, bincnt,
+        bincur, binoff, binbuf, total;
 };
 
 Layout layout(const GridInfo &g, int storage, int wide) {
@@ -1865,9 +2370,12 @@ Layout layout(const GridInfo &g, int storage, int wide) {
     L.diag = o; o += align_up((storage == ADLBR_F64 ? 8 : 4) * (size_t)N);
     L.scal = o; o += 256;
     L.mask = o; o += align_up((size_t)N + 64);
-    // partials: one per 256-point block or per 3D bin
+    // partials: one per 256-point block, per 3D bin or per tile of the
+    // tiled layout
     const size_t ntiles = g.dim == 2 ? (size_t)((g.nx + kTile - 1) / kTile) * ((g.ny + kTile - 1) / kTile) : 0;
-    L.part = o; o += align_up(8 * (std::max((size_t)N / 256, nbins) + 64));
+    const size_t nlt = (size_t)(g.dim == 2 ? tiles_of<2>(g) : tiles_of<3>(g));
+    L.part = o; o += align_up(8 * (std::max(std::max((size_t)N / 256, nbins), nlt) + 64));
+    L.rpart = o; o += align_up(8 * ((size_t)N / 256 + 64));
     L.trmax = o; o += ntiles ? align_up(4 * ntiles) : 0;
     const size_t nbricks = g.dim == 2 ? (size_t)((g.nx + kBrick - 1) / kBrick) * ((g.ny + kBrick - 1) / kBrick) : 0;
     L.brmax = o; o += nbricks ? align_up(4 * nbricks) : 0;
@@ -1884,7 +2392,17 @@ Layout layout(const GridInfo &g, int storage, int wide) {
 }  // namespace
 
 int batch_class(const adlbr_operator *op) {
-    return op->gi.dim * 1000 + op->wide * 100 + op->gi.periodic * 10 + op->storage;
+    return op->tiled * 10000 + op->gi.dim * 1000 + op->wide * 100 + op->gi.periodic * 10 +
+           op->storage;
+}
+
+long long batch_blocks(const adlbr_operator *op, int *block_points) {
+    if (op->tiled) {
+        *block_points = op->gi.dim == 2 ? Tile<2>::T : Tile<3>::T;
+        return op->gi.dim == 2 ? tiles_of<2>(op->gi) : tiles_of<3>(op->gi);
+    }
+    *block_points = kApplyPoints;
+    return (op->gi.N + kApplyPoints - 1) / kApplyPoints;
 }
 
 void batch_describe(const adlbr_operator *op, BatchProb *d) {
@@ -1896,6 +2414,11 @@ void batch_describe(const adlbr_operator *op, BatchProb *d) {
     d->ent = op->ent;
     d->went = op->went;
     d->dtcfl = op->dtcfl;
+    d->hnear = op->hnear;
+    d->maxdiag = op->maxdiag;
+    int bp = 0;
+    d->nblocks = batch_blocks(op, &bp);
+    d->block_points = bp;
 }
 
 size_t batch_footprint(const adlbr_operator *op) {
@@ -1916,6 +2439,7 @@ int batch_launch(const adlbr_operator *rep, const BatchProb *probs, const BatchP
 
 int cg_direction(const adlbr_operator *op, const void *z, void *q, void *p, CgState *st,
                  double *partial, int first, hipStream_t s) {
+    if (op->tiled) return ADLBR_E_UNSUPPORTED;  // the solvers gather over full lists
     return dispatch<CgDirF>(op, z, q, p, st, partial, first, s);
 }
 
@@ -1926,6 +2450,7 @@ int apply_K(const adlbr_operator *op, const void *u, void *out, double dt, hipSt
 
 int true_residual(const adlbr_operator *op, double dt, const void *b, const double *x,
                   double *out, double *partial, void *rout, hipStream_t s) {
+    if (op->tiled) return ADLBR_E_UNSUPPORTED;
     return dispatch<ResidualF>(op, dt, b, x, out, partial, rout, s);
 }
 
@@ -1935,6 +2460,7 @@ const void *operator_diag(const adlbr_operator *op) { return op->diag; }
 const void *operator_weights(const adlbr_operator *op) { return op->w; }
 const void *operator_slots(const adlbr_operator *op) { return op->sb; }
 int operator_wide(const adlbr_operator *op) { return op->wide; }
+int operator_tiled(const adlbr_operator *op) { return op->tiled; }
 
 }  // namespace adlbr
 
@@ -1970,11 +2496,17 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
         set_error("adlbr_operator_create: weights must be F64/F32, storage F64/F32/BF16/F16");
         return ADLBR_E_INVALID;
     }
-    if (flags & ~ADLBR_OP_WIDE) {
+    if (flags & ~(ADLBR_OP_WIDE | ADLBR_OP_TILED)) {
         set_error("adlbr_operator_create: unknown flags 0x%x", flags);
         return ADLBR_E_INVALID;
     }
     const int wide = flags & ADLBR_OP_WIDE ? 1 : 0;
+    const int tiled = flags & ADLBR_OP_TILED ? 1 : 0;
+    if (tiled && (gi.periodic || storage == ADLBR_F64)) {
+        set_error("adlbr_operator_create: the tiled layout needs a Neumann grid and F32, BF16 or "
+                  "F16 storage");
+        return ADLBR_E_UNSUPPORTED;
+    }
     if ((long long)(gi.dim == 2 ? 6 : 12) * gi.N >= (1ll << 31)) {
         set_error("adlbr_operator_create: too many edges for 32-bit list positions");
         return ADLBR_E_RANGE;
@@ -1998,6 +2530,7 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
     op->slots = gi.dim == 2 ? 3 : 6;
     op->storage = storage;
     op->wide = wide;
+    op->tiled = tiled;
     op->sb = b + L.sb;
     op->w = b + L.w;
     op->cnt = (uint8_t *)(b + L.cnt);
@@ -2008,6 +2541,9 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
     op->maxdiag = (double *)(b + L.scal);
     op->dtcfl = (double *)(b + L.scal + 8);
     op->rmax = (int32_t *)(b + L.scal + 16);
+    op->hnear = (int32_t *)(b + L.scal + 20);
+    op->wmax = (double *)(b + L.scal + 24);
+    op->rpart = (double *)(b + L.rpart);
     op->mask = (uint8_t *)(b + L.mask);
     op->part = (double *)(b + L.part);
     op->trmax = (int32_t *)(b + L.trmax);

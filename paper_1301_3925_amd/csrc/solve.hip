@@ -483,6 +483,11 @@ extern "C" int adlbr_solve(adlbr_operator *op, double dt, const void *b, void *x
         set_error("adlbr_solve: need dt >= 0, tol > 0, max_iter >= 1, a known method (and a net for FCG)");
         return ADLBR_E_INVALID;
     }
+    if (operator_tiled(op)) {
+        set_error("adlbr_solve: the operator has the tiled layout; the solvers need the list "
+                  "layout (create it without ADLBR_OP_TILED)");
+        return ADLBR_E_UNSUPPORTED;
+    }
     size_t need = 0;
     int rc = adlbr_solve_workspace(op, p->method, &need);
     if (rc) return rc;
