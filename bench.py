@@ -100,7 +100,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-implicit", action="store_true",
                     help="c4: leave out the implicit-step comparison")
-    ap.add_argument("--layout", default="tiled", choices=["tiled", "lists"],
+    ap.add_argument("--layout", default="lists", choices=["tiled", "lists"],
                     help="operator layout for explicit steps (FP64 storage always uses lists)")
     ap.add_argument("--workers", type=int, default=None,
                     help="host worker processes (default min(16, cpu count))")

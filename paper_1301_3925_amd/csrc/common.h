@@ -169,14 +169,20 @@ __device__ inline long long strip_block(long long L, const GridInfo &g, int poin
 
 // Index of weight q of point z in an operator's weights.  2D (S = 3):
 // point-major [N][3], so that the gather of an incoming edge's weight from
-// its source finds the source's three weights on one line.  3D (S = 6):
-// slot-major planes [6][N], read coalesced by the own part only (the 3D
-// incoming weights sit beside the entries).
+// its source finds the source's three weights on one line.  3D (S = 6),
+// with ADLBR_W3D_INLINE (the default): slot-major planes [6][N], read
+// coalesced by the own part only, and every incoming entry carries its
+// weight beside it (an 8-byte record in FP32).  Without it the 3D weights
+// are point-major too and gathered from the source, 4 bytes less per
+// incoming edge but slower (256^3 step 709 -> 911 us).
+#ifndef ADLBR_W3D_INLINE
+#define ADLBR_W3D_INLINE 1
+#endif
 template <int S> __host__ __device__ __forceinline__ long long widx(int q, long long z, long long N) {
-    return S == 3 ? z * S + q : (long long)q * N + z;
+    return S == 3 || !ADLBR_W3D_INLINE ? z * S + q : (long long)q * N + z;
 }
 template <int S> __host__ __device__ __forceinline__ unsigned widx32(int q, int z, int N) {
-    return S == 3 ? (unsigned)(z * S + q) : (unsigned)(q * N + z);
+    return S == 3 || !ADLBR_W3D_INLINE ? (unsigned)(z * S + q) : (unsigned)(q * N + z);
 }
 
 // First point of the calling wave's P consecutive 64-point groups in block

@@ -639,7 +639,7 @@ __global__ __launch_bounds__(256) void k_bin_build(
     const int32_t clamped_total = scan[255];
     for (unsigned e = (unsigned)clamped_total + threadIdx.x; e < E; e += 256) {
         ent[base + e] = 63;
-        went[base + e] = make_rec<TS>(63, TS{});
+        if (went) went[base + e] = make_rec<TS>(63, TS{});
     }
     __syncthreads();
     double dmax = 0.0;
@@ -649,7 +649,7 @@ __global__ __launch_bounds__(256) void k_bin_build(
         if (z >= N) continue;
         const int c = min(lcnt[tl], 255);
         const double d = sort_row_diag<DIM, WIDE, PER, TS, TA>(g, z, ent + base + loff[tl], c, 16,
-                                                               sb, w, went + base + loff[tl]);
+                                                               sb, w, went ? went + base + loff[tl] : nullptr);
         diag[z] = (TD)d;
         dmax = fmax(dmax, d);
     }
@@ -1207,7 +1207,7 @@ __device__ __forceinline__ unsigned wave_incl_scan(unsigned v) {
 // would touch another plane of the grid) or from the source's own weights
 // (2D: those lines are in cache from the own part of nearby rows, and the
 // gather costs less than streaming a second list).
-template <int DIM> constexpr bool kInlineW = DIM == 3;
+template <int DIM> constexpr bool kInlineW = DIM == 3 && ADLBR_W3D_INLINE;
 
 struct WaveLists {
     int start;
@@ -1248,6 +1248,9 @@ __device__ __forceinline__ WaveLists wave_lists(const int32_t *__restrict__ pos,
 template <typename TS> struct W3 {
     TS v[3];
 };
+template <typename TS> struct W6 {
+    TS v[6];
+};
 
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TU> struct OwnPart {
     static constexpr int S = DIM == 2 ? 3 : 6;
@@ -1268,8 +1271,12 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA, typename TU> s
         W3<TS> w3{};  // 2D: the three point-major weights in one load
         TS wr[S];
         if (S == 3) w3 = ((const W3<TS> *)w)[zi];
+        W6<TS> w6{};  // 3D point-major: the six weights in one record
+        if (S == 6 && !ADLBR_W3D_INLINE) w6 = ((const W6<TS> *)w)[zi];
 #pragma unroll
-        for (int q = 0; q < S; ++q) wr[q] = S == 3 ? w3.v[q < 3 ? q : 0] : w[widx32<S>(q, zi, N)];
+        for (int q = 0; q < S; ++q)
+            wr[q] = S == 3 ? w3.v[q < 3 ? q : 0]
+                           : (!ADLBR_W3D_INLINE ? w6.v[q < 6 ? q : 0] : w[widx32<S>(q, zi, N)]);
         bool okq[2 * S];
         TU ur[2 * S];
 #pragma unroll
@@ -1314,7 +1321,7 @@ template <typename TA> constexpr int kPreOf = sizeof(TA) == 8 ? 4 : 8;
 // z0 for lanes past the end, whose values are then dropped), with no per-lane
 // branch around the loads; value() forms the product.  All 64 lanes must call
 // issue().
-template <bool INLINE_W, typename TS, typename TA, typename TU> struct InEdge {
+template <bool INLINE_W, int S, typename TS, typename TA, typename TU> struct InEdge {
     TA ur;
     TS wy;
     TU uy;
@@ -1329,7 +1336,7 @@ template <bool INLINE_W, typename TS, typename TA, typename TU> struct InEdge {
         uy = TU{};
         if (e0 < L.total) {  // wave-uniform; then z0 < N.  N < 2^28 points, S N < 2^31
             const int y = ok ? (int)z0 + (v & 63) + (v >> 9) : (int)z0;
-            if (!INLINE_W) wy = w[widx32<INLINE_W ? 6 : 3>(ok ? (v >> 6) & 7 : 0, y, (int)N)];
+            if (!INLINE_W) wy = w[widx32<S>(ok ? (v >> 6) & 7 : 0, y, (int)N)];
             uy = u[(unsigned)y];
         }
     }
@@ -1391,7 +1398,7 @@ __device__ __forceinline__ TA incoming_reduce(const WaveLists &L, int32_t v, TA 
 // Up to kPre chunks are loaded before any is reduced, so their memory
 // latencies overlap.  The order of additions is fixed, so the result is
 // deterministic.  All 64 lanes must call this.
-template <bool INLINE_W, typename TS, typename TA, typename TU>
+template <bool INLINE_W, int S, typename TS, typename TA, typename TU>
 __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, long long N, TA uz,
                                             const TU *__restrict__ u, const TS *__restrict__ w,
                                             const int32_t *__restrict__ ent,
@@ -1414,7 +1421,7 @@ __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, lon
                 wv[j] = TS{};
             }
         }
-        InEdge<INLINE_W, TS, TA, TU> ie[kPre];
+        InEdge<INLINE_W, S, TS, TA, TU> ie[kPre];
 #pragma unroll
         for (int j = 0; j < kPre; ++j) ie[j].issue(L, z0, N, uz, v[j], wv[j], eb + 64 * j, u, w);
 #pragma unroll
@@ -1479,7 +1486,7 @@ __device__ __forceinline__ void apply_block(
     for (unsigned eb = 0; eb < tmax; eb += 64 * kPre) {
         load_chunks(eb);
         TA val[P][kPre];
-        InEdge<kInlineW<DIM>, TS, TA, TS> ie[P][kPre];
+        InEdge<kInlineW<DIM>, DIM == 2 ? 3 : 6, TS, TA, TS> ie[P][kPre];
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
@@ -1709,10 +1716,37 @@ __device__ __forceinline__ void block_minmax(float &lo, float &hi, float *red) {
     hi = fmaxf(fmaxf(red[4], red[5]), fmaxf(red[6], red[7]));
 }
 
+// Slots of a point from its packed store (unpacked where used, so that a
+// thread can hold several points' packed slots with their loads in flight).
+template <int DIM, bool WIDE>
+__device__ __forceinline__ Slots<DIM, WIDE> unpack(const typename Slots<DIM, WIDE>::store_t &v) {
+    Slots<DIM, WIDE> sl;
+    sl.load(&v, 0);
+    return sl;
+}
+
+// Coordinates of index k in a box of row length sx and plane size sx*sy
+// (inv = 1/sx, inv2 = 1/(sx*sy) in FP32): floor((k + 1/2) * inv) is exact for
+// k < 2^20, so no integer division is needed.
+struct Unravel {
+    int sx, sxy;
+    float inv, inv2;
+    __device__ __forceinline__ void at(int k, int &x, int &y, int &z) const {
+        z = (int)(((float)k + 0.5f) * inv2);
+        const int r = k - z * sxy;
+        y = (int)(((float)r + 0.5f) * inv);
+        x = r - y * sx;
+    }
+};
+
 // One block of the tiled step (MODE 0: out = u - hstep A u; 1: out = A u)
 // or of the diagonal pass (MODE 2: diag[z] += near incoming weights, and
 // dpart[tile] = the tile's largest diagonal).  Shared by the single-operator
-// and batched kernels, so both give bit-identical results.
+// and batched kernels, so both give bit-identical results.  The staged
+// region's points are visited once, four per thread at a time (their slots
+// and weights requested together): a point of the tile adds its own part
+// (into ownv) and scatters its near edges that land in the tile, a halo
+// point scatters its near edges that land in the tile.
 template <int DIM, bool WIDE, int MODE, typename TS, typename TD>
 __device__ __forceinline__ void tile_block(
     const GridInfo &g, long long tile, const TS *__restrict__ u, TS *__restrict__ out,
@@ -1721,6 +1755,7 @@ __device__ __forceinline__ void tile_block(
     const EntRec<TS> *__restrict__ went, int h, double bound_scale, float hstep,
     TD *__restrict__ diag, double *__restrict__ dpart) {
     using TL = Tile<DIM>;
+    typedef typename Slots<DIM, WIDE>::store_t store_t;
     constexpr int S = DIM == 2 ? 3 : 6;
     constexpr bool DIAG = MODE == 2;
     __shared__ float us[DIAG ? 1 : TL::H];
@@ -1731,6 +1766,7 @@ __device__ __forceinline__ void tile_block(
     h = min(max(h, 0), TL::HMAX);  // the staged region must fit the LDS arrays
     const TileBox b = tile_box<DIM>(g, tile, h);
     const int nst = b.sx * b.sy * b.sz;
+    const Unravel ur{b.sx, b.sx * b.sy, 1.0f / (float)b.sx, 1.0f / (float)(b.sx * b.sy)};
     // 1. stage u over tile + halo, with its range; clear the accumulators
     float lo = INFINITY, hi = -INFINITY;
     if (!DIAG) {
@@ -1741,12 +1777,11 @@ __device__ __forceinline__ void tile_block(
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 const int k = k0 + j * kBS + (int)threadIdx.x;
-                const bool ok = k < nst;
-                const int kk = ok ? k : 0;
-                const int lx = kk % b.sx, r = kk / b.sx, ly = r % b.sy, lz = r / b.sy;
+                int lx, ly, lz;
+                ur.at(k < nst ? k : 0, lx, ly, lz);
                 const int zg = (b.hx0 + lx) + g.nx * ((b.hy0 + ly) + g.ny * (b.hz0 + lz));
                 v[j] = Conv<TS, float>::ld(u[zg]);
-                li[j] = ok ? lx + TL::HX * (ly + TL::HY * lz) : -1;
+                li[j] = k < nst ? lx + TL::HX * (ly + TL::HY * lz) : -1;
             }
 #pragma unroll
             for (int j = 0; j < G; ++j)
@@ -1762,102 +1797,119 @@ __device__ __forceinline__ void tile_block(
     __syncthreads();
     double scale, inv;
     fixed_scale(DIAG ? bound_scale : bound_scale * ((double)hi - (double)lo), scale, inv);
-    // 2. the tile's own points: own part in registers, near edges landing in
-    // the tile into the accumulators
-    for (int j = 0; j < TL::PT; ++j) {
-        const int k = (int)threadIdx.x + j * kBS;
-        const int lx = k % TL::TX, ly = (k / TL::TX) % TL::TY, lz = k / (TL::TX * TL::TY);
-        const int x = b.x0 + lx, y = b.y0 + ly, zz = b.z0 + lz;
-        if (lx >= b.tw || ly >= b.th || lz >= b.td) continue;
-        const int zi = x + g.nx * (y + g.ny * zz);
-        Slots<DIM, WIDE> sl;
-        sl.load(sb, zi);
-        float wq[S];
-        load_weights<DIM, TS, float>(w, zi, N, wq);
-        const float uz = DIAG ? 0.f : us[sidx<DIM>(b, x, y, zz)];
-        // far neighbours of the own part: requested together, from in-grid
-        // addresses (the point itself where none is needed)
-        float uf[2 * S];
-        bool anyfar = false;
-        if (!DIAG) {
+    // 2. every staged point as a source
+    constexpr int G = 4;
+    for (int k0 = 0; k0 < nst; k0 += G * kBS) {  // block-uniform
+        store_t raw[G];
+        TS wr[G][S];
+        int xs[G], ys[G], zs[G];
+        bool val[G];
 #pragma unroll
-            for (int q = 0; q < S; ++q) anyfar |= wq[q] > 0.f && max_abs3(sl.o[q], DIM) > h;
+        for (int j = 0; j < G; ++j) {
+            const int k = k0 + j * kBS + (int)threadIdx.x;
+            val[j] = k < nst;
+            int lx, ly, lz;
+            ur.at(val[j] ? k : 0, lx, ly, lz);
+            xs[j] = b.hx0 + lx;
+            ys[j] = b.hy0 + ly;
+            zs[j] = b.hz0 + lz;
+            const int zi = xs[j] + g.nx * (ys[j] + g.ny * zs[j]);
+            raw[j] = sb[zi];
+            if (S == 3) {
+                const W3<TS> w3 = ((const W3<TS> *)w)[zi];
+#pragma unroll
+                for (int q = 0; q < S; ++q) wr[j][q] = w3.v[q < 3 ? q : 0];
+            } else {
+#pragma unroll
+                for (int q = 0; q < S; ++q) wr[j][q] = w[widx32<S>(q, zi, N)];
+            }
         }
-        if (!DIAG && __any(anyfar)) {
 #pragma unroll
-            for (int q = 0; q < S; ++q)
+        for (int j = 0; j < G; ++j) {
+            if (!val[j]) continue;
+            const int x = xs[j], y = ys[j], zz = zs[j];
+            const Slots<DIM, WIDE> sl = unpack<DIM, WIDE>(raw[j]);
+            float wq[S];
+#pragma unroll
+            for (int q = 0; q < S; ++q) wq[q] = Conv<TS, float>::ld(wr[j][q]);
+            const bool mine = !DIAG && in_tile<DIM>(b, x, y, zz);
+            const float uy = DIAG ? 0.f : us[sidx<DIM>(b, x, y, zz)];
+            // far neighbours of the own part (a wave-uniform test, then every
+            // load from an in-grid address: the point itself where none is
+            // needed)
+            float uf[2 * S];
+            bool anyfar = false;
+            if (mine) {
+#pragma unroll
+                for (int q = 0; q < S; ++q) anyfar |= wq[q] > 0.f && max_abs3(sl.o[q], DIM) > h;
+            }
+            if (__any(anyfar)) {
+                const int zi = x + g.nx * (y + g.ny * zz);
+#pragma unroll
+                for (int q = 0; q < S; ++q)
+#pragma unroll
+                    for (int sg = 0; sg < 2; ++sg) {
+                        const int s1 = sg ? 1 : -1;
+                        const int tx = x + s1 * sl.o[q][0], ty = y + s1 * sl.o[q][1];
+                        const int tz = DIM == 3 ? zz + s1 * sl.o[q][2] : 0;
+                        const bool ing = (unsigned)tx < (unsigned)g.nx && (unsigned)ty < (unsigned)g.ny &&
+                                         (DIM == 2 || (unsigned)tz < (unsigned)g.nz);
+                        const bool far = max_abs3(sl.o[q], DIM) > h;
+                        const int ti = mine && ing && far && wq[q] > 0.f ? tx + g.nx * (ty + g.ny * tz) : zi;
+                        uf[2 * q + sg] = Conv<TS, float>::ld(u[ti]);
+                    }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 2 * S; ++q) uf[q] = 0.f;
+            }
+            float a = 0.f;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                if (!(wq[q] > 0.f)) continue;
+                const bool near = max_abs3(sl.o[q], DIM) <= h;
+                if (!mine && !near) continue;
 #pragma unroll
                 for (int sg = 0; sg < 2; ++sg) {
                     const int s1 = sg ? 1 : -1;
                     const int tx = x + s1 * sl.o[q][0], ty = y + s1 * sl.o[q][1];
                     const int tz = DIM == 3 ? zz + s1 * sl.o[q][2] : 0;
-                    const bool ing = (unsigned)tx < (unsigned)g.nx && (unsigned)ty < (unsigned)g.ny &&
-                                     (DIM == 2 || (unsigned)tz < (unsigned)g.nz);
-                    const bool far = max_abs3(sl.o[q], DIM) > h;
-                    const int ti = ing && far && wq[q] > 0.f ? tx + g.nx * (ty + g.ny * tz) : zi;
-                    uf[2 * q + sg] = Conv<TS, float>::ld(u[ti]);
-                }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 2 * S; ++q) uf[q] = 0.f;
-        }
-        float a = 0.f;
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-            if (!(wq[q] > 0.f)) continue;
-            const bool near = max_abs3(sl.o[q], DIM) <= h;
-#pragma unroll
-            for (int sg = 0; sg < 2; ++sg) {
-                const int s1 = sg ? 1 : -1;
-                const int tx = x + s1 * sl.o[q][0], ty = y + s1 * sl.o[q][1];
-                const int tz = DIM == 3 ? zz + s1 * sl.o[q][2] : 0;
-                if (!((unsigned)tx < (unsigned)g.nx && (unsigned)ty < (unsigned)g.ny &&
-                      (DIM == 2 || (unsigned)tz < (unsigned)g.nz)))
-                    continue;  // Neumann truncation
-                if (DIAG) {
-                    if (near && in_tile<DIM>(b, tx, ty, tz))
+                    const bool lands = near && in_tile<DIM>(b, tx, ty, tz);
+                    if (!mine) {
+                        if (lands) {
+                            const float v = DIAG ? wq[q] : wq[q] * (us[sidx<DIM>(b, tx, ty, tz)] - uy);
+                            atomicAdd(&acc[tidx<DIM>(b, tx, ty, tz)],
+                                      (unsigned long long)to_fixed(v, scale));
+                        }
+                        continue;
+                    }
+                    if (!((unsigned)tx < (unsigned)g.nx && (unsigned)ty < (unsigned)g.ny &&
+                          (DIM == 2 || (unsigned)tz < (unsigned)g.nz)))
+                        continue;  // Neumann truncation
+                    const float ut = near ? us[sidx<DIM>(b, tx, ty, tz)] : uf[2 * q + sg];
+                    const float term = wq[q] * (uy - ut);
+                    a += term;
+                    if (lands)
                         atomicAdd(&acc[tidx<DIM>(b, tx, ty, tz)],
-                                  (unsigned long long)to_fixed(wq[q], scale));
-                    continue;
+                                  (unsigned long long)to_fixed(-term, scale));
                 }
-                const float ut = near ? us[sidx<DIM>(b, tx, ty, tz)] : uf[2 * q + sg];
-                const float term = wq[q] * (uz - ut);
-                a += term;
-                if (near && in_tile<DIM>(b, tx, ty, tz))
-                    atomicAdd(&acc[tidx<DIM>(b, tx, ty, tz)],
-                              (unsigned long long)to_fixed(-term, scale));
             }
-        }
-        if (!DIAG) ownv[k] = a;
-    }
-    // 3. the halo's sources: their near edges that land in the tile
-    for (int k = threadIdx.x; k < nst; k += kBS) {
-        const int lx = k % b.sx, r = k / b.sx, ly = r % b.sy, lz = r / b.sy;
-        const int x = b.hx0 + lx, y = b.hy0 + ly, zz = b.hz0 + lz;
-        if (in_tile<DIM>(b, x, y, zz)) continue;
-        const int yi = x + g.nx * (y + g.ny * zz);
-        Slots<DIM, WIDE> sl;
-        sl.load(sb, yi);
-        float wq[S];
-        load_weights<DIM, TS, float>(w, yi, N, wq);
-        const float uy = DIAG ? 0.f : us[sidx<DIM>(b, x, y, zz)];
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-            if (!(wq[q] > 0.f) || max_abs3(sl.o[q], DIM) > h) continue;
-#pragma unroll
-            for (int sg = 0; sg < 2; ++sg) {
-                const int s1 = sg ? 1 : -1;
-                const int tx = x + s1 * sl.o[q][0], ty = y + s1 * sl.o[q][1];
-                const int tz = DIM == 3 ? zz + s1 * sl.o[q][2] : 0;
-                if (!in_tile<DIM>(b, tx, ty, tz)) continue;
-                const float v = DIAG ? wq[q] : wq[q] * (us[sidx<DIM>(b, tx, ty, tz)] - uy);
-                atomicAdd(&acc[tidx<DIM>(b, tx, ty, tz)], (unsigned long long)to_fixed(v, scale));
-            }
+            if (mine) ownv[tidx<DIM>(b, x, y, zz)] = a;
         }
     }
     __syncthreads();
-    // 4. far incoming from the lists, then the result
+    // 3. far incoming from the lists (row starts of all of the thread's
+    // targets requested first), then the result
     double dmax = 0.0;
+    int p0[TL::PT], p1[TL::PT];
+#pragma unroll
+    for (int j = 0; j < TL::PT; ++j) {
+        const int k = (int)threadIdx.x + j * kBS;
+        const int lx = k % TL::TX, ly = (k / TL::TX) % TL::TY, lz = k / (TL::TX * TL::TY);
+        const bool live = !DIAG && lx < b.tw && ly < b.th && lz < b.td;
+        const int zi = live ? (b.x0 + lx) + g.nx * ((b.y0 + ly) + g.ny * (b.z0 + lz)) : 0;
+        p0[j] = live ? pos[zi] : 0;
+        p1[j] = live ? pos[zi + 1] : 0;
+    }
     for (int j = 0; j < TL::PT; ++j) {
         const int k = (int)threadIdx.x + j * kBS;
         const int lx = k % TL::TX, ly = (k / TL::TX) % TL::TY, lz = k / (TL::TX * TL::TY);
@@ -1872,9 +1924,8 @@ __device__ __forceinline__ void tile_block(
             continue;
         }
         const float uz = us[sidx<DIM>(b, x, y, zz)];
-        const int p0 = pos[zi], p1 = pos[zi + 1];
         float far = 0.f;
-        for (int p = p0; p < p1; ++p) {
+        for (int p = p0[j]; p < p1[j]; ++p) {
             int32_t v;
             TS wv;
             if (kInlineW<DIM>) {
@@ -1990,7 +2041,7 @@ __global__ __launch_bounds__(kBS) void k_cg_direction(
     const T zz = live ? zv[z] : (T)0;
     OwnPart<DIM, WIDE, PER, T, T, T> own;
     own.issue(g, z, live && !skip, zz, zv, sb, w);
-    T acc = skip ? (T)0 : wave_incoming<kInlineW<DIM>, T, T, T>(L, z, N, zz, zv, w, ent, went);
+    T acc = skip ? (T)0 : wave_incoming<kInlineW<DIM>, DIM == 2 ? 3 : 6, T, T, T>(L, z, N, zz, zv, w, ent, went);
     if (live && !skip) {
         acc += own.sum(zz);
         const T dt = (T)st->dt;
@@ -2040,7 +2091,7 @@ __global__ __launch_bounds__(kBS) void k_residual(
     const double xz = live ? x[z] : 0.0;
     OwnPart<DIM, WIDE, PER, T, double, double> own;
     own.issue(g, z, live, xz, x, sb, w);
-    double ax = wave_incoming<kInlineW<DIM>, T, double, double>(L, z, N, xz, x, w, ent, went);
+    double ax = wave_incoming<kInlineW<DIM>, DIM == 2 ? 3 : 6, T, double, double>(L, z, N, xz, x, w, ent, went);
     if (live) {
         ax += own.sum(xz);
         const double r = (double)b[z] - (xz + dt * ax);
@@ -2366,7 +2417,7 @@ Layout layout(const GridInfo &g, int storage, int wide) {
     L.cnt = o;  o += align_up((size_t)N + 64);
     L.pos = o;  o += align_up(4 * (size_t)N + 256);
     L.ent = o;  o += align_up(4 * (size_t)(2 * S) * N);
-    L.went = o; o += g.dim == 3 ? align_up((dtype_size(storage) == 4 ? 8 : dtype_size(storage)) * (size_t)(2 * S) * N) : 0;
+    L.went = o; o += g.dim == 3 && ADLBR_W3D_INLINE ? align_up((dtype_size(storage) == 4 ? 8 : dtype_size(storage)) * (size_t)(2 * S) * N) : 0;
     L.diag = o; o += align_up((storage == ADLBR_F64 ? 8 : 4) * (size_t)N);
     L.scal = o; o += 256;
     L.mask = o; o += align_up((size_t)N + 64);
@@ -2429,7 +2480,8 @@ size_t batch_footprint(const adlbr_operator *op) {
     // u and its successor, offsets, own weights, count, row start, and about
     // two incoming entries (each with its weight) per slot
     return (size_t)op->gi.N *
-           (2 * ts + sbs + (size_t)op->slots * ts + 2 * (size_t)op->slots * (4 + ts) + 1 + 4);
+           (2 * ts + sbs + (size_t)op->slots * ts + 2 * (size_t)op->slots * (4 + (op->went ? ts : 0)) +
+            1 + 4);
 }
 
 int batch_launch(const adlbr_operator *rep, const BatchProb *probs, const BatchProb *hprobs,
@@ -2536,7 +2588,7 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
     op->cnt = (uint8_t *)(b + L.cnt);
     op->pos = (int32_t *)(b + L.pos);
     op->ent = (int32_t *)(b + L.ent);
-    op->went = gi.dim == 3 ? b + L.went : nullptr;
+    op->went = gi.dim == 3 && ADLBR_W3D_INLINE ? b + L.went : nullptr;
     op->diag = b + L.diag;
     op->maxdiag = (double *)(b + L.scal);
     op->dtcfl = (double *)(b + L.scal + 8);
