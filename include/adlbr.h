@@ -67,7 +67,13 @@ extern "C" {
 #define ADLBR_ST_INCOMING 32  /* more than 255 stencils reach one point              */
 
 typedef enum { ADLBR_F64 = 0, ADLBR_F32 = 1, ADLBR_BF16 = 2, ADLBR_F16 = 3 } adlbr_dtype;
-typedef enum { ADLBR_NEUMANN = 0, ADLBR_PERIODIC = 1 } adlbr_boundary;
+/* Boundary of the operator: an edge whose target leaves the grid is
+ * dropped (ADLBR_NEUMANN: the truncation V(z;h) of Section 1), wrapped
+ * (ADLBR_PERIODIC) or mirrored back at the half-sample points -1/2 and
+ * n - 1/2 (ADLBR_REFLECT: u extended evenly, the reflecting boundary of the
+ * restoration test, Section 5).  A folded target that is the point itself
+ * is no edge. */
+typedef enum { ADLBR_NEUMANN = 0, ADLBR_PERIODIC = 1, ADLBR_REFLECT = 2 } adlbr_boundary;
 
 typedef struct adlbr_grid {
     int32_t dim;      /* 2 or 3 */

@@ -141,10 +141,12 @@ def stencil(D):
 
 # ------------------------------------------------------------- operator --
 
-def operator_matrix(dims, off, w, periodic: bool = False):
+def operator_matrix(dims, off, w, periodic: bool = False, reflect: bool = False):
     """The AD-LBR operator A = 1/2 grad E_h with h = 1 (eq. (def:E*) and
     its gradient flow, Section 1), assembled by scattering every directed
-    edge; Neumann truncation V(z; h) drops edges leaving the grid.
+    edge; Neumann truncation V(z; h) drops edges leaving the grid,
+    periodic wraps them, reflect mirrors them back into the grid (the
+    reflecting boundary of the restoration test, Section 5).
     Returns a scipy.sparse CSR matrix (duplicates summed)."""
     import scipy.sparse as sp
     dims = tuple(int(d) for d in dims)
@@ -158,7 +160,8 @@ def operator_matrix(dims, off, w, periodic: bool = False):
     ci = np.empty(cap, np.int64)
     v = np.empty(cap, np.float64)
     nd = np.array(list(dims) + [1] * (3 - dim), np.int64)
-    t = _load().or_operator_coo(dim, _p(nd), int(bool(periodic)), _p(off), _p(w),
+    mode = 2 if reflect else int(bool(periodic))
+    t = _load().or_operator_coo(dim, _p(nd), mode, _p(off), _p(w),
                                 _p(ri), _p(ci), _p(v))
     A = sp.coo_matrix((v[:t], (ri[:t], ci[:t])), shape=(n, n)).tocsr()
     A.sum_duplicates()
@@ -185,9 +188,10 @@ def explicit_steps(A, u0, dt: float, nsteps: int):
     return u
 
 
-def energy(dims, off, w, u, periodic: bool = False) -> float:
+def energy(dims, off, w, u, periodic: bool = False, reflect: bool = False) -> float:
     """E_h(u) = sum_z sum_{e in V(z;h)} gamma_z(e) |u(z+e) - u(z)|^2 with
-    h = 1 (eq. (def:E*)), evaluated literally (vectorized over z)."""
+    h = 1 (eq. (def:E*)), evaluated literally (vectorized over z); with
+    reflect, u(z+e) outside the grid is u at the mirrored point."""
     dims = tuple(int(d) for d in dims)
     dim = len(dims)
     u = np.asarray(u, dtype=np.float64)
@@ -201,6 +205,11 @@ def energy(dims, off, w, u, periodic: bool = False) -> float:
             if periodic:
                 for c in range(dim):
                     q[c] %= dims[c]
+                ok = np.ones(n, bool)
+            elif reflect:
+                for c in range(dim):
+                    m = q[c] % (2 * dims[c])
+                    q[c] = np.where(m < dims[c], m, 2 * dims[c] - 1 - m)
                 ok = np.ones(n, bool)
             else:
                 ok = np.all([(q[c] >= 0) & (q[c] < dims[c]) for c in range(dim)], axis=0)

@@ -401,13 +401,18 @@ int or_stencil3d(const double *D, int64_t n, int16_t *off, double *w,
 
 /* ----------------------------------------------------------- operator -- */
 
+static int64_t mirror(int64_t i, int64_t n);
+
 /* Scatter form of A = 1/2 grad E_h (eq. (def:E*)) with h = 1: every
  * directed edge (y, y + s*o_i(y)) whose target lies in the grid adds
  * w_i(y) (delta_y - delta_t)(delta_y - delta_t)^T.  Emits COO triplets
  * (4 per edge) that the caller sums into a sparse matrix.
- * dims: n[0..dim-1]; periodic != 0 wraps instead of dropping (Neumann
- * truncation V(z;h), Section 1).  Returns the number of triplets. */
-int64_t or_operator_coo(int dim, const int64_t *nd, int periodic,
+ * dims: n[0..dim-1]; mode 0 drops an edge whose target leaves the grid
+ * (Neumann truncation V(z;h), Section 1), mode 1 wraps it (periodic),
+ * mode 2 reflects it back (half-sample mirror: the even extension of u,
+ * the reflecting boundary of the restoration test, Section 5).  Returns
+ * the number of triplets. */
+int64_t or_operator_coo(int dim, const int64_t *nd, int mode,
                         const int16_t *off, const double *w,
                         int64_t *ri, int64_t *ci, double *v)
 {
@@ -426,9 +431,11 @@ int64_t or_operator_coo(int dim, const int64_t *nd, int periodic,
                 for (int c = 0; c < dim; ++c) {
                     int64_t len = nd[c];
                     q[c] = p[c] + s * (int64_t)off[(dim * i + c) * n + y];
-                    if (periodic) {
+                    if (mode == 1) {
                         q[c] %= len;
                         if (q[c] < 0) q[c] += len;
+                    } else if (mode == 2) {
+                        q[c] = mirror(q[c], len);
                     } else if (q[c] < 0 || q[c] >= len) {
                         inside = 0;
                     }
@@ -443,6 +450,15 @@ int64_t or_operator_coo(int dim, const int64_t *nd, int periodic,
         }
     }
     return t;
+}
+
+static int64_t mirror(int64_t i, int64_t n)
+{
+    /* half-sample symmetric extension: -1 -> 0, n -> n-1, period 2n */
+    int64_t p = 2 * n;
+    i %= p;
+    if (i < 0) i += p;
+    return i < n ? i : p - 1 - i;
 }
 
 /* ---------------------------------------------------------------- CED -- */

@@ -48,11 +48,11 @@ def _require_cuda(*ts):
             raise ValueError("tensor must be contiguous")
 
 
-def grid(dims, periodic: bool = False) -> capi.Grid:
+def grid(dims, periodic: bool = False, reflect: bool = False) -> capi.Grid:
     dims = [int(d) for d in dims]
     g = capi.Grid()
     g.dim = len(dims)
-    g.boundary = capi.PERIODIC if periodic else capi.NEUMANN
+    g.boundary = capi.REFLECT if reflect else capi.PERIODIC if periodic else capi.NEUMANN
     for i in range(3):
         g.n[i] = dims[i] if i < len(dims) else 1
     return g
@@ -122,9 +122,10 @@ class Operator:
 
     def __init__(self, dims, offsets, weights, storage=None, periodic: bool = False,
                  wide=None, stream=None, workspace=None, check: bool = True,
-                 tiled: bool = False):
+                 tiled: bool = False, reflect: bool = False):
         self._h = ctypes.c_void_p()
         self.tiled = bool(tiled)
+        self.reflect = bool(reflect)
         self._create(dims, offsets, weights, storage, periodic, bool(wide), stream, workspace)
         if not check:
             return
@@ -149,7 +150,7 @@ class Operator:
         self.storage = storage or torch.float32
         self.device = weights.device
         self.wide = wide
-        self._grid = grid(self.dims, periodic)
+        self._grid = grid(self.dims, periodic, self.reflect)
         flags = (capi.OP_WIDE if wide else 0) | (capi.OP_TILED if self.tiled else 0)
         nbytes = ctypes.c_size_t()
         capi.check(lib.adlbr_operator_workspace(ctypes.byref(self._grid),

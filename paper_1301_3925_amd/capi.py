@@ -17,7 +17,7 @@ OK = 0
 E_INVALID, E_NOT_SPD, E_RANGE, E_NOMEM, E_HIP, E_NOT_CONVERGED, E_UNSUPPORTED = range(-1, -8, -1)
 ST_NOT_SPD, ST_RANGE, ST_ITER, ST_CLAMPED, ST_STENCIL, ST_INCOMING = 1, 2, 4, 8, 16, 32
 F64, F32, BF16, F16 = 0, 1, 2, 3
-NEUMANN, PERIODIC = 0, 1
+NEUMANN, PERIODIC, REFLECT = 0, 1, 2
 OP_WIDE = 1
 OP_TILED = 2
 DT_ABS, DT_CFL = 0, 1

@@ -26,7 +26,8 @@ int check_grid(const adlbr_grid *g, GridInfo *gi) {
         set_error("grid dim must be 2 or 3 (got %d)", g->dim);
         return ADLBR_E_INVALID;
     }
-    if (g->boundary != ADLBR_NEUMANN && g->boundary != ADLBR_PERIODIC) {
+    if (g->boundary != ADLBR_NEUMANN && g->boundary != ADLBR_PERIODIC &&
+        g->boundary != ADLBR_REFLECT) {
         set_error("unknown boundary %d", g->boundary);
         return ADLBR_E_INVALID;
     }
@@ -43,7 +44,8 @@ int check_grid(const adlbr_grid *g, GridInfo *gi) {
         }
     }
     gi->dim = g->dim;
-    gi->periodic = g->boundary == ADLBR_PERIODIC;
+    // 0 Neumann; 1 periodic and 2 reflecting share the folded-target kernels
+    gi->periodic = g->boundary == ADLBR_PERIODIC ? 1 : g->boundary == ADLBR_REFLECT ? 2 : 0;
     gi->nx = (int)g->n[0];
     gi->ny = (int)g->n[1];
     gi->nz = g->dim == 3 ? (int)g->n[2] : 1;

@@ -181,17 +181,26 @@ __device__ __forceinline__ int wrap(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
+// A coordinate outside [0, n) brought back: wrapped (periodic grid,
+// mode 1) or mirrored at the half-sample points -1/2 and n - 1/2 (the
+// reflecting boundary, mode 2: -1 -> 0, n -> n - 1, period 2n).
+__device__ __forceinline__ int fold(int v, int n, int mode) {
+    if (mode != 2) return wrap(v, n);
+    const int m = wrap(v, 2 * n);
+    return m < n ? m : 2 * n - 1 - m;
+}
+
 // Target of the directed edge (p, s*o); returns false when it leaves a
 // Neumann grid.
 template <int DIM, bool PER>
 __device__ __forceinline__ bool edge_target(const Coord &p, long long i, const int *o, int s,
                                             const GridInfo &g, long long &t) {
     if (PER) {
-        const int x = wrap(p.x + s * o[0], g.nx);
-        const int y = wrap(p.y + s * o[1], g.ny);
-        const int zz = DIM == 3 ? wrap(p.z + s * o[2], g.nz) : 0;
+        const int x = fold(p.x + s * o[0], g.nx, g.periodic);
+        const int y = fold(p.y + s * o[1], g.ny, g.periodic);
+        const int zz = DIM == 3 ? fold(p.z + s * o[2], g.nz, g.periodic) : 0;
         t = x + (long long)g.nx * (y + (long long)g.ny * zz);
-        return t != i;  // an offset that wraps onto the point itself is no edge
+        return t != i;  // an offset folded onto the point itself is no edge
     } else {
         const int x = p.x + s * o[0], y = p.y + s * o[1];
         const int zz = DIM == 3 ? p.z + s * o[2] : 0;
@@ -206,9 +215,9 @@ template <int DIM, bool PER>
 __device__ __forceinline__ bool edge_target32(const Coord &p, int i, const int *o, int s,
                                               const GridInfo &g, int &t) {
     if (PER) {
-        const int x = wrap(p.x + s * o[0], g.nx);
-        const int y = wrap(p.y + s * o[1], g.ny);
-        const int zz = DIM == 3 ? wrap(p.z + s * o[2], g.nz) : 0;
+        const int x = fold(p.x + s * o[0], g.nx, g.periodic);
+        const int y = fold(p.y + s * o[1], g.ny, g.periodic);
+        const int zz = DIM == 3 ? fold(p.z + s * o[2], g.nz, g.periodic) : 0;
         t = x + g.nx * (y + g.ny * zz);
         return t != i;
     } else {
@@ -732,8 +741,8 @@ __device__ inline void tile_edges(const GridInfo &g, int x0, int y0, int tw, int
             for (int sg = -1; sg <= 1; sg += 2) {
                 int tx = x + sg * sl.o[q][0], ty = y + sg * sl.o[q][1];
                 if (PER) {
-                    tx = wrap(tx, g.nx);
-                    ty = wrap(ty, g.ny);
+                    tx = fold(tx, g.nx, g.periodic);
+                    ty = fold(ty, g.ny, g.periodic);
                 }
                 if (tx < x0 || tx >= x0 + tw || ty < y0 || ty >= y0 + th) continue;
                 long long t;

@@ -138,3 +138,73 @@ def test_overflow_field_reaches_centre_more_than_255_times():
     off, w, st = oracle.stencil3d(D)
     A = oracle.operator_matrix(dims, off, w)
     assert (A.getrow(c).toarray() != 0).sum() - 1 > 255
+
+
+# ----------------------------------------------------------------------------
+# The reflecting boundary (the restoration test's, Section 5): an edge whose
+# target leaves the grid is mirrored back (half-sample mirror, the even
+# extension of u).
+
+def test_reflect_operator_is_the_gradient_of_its_energy():
+    """A = 1/2 grad E_h with the mirrored targets, read off the energy by
+    polarization on tiny grids with offsets longer than the grid is from
+    its border (kappa 30 in 2D, 20 in 3D), equals the scattered operator."""
+    from oracle import brute
+    for dims, D in [((7, 6), synth.tensor2d_field(5, 7, 6, 30.0)),
+                    ((5, 4, 4), synth.tensor3d_field(6, (5, 4, 4), 20.0))]:
+        off, w, _ = oracle.stencil(D)
+        assert np.abs(off).max() >= 3
+        n = D.shape[1]
+        A = oracle.operator_matrix(dims, off, w, reflect=True).toarray()
+        Ad = brute.dense_operator_from_energy(
+            lambda v: oracle.energy(dims, off, w, v, reflect=True), n)
+        assert np.abs(A - Ad).max() <= 1e-12 * np.abs(Ad).max()
+        assert np.abs(A - A.T).max() <= 1e-15 * np.abs(A).max()
+        assert np.abs(A.sum(1)).max() <= 1e-12 * np.abs(A).max()
+
+
+def _mirror_field(D, dims):
+    """The tensor field on the doubled grid (2 n per axis) that the even
+    extension of u sees: D at the mirror image of each point, with the
+    off-diagonal entries of every mirrored axis negated (D -> M D M, M the
+    reflection)."""
+    d = len(dims)
+    big = tuple(2 * n for n in dims)
+    idx = np.indices(big[::-1]).reshape(d, -1)[::-1]  # x, y[, z]
+    src = np.zeros(idx.shape[1], np.int64)
+    sgn = np.ones((d, idx.shape[1]))
+    stride = 1
+    for c in range(d):
+        m = idx[c]
+        flip = m >= dims[c]
+        src += np.where(flip, 2 * dims[c] - 1 - m, m) * stride
+        sgn[c] = np.where(flip, -1.0, 1.0)
+        stride *= dims[c]
+    pairs = [(0, 0), (0, 1), (1, 1)] if d == 2 else \
+        [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    return np.stack([D[k][src] * sgn[a] * sgn[b] for k, (a, b) in enumerate(pairs)]), big, src
+
+
+def test_reflect_operator_equals_periodic_operator_on_the_even_extension():
+    """On the doubled grid with the mirrored tensor field and periodic
+    wrap, the even extension of u is mapped by the AD-LBR operator to the
+    even extension of A_reflect u (the weight function is unique, Lemma 5,
+    so the mirrored tensor's stencil is the mirrored stencil).  This ties
+    the reflecting mode to the periodic one, which the spectral tests pin."""
+    for dims, D in [((12, 10), synth.tensor2d_field(21, 12, 10, 30.0)),
+                    ((6, 5, 4), synth.tensor3d_field(22, (6, 5, 4), 20.0))]:
+        off, w, _ = oracle.stencil(D)
+        A = oracle.operator_matrix(dims, off, w, reflect=True)
+        Db, big, src = _mirror_field(D, dims)
+        ob, wb, _ = oracle.stencil(Db)
+        Ap = oracle.operator_matrix(big, ob, wb, periodic=True)
+        u = synth.uniform(3, D.shape[1])
+        ub = u[src]
+        # the base block of the doubled grid: every coordinate below n
+        base = np.ones(src.size, bool)
+        idx = np.indices(big[::-1]).reshape(len(dims), -1)[::-1]
+        for c in range(len(dims)):
+            base &= idx[c] < dims[c]
+        got = (Ap @ ub)[base]
+        ref = A @ u
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
