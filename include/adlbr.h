@@ -71,7 +71,7 @@ typedef enum { ADLBR_F64 = 0, ADLBR_F32 = 1, ADLBR_BF16 = 2, ADLBR_F16 = 3 } adl
  * dropped (ADLBR_NEUMANN: the truncation V(z;h) of Section 1), wrapped
  * (ADLBR_PERIODIC) or mirrored back at the half-sample points -1/2 and
  * n - 1/2 (ADLBR_REFLECT: u extended evenly, the reflecting boundary of the
- * restoration test, Section 5).  A folded target that is the point itself
+ * restoration test, Section 4).  A folded target that is the point itself
  * is no edge. */
 typedef enum { ADLBR_NEUMANN = 0, ADLBR_PERIODIC = 1, ADLBR_REFLECT = 2 } adlbr_boundary;
 
@@ -169,7 +169,7 @@ int adlbr_operator_destroy(adlbr_operator *op);
 /* Rebuild op in place from new stencils of the same grid (offsets and
  * weights as for adlbr_operator_create; the storage dtype and flags stay):
  * the stencils change when D does, e.g. every few steps of coherence-
- * enhancing diffusion (Section 5).  The operator keeps its workspace and
+ * enhancing diffusion (Section 4).  The operator keeps its workspace and
  * every device address in it, so batches and captured graphs that use op
  * stay valid.  Asynchronous on `stream`; status as for create. */
 int adlbr_operator_rebuild(adlbr_operator *op, const int16_t *offsets, const void *weights,
@@ -187,7 +187,7 @@ int adlbr_operator_diagonal(adlbr_operator *op, void *diag, int dtype,
  * alias. */
 int adlbr_apply(adlbr_operator *op, const void *u, void *Au, void *stream);
 
-/* Explicit Euler, u^{n+1} = u^n - dt A u^n (Section 5), nsteps times.
+/* Explicit Euler, u^{n+1} = u^n - dt A u^n (Section 4), nsteps times.
  * u: device [N] in/out (storage dtype); u_tmp: device [N] scratch of the
  * same dtype.  dt_mode ADLBR_DT_ABS: dt is the step; ADLBR_DT_CFL: the step
  * is dt * (1 / max A_zz), read on the device (no synchronization). */
@@ -195,6 +195,17 @@ int adlbr_apply(adlbr_operator *op, const void *u, void *Au, void *stream);
 #define ADLBR_DT_CFL 1
 int adlbr_step(adlbr_operator *op, void *u, void *u_tmp, double dt,
                int dt_mode, int64_t nsteps, void *stream);
+
+/* Explicit steps of a vector-valued image (the Conclusion: AD-LBR applies to
+ * each component independently; the components are coupled only through
+ * the common tensor, e.g. adlbr_structure_tensor_vec).
+ * u, u_tmp: device [ncomp][N] planes of the storage dtype (u in/out).  Up
+ * to four components share one kernel that loads each row's stencil and
+ * incoming lists once; every component is bit-identical to adlbr_step on
+ * that component alone.  List layout only (ADLBR_E_UNSUPPORTED for the
+ * tiled layout). */
+int adlbr_step_multi(adlbr_operator *op, void *u, void *u_tmp, int ncomp, double dt,
+                     int dt_mode, int64_t nsteps, void *stream);
 
 /* ------------------------------------------------------------------ *
  * Batched explicit steps (an extension: many images and volumes of uneven
@@ -248,7 +259,7 @@ int adlbr_batch_destroy(adlbr_batch *batch);
 
 /* ------------------------------------------------------------------ *
  * Solution-dependent diffusion tensor from the structure tensor
- * (Section 5, coherence-enhancing diffusion; edge-enhancing in 3D):
+ * (Section 4, coherence-enhancing diffusion; edge-enhancing in 3D):
  *   u_sigma = K_sigma * u, J = K_rho * (grad u_sigma grad u_sigma^T),
  *   D = sum_k lambda_k v_k v_k^T over the eigenpairs (mu_k, v_k) of J,
  *   mu_1 >= mu_2 (>= mu_3), with
@@ -272,6 +283,16 @@ int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
                            const adlbr_tensor_params *p, void *D,
                            void *workspace, size_t ws_bytes, void *stream);
 
+/* The common tensor of a vector-valued image (the Conclusion leaves the
+ * coupling of components to the tensor, which is the caller's choice; this
+ * is the usual one): J = K_rho * sum_c grad u_c,sigma grad u_c,sigma^T over
+ * the ncomp >= 1 components, then the same eigenvalue map.  u: device
+ * [ncomp][N] planes of dtype; the workspace is the single-component size.
+ * ncomp = 1 is adlbr_structure_tensor (bit-identical). */
+int adlbr_structure_tensor_vec(const adlbr_grid *g, const void *u, int ncomp, int dtype,
+                               const adlbr_tensor_params *p, void *D,
+                               void *workspace, size_t ws_bytes, void *stream);
+
 /* adlbr_structure_tensor without a workspace argument, for callers that
  * cannot allocate device memory (code under HIP graph capture, serving
  * loops, harnesses that forbid hipMalloc).  The scratch is a device array
@@ -288,7 +309,7 @@ int adlbr_structure_tensor_noalloc(const adlbr_grid *g, const void *u, int dtype
 /* ------------------------------------------------------------------ *
  * Implicit step: solve K x = b with K = I + dt A by conjugate gradients.
  * This is the linear system of the restoration problem
- * -lambda div(D grad u) + u = v (Section 5, eq. (elliptic), lambda = dt,
+ * -lambda div(D grad u) + u = v (Section 4, eq. (elliptic), lambda = dt,
  * which the paper solves by CG) and of one backward-Euler step of the
  * diffusion equation.  Vectors are in the operator's storage dtype, which
  * must be ADLBR_F32 or ADLBR_F64; scalars and dot products are FP64, and

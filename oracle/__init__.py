@@ -57,7 +57,7 @@ def _load():
         lib.or_stencil3d.argtypes = [P, I64, P, P, P]
         lib.or_operator_coo.argtypes = [ctypes.c_int, P, ctypes.c_int, P, P, P, P, P]
         lib.or_operator_coo.restype = I64
-        lib.or_structure_tensor_d.argtypes = [ctypes.c_int, P, P, ctypes.c_double,
+        lib.or_structure_tensor_d.argtypes = [ctypes.c_int, P, P, ctypes.c_int, ctypes.c_double,
                                               ctypes.c_double, ctypes.c_double,
                                               ctypes.c_double, ctypes.c_int, P]
         _lib = lib
@@ -146,7 +146,7 @@ def operator_matrix(dims, off, w, periodic: bool = False, reflect: bool = False)
     its gradient flow, Section 1), assembled by scattering every directed
     edge; Neumann truncation V(z; h) drops edges leaving the grid,
     periodic wraps them, reflect mirrors them back into the grid (the
-    reflecting boundary of the restoration test, Section 5).
+    reflecting boundary of the restoration test, Section 4).
     Returns a scipy.sparse CSR matrix (duplicates summed)."""
     import scipy.sparse as sp
     dims = tuple(int(d) for d in dims)
@@ -180,7 +180,7 @@ def apply(A, u):
 
 
 def explicit_steps(A, u0, dt: float, nsteps: int):
-    """Explicit Euler u^{n+1} = u^n - dt A u^n (Section 5, CED time
+    """Explicit Euler u^{n+1} = u^n - dt A u^n (Section 4, CED time
     discretization), in FP64."""
     u = np.array(u0, dtype=np.float64)
     for _ in range(nsteps):
@@ -226,24 +226,27 @@ CED, EED = 0, 1
 
 
 def structure_tensor_d(u, dims, sigma, rho, alpha, C, eig_map: int = CED):
-    """Diffusion tensor from the structure tensor of u (Section 5:
+    """Diffusion tensor from the structure tensor of u (Section 4:
     coherence-enhancing diffusion in 2D and 3D, edge-enhancing in 3D).
-    Returns D (3, N) in 2D or (6, N) in 3D, FP64."""
+    u of shape (C, N) is a vector-valued image whose components share the
+    tensor built from the sum of their gradient products (the Conclusion
+    leaves that coupling to the tensor).  Returns D (3, N) in 2D or (6, N)
+    in 3D, FP64."""
     dims = tuple(int(d) for d in dims)
     dim = len(dims)
-    u = _f64(u)
-    n = u.size
+    n = int(np.prod(dims))
+    u = _f64(u).reshape(-1, n)
     nd = np.array(list(dims) + [1] * (3 - dim), np.int64)
     D = np.zeros((3 if dim == 2 else 6, n), np.float64)
-    _load().or_structure_tensor_d(dim, _p(nd), _p(u), float(sigma), float(rho),
-                                  float(alpha), float(C), int(eig_map), _p(D))
+    _load().or_structure_tensor_d(dim, _p(nd), _p(u), int(u.shape[0]), float(sigma),
+                                  float(rho), float(alpha), float(C), int(eig_map), _p(D))
     return D
 
 
 # ------------------------------------------------------------ restoration --
 
 def restoration_exact(n: int, kappa: float, lam: float, alpha: float = 1.0 / 3.0):
-    """Exact solution of the restoration test (Section 5, eq. (elliptic),
+    """Exact solution of the restoration test (Section 4, eq. (elliptic),
     -lambda div(D grad u) + u = v on the whole plane) at the n x n cell
     centres of the unit square: u = u0 o f with f(x, y) = (x, y +
     alpha cos(2 pi x)), where u0 solves the one-dimensional problem

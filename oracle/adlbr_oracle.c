@@ -410,7 +410,7 @@ static int64_t mirror(int64_t i, int64_t n);
  * dims: n[0..dim-1]; mode 0 drops an edge whose target leaves the grid
  * (Neumann truncation V(z;h), Section 1), mode 1 wraps it (periodic),
  * mode 2 reflects it back (half-sample mirror: the even extension of u,
- * the reflecting boundary of the restoration test, Section 5).  Returns
+ * the reflecting boundary of the restoration test, Section 4).  Returns
  * the number of triplets. */
 int64_t or_operator_coo(int dim, const int64_t *nd, int mode,
                         const int16_t *off, const double *w,
@@ -591,15 +591,18 @@ static double coherence(double C, double dmu)
     return exp(-C / (dmu * dmu));
 }
 
-/* Structure-tensor diffusion tensor (Section 5: coherence-enhancing
+/* Structure-tensor diffusion tensor (Section 4: coherence-enhancing
  * diffusion in 2D and 3D; edge-enhancing variant for 3D):
  * u_sigma = K_sigma * u, J = K_rho * (grad u_sigma grad u_sigma^T),
+ * for a vector-valued image (ncomp planes of n values) the sum of the
+ * components' products grad u_c,sigma grad u_c,sigma^T before the K_rho
+ * blur (the common tensor; the Conclusion leaves the coupling to it),
  * D = sum lambda_k v_k v_k^T with the eigenvalue map `map`:
  *   map 0 (CED): lambda_1 = alpha, lambda_k = alpha + (1-alpha) exp(-C/(mu_1-mu_k)^2)
  *   map 1 (EED): lambda_k = 1 - exp(-C/mu_k^2) for k < d, lambda_d = 1
  * sigma, rho are standard deviations; kernels truncated at ceil(3 s) and
  * normalized; mirror boundary; central differences. */
-int or_structure_tensor_d(int dim, const int64_t *nd, const double *u,
+int or_structure_tensor_d(int dim, const int64_t *nd, const double *u, int ncomp,
                           double sigma, double rho, double alpha, double C,
                           int map, double *Dout)
 {
@@ -607,32 +610,26 @@ int or_structure_tensor_d(int dim, const int64_t *nd, const double *u,
     int nj = dim == 2 ? 3 : 6;
     double *us = (double *)malloc(sizeof(double) * n);
     double *tmp = (double *)malloc(sizeof(double) * n);
-    double *J = (double *)malloc(sizeof(double) * n * nj);
+    double *J = (double *)calloc((size_t)(n * nj), sizeof(double));
     double *Js = (double *)malloc(sizeof(double) * n);
-    blur(u, us, tmp, dim, nd, sigma);
-    int64_t nx = nd[0], ny = nd[1], nz = dim == 3 ? nd[2] : 1;
-    for (int64_t z = 0; z < n; ++z) {
-        int64_t p[3] = {z % nx, (z / nx) % ny, z / (nx * ny)};
-        int64_t st[3] = {1, nx, nx * ny};
-        double g[3] = {0.0, 0.0, 0.0};
-        for (int c = 0; c < dim; ++c) {
-            int64_t ip = reflect(p[c] + 1, nd[c]), im = reflect(p[c] - 1, nd[c]);
-            g[c] = 0.5 * (us[z + (ip - p[c]) * st[c]] - us[z + (im - p[c]) * st[c]]);
-        }
-        if (dim == 2) {
-            J[0 * n + z] = g[0] * g[0];
-            J[1 * n + z] = g[0] * g[1];
-            J[2 * n + z] = g[1] * g[1];
-        } else {
-            J[0 * n + z] = g[0] * g[0];
-            J[1 * n + z] = g[0] * g[1];
-            J[2 * n + z] = g[0] * g[2];
-            J[3 * n + z] = g[1] * g[1];
-            J[4 * n + z] = g[1] * g[2];
-            J[5 * n + z] = g[2] * g[2];
+    int64_t nx = nd[0], ny = nd[1];
+    for (int comp = 0; comp < ncomp; ++comp) {
+        blur(u + comp * n, us, tmp, dim, nd, sigma);
+        for (int64_t z = 0; z < n; ++z) {
+            int64_t p[3] = {z % nx, (z / nx) % ny, z / (nx * ny)};
+            int64_t st[3] = {1, nx, nx * ny};
+            double g[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < dim; ++c) {
+                int64_t ip = reflect(p[c] + 1, nd[c]), im = reflect(p[c] - 1, nd[c]);
+                g[c] = 0.5 * (us[z + (ip - p[c]) * st[c]] - us[z + (im - p[c]) * st[c]]);
+            }
+            /* upper triangle of g g^T, row by row */
+            int q = 0;
+            for (int a = 0; a < dim; ++a)
+                for (int b = a; b < dim; ++b, ++q)
+                    J[q * n + z] += g[a] * g[b];
         }
     }
-    (void)nz;
     for (int k = 0; k < nj; ++k) {
         blur(J + k * n, Js, tmp, dim, nd, rho);
         memcpy(J + k * n, Js, sizeof(double) * n);

@@ -4,7 +4,7 @@ INFRASTRUCTURE ONLY.
 The implicit step of the diffusion equation, (I + dt A) x = b with A the
 AD-LBR operator, is the linear system the paper solves by conjugate
 gradients for the restoration problem -lambda div(D grad u) + u = v
-(Section 5, eq. (elliptic)).  Here:
+(Section 4, eq. (elliptic)).  Here:
 
   jacobi_pcg   textbook preconditioned CG with P = diag(K)
   fcg          flexible CG (truncation 1, Polak-Ribiere form) for a

@@ -239,6 +239,20 @@ class Operator:
         return u
 
 
+    def step_multi(self, u, dt: float, nsteps: int, cfl_fraction: bool = False, u_tmp=None,
+                   stream=None):
+        """nsteps explicit steps of every component of u ([C, N], in place)
+        with this one operator (adlbr_step_multi)."""
+        torch = _torch()
+        _require_cuda(u)
+        if u.dim() != 2 or u.shape[1] != self.N or u.dtype != self.storage:
+            raise ValueError(f"u must be [C, {self.N}] of {self.storage}")
+        u_tmp = torch.empty_like(u) if u_tmp is None else u_tmp
+        mode = capi.DT_CFL if cfl_fraction else capi.DT_ABS
+        capi.check(capi.load().adlbr_step_multi(self._h, _ptr(u), _ptr(u_tmp), int(u.shape[0]),
+                                                float(dt), mode, int(nsteps), _stream(stream)))
+        return u
+
     def solve(self, b, dt: float, method: str = "jacobi", tol: float = 1e-6,
               max_iter: int = 10000, check_every: int = 10, x=None, net=None,
               workspace=None, stream=None):
@@ -338,7 +352,10 @@ class Batch:
 
 def structure_tensor(u, dims, sigma: float, rho: float, alpha: float, C: float,
                      eig_map: str = "ced", out=None, workspace=None, stream=None):
-    """Diffusion tensor from the structure tensor of u (adlbr_structure_tensor)."""
+    """Diffusion tensor from the structure tensor of u (adlbr_structure_tensor).
+    u of shape [C, N] is a vector-valued image: its components share one
+    tensor built from the sum of their gradient products
+    (adlbr_structure_tensor_vec)."""
     torch = _torch()
     lib = capi.load()
     _require_cuda(u)
@@ -350,12 +367,23 @@ def structure_tensor(u, dims, sigma: float, rho: float, alpha: float, C: float,
     if workspace is None or workspace.numel() < nbytes.value:
         workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=u.device)
     nj = 3 if len(dims) == 2 else 6
-    out = torch.empty((nj, u.numel()), dtype=u.dtype, device=u.device) if out is None else out
+    npts = 1
+    for d in dims:
+        npts *= d
+    if u.dim() not in (1, 2) or u.shape[-1] != npts or not u.is_contiguous():
+        raise ValueError(f"u must be a contiguous [{npts}] or [C, {npts}] tensor")
+    out = torch.empty((nj, npts), dtype=u.dtype, device=u.device) if out is None else out
     p = capi.TensorParams(float(sigma), float(rho), float(alpha), float(C),
                           capi.MAP_CED if eig_map == "ced" else capi.MAP_EED)
-    capi.check(lib.adlbr_structure_tensor(ctypes.byref(g), _ptr(u), code, ctypes.byref(p),
-                                          _ptr(out), _ptr(workspace), workspace.numel(),
-                                          _stream(stream)))
+    if u.dim() == 1:
+        capi.check(lib.adlbr_structure_tensor(ctypes.byref(g), _ptr(u), code, ctypes.byref(p),
+                                              _ptr(out), _ptr(workspace), workspace.numel(),
+                                              _stream(stream)))
+    else:
+        capi.check(lib.adlbr_structure_tensor_vec(ctypes.byref(g), _ptr(u), int(u.shape[0]),
+                                                  code, ctypes.byref(p), _ptr(out),
+                                                  _ptr(workspace), workspace.numel(),
+                                                  _stream(stream)))
     return out
 
 

@@ -85,6 +85,7 @@ SIGNATURES = {
                                ctypes.POINTER(_P)], _I),
     "adlbr_operator_destroy": ([_P], _I),
     "adlbr_operator_rebuild": ([_P, _P, _P, _I, _P, _P], _I),
+    "adlbr_step_multi": ([_P, _P, _P, _I, _D, _I, _I64, _P], _I),
     "adlbr_operator_dt_cfl": ([_P, ctypes.POINTER(_D), _P], _I),
     "adlbr_operator_diagonal": ([_P, _P, _I, _P], _I),
     "adlbr_apply": ([_P, _P, _P, _P], _I),
@@ -102,6 +103,8 @@ SIGNATURES = {
     "adlbr_solve": ([_P, _D, _P, _P, ctypes.POINTER(SolveParams), _P, _SZ,
                      ctypes.POINTER(SolveReport), _P], _I),
     "adlbr_structure_tensor": ([_GP, _P, _I, ctypes.POINTER(TensorParams), _P, _P, _SZ, _P], _I),
+    "adlbr_structure_tensor_vec": ([_GP, _P, _I, _I, ctypes.POINTER(TensorParams), _P, _P, _SZ,
+                                    _P], _I),
     "adlbr_structure_tensor_noalloc": ([_GP, _P, _I, ctypes.POINTER(TensorParams), _P, _P], _I),
     "adlbr_net_param_count": ([_I, _I, _I, ctypes.POINTER(_SZ)], _I),
     "adlbr_net_features": ([_P, _D, _P, _P], _I),

@@ -1533,6 +1533,79 @@ __global__ __launch_bounds__(kBS) void k_apply(
         pos, ent, went, h);
 }
 
+
+// Explicit step of a vector-valued image, ncomp <= kMaxComp components
+// [c][N] stepped with one operator (the paper's extension to vector-valued
+// images: each component independently, coupled only through the common
+// tensor).  A wave loads its rows' slots, weights and incoming entries once
+// and uses them for every component; each component's arithmetic is the
+// single-component kernel's in the same order, so every component comes out
+// bit-identical to stepping it alone.
+constexpr int kMaxComp = 4;
+
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA>
+__global__ __launch_bounds__(kBS) void k_step_multi(
+    GridInfo g, int ncomp, const TS *__restrict__ u, TS *__restrict__ out,
+    const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
+    const int32_t *__restrict__ pos, const int32_t *__restrict__ ent,
+    const EntRec<TS> *__restrict__ went, double dt, const double *__restrict__ dtcfl,
+    int dt_mode) {
+    constexpr int kPre = kPreOf<TA>;
+    constexpr int S = DIM == 2 ? 3 : 6;
+    const TA h = (TA)(dt_mode == ADLBR_DT_CFL ? dt * dtcfl[0] : dt);
+    const long long blk = strip_block(xcd_block(blockIdx.x, gridDim.x), g, kApplyPoints);
+    const long long N = g.N;
+    const int lane = (int)(threadIdx.x & 63u);
+    const long long z0 = wave_group(g, blk, 1);
+    const long long z = z0 + lane;
+    const WaveLists L = wave_lists(pos, z, N);
+    TA uz[kMaxComp], acc[kMaxComp], owns[kMaxComp];
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+        uz[c] = acc[c] = owns[c] = (TA)0;
+        if (c < ncomp) {
+            uz[c] = z < N ? Conv<TS, TA>::ld(u[c * N + z]) : (TA)0;
+            OwnPart<DIM, WIDE, PER, TS, TA, TS> own;
+            own.issue(g, z, z < N, uz[c], u + c * N, sb, w);
+            owns[c] = own.sum(uz[c]);
+        }
+    }
+    for (unsigned eb = 0; eb < L.total; eb += 64 * kPre) {
+        int32_t v[kPre];
+        TS wv[kPre];
+#pragma unroll
+        for (int j = 0; j < kPre; ++j) {
+            const unsigned e = eb + 64 * j + lane;
+            if (kInlineW<DIM>) {
+                load_rec<TS>(went, ent, L.start + e, e < L.total, v[j], wv[j]);
+            } else {
+                v[j] = e < L.total ? ent[L.start + e] : -1;
+                wv[j] = TS{};
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kMaxComp; ++c) {
+            if (c >= ncomp) continue;
+            InEdge<kInlineW<DIM>, S, TS, TA, TS> ie[kPre];
+            TA val[kPre];
+#pragma unroll
+            for (int j = 0; j < kPre; ++j)
+                ie[j].issue(L, z0, N, uz[c], v[j], wv[j], eb + 64 * j, u + c * N, w);
+#pragma unroll
+            for (int j = 0; j < kPre; ++j) val[j] = ie[j].value();
+#pragma unroll
+            for (int j = 0; j < kPre; ++j) acc[c] += incoming_reduce<TA>(L, v[j], val[j], eb + 64 * j);
+        }
+    }
+    if (z >= N) return;
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c)
+        if (c < ncomp) {
+            const TA a = acc[c] + owns[c];
+            out[c * N + z] = Conv<TS, TA>::st(uz[c] - h * a);
+        }
+}
+
 // The problem that block b belongs to (first_block ascending): the lanes of
 // a wave test 64 descriptors at once and the highest lane whose first block
 // is <= b wins, so the search costs one round of loads, not a chain of
@@ -2352,6 +2425,19 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct BatchF 
     }
 };
 
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct MultiF {
+    static int run(const adlbr_operator *op, const void *u, void *out, int ncomp, double dt,
+                   int mode, hipStream_t s) {
+        typedef typename Slots<DIM, WIDE>::store_t store_t;
+        const unsigned nb = (unsigned)((op->gi.N + kApplyPoints - 1) / kApplyPoints);
+        hipLaunchKernelGGL((k_step_multi<DIM, WIDE, PER, TS, TA>), dim3(nb), dim3(kBS), 0, s,
+                           op->gi, ncomp, (const TS *)u, (TS *)out, (const store_t *)op->sb,
+                           (const TS *)op->w, op->pos, op->ent, (const EntRec<TS> *)op->went, dt,
+                           op->dtcfl, mode);
+        return ADLBR_OK;
+    }
+};
+
 template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct CgDirF {
     static int run(const adlbr_operator *op, const void *z, void *q, void *p, CgState *st,
                    double *partial, int first, hipStream_t s) {
@@ -2704,6 +2790,37 @@ extern "C" int adlbr_apply(adlbr_operator *op, const void *u, void *Au, void *st
     int rc = dispatch<ApplyF>(op, u, Au, false, 0.0, 0, as_stream(stream));
     if (rc) return rc;
     ADLBR_LAUNCH_CHECK();
+    return ADLBR_OK;
+}
+
+extern "C" int adlbr_step_multi(adlbr_operator *op, void *u, void *u_tmp, int ncomp, double dt,
+                                int dt_mode, int64_t nsteps, void *stream) {
+    clear_error();
+    if (!op || !u || !u_tmp || u == u_tmp || nsteps < 0 || ncomp < 1 ||
+        (dt_mode != ADLBR_DT_ABS && dt_mode != ADLBR_DT_CFL)) {
+        set_error("adlbr_step_multi: bad argument");
+        return ADLBR_E_INVALID;
+    }
+    if (op->tiled) {
+        set_error("adlbr_step_multi: needs the list layout (create without ADLBR_OP_TILED)");
+        return ADLBR_E_UNSUPPORTED;
+    }
+    hipStream_t s = as_stream(stream);
+    const size_t plane = (size_t)op->gi.N * dtype_size(op->storage);
+    // components in groups of kMaxComp, each group stepped nsteps times
+    for (int c0 = 0; c0 < ncomp; c0 += kMaxComp) {
+        const int nc = std::min(kMaxComp, ncomp - c0);
+        char *ua = (char *)u + c0 * plane, *ub = (char *)u_tmp + c0 * plane;
+        void *a = ua, *b = ub;
+        for (int64_t k = 0; k < nsteps; ++k) {
+            int rc = dispatch<MultiF>(op, (const void *)a, b, nc, dt, dt_mode, s);
+            if (rc) return rc;
+            std::swap(a, b);
+        }
+        ADLBR_LAUNCH_CHECK();
+        if (a != ua)
+            ADLBR_CHECK_HIP(hipMemcpyAsync(ua, a, nc * plane, hipMemcpyDeviceToDevice, s));
+    }
     return ADLBR_OK;
 }
 

@@ -11,7 +11,7 @@
 //
 // Jacobi-PCG per iteration: update (x, r, z = r / diag K, <r,z>, <r,r>,
 // beta) -> direction (q = K z + beta q, p = z + beta p, <p,q>, alpha).
-// Flexible CG (Section 5 solves the restoration system by CG; the flexible
+// Flexible CG (Section 4 solves the restoration system by CG; the flexible
 // variant admits the learned preconditioner): update (x, r, <r,r>) ->
 // z = N(r) with the dots <z,r>, <z,r_prev> -> scalars (|r|^2 checks, beta)
 // -> direction.

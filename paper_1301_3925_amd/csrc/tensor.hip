@@ -1,5 +1,5 @@
 // Solution-dependent diffusion tensor from the structure tensor
-// (Section 5: coherence-enhancing diffusion, 2D and 3D; edge-enhancing
+// (Section 4: coherence-enhancing diffusion, 2D and 3D; edge-enhancing
 // diffusion in 3D):
 //   u_sigma = K_sigma * u,  J = K_rho * (grad u_sigma grad u_sigma^T),
 //   D = sum_k lambda_k v_k v_k^T over the eigenpairs of J.
@@ -85,8 +85,10 @@ __global__ void k_blur(GridInfo g, const T *__restrict__ in, T *__restrict__ out
 }
 
 // grad u_sigma by central differences (mirror boundary), outer products.
+// add != 0 adds the products to J (the next component of a vector-valued
+// image) instead of overwriting it.
 template <typename T>
-__global__ void k_grad_outer(GridInfo g, const T *__restrict__ us, T *__restrict__ J) {
+__global__ void k_grad_outer(GridInfo g, const T *__restrict__ us, T *__restrict__ J, int add) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long N = g.N;
     if (i >= N) return;
@@ -100,19 +102,16 @@ __global__ void k_grad_outer(GridInfo g, const T *__restrict__ us, T *__restrict
     const T gy = half * (us[i + (long long)(mirror(y + 1, ny) - y) * nx] -
                          us[i + (long long)(mirror(y - 1, ny) - y) * nx]);
     if (g.dim == 2) {
-        J[i] = gx * gx;
-        J[N + i] = gx * gy;
-        J[2 * N + i] = gy * gy;
+        const T p[3] = {gx * gx, gx * gy, gy * gy};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) J[k * N + i] = add ? J[k * N + i] + p[k] : p[k];
     } else {
         const long long sz = (long long)nx * ny;
         const T gz = half * (us[i + (long long)(mirror(z + 1, g.nz) - z) * sz] -
                              us[i + (long long)(mirror(z - 1, g.nz) - z) * sz]);
-        J[i] = gx * gx;
-        J[N + i] = gx * gy;
-        J[2 * N + i] = gx * gz;
-        J[3 * N + i] = gy * gy;
-        J[4 * N + i] = gy * gz;
-        J[5 * N + i] = gz * gz;
+        const T p[6] = {gx * gx, gx * gy, gx * gz, gy * gy, gy * gz, gz * gz};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) J[k * N + i] = add ? J[k * N + i] + p[k] : p[k];
     }
 }
 
@@ -240,57 +239,78 @@ __global__ void k_eigmap3(long long N, const T *__restrict__ J, T *__restrict__ 
 constexpr int kTile = 32;
 
 template <typename T, int RS>
-__global__ __launch_bounds__(256) void k_st_grad_tiled(int nx, int ny, const T *__restrict__ u,
+__global__ __launch_bounds__(256) void k_st_grad_tiled(int nx, int ny, int ncomp,
+                                                       const T *__restrict__ u,
                                                        T *__restrict__ J, Taps ts) {
     constexpr int E = kTile + 2 + 2 * RS;   // u region edge
     constexpr int EU = kTile + 2;           // u_sigma region edge
+    constexpr int KO = kTile * kTile / 256;  // outputs per thread
+    static_assert(kTile * kTile % 256 == 0, "whole outputs per thread");
     __shared__ T su[E * E];
     __shared__ T sx[E * EU];                // blurred along x
     __shared__ T ss[EU * EU];               // u_sigma
     const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
-    {  // all of a thread's loads, then its LDS stores
-        constexpr int B = (E * E + 255) / 256;
-        T v[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const int k0 = b * 256 + (int)threadIdx.x, k = k0 < E * E ? k0 : 0;
-            const int gx = mirror(x0 - 1 - RS + k % E, nx), gy = mirror(y0 - 1 - RS + k / E, ny);
-            v[b] = u[(long long)gy * nx + gx];
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b)
-            if (b * 256 + (int)threadIdx.x < E * E) su[b * 256 + threadIdx.x] = v[b];
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < E * EU; k += 256) {
-        const int yy = k / EU, xx = k % EU;
-        T a = (T)0;
-#pragma unroll
-        for (int j = 0; j <= 2 * RS; ++j) a += tap<T>(ts, j) * su[yy * E + xx + j];
-        sx[k] = a;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < EU * EU; k += 256) {
-        const int yy = k / EU, xx = k % EU;
-        T a = (T)0;
-#pragma unroll
-        for (int j = 0; j <= 2 * RS; ++j) a += tap<T>(ts, j) * sx[(yy + j) * EU + xx];
-        ss[k] = a;
-    }
-    __syncthreads();
     const long long N = (long long)nx * ny;
-    for (int k = threadIdx.x; k < kTile * kTile; k += 256) {
+    T jxx[KO], jxy[KO], jyy[KO];
+#pragma unroll
+    for (int o = 0; o < KO; ++o) jxx[o] = jxy[o] = jyy[o] = (T)0;
+    for (int c = 0; c < ncomp; ++c) {
+        const T *uc = u + c * N;
+        {  // all of a thread's loads, then its LDS stores
+            constexpr int B = (E * E + 255) / 256;
+            T v[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int k0 = b * 256 + (int)threadIdx.x, k = k0 < E * E ? k0 : 0;
+                const int gx = mirror(x0 - 1 - RS + k % E, nx), gy = mirror(y0 - 1 - RS + k / E, ny);
+                v[b] = uc[(long long)gy * nx + gx];
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (b * 256 + (int)threadIdx.x < E * E) su[b * 256 + threadIdx.x] = v[b];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < E * EU; k += 256) {
+            const int yy = k / EU, xx = k % EU;
+            T a = (T)0;
+#pragma unroll
+            for (int j = 0; j <= 2 * RS; ++j) a += tap<T>(ts, j) * su[yy * E + xx + j];
+            sx[k] = a;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < EU * EU; k += 256) {
+            const int yy = k / EU, xx = k % EU;
+            T a = (T)0;
+#pragma unroll
+            for (int j = 0; j <= 2 * RS; ++j) a += tap<T>(ts, j) * sx[(yy + j) * EU + xx];
+            ss[k] = a;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < KO; ++o) {
+            const int k = o * 256 + (int)threadIdx.x;
+            const int ty = k / kTile, tx = k % kTile;
+            const int cc = (ty + 1) * EU + (tx + 1);
+            const T half = (T)0.5;
+            const T gxv = half * (ss[cc + 1] - ss[cc - 1]);
+            const T gyv = half * (ss[cc + EU] - ss[cc - EU]);
+            jxx[o] += gxv * gxv;
+            jxy[o] += gxv * gyv;
+            jyy[o] += gyv * gyv;
+        }
+        // the next component overwrites su, sx and ss
+        __syncthreads();
+    }
+#pragma unroll
+    for (int o = 0; o < KO; ++o) {
+        const int k = o * 256 + (int)threadIdx.x;
         const int ty = k / kTile, tx = k % kTile;
         const int gx = x0 + tx, gy = y0 + ty;
         if (gx >= nx || gy >= ny) continue;
-        const int c = (ty + 1) * EU + (tx + 1);
-        const T half = (T)0.5;
-        const T gxv = half * (ss[c + 1] - ss[c - 1]);
-        const T gyv = half * (ss[c + EU] - ss[c - EU]);
         const long long i = (long long)gy * nx + gx;
-        J[i] = gxv * gxv;
-        J[N + i] = gxv * gyv;
-        J[2 * N + i] = gyv * gyv;
+        J[i] = jxx[o];
+        J[N + i] = jxy[o];
+        J[2 * N + i] = jyy[o];
     }
 }
 
@@ -410,13 +430,14 @@ __global__ __launch_bounds__(256) void k_st_smooth_map_tiled(int nx, int ny,
 
 // The tiled path covers the common radii (sigma <= 1: r_sigma <= 3;
 // rho <= 4: r_rho <= 12) in FP32; other cases use the streaming passes.
-template <typename T> bool run_tensor_tiled(const GridInfo &g, const T *u, const Taps &ts,
-                                            const Taps &tr, const adlbr_tensor_params *p, T *D,
-                                            T *wa, hipStream_t s) {
+template <typename T> bool run_tensor_tiled(const GridInfo &g, const T *u, int ncomp,
+                                            const Taps &ts, const Taps &tr,
+                                            const adlbr_tensor_params *p, T *D, T *wa,
+                                            hipStream_t s) {
     if (g.dim != 2 || sizeof(T) != 4) return false;
     const dim3 grid((g.nx + kTile - 1) / kTile, (g.ny + kTile - 1) / kTile);
 #define ADLBR_ST1(RS)                                                                       \
-    if (ts.r == RS) hipLaunchKernelGGL((k_st_grad_tiled<T, RS>), grid, dim3(256), 0, s, g.nx, g.ny, u, wa, ts);
+    if (ts.r == RS) hipLaunchKernelGGL((k_st_grad_tiled<T, RS>), grid, dim3(256), 0, s, g.nx, g.ny, ncomp, u, wa, ts);
     if (ts.r < 1 || ts.r > 3) return false;
     if (tr.r < 1 || tr.r > 12) return false;
     ADLBR_ST1(1) ADLBR_ST1(2) ADLBR_ST1(3)
@@ -430,31 +451,40 @@ template <typename T> bool run_tensor_tiled(const GridInfo &g, const T *u, const
     return true;
 }
 
+// u holds ncomp planes of N values; J sums the gradient outer products of
+// every component (the common tensor of a vector-valued image).  The
+// workspace halves wa, wb (nj N values each): in 2D J gathers in wa and the
+// per-component blur passes use wb; in 3D the other way round.
 template <typename T>
-int run_tensor(const GridInfo &g, const T *u, const adlbr_tensor_params *p, T *D, T *wa, T *wb,
-               hipStream_t s) {
+int run_tensor(const GridInfo &g, const T *u, int ncomp, const adlbr_tensor_params *p, T *D,
+               T *wa, T *wb, hipStream_t s) {
     const long long N = g.N;
     const int nj = g.dim == 2 ? 3 : 6;
     const unsigned nb = (unsigned)((N + 255) / 256);
     const Taps ts = make_taps(p->sigma), tr = make_taps(p->rho);
-    if (run_tensor_tiled<T>(g, u, ts, tr, p, D, wa, s)) {
+    if (run_tensor_tiled<T>(g, u, ncomp, ts, tr, p, D, wa, s)) {
         ADLBR_LAUNCH_CHECK();
         return ADLBR_OK;
     }
-    // u_sigma
     if (g.dim == 2) {
-        hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, u, wa, 0, ts);
-        hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, (const T *)wa, wb, 1, ts);
-        hipLaunchKernelGGL(k_grad_outer<T>, dim3(nb), dim3(256), 0, s, g, (const T *)wb, wa);
+        for (int c = 0; c < ncomp; ++c) {  // u_sigma of component c, its products
+            hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, u + c * N, wb, 0, ts);
+            hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, (const T *)wb, wb + N, 1, ts);
+            hipLaunchKernelGGL(k_grad_outer<T>, dim3(nb), dim3(256), 0, s, g, (const T *)(wb + N), wa,
+                               c > 0 ? 1 : 0);
+        }
         hipLaunchKernelGGL(k_blur<T>, dim3(nb, nj), dim3(256), 0, s, g, (const T *)wa, wb, 0, tr);
         hipLaunchKernelGGL(k_blur<T>, dim3(nb, nj), dim3(256), 0, s, g, (const T *)wb, wa, 1, tr);
         hipLaunchKernelGGL(k_eigmap2<T>, dim3(nb), dim3(256), 0, s, N, (const T *)wa, D,
                            (T)p->alpha, (T)p->C, p->eig_map);
     } else {
-        hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, u, wa, 0, ts);
-        hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, (const T *)wa, wb, 1, ts);
-        hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, (const T *)wb, wa, 2, ts);
-        hipLaunchKernelGGL(k_grad_outer<T>, dim3(nb), dim3(256), 0, s, g, (const T *)wa, wb);
+        for (int c = 0; c < ncomp; ++c) {
+            hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, u + c * N, wa, 0, ts);
+            hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, (const T *)wa, wa + N, 1, ts);
+            hipLaunchKernelGGL(k_blur<T>, dim3(nb, 1), dim3(256), 0, s, g, (const T *)(wa + N), wa, 2, ts);
+            hipLaunchKernelGGL(k_grad_outer<T>, dim3(nb), dim3(256), 0, s, g, (const T *)wa, wb,
+                               c > 0 ? 1 : 0);
+        }
         hipLaunchKernelGGL(k_blur<T>, dim3(nb, nj), dim3(256), 0, s, g, (const T *)wb, wa, 0, tr);
         hipLaunchKernelGGL(k_blur<T>, dim3(nb, nj), dim3(256), 0, s, g, (const T *)wa, wb, 1, tr);
         hipLaunchKernelGGL(k_blur<T>, dim3(nb, nj), dim3(256), 0, s, g, (const T *)wb, wa, 2, tr);
@@ -510,12 +540,12 @@ int tensor_args(const char *who, const adlbr_grid *g, const void *u, int dtype,
     return ADLBR_OK;
 }
 
-int tensor_run(const GridInfo &gi, const void *u, int dtype, const adlbr_tensor_params *p,
-               void *D, char *b, size_t half, hipStream_t s) {
+int tensor_run(const GridInfo &gi, const void *u, int ncomp, int dtype,
+               const adlbr_tensor_params *p, void *D, char *b, size_t half, hipStream_t s) {
     if (dtype == ADLBR_F32)
-        return run_tensor<float>(gi, (const float *)u, p, (float *)D, (float *)b,
+        return run_tensor<float>(gi, (const float *)u, ncomp, p, (float *)D, (float *)b,
                                  (float *)(b + half), s);
-    return run_tensor<double>(gi, (const double *)u, p, (double *)D, (double *)b,
+    return run_tensor<double>(gi, (const double *)u, ncomp, p, (double *)D, (double *)b,
                               (double *)(b + half), s);
 }
 
@@ -549,14 +579,18 @@ int scratch_address(char **out) {
 }
 }  // namespace
 
-extern "C" int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
-                                      const adlbr_tensor_params *p, void *D, void *workspace,
-                                      size_t ws_bytes, void *stream) {
+extern "C" int adlbr_structure_tensor_vec(const adlbr_grid *g, const void *u, int ncomp,
+                                          int dtype, const adlbr_tensor_params *p, void *D,
+                                          void *workspace, size_t ws_bytes, void *stream) {
     clear_error();
     GridInfo gi;
     size_t half = 0;
     int rc = tensor_args("adlbr_structure_tensor", g, u, dtype, p, D, &gi, &half);
     if (rc) return rc;
+    if (ncomp < 1) {
+        set_error("adlbr_structure_tensor: ncomp = %d, need at least one component", ncomp);
+        return ADLBR_E_INVALID;
+    }
     if (!workspace) {
         set_error("adlbr_structure_tensor: null workspace");
         return ADLBR_E_INVALID;
@@ -566,7 +600,13 @@ extern "C" int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dt
                   2 * half);
         return ADLBR_E_NOMEM;
     }
-    return tensor_run(gi, u, dtype, p, D, (char *)workspace, half, as_stream(stream));
+    return tensor_run(gi, u, ncomp, dtype, p, D, (char *)workspace, half, as_stream(stream));
+}
+
+extern "C" int adlbr_structure_tensor(const adlbr_grid *g, const void *u, int dtype,
+                                      const adlbr_tensor_params *p, void *D, void *workspace,
+                                      size_t ws_bytes, void *stream) {
+    return adlbr_structure_tensor_vec(g, u, 1, dtype, p, D, workspace, ws_bytes, stream);
 }
 
 extern "C" int adlbr_structure_tensor_noalloc(const adlbr_grid *g, const void *u, int dtype,
@@ -585,5 +625,5 @@ extern "C" int adlbr_structure_tensor_noalloc(const adlbr_grid *g, const void *u
     char *b = nullptr;
     rc = scratch_address(&b);
     if (rc) return rc;
-    return tensor_run(gi, u, dtype, p, D, b, half, as_stream(stream));
+    return tensor_run(gi, u, 1, dtype, p, D, b, half, as_stream(stream));
 }

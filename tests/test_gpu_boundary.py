@@ -2,7 +2,7 @@
 correctness of the GPU operator.
 
 - ADLBR_REFLECT (targets mirrored back into the grid, the reflecting
-  boundary of the restoration test, Section 5): apply, diagonal and CFL
+  boundary of the restoration test, Section 4): apply, diagonal and CFL
   bound against the oracle's reflecting operator (FP64 1e-12, FP32 1e-5) on
   grids whose offsets reach several points past the border, 2D and 3D;
   explicit steps; batches (bit-identical to single steps); the restoration
@@ -130,7 +130,6 @@ def _gpu_smallest_eigenvalues(lib, n, k=7):
     off, w, _ = lib.build_stencils(torch.from_numpy(D).cuda(), (n, n), periodic=True)
     op = lib.Operator((n, n), off, w, storage=torch.float64, periodic=True)
     dt = n * n / (4 * math.pi ** 2 * 2.0)
-    ws = []
 
     def mv(v):
         b = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64).reshape(-1)).cuda()

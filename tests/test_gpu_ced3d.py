@@ -1,4 +1,4 @@
-"""3D coherence-enhancing diffusion end to end (Section 5, the synthetic 3D
+"""3D coherence-enhancing diffusion end to end (Section 4, the synthetic 3D
 experiment): u0 = cos(2 (r/R)^3) with r the distance to the centre of the
 unit cube and R = 1/2, plus Gaussian noise of variance 0.5, on 100^3 voxels;
 sigma = 0.5, rho = 4, alpha = 1e-2, C = 1e-5; 20 explicit steps of

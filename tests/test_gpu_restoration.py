@@ -1,4 +1,4 @@
-"""The restoration test on the GPU (Section 5, the synthetic test with an
+"""The restoration test on the GPU (Section 4, the synthetic test with an
 analytic solution, eq. (elliptic)): -lambda div(D grad u) + u = v on the
 unit square with lambda = 1e-3, discretized as (I + lambda h^-2 A) u = v on
 N x N pixels (h = 1/N), A the AD-LBR operator of the library, solved by the

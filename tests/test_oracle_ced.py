@@ -29,7 +29,7 @@ def _eig2(D):
 
 
 def test_ced2d_spd_eigen_range():
-    """Section 5 (CED): eigenvalues of D are alpha and
+    """Section 4 (CED): eigenvalues of D are alpha and
     alpha + (1 - alpha) exp(-C/(mu1-mu2)^2), so D is SPD with spectrum in
     [alpha, 1] and kappa <= alpha^-1/2."""
     n = (96, 80)
@@ -69,7 +69,7 @@ def test_ced_straight_stripes_orientation():
 
 
 def test_ced3d_spd_eigen_range_and_eed():
-    """3D CED (Section 5, 3D experiments): spectrum in [alpha, 1]; EED
+    """3D CED (Section 4, 3D experiments): spectrum in [alpha, 1]; EED
     tensor: lambda_3 = 1 and the others in (0, 1]."""
     n = (16, 16, 16)
     u = synth.ced_image3d(2003, 16)
@@ -101,7 +101,7 @@ def test_ced_rotation_covariance():
 
 
 # ----------------------------------------------------------------------------
-# Value pins of the whole pipeline (Section 5: u_sigma = K_sigma * u,
+# Value pins of the whole pipeline (Section 4: u_sigma = K_sigma * u,
 # J = K_rho * (grad u_sigma grad u_sigma^T), eigenvalue map).  Two
 # independent routes: a library one (scipy's Gaussian filter with mirror
 # extension, numpy's symmetric eigensolver) on a generic image, and a closed
@@ -115,7 +115,7 @@ def _taps(s):
 
 
 def _eigmap(J, alpha, C, eig_map):
-    """D from J (..., d, d) by the eigenvalue map of Section 5 (CED) or the
+    """D from J (..., d, d) by the eigenvalue map of Section 4 (CED) or the
     edge-enhancing map, eigenvalues taken in descending order."""
     mu, V = np.linalg.eigh(J)          # ascending
     mu, V = mu[..., ::-1], V[..., :, ::-1]
@@ -143,24 +143,29 @@ def _planes(Dm, dim):
 
 
 def _scipy_pipeline(u, dims, sigma, rho, alpha, C, eig_map):
+    """u: one image, or (C, N) components whose products g g^T are summed
+    before the rho blur."""
     from scipy import ndimage
     dim = len(dims)
-    a = u.reshape(dims[::-1])            # axes (z,) y, x
     blur = lambda f, s: ndimage.gaussian_filter(f, s, mode="reflect",
                                                 radius=math.ceil(3 * s))
-    us = blur(a, sigma)
-    pad = np.pad(us, 1, mode="symmetric")  # half-sample mirror
-    g = []
-    for c in range(dim):                   # c = 0 is x, the last array axis
-        ax = dim - 1 - c
-        hi = [slice(1, -1)] * dim
-        lo = [slice(1, -1)] * dim
-        hi[ax], lo[ax] = slice(2, None), slice(None, -2)
-        g.append(0.5 * (pad[tuple(hi)] - pad[tuple(lo)]))
-    J = np.empty(a.shape + (dim, dim))
-    for i in range(dim):
-        for j in range(i, dim):
-            J[..., i, j] = J[..., j, i] = blur(g[i] * g[j], rho)
+    prods = {}
+    for comp in np.asarray(u).reshape(-1, int(np.prod(dims))):
+        a = comp.reshape(dims[::-1])           # axes (z,) y, x
+        pad = np.pad(blur(a, sigma), 1, mode="symmetric")  # half-sample mirror
+        g = []
+        for c in range(dim):                   # c = 0 is x, the last array axis
+            ax = dim - 1 - c
+            hi = [slice(1, -1)] * dim
+            lo = [slice(1, -1)] * dim
+            hi[ax], lo[ax] = slice(2, None), slice(None, -2)
+            g.append(0.5 * (pad[tuple(hi)] - pad[tuple(lo)]))
+        for i in range(dim):
+            for j in range(i, dim):
+                prods[i, j] = prods.get((i, j), 0.0) + g[i] * g[j]
+    J = np.empty(tuple(dims[::-1]) + (dim, dim))
+    for (i, j), pij in prods.items():
+        J[..., i, j] = J[..., j, i] = blur(pij, rho)
     return _planes(_eigmap(J, alpha, C, eig_map), dim)
 
 
@@ -181,7 +186,7 @@ def test_ced2d_matches_scipy_gaussian_pipeline():
 
 def test_ced3d_matches_scipy_gaussian_pipeline():
     """The same library cross-check in 3D, CED and edge-enhancing maps, on
-    a volume of 3D synthetic type (Section 5, 3D experiments)."""
+    a volume of 3D synthetic type (Section 4, 3D experiments)."""
     dims = (15, 13, 12)
     rng = np.random.default_rng(9)
     u = synth.ced_image3d(4, 15)[: np.prod(dims)] + 0.1 * rng.standard_normal(np.prod(dims))
@@ -218,7 +223,7 @@ def _closed_form_J(dims, a, b, m, sigma, rho):
 
 
 def test_ced3d_closed_form_three_distinct_eigenvalues():
-    """3D eigenvalue assignment (Section 5, 3D CED; edge-enhancing map).
+    """3D eigenvalue assignment (Section 4, 3D CED; edge-enhancing map).
     For u = a cos(kx x') + b cos(ky y'), constant in z, J is known in closed
     form: mu_3 = 0 on e_z, and mu_1 > mu_2 > 0 in the x-y plane.  C is set
     so that the three CED eigenvalues alpha, lambda_2, lambda_3 are far
@@ -250,7 +255,7 @@ def test_ced3d_closed_form_three_distinct_eigenvalues():
 
 
 def test_ced2d_closed_form():
-    """2D counterpart of the closed form (Section 5, CED): distinct mu_1 >
+    """2D counterpart of the closed form (Section 4, CED): distinct mu_1 >
     mu_2 at interior points, lambda_1 = alpha across the structure."""
     dims = (44, 38)
     a, b, m = 1.0, 0.7, (6, 5)
@@ -268,3 +273,60 @@ def test_ced2d_closed_form():
     E = _planes(_eigmap(J, ALPHA, C, oracle.CED), 2)
     sel = inner.reshape(-1)
     assert np.abs(D[:, sel] - E[:, sel]).max() <= 1e-10
+
+
+# ----------------------------------------------------------------------------
+# Vector-valued images (the Conclusion: the components share one tensor, the
+# coupling is the tensor's).  The oracle sums the components' products
+# grad u_c,sigma grad u_c,sigma^T before the rho blur.
+
+def test_vector_tensor_matches_scipy_pipeline():
+    """Three components, 2D and 3D, CED and edge-enhancing maps: the summed
+    tensor equals the library route with the same sum."""
+    for dims, mk in (((41, 37), lambda k: synth.ced_image2d(70 + k, 41, 37, ndiscs=3)),
+                     ((15, 13, 12), lambda k: synth.uniform(80 + k, 15 * 13 * 12))):
+        u = np.stack([mk(k).reshape(-1) for k in range(3)])
+        for eig_map, C in ((oracle.CED, 1e-6), (oracle.EED, 1e-6)):
+            D = oracle.structure_tensor_d(u, dims, 1.5, 2.5, ALPHA, C, eig_map)
+            R = _scipy_pipeline(u, dims, 1.5, 2.5, ALPHA, C, eig_map)
+            assert np.abs(D - R).max() <= 1e-12, (dims, eig_map)
+
+
+def test_vector_tensor_sums_outer_products():
+    """Components u and a u give the tensor of sqrt(1 + a^2) u: the products
+    add (a sum of gradients before the product would give (1 + a)^2), and
+    the CED map sees the scale through C / (mu_1 - mu_2)^2."""
+    dims = (48, 40)
+    u = synth.uniform(5, 48 * 40)
+    a, C = 0.75, 1e-6       # C near (mu_1 - mu_2)^2 of this noise
+    D2 = oracle.structure_tensor_d(np.stack([u, a * u]), dims, 1.0, 3.0, ALPHA, C)
+    D1 = oracle.structure_tensor_d(math.sqrt(1 + a * a) * u, dims, 1.0, 3.0, ALPHA, C)
+    Dw = oracle.structure_tensor_d((1 + a) * u, dims, 1.0, 3.0, ALPHA, C)
+    assert np.abs(D2 - D1).max() <= 1e-12
+    assert np.abs(D2 - Dw).max() > 0.1
+    # a zero component changes nothing
+    Dz = oracle.structure_tensor_d(np.stack([u, np.zeros(u.size)]), dims, 1.0, 3.0, ALPHA, C)
+    D0 = oracle.structure_tensor_d(u, dims, 1.0, 3.0, ALPHA, C)
+    assert np.array_equal(Dz, D0)
+
+
+def test_vector_tensor_orthogonal_ramps_isotropic():
+    """u_1 = x, u_2 = y: away from the mirrored border each component's
+    gradient is a unit axis vector, their products sum to Id, so mu_1 = mu_2
+    and the CED map gives D = alpha Id; either ramp alone gives the coherence
+    direction along the other axis."""
+    nx, ny = 40, 36
+    x = np.tile(np.arange(nx, dtype=np.float64), ny)
+    y = np.repeat(np.arange(ny, dtype=np.float64), nx)
+    sig, rho = 1.0, 2.0
+    D = oracle.structure_tensor_d(np.stack([x, y]), (nx, ny), sig, rho, ALPHA, 1e-3)
+    m = math.ceil(3 * sig) + math.ceil(3 * rho) + 1
+    inner = ((x >= m) & (x < nx - m) & (y >= m) & (y < ny - m))
+    assert inner.sum() > 100
+    assert np.allclose(D[0][inner], ALPHA, rtol=1e-12, atol=0)
+    assert np.abs(D[1][inner]).max() <= 1e-12
+    assert np.allclose(D[2][inner], ALPHA, rtol=1e-12, atol=0)
+    Dx = oracle.structure_tensor_d(x, (nx, ny), sig, rho, ALPHA, 1e-3)
+    lam2 = ALPHA + (1 - ALPHA) * math.exp(-1e-3)
+    assert np.allclose(Dx[0][inner], ALPHA, rtol=1e-12)
+    assert np.allclose(Dx[2][inner], lam2, rtol=1e-12)

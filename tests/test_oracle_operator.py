@@ -141,7 +141,7 @@ def test_overflow_field_reaches_centre_more_than_255_times():
 
 
 # ----------------------------------------------------------------------------
-# The reflecting boundary (the restoration test's, Section 5): an edge whose
+# The reflecting boundary (the restoration test's, Section 4): an edge whose
 # target leaves the grid is mirrored back (half-sample mirror, the even
 # extension of u).
 

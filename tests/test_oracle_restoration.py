@@ -1,5 +1,5 @@
 """Pins of the restoration test's exact solution and of the discrete
-problem the GPU solves for it (Section 5, the synthetic restoration test,
+problem the GPU solves for it (Section 4, the synthetic restoration test,
 eq. (elliptic)).
 
 - The closed form u = u0 o f solves -lambda div(D grad u) + u = v at every

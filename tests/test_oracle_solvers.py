@@ -1,6 +1,6 @@
 """Pins of the solver and CNN oracle (oracle/solvers.py).
 
-The paper solves its linear systems by conjugate gradients (Section 5,
+The paper solves its linear systems by conjugate gradients (Section 4,
 restoration test); the flexible CG and the learned preconditioner are not in
 the paper, so they are pinned by dense solves, textbook identities, a
 library convolution and finite differences.
