@@ -26,6 +26,8 @@
 //          |y - z| < 2^22.
 //   diag   [N] A_zz (double for FP64 storage, float otherwise).
 #include <algorithm>
+#include <cstddef>
+#include <type_traits>
 #include <new>
 
 #include "common.h"
@@ -415,8 +417,10 @@ __device__ inline void sort_row(int32_t *e, int c) {
 
 // The weights of the 3D incoming entries, one EntRec per entry.  FP32: the
 // entry again with its weight in one 8-byte record, so that one vector load
-// brings both; other dtypes: the weight alone, beside ent (a record would
-// need padding: 16 bytes for FP64, 8 for 16-bit weights).
+// brings both; other dtypes: the weight alone, beside ent.  (A 16-bit weight
+// padded into an 8-byte record was measured slower than the two arrays, 6
+// bytes per entry: 637 against 561 us per step of 256^3 in BF16.  FP64
+// would need 16 bytes.)
 template <typename TS> struct alignas(8) EntW {
     int32_t e;
     TS w;
@@ -434,15 +438,32 @@ template <typename TS> __device__ __forceinline__ EntRec<TS> make_rec(int32_t e,
     if constexpr (kPackedEW<TS>) return EntRec<TS>{e, w};
     else return w;
 }
+// A 16-bit value read under a per-lane condition is widened by the compiler
+// inside the conditional block, which then waits for that one load: the
+// loads of a chunk would be serialized.  16-bit reads are therefore made
+// unconditional, from an address that is always valid, and the values that
+// do not count are dropped afterwards.
+template <typename TS> constexpr bool kNarrow = sizeof(TS) == 2;
+
 // Entry i and its weight (-1 and 0 when !ok).
 template <typename TS>
 __device__ __forceinline__ void load_rec(const EntRec<TS> *__restrict__ went,
                                          const int32_t *__restrict__ ent, long long i, bool ok,
                                          int32_t &v, TS &w) {
     if constexpr (kPackedEW<TS>) {
-        const EntRec<TS> r = ok ? went[i] : EntRec<TS>{-1, TS{}};
-        v = r.e;
-        w = r.w;
+        // one 8-byte load: the entry, then the weight's bits
+        static_assert(sizeof(EntRec<TS>) == 8 && offsetof(EntW<TS>, w) == 4, "record layout");
+        const uint2 r = ok ? reinterpret_cast<const uint2 *>(went)[i] : make_uint2(~0u, 0u);
+        v = (int32_t)r.x;
+        w = __builtin_bit_cast(TS, r.y);
+    } else if constexpr (kNarrow<TS>) {
+        // entry 0 always exists (the arrays are sized for every possible edge)
+        v = ent[ok ? i : 0];
+        w = went[ok ? i : 0];
+        if (!ok) {
+            v = -1;
+            w = TS{};
+        }
     } else {
         v = ok ? ent[i] : -1;
         w = ok ? went[i] : TS{};
@@ -1343,8 +1364,12 @@ template <bool INLINE_W, int S, typename TS, typename TA, typename TU> struct In
         ur = __shfl(uz, ok ? (v & 63) : 0, 64);  // all lanes take part
         wy = INLINE_W ? wv : TS{};
         uy = TU{};
-        if (e0 < L.total) {  // wave-uniform; then z0 < N.  N < 2^28 points, S N < 2^31
-            const int y = ok ? (int)z0 + (v & 63) + (v >> 9) : (int)z0;
+        // a wave with entries left has z0 < N; N < 2^28 points, S N < 2^31
+        const int y = ok ? (int)z0 + (v & 63) + (v >> 9) : (e0 < L.total ? (int)z0 : 0);
+        if constexpr (kNarrow<TS> || kNarrow<TU>) {  // unconditional (see kNarrow)
+            if (!INLINE_W) wy = w[widx32<S>(ok ? (v >> 6) & 7 : 0, y, (int)N)];
+            uy = u[(unsigned)y];
+        } else if (e0 < L.total) {  // wave-uniform: skip chunks past the lists
             if (!INLINE_W) wy = w[widx32<S>(ok ? (v >> 6) & 7 : 0, y, (int)N)];
             uy = u[(unsigned)y];
         }
@@ -2575,7 +2600,8 @@ size_t batch_footprint(const adlbr_operator *op) {
     // u and its successor, offsets, own weights, count, row start, and about
     // two incoming entries (each with its weight) per slot
     return (size_t)op->gi.N *
-           (2 * ts + sbs + (size_t)op->slots * ts + 2 * (size_t)op->slots * (4 + (op->went ? ts : 0)) +
+           (2 * ts + sbs + (size_t)op->slots * ts +
+            2 * (size_t)op->slots * (op->went ? (ts <= 4 ? 8 : 4 + ts) : 4) +
             1 + 4);
 }
 
