@@ -1379,59 +1379,44 @@ template <bool INLINE_W, int S, typename TS, typename TA, typename TU> struct In
     }
 };
 
-// Cross-lane moves within a wavefront by DPP (no LDS traffic): CTRL is a
-// row_shr:n (0x110 + n) or row_bcast:15 / row_bcast:31 (0x142 / 0x143)
-// control, RM the rows written; lanes without a source read 0.
-template <int CTRL, int RM> __device__ __forceinline__ int dpp_i(int x) {
-    return __builtin_amdgcn_update_dpp(0, x, CTRL, RM, 0xf, true);
-}
-template <int CTRL, int RM> __device__ __forceinline__ float dpp_v(float x) {
-    return __int_as_float(dpp_i<CTRL, RM>(__float_as_int(x)));
-}
-template <int CTRL, int RM> __device__ __forceinline__ double dpp_v(double x) {
-    const long long b = __double_as_longlong(x);
-    const unsigned lo = (unsigned)dpp_i<CTRL, RM>((int)(unsigned)(b & 0xffffffffll));
-    const unsigned hi = (unsigned)dpp_i<CTRL, RM>((int)(b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-// One step of the segmented scan: add the moved value when it comes from a
-// lane of the same segment (row).  Lanes without a source get (0, row 0),
-// which adds 0.
-template <int CTRL, int RM, typename TA> __device__ __forceinline__ void seg_step(TA &x, int row) {
-    const TA xs = dpp_v<CTRL, RM>(x);
-    const int rs = dpp_i<CTRL, RM>(row);
-    if (rs == row) x += xs;
-}
-
-// This lane's row sum over chunk [e0, e0 + 64): segmented inclusive scan of
-// the edge values over the lanes (entries are grouped by row, rows ascend;
-// steps of 1, 2, 4, 8 lanes within each row of 16, then the last lane of
-// row 0 into row 1 and of row 2 into row 3, then lane 31 into rows 2 and
-// 3), then the value at the end of this row's run.  Wave-uniform early out
-// past the end.  All 64 lanes must call it.
-template <typename TA>
-__device__ __forceinline__ TA incoming_reduce(const WaveLists &L, int32_t v, TA x, unsigned e0) {
-    if (e0 >= L.total) return (TA)0;
-    const int lane = (int)(threadIdx.x & 63u);
-    const int row = e0 + lane < L.total ? (v & 63) : 64;
-    seg_step<0x111, 0xf>(x, row);
-    seg_step<0x112, 0xf>(x, row);
-    seg_step<0x114, 0xf>(x, row);
-    seg_step<0x118, 0xf>(x, row);
-    seg_step<0x142, 0xa>(x, row);
-    seg_step<0x143, 0xc>(x, row);
-    const unsigned lo = L.lo > e0 ? L.lo : e0;
-    const unsigned hi = L.hi < e0 + 64 ? L.hi : e0 + 64;
-    const TA mine = __shfl(x, (int)((hi - 1 - e0) & 63u), 64);
-    return hi > lo ? mine : (TA)0;
+// Rows of one wave from a window of evaluated incoming edges: the values of
+// the window's KPRE chunks (64 entries each, from entry eb on) go to the
+// wave's slice of LDS, then every lane adds, in list order, the values of
+// its own row that fall in the window.  Across the windows each row's
+// incoming part is thus a plain sum in list order (deterministic).  LDS
+// serves the wave's reads in order after its writes; the wave barriers keep
+// the compiler from moving the accesses across them.  Needs blocks of kBS
+// threads; all 64 lanes of the wave call it together.
+template <typename TA, int KPRE>
+__device__ __forceinline__ void add_window_rows(const WaveLists &L, unsigned eb,
+                                                const TA (&val)[KPRE], TA &acc) {
+    __shared__ TA win[kBS / 64][64 * KPRE];
+    TA *sw = win[threadIdx.x >> 6];
+    const unsigned lane = threadIdx.x & 63u;
+#pragma unroll
+    for (int j = 0; j < KPRE; ++j) sw[64 * j + lane] = val[j];
+    __builtin_amdgcn_wave_barrier();
+    const unsigned end = eb + 64u * KPRE;
+    const unsigned lo = L.lo > eb ? L.lo : eb;
+    const unsigned hi = L.hi < end ? L.hi : end;
+    unsigned e = lo;
+    for (; e + 4 <= hi; e += 4) {
+        const TA a0 = sw[e - eb], a1 = sw[e + 1 - eb], a2 = sw[e + 2 - eb], a3 = sw[e + 3 - eb];
+        acc += a0;
+        acc += a1;
+        acc += a2;
+        acc += a3;
+    }
+    for (; e < hi; ++e) acc += sw[e - eb];
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Incoming part of the rows of one wavefront, computed cooperatively: the
 // wave's entries are taken 64 at a time (coalesced loads, every lane busy),
-// each lane evaluates one edge, and a segmented scan sums each row's run.
-// Up to kPre chunks are loaded before any is reduced, so their memory
-// latencies overlap.  The order of additions is fixed, so the result is
-// deterministic.  All 64 lanes must call this.
+// each lane evaluates one edge, and each row's values are then summed by
+// its own lane (add_window_rows).  Up to kPre chunks are loaded before any
+// is summed, so their memory latencies overlap.  All 64 lanes must call
+// this.
 template <bool INLINE_W, int S, typename TS, typename TA, typename TU>
 __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, long long N, TA uz,
                                             const TU *__restrict__ u, const TS *__restrict__ w,
@@ -1460,8 +1445,7 @@ __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, lon
         for (int j = 0; j < kPre; ++j) ie[j].issue(L, z0, N, uz, v[j], wv[j], eb + 64 * j, u, w);
 #pragma unroll
         for (int j = 0; j < kPre; ++j) val[j] = ie[j].value();
-#pragma unroll
-        for (int j = 0; j < kPre; ++j) acc += incoming_reduce<TA>(L, v[j], val[j], eb + 64 * j);
+        add_window_rows<TA, kPre>(L, eb, val, acc);
     }
     return acc;
 }
@@ -1531,10 +1515,7 @@ __device__ __forceinline__ void apply_block(
 #pragma unroll
             for (int j = 0; j < kPre; ++j) val[k][j] = ie[k][j].value();
 #pragma unroll
-        for (int k = 0; k < P; ++k)
-#pragma unroll
-            for (int j = 0; j < kPre; ++j)
-                acc[k] += incoming_reduce<TA>(L[k], v[k][j], val[k][j], eb + 64 * j);
+        for (int k = 0; k < P; ++k) add_window_rows<TA, kPre>(L[k], eb, val[k], acc[k]);
     }
 #pragma unroll
     for (int k = 0; k < P; ++k) {
@@ -1618,8 +1599,7 @@ __global__ __launch_bounds__(kBS) void k_step_multi(
                 ie[j].issue(L, z0, N, uz[c], v[j], wv[j], eb + 64 * j, u + c * N, w);
 #pragma unroll
             for (int j = 0; j < kPre; ++j) val[j] = ie[j].value();
-#pragma unroll
-            for (int j = 0; j < kPre; ++j) acc[c] += incoming_reduce<TA>(L, v[j], val[j], eb + 64 * j);
+            add_window_rows<TA, kPre>(L, eb, val, acc[c]);
         }
     }
     if (z >= N) return;
