@@ -368,18 +368,47 @@ __device__ __forceinline__ void listed_edges(const GridInfo &g, long long z, boo
     for (int k = 0; k < 2 * S; ++k) f(k, live ? edge_k<DIM, PER>(p, z, s, wq, k, g, hnear) : -1ll);
 }
 
-// Count the listed edges landing in each bin of targets (wave-aggregated
-// atomics, one per distinct bin per wavefront).
+// The bins of a block's edge targets lie near the block's own bin (offsets
+// are short against the grid), so both binning passes count them first in
+// an LDS window of kWinBins bins centred there: one global atomic per
+// window bin and block instead of one per bin, wavefront and edge slot,
+// which took the global counters of the busy bins out of contention.
+// Targets outside the window go to the global counters directly.
+constexpr int kWinBins = 2048;
+
+struct BinWindow {
+    long long b0;  // bin of window index 0 (may be negative)
+    __device__ explicit BinWindow(unsigned block) {
+        b0 = (((long long)block * kBS) >> kBinShift) - kWinBins / 2;
+    }
+    // window index of target t's bin, -1 outside (or no target)
+    __device__ int rel(long long t) const {
+        if (t < 0) return -1;
+        const long long r = (t >> kBinShift) - b0;
+        return r >= 0 && r < kWinBins ? (int)r : -1;
+    }
+};
+
+// Count the listed edges landing in each bin of targets.
 template <int DIM, bool WIDE, bool PER>
 __global__ __launch_bounds__(256) void k_bin_count(GridInfo g,
                                                    const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
                                                    const uint8_t *__restrict__ mask,
                                                    const int32_t *__restrict__ hnear,
                                                    uint32_t *__restrict__ bincnt) {
+    __shared__ uint32_t hist[kWinBins];
+    for (int i = threadIdx.x; i < kWinBins; i += 256) hist[i] = 0;
+    __syncthreads();
+    const BinWindow win(blockIdx.x);
     const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     listed_edges<DIM, WIDE, PER>(g, z, z < g.N, sb, mask, *hnear, [&](int, long long t) {
-        bin_append(t >= 0 ? (int)(t >> kBinShift) : -1, bincnt, true);  // every lane
+        const int r = win.rel(t);
+        bin_append(r, hist, true);  // every lane
+        if (t >= 0 && r < 0) atomicAdd(&bincnt[t >> kBinShift], 1u);
     });
+    __syncthreads();
+    for (int i = threadIdx.x; i < kWinBins; i += 256)
+        if (hist[i]) atomicAdd(&bincnt[win.b0 + i], hist[i]);
 }
 
 // Sort one row's entries ascending (the order is then independent of the
@@ -586,17 +615,40 @@ __device__ inline double sort_row_diag(const GridInfo &g, long long z, int32_t *
 }
 
 // Place every listed edge (target, entry) in its bin's region of binbuf
-// (the same edges as k_bin_count).
+// (the same edges as k_bin_count): the block counts its window bins in LDS,
+// reserves each bin's range with one global atomic, then places its edges
+// within the ranges by LDS cursors.  The order within a bin depends on
+// timing; k_bin_build sorts every row.
 template <int DIM, bool WIDE, bool PER>
-__global__ void k_bin_fill(GridInfo g, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
+__global__ __launch_bounds__(256) void k_bin_fill(GridInfo g, const typename Slots<DIM, WIDE>::store_t *__restrict__ sb,
                            const uint8_t *__restrict__ mask, const int32_t *__restrict__ hnear,
                            const uint32_t *__restrict__ binoff, uint32_t *__restrict__ bincur,
                            int2 *__restrict__ binbuf) {
+    __shared__ uint32_t hist[kWinBins];  // counts, then cursors
+    __shared__ uint32_t base[kWinBins];  // the block's range start in each bin
+    for (int i = threadIdx.x; i < kWinBins; i += 256) hist[i] = 0;
+    __syncthreads();
+    const BinWindow win(blockIdx.x);
     const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    listed_edges<DIM, WIDE, PER>(g, z, z < g.N, sb, mask, *hnear, [&](int k, long long t) {
-        const int bin = t >= 0 ? (int)(t >> kBinShift) : -1;
-        const unsigned slot = bin_append(bin, bincur, false);  // every lane
-        if (bin >= 0) {
+    const int hn = *hnear;
+    listed_edges<DIM, WIDE, PER>(g, z, z < g.N, sb, mask, hn, [&](int, long long t) {
+        bin_append(win.rel(t), hist, true);  // every lane
+    });
+    __syncthreads();
+    for (int i = threadIdx.x; i < kWinBins; i += 256) {
+        const uint32_t c = hist[i];
+        base[i] = c ? atomicAdd(&bincur[win.b0 + i], c) : 0u;
+        hist[i] = 0;
+    }
+    __syncthreads();
+    listed_edges<DIM, WIDE, PER>(g, z, z < g.N, sb, mask, hn, [&](int k, long long t) {
+        const int r = win.rel(t);
+        const int far = t >= 0 && r < 0 ? (int)(t >> kBinShift) : -1;
+        const unsigned near_slot = bin_append(r, hist, false);   // every lane
+        const unsigned far_slot = bin_append(far, bincur, false);  // every lane
+        if (t >= 0) {
+            const long long bin = t >> kBinShift;
+            const unsigned slot = r >= 0 ? base[r] + near_slot : far_slot;
             const int32_t e = (int32_t)(((z - t) << 9) | ((k >> 1) << 6) | (t & 63));
             binbuf[(long long)binoff[bin] + slot] = make_int2((int)t, e);
         }
