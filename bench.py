@@ -8,7 +8,8 @@ FP32.  One benchmark step is one pass of the hot path over the whole batch:
 the AD-LBR stencils of all 72 tensor fields, the assembly of all 72
 operators (in place, so the captured graph stays valid), then 100 explicit
 Euler steps of every problem at 0.9 x its own CFL bound, replayed from one
-captured HIP graph with the autotuned launch variants.  The value is
+captured HIP graph (one grouped launch per class of problems and chunk of
+about 224 MiB; --tune lets the autotuner choose instead).  The value is
 whole-job throughput in Mpoint-steps/s (grid points x explicit steps /
 wall time), with every input resident in HBM before the timed region.
 
@@ -53,10 +54,14 @@ ALGO_BYTES = {(2, 8): 16 + 3 * 8 + 4, (2, 4): 8 + 3 * 4 + 4, (2, 2): 4 + 3 * 2 +
 # SHA-256 of the kernel sources they were taken on.  A change to those
 # sources makes the figure stale: traffic is then null.
 TRAFFIC = {
-    "c2": {"sha256": "b038c868729927a94f3ef5669159a50a3d9c643d99e6c7c56622462292268f31",
-           "bytes_per_launch": 221488231},
-    "c3": {"sha256": "b038c868729927a94f3ef5669159a50a3d9c643d99e6c7c56622462292268f31",
-           "bytes_per_launch": 2435736144},
+    "c2": {"sha256": "3f82bf071d809f0f1fd50836255e62c4d096574d919565470a8a453e28762c8c",
+           "bytes_per_launch": 221604480},
+    "c3": {"sha256": "3f82bf071d809f0f1fd50836255e62c4d096574d919565470a8a453e28762c8c",
+           "bytes_per_launch": 2434432000},
+    "c3-bf16": {"sha256": "3f82bf071d809f0f1fd50836255e62c4d096574d919565470a8a453e28762c8c",
+                "bytes_per_launch": 1756694272},
+    "c4": {"sha256": "3f82bf071d809f0f1fd50836255e62c4d096574d919565470a8a453e28762c8c",
+           "bytes_per_launch": 6373427996},
 }
 TRAFFIC_SOURCES = ("paper_1301_3925_amd/csrc/operator.hip", "paper_1301_3925_amd/csrc/common.h")
 
@@ -98,6 +103,9 @@ def parse():
                     help="c5: how many times flexible-CG residuals join the training pool")
     ap.add_argument("--dtype", default=None, help="storage dtype for c3: f64|f32|bf16|f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="c4: pick each class's launch variant with the autotuner instead of "
+                         "the fixed grouped launch with 224 MiB chunks")
     ap.add_argument("--no-implicit", action="store_true",
                     help="c4: leave out the implicit-step comparison")
     ap.add_argument("--layout", default="lists", choices=["tiled", "lists"],
@@ -302,8 +310,21 @@ def run_c4(args, dev, stream, probs, fields, cpu):
     torch.cuda.synchronize()
     log("built 72 operators")
     b = adlbr.Batch(ops, us, dt=0.9, dt_mode="cfl")
-    variants = b.tune(steps=10)
-    log(f"tuned: {variants}")
+    if args.tune:
+        variants = b.tune(steps=10)
+        log(f"tuned: {variants}")
+    else:
+        # grouped launch in XCD-contiguous block order, classes cut into
+        # chunks of about 224 MiB, fixed so that the counter runs see the
+        # launches that are timed.  Timed over every variant and chunk
+        # budget (100 steps of the batch): 218 ms; the plain block order
+        # takes 213 ms but reads 1.8x the bytes out of L2 (every XCD fetches
+        # the neighbour rows of blocks the other XCDs run); per-problem
+        # launches 226 ms; the other settings 214-271 ms
+        for c in range(len(b.variants())):
+            b.set_variant(c, 1, 224 << 20)
+        variants = b.variants()
+        log(f"variants: {variants}")
 
     def one_pass(ev=None):
         # the whole hot path over the batch: stencils, in-place assembly,
@@ -369,7 +390,7 @@ def run_c4(args, dev, stream, probs, fields, cpu):
         "per_problem_launches": {"value": round(pts * nsteps / seq / 1e6, 2),
                                  "unit": "Mpoint-steps/s", "seconds": round(seq, 4),
                                  "what": "the 100 steps alone, adlbr_step per problem"},
-        "autotuned_variants": variants,
+        "launch_variants": variants,
         "roofline": {"bound": "hbm",
                      "kernel": ("k_apply_tiled_batch" if args.layout == "tiled" else "k_apply_batch") +
                                " (batched explicit step, FP32)",
@@ -546,7 +567,8 @@ def run_fixed(args, dev, stream):
         "roofline": {"bound": "hbm", "kernel": f"{'k_apply_tiled' if layout == 'tiled' else 'k_apply'} (explicit step, {dim}D {sdt})",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic_for("c3") if (dim == 3 and sdt == "f32") else None,
+                     "traffic": (traffic_for("c3") if sdt == "f32" else traffic_for("c3-bf16") if sdt == "bf16"
+                                 else None) if dim == 3 else None,
                      "algo_bytes_per_point": ALGO_BYTES[(dim, esz)],
                      "avg_launch_us": round(step_s * 1e6, 3)},
     }

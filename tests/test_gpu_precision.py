@@ -1,0 +1,73 @@
+"""Why 16-bit storage drifts from FP64 (the explicit scheme of Section 4 run
+with u and the weights stored in BF16 or FP16, FP32 arithmetic).
+
+Each step rounds u - h A u back to the storage format.  Once the smoothing
+has made h A u smaller than half a unit in the last place of u, the update
+rounds away and the point stops moving: the run stagnates while the FP64 run
+keeps diffusing.  The test emulates exactly that on the CPU -- the oracle's
+operator on the rounded weights, FP32 products, one rounding of u per step
+-- and checks that the GPU's 16-bit run follows the emulation far more
+closely than either follows FP64, on a 64^3 field of the 256^3 workload's
+recipe.  So the drift is the storage format's, not the kernel's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_3925_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16(x):
+    """Round FP32 values to the nearest BF16 (ties to even), as FP32."""
+    a = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    r = ((a + 0x7FFF + ((a >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def _f16(x):
+    return np.asarray(x, np.float32).astype(np.float16).astype(np.float32)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_16bit_drift_is_the_storage_rounding(storage):
+    import torch
+    import paper_1301_3925_amd as adlbr
+    q = {"bf16": _bf16, "f16": _f16}[storage]
+    tdt = {"bf16": torch.bfloat16, "f16": torch.float16}[storage]
+    dims = (64, 64, 64)
+    D = synth.tensor3d_field(1303, dims, 50.0)
+    off, w, _ = adlbr.build_stencils(torch.from_numpy(D).cuda(), dims)
+    on, wn = off.cpu().numpy(), w.cpu().numpy()
+    A = oracle.operator_matrix(dims, on, wn).tocsr()
+    wq = q(wn).astype(np.float64)
+    Aq64 = oracle.operator_matrix(dims, on, wq)
+    Aq = Aq64.tocsr().astype(np.float32)
+    hq = np.float32(0.9 * oracle.cfl(Aq64))
+    u0 = synth.uniform(7, A.shape[0])
+    op = adlbr.Operator(dims, off, w, storage=tdt)
+    ug = torch.from_numpy(u0).to(tdt).cuda()
+    ue = q(u0)
+    ref = ue.astype(np.float64)
+    h = 0.9 * oracle.cfl(A)
+    done = 0
+    for mark in (50, 100, 200):
+        op.step(ug, 0.9, mark - done, cfl_fraction=True)
+        lost = 0.0
+        for _ in range(mark - done):
+            upd = (hq * (Aq @ ue)).astype(np.float32)
+            new = q(ue - upd)
+            lost = float(np.mean((new == ue) & (upd != 0)))
+            ue = new
+            ref = ref - h * (A @ ref)
+        done = mark
+        got = ug.double().cpu().numpy()
+        drift = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        emul = np.linalg.norm(got - ue) / np.linalg.norm(ref)
+        print(storage, mark, "GPU vs FP64", drift, "GPU vs emulation", emul, "updates lost", lost)
+        # the GPU follows the rounded-storage emulation fifty times closer
+        # than either follows FP64 (measured: 170 to 1600 times)
+        assert emul <= 0.02 * drift
+    # by step 200 almost every update rounds away
+    assert lost >= (0.99 if storage == "bf16" else 0.95)
