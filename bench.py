@@ -103,6 +103,9 @@ def parse():
                     help="c5: how many times flexible-CG residuals join the training pool")
     ap.add_argument("--dtype", default=None, help="storage dtype for c3: f64|f32|bf16|f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-variant", type=int, default=1,
+                    help="c4: launch variant of every class (adlbr_batch_set_variant; "
+                         "1 = XCD-contiguous block order)")
     ap.add_argument("--tune", action="store_true",
                     help="c4: pick each class's launch variant with the autotuner instead of "
                          "the fixed grouped launch with 224 MiB chunks")
@@ -322,7 +325,7 @@ def run_c4(args, dev, stream, probs, fields, cpu):
         # the neighbour rows of blocks the other XCDs run); per-problem
         # launches 226 ms; the other settings 214-271 ms
         for c in range(len(b.variants())):
-            b.set_variant(c, 1, 224 << 20)
+            b.set_variant(c, args.batch_variant, 224 << 20)
         variants = b.variants()
         log(f"variants: {variants}")
 
