@@ -197,11 +197,13 @@ def test_c5_full_size_jacobi_residual_by_oracle(lib):
     assert np.linalg.norm(r) / np.linalg.norm(bn) <= 1.2e-6
 
 
-def test_c4_full_batch_autotuned_bitwise(lib):
+def test_c4_full_batch_bitwise(lib):
     """The whole uneven batch (64 images 256^2..1536^2, 8 volumes
-    64^3..192^3, FP32), autotuned and run through the captured graph as
-    bench.py runs it: every problem bit-identical to stepping it alone, and
-    a sampled row of one image against the oracle's operator."""
+    64^3..192^3, FP32), run through the captured graph in the launch
+    configuration bench.py times (XCD-ordered grouped launches, 224 MiB
+    chunks) and as the autotuner picks it: every problem bit-identical to
+    stepping it alone, and a sampled row of one image against the oracle's
+    operator."""
     import torch
     probs = synth.batch_problems(1304)
     ops, us, refs, offs = [], [], [], []
@@ -216,14 +218,24 @@ def test_c4_full_batch_autotuned_bitwise(lib):
         us.append(u0)
         refs.append(u0.clone())
     nsteps = 3
-    b = lib.Batch(ops, us, dt=0.9, dt_mode="cfl")
-    b.tune(steps=3, use_cache=False)
-    b.run(nsteps)
+    starts = [u.clone() for u in us]
     for op, r in zip(ops, refs):
         op.step(r, 0.9, nsteps, cfl_fraction=True)
-    torch.cuda.synchronize()
-    for k, (u, r) in enumerate(zip(us, refs)):
-        assert torch.equal(u, r), k
+    b = lib.Batch(ops, us, dt=0.9, dt_mode="cfl")
+    for config in ("bench", "tuned"):
+        for u, s0 in zip(us, starts):
+            u.copy_(s0)
+        if config == "bench":
+            for c in range(len(b.variants())):
+                b.set_variant(c, 1, 224 << 20)
+        else:
+            b.tune(steps=3, use_cache=False)
+            for u, s0 in zip(us, starts):
+                u.copy_(s0)
+        b.run(nsteps)
+        torch.cuda.synchronize()
+        for k, (u, r) in enumerate(zip(us, refs)):
+            assert torch.equal(u, r), (config, k)
     # one explicit step of the first image at sampled rows, by the oracle
     k = 0
     dims = tuple(probs[k]["n"])
