@@ -95,7 +95,7 @@ def parse():
                     choices=["c1", "c2", "c3", "c3-precision", "c4", "c5", "c5-3d", "copy"])
     ap.add_argument("--train-steps", type=int, default=None,
                     help="c5: training steps (default 3000 in 2D, 300 in 3D)")
-    ap.add_argument("--train-steps-3d", type=int, default=300,
+    ap.add_argument("--train-steps-3d", type=int, default=3000,
                     help="c4: training steps of the 3D implicit-step comparison")
     ap.add_argument("--off-policy", action="store_true",
                     help="c5: train on Jacobi-PCG residuals only (no flexible-CG residuals)")
@@ -117,7 +117,7 @@ def parse():
                     help="host worker processes (default min(16, cpu count))")
     args = ap.parse_args()
     if args.train_steps is None:
-        args.train_steps = 300 if args.workload == "c5-3d" else 3000
+        args.train_steps = 3000
     if args.workers is None:
         args.workers = max(1, min(16, os.cpu_count() or 1))
     return args

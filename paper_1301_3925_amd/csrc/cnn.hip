@@ -488,6 +488,122 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w2d_mfma(GridInfo g, const flo
             ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
 
+// 3D weight gradient on the matrix cores, for 3x3x3 layers: the sums of
+// k_conv_bwd_w as GEMMs D_t[co][ci] += A[co][4 points] B_t[4 points][ci]
+// with v_mfma_f32_16x16x4f32 (FP32 operands and accumulation), as in 2D.
+// Each block walks 8 x 8 x 4 tiles of points: ga on the tile and x on the
+// tile plus a one-point halo (10 x 10 x 6, 0 outside the grid) are staged
+// in LDS (every load of a thread is issued before its stores), then every
+// wave takes a quarter of the tile's 64 four-point steps for all 27 taps.
+// The four waves' sums are added in LDS in wave order (the x buffer is
+// reused for that once the tiles are done) and written as this block's
+// partials (same layout as k_conv_bwd_w).
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_bwd_w3d_mfma(GridInfo g, const float *__restrict__ in,
+                                                           const float *__restrict__ in_gate,
+                                                           int relu_in,
+                                                           const float *__restrict__ ga,
+                                                           float *__restrict__ partials) {
+    constexpr int TX = 8, TY = 8, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+    constexpr int TP = TX * TY * TZ, HP = HX * HY * HZ, T = 27;
+    constexpr int stride = COUT * CIN * T + COUT;
+    constexpr int SX = CIN * HP > stride ? CIN * HP : stride;
+    __shared__ float sx[SX];  // x on the halo region; at the end the wave sums
+    __shared__ float sg[COUT * TP];
+    static_assert(CIN <= 16 && COUT <= 16, "one 16 x 16 MFMA tile");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, ntz = (nz + TZ - 1) / TZ;
+    const int i = lane & 15, kk = lane >> 4;  // A row (co) / B column (ci), k
+    f32x4v acc[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    float accb = 0.f;  // bias: sum of ga[co = i] over this lane's points
+    const long long ntiles = (long long)ntx * nty * ntz;
+    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int x0 = (int)(tile % ntx) * TX, y0 = (int)((tile / ntx) % nty) * TY,
+                  z0 = (int)(tile / ((long long)ntx * nty)) * TZ;
+        __syncthreads();
+        {
+            constexpr int NB = (CIN * HP + 255) / 256;
+            float v[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int e = b * 256 + tid;
+                v[b] = 0.f;
+                if (e < CIN * HP) {
+                    const int ci = e / HP, q = e % HP;
+                    const int gx = x0 - 1 + q % HX, gy = y0 - 1 + (q / HX) % HY,
+                              gz = z0 - 1 + q / (HX * HY);
+                    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
+                        const long long k = ((long long)gz * ny + gy) * nx + gx;
+                        float x = in[ci * g.N + k];
+                        if (in_gate) x *= in_gate[ci * g.N + k];
+                        v[b] = relu_in ? fmaxf(x, 0.f) : x;
+                    }
+                }
+            }
+            constexpr int NG = (COUT * TP + 255) / 256;
+            float w[NG];
+#pragma unroll
+            for (int b = 0; b < NG; ++b) {
+                const int e = b * 256 + tid;
+                w[b] = 0.f;
+                if (e < COUT * TP) {
+                    const int co = e / TP, q = e % TP;
+                    const int gx = x0 + q % TX, gy = y0 + (q / TX) % TY, gz = z0 + q / (TX * TY);
+                    if (gx < nx && gy < ny && gz < nz)
+                        w[b] = ga[co * g.N + ((long long)gz * ny + gy) * nx + gx];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (b * 256 + tid < CIN * HP) sx[b * 256 + tid] = v[b];
+#pragma unroll
+            for (int b = 0; b < NG; ++b)
+                if (b * 256 + tid < COUT * TP) sg[b * 256 + tid] = w[b];
+        }
+        __syncthreads();
+        for (int ks = wave; ks < TP / 4; ks += 4) {
+            const int p = ks * 4 + kk;
+            const int px = p % TX, py = (p / TX) % TY, pz = p / (TX * TY);
+            const float a = i < COUT ? sg[i * TP + p] : 0.f;
+            accb += a;
+            const int hb = i * HP + (pz * HY + py) * HX + px;  // tap (-1, -1, -1)
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const int off = ((t / 9) * HY + (t / 3) % 3) * HX + t % 3;
+                const float b = i < CIN ? sx[hb + off] : 0.f;
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // D: lane holds D[co = 4 (lane >> 4) + c][ci = lane & 15].  Bias: lanes
+    // with the same co (i) hold disjoint point sets.
+    for (int d = 16; d < 64; d <<= 1) accb += __shfl_xor(accb, d, 64);
+    __syncthreads();  // the tiles are done with sx
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int co = 4 * kk + c, ci = i;
+                    if (co < COUT && ci < CIN) {
+                        float &r = sx[(co * CIN + ci) * T + t];
+                        r = w == 0 ? acc[t][c] : r + acc[t][c];
+                    }
+                }
+            if (kk == 0 && i < COUT) {
+                float &r = sx[COUT * CIN * T + i];
+                r = w == 0 ? accb : r + accb;
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < stride; e += 256) partials[(long long)blockIdx.x * stride + e] = sx[e];
+}
+
 // grad[k] += sum over blocks of partials[b][k] (block order: deterministic);
 // weights go to gW[0 .. nw), biases (the last nb entries) to gb (if given).
 __global__ void k_reduce_partials(const float *partials, int nblocks, int stride, int nw,
@@ -630,6 +746,10 @@ int bwd_w_launch(const GridInfo &g, int cin, int cout, int taps, const float *in
     if (cin == CI && cout == CO) {                                                            \
         if (DIM == 2 && taps == 9 && CI <= 16 && CO <= 16)                                    \
             hipLaunchKernelGGL((k_conv_bwd_w2d_mfma<CI, (CO <= 16 ? CO : 16)>),               \
+                               dim3(kWgBlocks), dim3(kBS), 0, s, g, in, in_gate, relu_in, ga, \
+                               partials);                                                     \
+        else if (DIM == 3 && taps == 27 && CI <= 16 && CO <= 16)                              \
+            hipLaunchKernelGGL((k_conv_bwd_w3d_mfma<CI, (CO <= 16 ? CO : 16)>),               \
                                dim3(kWgBlocks), dim3(kBS), 0, s, g, in, in_gate, relu_in, ga, \
                                partials);                                                     \
         else                                                                                  \

@@ -30,9 +30,9 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
-def _case(lib, dim):
+def _case(lib, dim, dims=None):
     import torch
-    dims = (40, 32) if dim == 2 else (10, 9, 8)
+    dims = dims or ((40, 32) if dim == 2 else (10, 9, 8))
     D = synth.tensor2d_field(3, *dims, 50.0) if dim == 2 else synth.tensor3d_field(4, dims, 20.0)
     off, w, _ = lib.build_stencils(torch.from_numpy(D).cuda(), dims)
     op = lib.Operator(dims, off, w, storage=torch.float32)
@@ -67,10 +67,14 @@ def test_features_gates_forward(lib, dim):
     assert _rel(z, zr) <= 1e-5
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_backward_all_parameters(lib, dim):
+@pytest.mark.parametrize("dim,dims", [(2, None), (3, None), (3, (19, 17, 9))],
+                         ids=["2d", "3d", "3d-tiles"])
+def test_backward_all_parameters(lib, dim, dims):
+    """Every parameter's gradient against the oracle's chain rule; the 3D
+    grids span several 8 x 8 x 4 tiles of the matrix-core weight gradient,
+    ragged in every direction."""
     import torch
-    dims, op, A, dt, net, P, F, diag = _case(lib, dim)
+    dims, op, A, dt, net, P, F, diag = _case(lib, dim, dims)
     rng = np.random.default_rng(7)
     r = rng.normal(size=op.N).astype(np.float32).astype(np.float64)
     gz = rng.normal(size=op.N).astype(np.float32).astype(np.float64)
