@@ -95,7 +95,7 @@ def parse():
                     choices=["c1", "c2", "c3", "c3-precision", "c4", "c5", "c5-3d", "copy"])
     ap.add_argument("--train-steps", type=int, default=None,
                     help="c5, c5-3d: training steps (default 3000)")
-    ap.add_argument("--train-steps-3d", type=int, default=3000,
+    ap.add_argument("--train-steps-3d", type=int, default=4000,
                     help="c4: training steps of the 3D implicit-step comparison")
     ap.add_argument("--off-policy", action="store_true",
                     help="c5: train on Jacobi-PCG residuals only (no flexible-CG residuals)")

@@ -383,6 +383,7 @@ __device__ __forceinline__ int halo_idx(int p, int t) {
 // issued before its first LDS store, so the block waits for one round trip to
 // memory instead of one per item.  Needs blockDim.x == 256.
 constexpr int k3StageItems = k3Halo * 4, k3StageIters = (k3StageItems + 255) / 256;
+template <int STRIDE = kStride>
 __device__ __forceinline__ void stage3d(const GridInfo &g, const Tile3 &T, const uint2 *__restrict__ in,
                                         short *sx) {
     uint2 v[k3StageIters];
@@ -398,7 +399,7 @@ __device__ __forceinline__ void stage3d(const GridInfo &g, const Tile3 &T, const
 #pragma unroll
     for (int it = 0; it < k3StageIters; ++it) {
         const int k = (int)threadIdx.x + 256 * it;
-        if (k < k3StageItems) *(uint2 *)(sx + (k >> 2) * kStride + 4 * (k & 3)) = v[it];
+        if (k < k3StageItems) *(uint2 *)(sx + (k >> 2) * STRIDE + 4 * (k & 3)) = v[it];
     }
 }
 
@@ -510,12 +511,16 @@ __global__ __launch_bounds__(256) void k_net3d_mfma(GridInfo g, const uint2 *__r
 }
 
 // Layer 4 (16 -> 1) and the output: z = F0 r + sum_t sum_ci W4[ci][t]
-// a3(p + off_t)[ci], on the matrix cores like layers 2 and 3 with only row
-// co = 0 of the A operand non-zero (lanes 0 .. 15 then hold the outputs of
-// their group's 16 points); with part, the block's FP64 partials of <z, r>
-// in part[blockIdx] and of <z, rp> in part[gridDim + blockIdx].
+// a3(p + off_t)[ci], one thread per point of an 8 x 8 x 4 tile: a3 of the
+// tile and its halo staged in LDS (16 channels, 32 bytes a point), the 16
+// channels of every tap taken as 8 BF16 pairs by v_dot2c_f32_bf16 (FP32
+// accumulation) against the tap's weight pairs, which are uniform (scalar
+// loads).  On the matrix cores this layer would use one row of 16.  With
+// part, the block's FP64 partials of <z, r> in part[blockIdx] and of
+// <z, rp> in part[gridDim + blockIdx].
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 __global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint2 *__restrict__ a3,
-                                                  const bf16x4 *__restrict__ w4pack,
+                                                  const uint32_t *__restrict__ w4,
                                                   const float *__restrict__ r,
                                                   const float *__restrict__ F0,
                                                   float *__restrict__ zout,
@@ -523,49 +528,35 @@ __global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint2 *__res
                                                   double *__restrict__ part,
                                                   const CgState *__restrict__ st) {
     if (st && (st->done || st->bad)) return;
-    __shared__ __attribute__((aligned(16))) short sx[k3Halo * kStride];
+    __shared__ __attribute__((aligned(16))) short sx[k3Halo * 16];
     const Tile3 T = tile3(g, blockIdx.x);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n = lane & 15, kq = (lane >> 4) * 4;
-    // the output's inputs for this lane's four points (lanes 0 .. 15 write
-    // them), requested before the matrix work
-    float rv[4], fv[4], pv[4];
-    int iv[4];  // N < 2^28
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int p = (wave * 4 + j) * 16 + n;
-        const int x = T.x0 + 1 + p % k3X, y = T.y0 + 1 + (p / k3X) % k3Y,
-                  z = T.z0 + 1 + p / (k3X * k3Y);
-        const bool live = kq == 0 && in_grid3(x, y, z, g.nx, g.ny, g.nz);
-        iv[j] = live ? (int)(x + (long long)g.nx * (y + (long long)g.ny * z)) : -1;
-        const int ii = live ? iv[j] : 0;  // loads from point 0 and selects: no branches
-        const float r0 = r[ii], f0 = F0[ii], p0 = (rp ? rp : r)[ii];
-        rv[j] = live ? r0 : 0.f;
-        fv[j] = live ? f0 : 0.f;
-        pv[j] = live && rp ? p0 : 0.f;
-    }
-    bf16x4 wb[k3T];  // A: row co = n, ci = kq + c; only row 0 is W4 (packed [t][kq / 4])
-#pragma unroll
-    for (int t = 0; t < k3T; ++t) wb[t] = n == 0 ? w4pack[t * 4 + (kq >> 2)] : bf16x4{0, 0, 0, 0};
-    stage3d(g, T, a3, sx);
+    const int p = threadIdx.x;
+    const int x = T.x0 + 1 + p % k3X, y = T.y0 + 1 + (p / k3X) % k3Y, z = T.z0 + 1 + p / (k3X * k3Y);
+    const bool live = in_grid3(x, y, z, g.nx, g.ny, g.nz);
+    const int i = live ? (int)(x + (long long)g.nx * (y + (long long)g.ny * z)) : 0;  // N < 2^28
+    // the output's inputs, requested before the staging: loads from point
+    // 0 for a point outside the grid, dropped below
+    const float r0 = r[i], f0 = F0[i], p0 = (rp ? rp : r)[i];
+    stage3d<16>(g, T, a3, sx);
     __syncthreads();
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < k3T; ++t) {
+        const uint4 *src = (const uint4 *)(sx + halo_idx(p, t) * 16);
+        const uint4 lo = src[0], hi = src[1];
+        const uint32_t v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, v[k]),
+                                                  __builtin_bit_cast(bf16x2v, w4[t * 8 + k]), acc,
+                                                  false);
+    }
     double zr = 0.0, zrp = 0.0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int p = (wave * 4 + j) * 16 + n;
-        const short *base = sx + halo_idx(p, 13) * kStride + kq;  // tap 13: the point itself
-        f32x4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < k3T; ++t) {
-            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-            const bf16x4 b = *(const bf16x4 *)(base + (dz * (k3HX * k3HY) + dy * k3HX + dx) * kStride);
-            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wb[t], b, d, 0, 0, 0);
-        }
-        if (iv[j] < 0) continue;
-        const float zi = fv[j] * rv[j] + d[0];
-        zout[iv[j]] = zi;
-        zr += (double)zi * (double)rv[j];
-        zrp += (double)zi * (double)pv[j];
+    if (live) {
+        const float zi = f0 * r0 + acc;
+        zout[i] = zi;
+        zr = (double)zi * (double)r0;
+        zrp = rp ? (double)zi * (double)p0 : 0.0;
     }
     if (part) block_partial_sum2(zr, zrp, part, part + gridDim.x);
 }
@@ -640,8 +631,8 @@ int net_apply_mfma3d(const adlbr_net *net, const adlbr_operator *op, const float
                        net->gates8, 16, (uint2 *)B, st);
     hipLaunchKernelGGL(k_net3d_mfma, dim3(nt), dim3(256), 0, s, g, (const uint2 *)B, pk + k3T * 64,
                        net->gates8, 0, (uint2 *)A, st);
-    hipLaunchKernelGGL(k_net3d_l4, dim3(nt), dim3(256), 0, s, g, (const uint2 *)A, pk + k3Pack4, r,
-                       net->features, z, rp, part, st);
+    hipLaunchKernelGGL(k_net3d_l4, dim3(nt), dim3(256), 0, s, g, (const uint2 *)A,
+                       (const uint32_t *)(pk + k3Pack4), r, net->features, z, rp, part, st);
     ADLBR_LAUNCH_CHECK();
     return ADLBR_OK;
 }
