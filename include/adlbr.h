@@ -239,6 +239,23 @@ int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *const *u,
  * the class whole.  Every choice computes the same bits.  Synchronizes
  * `stream`. */
 int adlbr_batch_tune(adlbr_batch *batch, int steps, int use_cache, void *stream);
+/* The tuner's cache on disk (a JSON file, so that one process's timings
+ * serve later ones):
+ *   {"format": "adlbr-batch-tune", "version": 1, "entries": [
+ *     {"class": K, "log2_points": L, "problems": P, "variant": V,
+ *      "chunk_bytes": B}, ...]}
+ * with K the class key (adlbr_batch_variant), L = floor(log2 of the class's
+ * points), P its problem count.  save writes every choice this process
+ * holds; load merges a file's entries into it (all or nothing:
+ * ADLBR_E_INVALID, cache unchanged, on an unreadable or malformed file);
+ * adlbr_batch_create and adlbr_batch_tune(use_cache = 1) then take a
+ * class's cached choice without timing.  clear empties the process's cache;
+ * lookup reports (found = 0/1) the choice for one class.  Host only. */
+int adlbr_batch_tune_save(const char *path);
+int adlbr_batch_tune_load(const char *path);
+int adlbr_batch_tune_clear(void);
+int adlbr_batch_tune_lookup(int class_key, int64_t points, int nprob, int *found, int *variant,
+                            size_t *chunk_bytes);
 /* Force launch variant (0..7) and chunk budget (bytes, 0 = no chunks; a
  * problem larger than the budget gets a chunk of its own) for class cls
  * instead of tuning.  Synchronizes `stream`; ADLBR_E_INVALID for a bad

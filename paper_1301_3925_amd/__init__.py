@@ -280,6 +280,31 @@ class Operator:
         return x, rep.as_dict()
 
 
+def tune_cache_save(path) -> None:
+    """Write the batch tuner's choices of this process to a JSON file
+    (adlbr_batch_tune_save)."""
+    capi.check(capi.load().adlbr_batch_tune_save(str(path).encode()))
+
+
+def tune_cache_load(path) -> None:
+    """Merge a tuner cache file into this process's cache
+    (adlbr_batch_tune_load); later batches take its choices untimed."""
+    capi.check(capi.load().adlbr_batch_tune_load(str(path).encode()))
+
+
+def tune_cache_clear() -> None:
+    capi.check(capi.load().adlbr_batch_tune_clear())
+
+
+def tune_cache_lookup(class_key: int, points: int, nprob: int):
+    """(variant, chunk_bytes) cached for a class, or None."""
+    found, var, cb = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+    capi.check(capi.load().adlbr_batch_tune_lookup(int(class_key), int(points), int(nprob),
+                                                   ctypes.byref(found), ctypes.byref(var),
+                                                   ctypes.byref(cb)))
+    return (var.value, cb.value) if found.value else None
+
+
 class Batch:
     """Many operators stepped together (adlbr_batch_*): one grouped launch
     per class and step, the whole run captured into one HIP graph.

@@ -93,6 +93,11 @@ SIGNATURES = {
     "adlbr_batch_workspace": ([_I, ctypes.POINTER(_SZ)], _I),
     "adlbr_batch_create": ([_I, _P, _P, _P, _P, _I, _P, _SZ, _P, ctypes.POINTER(_P)], _I),
     "adlbr_batch_tune": ([_P, _I, _I, _P], _I),
+    "adlbr_batch_tune_save": ([ctypes.c_char_p], _I),
+    "adlbr_batch_tune_load": ([ctypes.c_char_p], _I),
+    "adlbr_batch_tune_clear": ([], _I),
+    "adlbr_batch_tune_lookup": ([_I, _I64, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                                 ctypes.POINTER(_SZ)], _I),
     "adlbr_batch_set_variant": ([_P, _I, _I, _SZ, _P], _I),
     "adlbr_batch_variant": ([_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
                              ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_SZ)], _I),

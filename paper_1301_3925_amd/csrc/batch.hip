@@ -14,11 +14,15 @@
 // keeps the fastest, also in a per-process cache keyed by the class and its
 // size.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <map>
 #include <mutex>
 #include <new>
 #include <vector>
+#include <cerrno>
 
 #include "common.h"
 
@@ -60,12 +64,35 @@ std::mutex g_cache_mu;
 // (class, log2 points, problems) -> (variant, chunk budget)
 std::map<long long, std::pair<int, size_t>> g_cache;
 
+int log2_floor(long long pts) {
+    int lg = 0;
+    while (lg < 62 && (1ll << (lg + 1)) <= pts) ++lg;
+    return lg;
+}
+long long make_key(int cls, int lg, long long nprob) {
+    return ((long long)cls * 64 + lg) * 4096 + std::min<long long>(nprob, 4095);
+}
 long long cache_key(const adlbr_batch::Class &c) {
     long long pts = 0;
     for (const BatchProb &p : c.host) pts += p.g.N;
-    int lg = 0;
-    while ((1ll << (lg + 1)) <= pts) ++lg;
-    return ((long long)c.key * 64 + lg) * 4096 + (long long)std::min<size_t>(c.host.size(), 4095);
+    return make_key(c.key, log2_floor(pts), (long long)c.host.size());
+}
+
+// The integer after "name": in [b, e), false if absent or not a number.
+bool json_int(const std::string &t, size_t b, size_t e, const char *name, long long *out) {
+    const std::string k = std::string("\"") + name + "\"";
+    const size_t at = t.find(k, b);
+    if (at == std::string::npos || at >= e) return false;
+    size_t i = t.find(':', at + k.size());
+    if (i == std::string::npos || i >= e) return false;
+    ++i;
+    while (i < e && (t[i] == ' ' || t[i] == '\t' || t[i] == '\n' || t[i] == '\r')) ++i;
+    char *end = nullptr;
+    errno = 0;
+    const long long v = std::strtoll(t.c_str() + i, &end, 10);
+    if (errno || end == t.c_str() + i || (size_t)(end - t.c_str()) > e) return false;
+    *out = v;
+    return true;
 }
 
 // Lay out the class's problems in the order of the variant, cut them into
@@ -403,5 +430,120 @@ extern "C" int adlbr_batch_destroy(adlbr_batch *b) {
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->own) (void)hipStreamDestroy(b->own);
     delete b;
+    return ADLBR_OK;
+}
+
+// ------------------------------------------------ the tuner's file cache --
+extern "C" int adlbr_batch_tune_save(const char *path) {
+    clear_error();
+    if (!path) {
+        set_error("adlbr_batch_tune_save: null path");
+        return ADLBR_E_INVALID;
+    }
+    std::map<long long, std::pair<int, size_t>> snap;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        snap = g_cache;
+    }
+    FILE *f = std::fopen(path, "w");
+    if (!f) {
+        set_error("adlbr_batch_tune_save: cannot open %s for writing", path);
+        return ADLBR_E_INVALID;
+    }
+    std::fprintf(f, "{\"format\": \"adlbr-batch-tune\", \"version\": 1, \"entries\": [");
+    bool first = true;
+    for (const auto &kv : snap) {
+        const long long key = kv.first;
+        const long long np = key % 4096, lg = (key / 4096) % 64, cls = key / (4096 * 64);
+        std::fprintf(f, "%s\n  {\"class\": %lld, \"log2_points\": %lld, \"problems\": %lld, "
+                        "\"variant\": %d, \"chunk_bytes\": %zu}",
+                     first ? "" : ",", cls, lg, np, kv.second.first, kv.second.second);
+        first = false;
+    }
+    std::fprintf(f, "\n]}\n");
+    const bool bad = std::ferror(f) != 0;
+    if (std::fclose(f) != 0 || bad) {
+        set_error("adlbr_batch_tune_save: write to %s failed", path);
+        return ADLBR_E_INVALID;
+    }
+    return ADLBR_OK;
+}
+
+extern "C" int adlbr_batch_tune_load(const char *path) {
+    clear_error();
+    if (!path) {
+        set_error("adlbr_batch_tune_load: null path");
+        return ADLBR_E_INVALID;
+    }
+    FILE *f = std::fopen(path, "r");
+    if (!f) {
+        set_error("adlbr_batch_tune_load: cannot open %s", path);
+        return ADLBR_E_INVALID;
+    }
+    std::string t;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) t.append(buf, n);
+    std::fclose(f);
+    if (t.find("\"adlbr-batch-tune\"") == std::string::npos) {
+        set_error("adlbr_batch_tune_load: %s is not a tuner cache", path);
+        return ADLBR_E_INVALID;
+    }
+    size_t pos = t.find("\"entries\"");
+    if (pos == std::string::npos || (pos = t.find('[', pos)) == std::string::npos) {
+        set_error("adlbr_batch_tune_load: %s has no entries list", path);
+        return ADLBR_E_INVALID;
+    }
+    const size_t close = t.find(']', pos);
+    if (close == std::string::npos) {
+        set_error("adlbr_batch_tune_load: %s: unterminated entries list", path);
+        return ADLBR_E_INVALID;
+    }
+    // parse every entry first; the cache changes only if all are valid
+    std::vector<std::pair<long long, std::pair<int, size_t>>> got;
+    size_t b = pos;
+    while ((b = t.find('{', b)) != std::string::npos && b < close) {
+        const size_t e = t.find('}', b);
+        if (e == std::string::npos || e > close) {
+            set_error("adlbr_batch_tune_load: %s: unterminated entry", path);
+            return ADLBR_E_INVALID;
+        }
+        long long cls, lg, np, var, cb;
+        if (!json_int(t, b, e, "class", &cls) || !json_int(t, b, e, "log2_points", &lg) ||
+            !json_int(t, b, e, "problems", &np) || !json_int(t, b, e, "variant", &var) ||
+            !json_int(t, b, e, "chunk_bytes", &cb) || cls < 0 || cls > (1ll << 30) || lg < 0 ||
+            lg > 62 || np < 1 || np > 4095 || var < 0 || var >= kVariants || cb < 0) {
+            set_error("adlbr_batch_tune_load: %s: malformed entry at byte %zu", path, b);
+            return ADLBR_E_INVALID;
+        }
+        got.push_back({make_key((int)cls, (int)lg, np), {(int)var, (size_t)cb}});
+        b = e + 1;
+    }
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (const auto &kv : got) g_cache[kv.first] = kv.second;
+    return ADLBR_OK;
+}
+
+extern "C" int adlbr_batch_tune_clear(void) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_cache.clear();
+    return ADLBR_OK;
+}
+
+extern "C" int adlbr_batch_tune_lookup(int class_key, int64_t points, int nprob, int *found,
+                                       int *variant, size_t *chunk_bytes) {
+    clear_error();
+    if (class_key < 0 || points < 1 || nprob < 1 || !found) {
+        set_error("adlbr_batch_tune_lookup: bad argument");
+        return ADLBR_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    const auto it = g_cache.find(make_key(class_key, log2_floor(points), nprob));
+    *found = it != g_cache.end();
+    if (*found) {
+        if (variant) *variant = it->second.first;
+        if (chunk_bytes) *chunk_bytes = it->second.second;
+    }
     return ADLBR_OK;
 }

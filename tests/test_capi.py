@@ -69,3 +69,51 @@ def test_null_arguments_rejected_before_any_launch(lib):
     rc = lib.adlbr_operator_create(ctypes.byref(g), None, None, capi.F64, capi.F32, 0, None, 0,
                                    None, None, ctypes.byref(h))
     assert rc == capi.E_INVALID
+
+
+def test_tuner_cache_file_round_trip(lib, tmp_path):
+    """The batch tuner's JSON cache: load merges a file's entries (keyed by
+    class, floor(log2 points) and problem count), save writes them back in
+    the same format, a malformed file changes nothing.  Host code only."""
+    import json
+    import paper_1301_3925_amd as adlbr
+    adlbr.tune_cache_clear()
+    src = tmp_path / "tune.json"
+    src.write_text(json.dumps({"format": "adlbr-batch-tune", "version": 1, "entries": [
+        {"class": 2001, "log2_points": 25, "problems": 64, "variant": 1, "chunk_bytes": 234881024},
+        {"class": 3001, "log2_points": 24, "problems": 8, "variant": 6, "chunk_bytes": 0}]}))
+    adlbr.tune_cache_load(src)
+    # any point count in [2^25, 2^26) falls in the first entry's bucket
+    assert adlbr.tune_cache_lookup(2001, 56455727, 64) == (1, 234881024)
+    assert adlbr.tune_cache_lookup(2001, 1 << 25, 64) == (1, 234881024)
+    assert adlbr.tune_cache_lookup(2001, 1 << 26, 64) is None
+    assert adlbr.tune_cache_lookup(3001, 23505948, 8) == (6, 0)
+    assert adlbr.tune_cache_lookup(3001, 23505948, 9) is None
+    out = tmp_path / "saved.json"
+    adlbr.tune_cache_save(out)
+    saved = json.loads(out.read_text())
+    assert saved["format"] == "adlbr-batch-tune"
+    got = sorted((e["class"], e["log2_points"], e["problems"], e["variant"], e["chunk_bytes"])
+                 for e in saved["entries"])
+    assert got == [(2001, 25, 64, 1, 234881024), (3001, 24, 8, 6, 0)]
+    adlbr.tune_cache_clear()
+    assert adlbr.tune_cache_lookup(2001, 56455727, 64) is None
+    adlbr.tune_cache_load(out)
+    assert adlbr.tune_cache_lookup(3001, 23505948, 8) == (6, 0)
+    # malformed files: refused, the cache unchanged
+    for bad in ({"format": "something-else", "entries": []},
+                {"format": "adlbr-batch-tune", "entries": [{"class": 1, "log2_points": 3,
+                                                            "problems": 2, "variant": 9,
+                                                            "chunk_bytes": 0}]},
+                {"format": "adlbr-batch-tune", "entries": [{"class": 1, "problems": 2,
+                                                            "variant": 0, "chunk_bytes": 0}]}):
+        f = tmp_path / "bad.json"
+        f.write_text(json.dumps(bad))
+        with pytest.raises(adlbr.AdlbrError) as ei:
+            adlbr.tune_cache_load(f)
+        assert ei.value.code == capi.E_INVALID
+    with pytest.raises(adlbr.AdlbrError):
+        adlbr.tune_cache_load(tmp_path / "missing.json")
+    assert adlbr.tune_cache_lookup(3001, 23505948, 8) == (6, 0)
+    assert adlbr.tune_cache_lookup(1, 8, 2) is None
+    adlbr.tune_cache_clear()

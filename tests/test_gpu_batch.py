@@ -150,3 +150,35 @@ def test_rebuild_in_place_keeps_the_batch_graph_valid(lib):
         assert torch.equal(u, r), k
     for op, f in zip(ops, fresh):
         assert op.dt_cfl() == f.dt_cfl()
+
+
+def test_tuner_cache_file_serves_a_new_batch(lib, tmp_path):
+    """Tune, save the tuner's choices to a JSON file, forget them, load the
+    file: a new batch of the same classes starts with the saved variants
+    and chunk budgets (adlbr_batch_create takes them from the cache), and
+    still steps bit-identically to single-operator steps."""
+    import torch
+    lib.tune_cache_clear()
+    ops, us = _problems(lib, torch.float32)
+    b = lib.Batch(ops, us, dt=0.9, dt_mode="cfl")
+    tuned = b.tune(steps=2, use_cache=False)
+    path = tmp_path / "tune.json"
+    lib.tune_cache_save(path)
+    lib.tune_cache_clear()
+    # with an empty cache a new batch starts from the default variant
+    fresh = lib.Batch(ops, [u.clone() for u in us], dt=0.9, dt_mode="cfl").variants()
+    assert all(v["variant"] == 1 and v["chunk_bytes"] == 0 for v in fresh)
+    lib.tune_cache_load(path)
+    us2 = [u.clone() for u in us]
+    b2 = lib.Batch(ops, us2, dt=0.9, dt_mode="cfl")
+    got = b2.variants()
+    key = lambda v: (v["class"], v["variant"], v["chunk_bytes"], v["problems"])
+    assert sorted(map(key, got)) == sorted(map(key, tuned))
+    ref = [u.clone() for u in us]
+    for op, u in zip(ops, ref):
+        op.step(u, 0.9, 5, cfl_fraction=True)
+    b2.run(5)
+    torch.cuda.synchronize()
+    for k, (u, r) in enumerate(zip(us2, ref)):
+        assert torch.equal(u, r), k
+    lib.tune_cache_clear()
