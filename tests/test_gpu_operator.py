@@ -177,3 +177,28 @@ def test_apply_deterministic(lib):
     off, w, _ = lib.build_stencils(torch.from_numpy(D).cuda(), dims)
     op2 = lib.Operator(dims, off, w, storage=torch.float32)
     assert torch.equal(op.apply(u), op2.apply(u))
+
+
+def test_3d_bins_outside_the_lds_window(lib):
+    """The 3D assembly counts and places edges through an LDS window of 2048
+    bins of 1024 targets around each block's own bin; targets farther away
+    go to the global counters.  On a 740 x 740 x 3 grid a plane is 534.8
+    bins, so every edge two planes up or down lands outside the window and
+    every edge one plane away inside it: the operator must equal the
+    oracle's either way (FP64 1e-12, FP32 1e-5), with its diagonal and CFL
+    bound."""
+    import torch
+    dims = (740, 740, 3)
+    D = synth.tensor3d_field(31, dims, 4.0)
+    off, w, st = lib.build_stencils(torch.from_numpy(D).cuda(), dims)
+    on, wn = off.cpu().numpy(), w.cpu().numpy()
+    assert np.abs(on.reshape(6, 3, -1)[:, 2]).max() == 2  # edges two planes away exist
+    A = oracle.operator_matrix(dims, on, wn)
+    u = synth.uniform(8, A.shape[0])
+    op = lib.Operator(dims, off, w, storage=torch.float64)
+    assert _rel(op.apply(torch.from_numpy(u).cuda()).cpu().numpy(), A @ u) <= 1e-12
+    assert np.allclose(op.diagonal().cpu().numpy(), A.diagonal(), rtol=1e-13, atol=1e-15)
+    assert abs(op.dt_cfl() - oracle.cfl(A)) <= 1e-14 * oracle.cfl(A)
+    op32 = lib.Operator(dims, off, w, storage=torch.float32)
+    ug = torch.from_numpy(u).float().cuda()
+    assert _rel(op32.apply(ug).double().cpu().numpy(), A @ ug.double().cpu().numpy()) <= 1e-5
