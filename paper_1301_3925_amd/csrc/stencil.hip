@@ -104,28 +104,57 @@ struct Form3 {
     double xx, yy, zz, xy, xz, yz;
 };
 
-struct V3 {
-    ll x, y, z;
+// Lattice vectors with integer components of type I.  The reduction runs
+// first in 32-bit integers, whose products and coefficient sums are exact
+// while every component stays within +-32767 (|2 * 32767^2| < 2^31); a
+// point whose reduction leaves that range is reduced again in 64-bit
+// integers.  Either way the coefficients, hence the doubles and every
+// decision, are the same as the 64-bit reduction's.
+template <typename I> struct V3T {
+    I x, y, z;
 };
+typedef V3T<ll> V3;
+constexpr int kSmall = 32767;
 
-__device__ __forceinline__ double form3(const Form3 &q, const V3 &a, const V3 &b) {
-    const ll cxx = a.x * b.x, cyy = a.y * b.y, czz = a.z * b.z;
-    const ll cxy = a.x * b.y + a.y * b.x;
-    const ll cxz = a.x * b.z + a.z * b.x;
-    const ll cyz = a.y * b.z + a.z * b.y;
+template <typename I>
+__device__ __forceinline__ double form3(const Form3 &q, const V3T<I> &a, const V3T<I> &b) {
+    const I cxx = a.x * b.x, cyy = a.y * b.y, czz = a.z * b.z;
+    const I cxy = a.x * b.y + a.y * b.x;
+    const I cxz = a.x * b.z + a.z * b.x;
+    const I cyz = a.y * b.z + a.z * b.y;
     return (((((double)cxx * q.xx + (double)cyy * q.yy) + (double)czz * q.zz) +
              (double)cxy * q.xy) + (double)cxz * q.xz) + (double)cyz * q.yz;
 }
 
-__device__ __forceinline__ V3 v3_axpy(ll a, const V3 &x, const V3 &y) {  // y - a x
-    return V3{y.x - a * x.x, y.y - a * x.y, y.z - a * x.z};
+template <typename I> __device__ __forceinline__ bool small3(const V3T<I> &v) {
+    return v.x >= -kSmall && v.x <= kSmall && v.y >= -kSmall && v.y <= kSmall &&
+           v.z >= -kSmall && v.z <= kSmall;
 }
 
-__device__ int reduce_pair3(const Form3 &q, V3 &e, V3 &f) {
+// y - k x; with 32-bit integers false (and no result) when k or the result
+// leaves +-32767.  The coefficient arrives as the 64-bit integer the 64-bit
+// reduction uses, so the two agree even where a rounded coefficient is too
+// large for a double to hold its neighbours exactly.
+template <typename I>
+__device__ __forceinline__ bool v3_axpy(ll k, const V3T<I> &x, const V3T<I> &y, V3T<I> &out) {
+    if constexpr (sizeof(I) == 4) {
+        if (k < -kSmall || k > kSmall) return false;
+        const int ki = (int)k;
+        out = V3T<I>{y.x - ki * x.x, y.y - ki * x.y, y.z - ki * x.z};
+        return small3(out);
+    } else {
+        out = V3T<I>{y.x - k * x.x, y.y - k * x.y, y.z - k * x.z};
+        return true;
+    }
+}
+
+// Lagrange on the pair: iterations used, -1 past kMaxIter, -2 when 32-bit
+// integers overflow.
+template <typename I> __device__ int reduce_pair3(const Form3 &q, V3T<I> &e, V3T<I> &f) {
     for (int it = 1; it <= kMaxIter; ++it) {
         const double r = round(form3(q, e, f) / form3(q, f, f));
-        const ll k = (ll)r;
-        const V3 g = v3_axpy(k, f, e);
+        V3T<I> g;
+        if (!v3_axpy<I>((ll)r, f, e, g)) return -2;
         e = f;
         f = g;
         if (!(form3(q, e, e) > form3(q, f, f))) return it;
@@ -137,17 +166,19 @@ __device__ int reduce_pair3(const Form3 &q, V3 &e, V3 &f) {
 // Lagrange, replace the third by its offset from the closest vector of the
 // plane lattice of the first two (searched among round(y) + {-1,0,1}^2,
 // first minimum in i-major order), until the third is not shorter than the
-// second.
-__device__ bool greedy3(const Form3 &q, V3 b[3]) {
+// second.  1: reduced; 0: past kMaxIter; -2: 32-bit overflow.
+template <typename I> __device__ int greedy3(const Form3 &q, V3T<I> b[3]) {
     for (int it = 0; it < kMaxIter; ++it) {
         // stable insertion sort of three vectors by squared norm
         for (int i = 1; i < 3; ++i)
             for (int j = i; j > 0 && form3(q, b[j - 1], b[j - 1]) > form3(q, b[j], b[j]); --j) {
-                const V3 t = b[j];
+                const V3T<I> t = b[j];
                 b[j] = b[j - 1];
                 b[j - 1] = t;
             }
-        if (reduce_pair3(q, b[0], b[1]) < 0) return false;
+        const int rp = reduce_pair3<I>(q, b[0], b[1]);
+        if (rp == -2) return -2;
+        if (rp < 0) return 0;
         const double g11 = form3(q, b[0], b[0]), g12 = form3(q, b[0], b[1]);
         const double g22 = form3(q, b[1], b[1]);
         const double p1 = form3(q, b[0], b[2]), p2 = form3(q, b[1], b[2]);
@@ -156,10 +187,11 @@ __device__ bool greedy3(const Form3 &q, V3 b[3]) {
         const double y2 = (p2 * g11 - p1 * g12) / det;
         const ll c1 = (ll)round(y1), c2 = (ll)round(y2);
         double best = INFINITY;
-        V3 bv = b[2];
+        V3T<I> bv = b[2];
         for (int i = -1; i <= 1; ++i)
             for (int j = -1; j <= 1; ++j) {
-                const V3 v = v3_axpy(c2 + j, b[1], v3_axpy(c1 + i, b[0], b[2]));
+                V3T<I> t, v;
+                if (!v3_axpy<I>(c1 + i, b[0], b[2], t) || !v3_axpy<I>(c2 + j, b[1], t, v)) return -2;
                 const double n2 = form3(q, v, v);
                 if (n2 < best) {
                     best = n2;
@@ -167,9 +199,9 @@ __device__ bool greedy3(const Form3 &q, V3 b[3]) {
                 }
             }
         b[2] = bv;
-        if (form3(q, b[2], b[2]) >= form3(q, b[1], b[1])) return true;
+        if (form3(q, b[2], b[2]) >= form3(q, b[1], b[1])) return 1;
     }
-    return false;
+    return 0;
 }
 
 __device__ __forceinline__ V3 cross3(const V3 &a, const V3 &b) {
@@ -234,7 +266,14 @@ __global__ void k_stencil3d(const TD *__restrict__ D, long long N, int16_t *__re
     } else {
         const Form3 q{a, b, c, xy, xz, yz};
         V3 r[3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-        if (!greedy3(q, r)) {
+        V3T<int> ri[3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        int red = greedy3<int>(q, ri);
+        if (red == -2) {
+            red = greedy3<ll>(q, r);  // left the 32-bit range: again in 64 bits
+        } else {
+            for (int k = 0; k < 3; ++k) r[k] = V3{ri[k].x, ri[k].y, ri[k].z};
+        }
+        if (red != 1) {
             st |= ADLBR_ST_ITER;
         } else {
             V3 e[4];

@@ -4,8 +4,12 @@ Offsets are integers decided in FP64: they must match bit for bit.  Weights
 are FP64 values computed by different formulas on the two sides (oracle: the
 paper's perpendicular form; GPU: the adjugate form), each a difference of
 products of size |D| r^2 for stencil radius r, so the bound is
-|w_gpu - w_oracle| <= 1e-14 |D|_max max(1, r^2) per point; FP32 weights must
-equal the FP32 rounding of the oracle's value to 1e-6 relative.
+|w_gpu - w_oracle| <= 1e-14 |D|_max max(1, r^2) per point.  In 3D a weight
+-1/2 <e_i, D e_j> is a sum of products of size |D| |e_i|_1 |e_j|_1 over the
+superbase vectors, which can be far longer than the offsets e_k x e_l once
+the anisotropy is extreme; there the bound takes max(1, r^2, max_i |e_i|_1^2).
+FP32 weights must equal the FP32 rounding of the oracle's value to 1e-6
+relative.
 """
 import math
 
@@ -47,6 +51,9 @@ def _check(lib, D, dims, D_dtype="f64", w_dtype="f64"):
     assert np.array_equal(off, ro), "offsets differ"
     if w_dtype == "f64":
         r2 = (ro.astype(np.float64) ** 2).sum(1).max(0)
+        if len(dims) == 3:
+            sb = oracle.superbase3d(Dref)[0].astype(np.float64)
+            r2 = np.maximum(r2, np.abs(sb).sum(1).max(0) ** 2)
         scale = np.nan_to_num(np.abs(Dref), nan=0.0, posinf=0.0).max(0) * np.maximum(1.0, r2)
         assert np.all(np.abs(w - rw) <= 1e-14 * scale)
     else:
@@ -99,6 +106,22 @@ def test_c3_recipe_3d(lib):
 def test_random_tensors_3d(lib, kmax):
     D = synth.random_spd3(200 + int(kmax), 6000, kmax)
     _check(lib, D, (30, 20, 10))
+
+
+@pytest.mark.parametrize("kmax", [1e6, 1e7])
+def test_extreme_anisotropy_3d(lib, kmax):
+    """Reduced bases with components in the tens of thousands and beyond the
+    16-bit offset range: the 32-bit reduction overflows and the point is
+    reduced again in 64-bit integers; offsets, weights and status still
+    match the oracle.  (Past kappa ~ 1e8 the FP64 greedy reduction itself
+    runs out of 64-bit integers on both sides, so no parity is claimed
+    there.)"""
+    D = synth.random_spd3(7, 4000, kmax)
+    off, _ = _check(lib, D, (40, 10, 10))
+    assert np.abs(off).max() > 10000
+    if kmax >= 1e7:
+        b, _ = oracle.reduce3d(D)
+        assert (np.abs(b).max((0, 1)) > 32767).sum() >= 1  # the 64-bit path ran
 
 
 def test_identity_and_ties_3d(lib):
