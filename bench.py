@@ -103,6 +103,8 @@ def parse():
                     help="c5: how many times flexible-CG residuals join the training pool")
     ap.add_argument("--dtype", default=None, help="storage dtype for c3: f64|f32|bf16|f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--build-streams", type=int, default=8,
+                    help="c4: streams the per-problem stencil builds and assemblies run on")
     ap.add_argument("--batch-variant", type=int, default=1,
                     help="c4: launch variant of every class (adlbr_batch_set_variant; "
                          "1 = XCD-contiguous block order)")
@@ -329,14 +331,37 @@ def run_c4(args, dev, stream, probs, fields, cpu):
         variants = b.variants()
         log(f"variants: {variants}")
 
+    # The per-problem builds are chains of small, latency-bound launches
+    # with buffers of their own: they run on build streams (default
+    # priority), largest problem first on the least loaded stream, forked
+    # from and joined back into the batch's stream before the steps.
+    nbs = max(1, args.build_streams)
+    bstreams = [torch.cuda.Stream() for _ in range(nbs)] if nbs > 1 else [stream]
+    load = [0] * nbs
+    plan = []
+    for i in sorted(range(len(probs)), key=lambda i: -int(np.prod(probs[i]["n"]))):
+        k = load.index(min(load))
+        load[k] += int(np.prod(probs[i]["n"])) * (6 if probs[i]["dim"] == 3 else 3)
+        plan.append((i, bstreams[k]))
+    fork = torch.cuda.Event()
+    joins = [torch.cuda.Event() for _ in bstreams]
+
     def one_pass(ev=None):
         # the whole hot path over the batch: stencils, in-place assembly,
         # 100 explicit steps of every problem from the captured graph
         if ev is not None:
             ev[0].record(stream)
-        for p, Dg, out, op in zip(probs, Ds, outs, ops):
-            adlbr.build_stencils(Dg, p["n"], out=out)
-            op.rebuild(out[0], out[1])
+        if nbs > 1:
+            fork.record(stream)
+            for bs in bstreams:
+                bs.wait_event(fork)
+        for i, bs in plan:
+            adlbr.build_stencils(Ds[i], probs[i]["n"], out=outs[i], stream=bs)
+            ops[i].rebuild(outs[i][0], outs[i][1], stream=bs)
+        if nbs > 1:
+            for bs, j in zip(bstreams, joins):
+                j.record(bs)
+                stream.wait_event(j)
         if ev is not None:
             ev[1].record(stream)
         b.run(nsteps)
@@ -386,8 +411,9 @@ def run_c4(args, dev, stream, probs, fields, cpu):
                    "explicit_steps_per_pass": nsteps, "seed": 1304, "kappa": "U[1,50] (2D), <=50 (3D)",
                    "layout": args.layout,
                    "dt": "0.9/max A_zz per problem",
-                   "pass": "stencils + assembly of all problems, then 100 explicit steps of "
-                           "every problem in one graph replay"},
+                   "build_streams": max(1, args.build_streams),
+                   "pass": "stencils + assembly of all problems (on the build streams), then "
+                           "100 explicit steps of every problem in one graph replay"},
         "phases_ms_per_pass": {"stencils_and_assembly": round(build_ms, 3),
                                "explicit_steps_x100": round(steps_ms, 3)},
         "per_problem_launches": {"value": round(pts * nsteps / seq / 1e6, 2),
