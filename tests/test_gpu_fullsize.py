@@ -76,7 +76,7 @@ def _crop_row(dims, off, w, u, z, R):
         c = (coords[0] - lo[0]) + cdims[0] * ((coords[1] - lo[1]) + cdims[1] * (coords[2] - lo[2]))
     A = oracle.operator_matrix(cdims, off[:, :, lin], w[:, lin].astype(np.float64)).tocsr()
     row = A.getrow(c)
-    return float(row @ u[lin].astype(np.float64)), float(A[c, c])
+    return float((row @ u[lin].astype(np.float64))[0]), float(A[c, c])
 
 
 @pytest.fixture(scope="module")
