@@ -345,21 +345,25 @@ __global__ void k_pack_mfma(const float *__restrict__ L1, const float *__restric
 
 // ------------------------------------------------------------------ 3D --
 // The 3D inference runs layer by layer: the thin layers (1 -> 16, 16 -> 1)
-// on the vector units, one thread per point; the two 16 -> 16 layers on the
-// matrix cores as implicit GEMMs over 8 x 8 x 4 tiles (27 taps x one
+// on the vector units, k3PPT points per thread; the two 16 -> 16 layers on the
+// matrix cores as implicit GEMMs over 8 x 8 x 8 tiles (27 taps x one
 // v_mfma_f32_16x16x16_bf16 per 16-pixel group, the tile plus a one-point
 // halo staged in LDS).  Activations cross HBM between layers as BF16
 // [N][16] (32 bytes a point), gates as the 8-bit g1, g2 of every point.
-constexpr int k3X = 8, k3Y = 8, k3Z = 4;                 // output tile
+constexpr int k3X = 8, k3Y = 8, k3Z = 8;                 // output tile
 constexpr int k3HX = k3X + 2, k3HY = k3Y + 2, k3HZ = k3Z + 2;
-constexpr int k3Halo = k3HX * k3HY * k3HZ;               // 600 staged points
+constexpr int k3Halo = k3HX * k3HY * k3HZ;               // 1000 staged points
+constexpr int k3Pts = k3X * k3Y * k3Z;                   // 512 outputs per block
+constexpr int k3PPT = k3Pts / 256;                       // points per thread (layers 1, 4)
+constexpr int k3GPW = k3Pts / 64;                        // 16-point groups per wave (MFMA)
+static_assert(k3Pts % 256 == 0, "whole points per thread");
 constexpr int k3T = 27;
 
 __device__ __forceinline__ bool in_grid3(int x, int y, int z, int nx, int ny, int nz) {
     return x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz;
 }
 
-// The tile of block b (8 x 8 x 4 points) and the origin of its halo.
+// The tile of block b (8 x 8 x 8 points) and the origin of its halo.
 struct Tile3 {
     int x0, y0, z0;  // halo origin = tile origin - 1
 };
@@ -378,34 +382,38 @@ __device__ __forceinline__ int halo_idx(int p, int t) {
     return (pz + 1 + dz) * (k3HX * k3HY) + (py + 1 + dy) * k3HX + (px + 1 + dx);
 }
 
-// Stage a BF16 [N][16] field over the tile's halo into LDS (kStride shorts
-// per point, 0 outside the grid), 8 bytes per item: every load of a thread is
-// issued before its first LDS store, so the block waits for one round trip to
-// memory instead of one per item.  Needs blockDim.x == 256.
+// Stage a BF16 [N][16] field over the tile's halo into LDS (STRIDE shorts
+// per point, 0 outside the grid), 8 bytes per item: a thread issues kB loads
+// before their LDS stores, so the block waits for one round trip to memory
+// per kB items instead of one per item (all of them at once by default; a
+// kernel short of registers takes fewer).  Needs blockDim.x == 256.
 constexpr int k3StageItems = k3Halo * 4, k3StageIters = (k3StageItems + 255) / 256;
-template <int STRIDE = kStride>
+template <int STRIDE = kStride, int kB = k3StageIters>
 __device__ __forceinline__ void stage3d(const GridInfo &g, const Tile3 &T, const uint2 *__restrict__ in,
                                         short *sx) {
-    uint2 v[k3StageIters];
 #pragma unroll
-    for (int it = 0; it < k3StageIters; ++it) {
-        const int k = (int)threadIdx.x + 256 * it;
-        const int h = k >> 2, q = k & 3;
-        const int x = T.x0 + h % k3HX, y = T.y0 + (h / k3HX) % k3HY, z = T.z0 + h / (k3HX * k3HY);
-        v[it] = make_uint2(0u, 0u);
-        if (k < k3StageItems && in_grid3(x, y, z, g.nx, g.ny, g.nz))
-            v[it] = in[4 * (x + (long long)g.nx * (y + (long long)g.ny * z)) + q];
-    }
+    for (int i0 = 0; i0 < k3StageIters; i0 += kB) {
+        uint2 v[kB];
 #pragma unroll
-    for (int it = 0; it < k3StageIters; ++it) {
-        const int k = (int)threadIdx.x + 256 * it;
-        if (k < k3StageItems) *(uint2 *)(sx + (k >> 2) * STRIDE + 4 * (k & 3)) = v[it];
+        for (int j = 0; j < kB; ++j) {
+            const int k = (int)threadIdx.x + 256 * (i0 + j);
+            const int h = k >> 2, q = k & 3;
+            const int x = T.x0 + h % k3HX, y = T.y0 + (h / k3HX) % k3HY, z = T.z0 + h / (k3HX * k3HY);
+            v[j] = make_uint2(0u, 0u);
+            if (i0 + j < k3StageIters && k < k3StageItems && in_grid3(x, y, z, g.nx, g.ny, g.nz))
+                v[j] = in[4 * (x + (long long)g.nx * (y + (long long)g.ny * z)) + q];
+        }
+#pragma unroll
+        for (int j = 0; j < kB; ++j) {
+            const int k = (int)threadIdx.x + 256 * (i0 + j);
+            if (i0 + j < k3StageIters && k < k3StageItems) *(uint2 *)(sx + (k >> 2) * STRIDE + 4 * (k & 3)) = v[j];
+        }
     }
 }
 
 // Layer 1: a1[p][co] = g1[p][co] sum_t W1[co][t] r(p + off_t), r = 0 outside
-// the grid (tap t = (dz + 1) 9 + (dy + 1) 3 + (dx + 1)); one thread per
-// point of an 8 x 8 x 4 tile, r of the tile and its halo staged in LDS.
+// the grid (tap t = (dz + 1) 9 + (dy + 1) 3 + (dx + 1)); k3PPT points per
+// thread of an 8 x 8 x 8 tile, r of the tile and its halo staged in LDS.
 __global__ __launch_bounds__(256) void k_net3d_l1(GridInfo g, const float *__restrict__ r,
                                                   const float *__restrict__ W1,
                                                   const uint8_t *__restrict__ G8,
@@ -430,9 +438,11 @@ __global__ __launch_bounds__(256) void k_net3d_l1(GridInfo g, const float *__res
             if ((int)threadIdx.x + 256 * it < k3Halo) sr[threadIdx.x + 256 * it] = v[it];
     }
     __syncthreads();
-    const int p = threadIdx.x;
+#pragma unroll 1
+    for (int k = 0; k < k3PPT; ++k) {
+    const int p = (int)threadIdx.x + 256 * k;
     const int x = T.x0 + 1 + p % k3X, y = T.y0 + 1 + (p / k3X) % k3Y, z = T.z0 + 1 + p / (k3X * k3Y);
-    if (!in_grid3(x, y, z, g.nx, g.ny, g.nz)) return;
+    if (!in_grid3(x, y, z, g.nx, g.ny, g.nz)) continue;
     const long long i = x + (long long)g.nx * (y + (long long)g.ny * z);
     float rv[k3T];
 #pragma unroll
@@ -454,6 +464,7 @@ __global__ __launch_bounds__(256) void k_net3d_l1(GridInfo g, const float *__res
     }
     a1[2 * i] = make_uint4(outw[0], outw[1], outw[2], outw[3]);
     a1[2 * i + 1] = make_uint4(outw[4], outw[5], outw[6], outw[7]);
+    }
 }
 
 // Layers 2 and 3 (16 -> 16): out[p][co] = g[p][co] sum_t sum_ci W_t[co][ci]
@@ -475,19 +486,19 @@ __global__ __launch_bounds__(256) void k_net3d_mfma(GridInfo g, const uint2 *__r
 #pragma unroll
     for (int t = 0; t < k3T; ++t) wb[t] = wpack[t * 64 + lane];
     const int n = lane & 15, kq = (lane >> 4) * 4;
-    uint32_t gv[4];  // the gates of this lane's four output points, requested before the matrix work
+    uint32_t gv[k3GPW];  // the gates of this lane's output points, requested before the matrix work
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int p = (wave * 4 + j) * 16 + n;
+    for (int j = 0; j < k3GPW; ++j) {
+        const int p = (wave * k3GPW + j) * 16 + n;
         const int x = x0 + 1 + p % k3X, y = y0 + 1 + (p / k3X) % k3Y, z = z0 + 1 + p / (k3X * k3Y);
         const long long i = in_grid3(x, y, z, g.nx, g.ny, g.nz) ? x + (long long)g.nx * (y + (long long)g.ny * z) : 0;
         gv[j] = *(const uint32_t *)(G8 + 32 * i + goff + kq);
     }
-    stage3d(g, T, in, sx);
+    stage3d<kStride, 8>(g, T, in, sx);  // 8 loads in flight: the weights stay in registers
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int p = (wave * 4 + j) * 16 + n;  // this lane's output point in the tile
+    for (int j = 0; j < k3GPW; ++j) {
+        const int p = (wave * k3GPW + j) * 16 + n;  // this lane's output point in the tile
         const int px = p % k3X, py = (p / k3X) % k3Y, pz = p / (k3X * k3Y);
         const short *base = sx + ((pz + 1) * (k3HX * k3HY) + (py + 1) * k3HX + (px + 1)) * kStride + kq;
         f32x4 d = {0.f, 0.f, 0.f, 0.f};
@@ -511,7 +522,7 @@ __global__ __launch_bounds__(256) void k_net3d_mfma(GridInfo g, const uint2 *__r
 }
 
 // Layer 4 (16 -> 1) and the output: z = F0 r + sum_t sum_ci W4[ci][t]
-// a3(p + off_t)[ci], one thread per point of an 8 x 8 x 4 tile: a3 of the
+// a3(p + off_t)[ci], k3PPT points per thread of an 8 x 8 x 8 tile: a3 of the
 // tile and its halo staged in LDS (16 channels, 32 bytes a point), the 16
 // channels of every tap taken as 8 BF16 pairs by v_dot2c_f32_bf16 (FP32
 // accumulation) against the tap's weight pairs, which are uniform (scalar
@@ -530,33 +541,45 @@ __global__ __launch_bounds__(256) void k_net3d_l4(GridInfo g, const uint2 *__res
     if (st && (st->done || st->bad)) return;
     __shared__ __attribute__((aligned(16))) short sx[k3Halo * 16];
     const Tile3 T = tile3(g, blockIdx.x);
-    const int p = threadIdx.x;
-    const int x = T.x0 + 1 + p % k3X, y = T.y0 + 1 + (p / k3X) % k3Y, z = T.z0 + 1 + p / (k3X * k3Y);
-    const bool live = in_grid3(x, y, z, g.nx, g.ny, g.nz);
-    const int i = live ? (int)(x + (long long)g.nx * (y + (long long)g.ny * z)) : 0;  // N < 2^28
-    // the output's inputs, requested before the staging: loads from point
-    // 0 for a point outside the grid, dropped below
-    const float r0 = r[i], f0 = F0[i], p0 = (rp ? rp : r)[i];
+    // the outputs' inputs, requested before the staging: loads from point 0
+    // for a point outside the grid, dropped below
+    int ip[k3PPT];
+    bool live[k3PPT];
+    float r0[k3PPT], f0[k3PPT], p0[k3PPT];
+#pragma unroll
+    for (int k = 0; k < k3PPT; ++k) {
+        const int p = (int)threadIdx.x + 256 * k;
+        const int x = T.x0 + 1 + p % k3X, y = T.y0 + 1 + (p / k3X) % k3Y, z = T.z0 + 1 + p / (k3X * k3Y);
+        live[k] = in_grid3(x, y, z, g.nx, g.ny, g.nz);
+        ip[k] = live[k] ? (int)(x + (long long)g.nx * (y + (long long)g.ny * z)) : 0;  // N < 2^28
+        r0[k] = r[ip[k]];
+        f0[k] = F0[ip[k]];
+        p0[k] = (rp ? rp : r)[ip[k]];
+    }
     stage3d<16>(g, T, a3, sx);
     __syncthreads();
-    float acc = 0.f;
-#pragma unroll
-    for (int t = 0; t < k3T; ++t) {
-        const uint4 *src = (const uint4 *)(sx + halo_idx(p, t) * 16);
-        const uint4 lo = src[0], hi = src[1];
-        const uint32_t v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, v[k]),
-                                                  __builtin_bit_cast(bf16x2v, w4[t * 8 + k]), acc,
-                                                  false);
-    }
     double zr = 0.0, zrp = 0.0;
-    if (live) {
-        const float zi = f0 * r0 + acc;
-        zout[i] = zi;
-        zr = (double)zi * (double)r0;
-        zrp = rp ? (double)zi * (double)p0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < k3PPT; ++k) {
+        const int p = (int)threadIdx.x + 256 * k;
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < k3T; ++t) {
+            const uint4 *src = (const uint4 *)(sx + halo_idx(p, t) * 16);
+            const uint4 lo = src[0], hi = src[1];
+            const uint32_t v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                acc = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, v[c]),
+                                                      __builtin_bit_cast(bf16x2v, w4[t * 8 + c]), acc,
+                                                      false);
+        }
+        if (live[k]) {
+            const float zi = f0[k] * r0[k] + acc;
+            zout[ip[k]] = zi;
+            zr += (double)zi * (double)r0[k];
+            zrp += rp ? (double)zi * (double)p0[k] : 0.0;
+        }
     }
     if (part) block_partial_sum2(zr, zrp, part, part + gridDim.x);
 }
@@ -620,8 +643,7 @@ int net_apply_mfma3d(const adlbr_net *net, const adlbr_operator *op, const float
                      const float *rp, double *part, const CgState *st, hipStream_t s) {
     const GridInfo &g = operator_grid(op);
     const long long N = g.N;
-    const float *L = net->layers;
-    const size_t l2 = 16 * 27, l3 = l2 + 16 * 16 * 27, l4 = l3 + 16 * 16 * 27;
+    const float *L = net->layers;  // layer 1's weights come first
     const bf16x4 *pk = (const bf16x4 *)(net->layers + kPackOffset3);
     // activations as BF16 [N][16] in the two halves of the FP32 scratch
     uint4 *A = (uint4 *)net->scratch, *B = (uint4 *)(net->scratch + 8 * N);
