@@ -103,6 +103,9 @@ def parse():
                     help="c5: how many times flexible-CG residuals join the training pool")
     ap.add_argument("--dtype", default=None, help="storage dtype for c3: f64|f32|bf16|f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-records", action="store_true",
+                    help="c4: 2D operators without records (each incoming weight gathered "
+                         "from its source instead of stored with the entry)")
     ap.add_argument("--build-streams", type=int, default=8,
                     help="c4: streams the per-problem stencil builds and assemblies run on")
     ap.add_argument("--batch-variant", type=int, default=1,
@@ -307,7 +310,8 @@ def run_c4(args, dev, stream, probs, fields, cpu):
                torch.empty(2, dtype=torch.int32, device=dev))
         adlbr.build_stencils(Dg, p["n"], out=out)
         ops.append(adlbr.Operator(p["n"], out[0], out[1], storage=torch.float32,
-                                  tiled=args.layout == "tiled"))
+                                  tiled=args.layout == "tiled",
+                                  records=args.layout == "lists" and not args.no_records))
         us.append(torch.from_numpy(synth_u0(p, N)).float().to(dev))
         Ds.append(Dg)
         outs.append(out)
@@ -412,6 +416,7 @@ def run_c4(args, dev, stream, probs, fields, cpu):
                    "layout": args.layout,
                    "dt": "0.9/max A_zz per problem",
                    "build_streams": max(1, args.build_streams),
+                   "records_2d": args.layout == "lists" and not args.no_records,
                    "pass": "stencils + assembly of all problems (on the build streams), then "
                            "100 explicit steps of every problem in one graph replay"},
         "phases_ms_per_pass": {"stencils_and_assembly": round(build_ms, 3),

@@ -158,6 +158,17 @@ int adlbr_build_stencils(const adlbr_grid *g, const void *D, int D_dtype,
  * list layout (results equal to rounding; each layout is deterministic);
  * adlbr_solve and the residual need the list layout (ADLBR_E_UNSUPPORTED). */
 #define ADLBR_OP_TILED 2
+/* Records (list layout; 2D, since 3D operators always keep them): every
+ * incoming entry is also stored with its edge's weight (8 bytes per edge
+ * for F32 storage, entry and weight side by side), and a batch of such 2D
+ * operators reads the weight from there instead of gathering it from the
+ * source's weights.  The batch's grouped step is faster; the assembly
+ * writes the extra 6 x N records per rebuild and the workspace grows by
+ * them.  Single-operator calls (apply, step, solve) read the lists as
+ * without the flag, and results are bit-identical either way.  Operators
+ * with and without records fall in different batch classes.  With
+ * ADLBR_OP_TILED: ADLBR_E_UNSUPPORTED. */
+#define ADLBR_OP_RECORDS 4
 
 int adlbr_operator_workspace(const adlbr_grid *g, int storage, int flags,
                              size_t *bytes);

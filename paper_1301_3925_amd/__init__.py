@@ -110,7 +110,9 @@ class Operator:
 
     tiled=True asks for the tiled layout (ADLBR_OP_TILED: explicit steps
     with tile + halo staged in LDS, near edges unlisted; Neumann grids,
-    F32/BF16/F16 storage; not for solve).
+    F32/BF16/F16 storage; not for solve).  records=True keeps every 2D
+    incoming entry with its weight (ADLBR_OP_RECORDS), which a Batch of
+    such operators reads instead of gathering the weights.
 
     Holds its device workspace (a torch uint8 tensor) for its lifetime.
     With check=True (the default) the constructor synchronizes and raises
@@ -122,9 +124,10 @@ class Operator:
 
     def __init__(self, dims, offsets, weights, storage=None, periodic: bool = False,
                  wide=None, stream=None, workspace=None, check: bool = True,
-                 tiled: bool = False, reflect: bool = False):
+                 tiled: bool = False, reflect: bool = False, records: bool = False):
         self._h = ctypes.c_void_p()
         self.tiled = bool(tiled)
+        self.records = bool(records)
         self.reflect = bool(reflect)
         self._create(dims, offsets, weights, storage, periodic, bool(wide), stream, workspace)
         if not check:
@@ -151,7 +154,8 @@ class Operator:
         self.device = weights.device
         self.wide = wide
         self._grid = grid(self.dims, periodic, self.reflect)
-        flags = (capi.OP_WIDE if wide else 0) | (capi.OP_TILED if self.tiled else 0)
+        flags = ((capi.OP_WIDE if wide else 0) | (capi.OP_TILED if self.tiled else 0) |
+                 (capi.OP_RECORDS if self.records else 0))
         nbytes = ctypes.c_size_t()
         capi.check(lib.adlbr_operator_workspace(ctypes.byref(self._grid),
                                                 _dtype_code(self.storage), flags,

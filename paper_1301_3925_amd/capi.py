@@ -20,6 +20,7 @@ F64, F32, BF16, F16 = 0, 1, 2, 3
 NEUMANN, PERIODIC, REFLECT = 0, 1, 2
 OP_WIDE = 1
 OP_TILED = 2
+OP_RECORDS = 4
 DT_ABS, DT_CFL = 0, 1
 MAP_CED, MAP_EED = 0, 1
 

@@ -1509,8 +1509,10 @@ __device__ __forceinline__ TA wave_incoming(const WaveLists &L, long long z, lon
 // and gathers of the same chunk in every group, then the reductions -- so
 // several independent memory chains are in flight per wave.  blk is the
 // block's index within its grid.  Shared by the single-operator and the
-// batched kernels, so both give bit-identical results.
-template <int DIM, bool WIDE, bool PER, bool STEP, typename TS, typename TA>
+// batched kernels, so both give bit-identical results.  INLW: the weights
+// of incoming edges come with their entries (went) instead of from the
+// sources' weights (2D operators with records in a batch).
+template <int DIM, bool WIDE, bool PER, bool STEP, typename TS, typename TA, bool INLW = kInlineW<DIM>>
 __device__ __forceinline__ void apply_block(
     const GridInfo &g, long long blk, const TS *__restrict__ u, TS *__restrict__ out,
     const typename Slots<DIM, WIDE>::store_t *__restrict__ sb, const TS *__restrict__ w,
@@ -1540,7 +1542,7 @@ __device__ __forceinline__ void apply_block(
 #pragma unroll
             for (int j = 0; j < kPre; ++j) {
                 const unsigned e = eb + 64 * j + lane;
-                if (kInlineW<DIM>) {
+                if (INLW) {
                     load_rec<TS>(went, ent, L[k].start + e, e < L[k].total, v[k][j], wv[k][j]);
                 } else {
                     v[k][j] = e < L[k].total ? ent[L[k].start + e] : -1;
@@ -1556,7 +1558,7 @@ __device__ __forceinline__ void apply_block(
     for (unsigned eb = 0; eb < tmax; eb += 64 * kPre) {
         load_chunks(eb);
         TA val[P][kPre];
-        InEdge<kInlineW<DIM>, DIM == 2 ? 3 : 6, TS, TA, TS> ie[P][kPre];
+        InEdge<INLW, DIM == 2 ? 3 : 6, TS, TA, TS> ie[P][kPre];
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
@@ -1685,14 +1687,14 @@ __device__ __forceinline__ int find_prob(const BatchProb *__restrict__ probs, in
 // a block finds its problem (find_prob), then runs the single-operator block
 // body.  XCD: remap block indices so that each XCD takes a contiguous range
 // (neighbouring blocks share its L2).
-template <int DIM, bool WIDE, bool PER, typename TS, typename TA, bool XCD>
+template <int DIM, bool WIDE, bool PER, typename TS, typename TA, bool XCD, bool INLW = kInlineW<DIM>>
 __global__ __launch_bounds__(kBS) void k_apply_batch(const BatchProb *__restrict__ probs, int nprob,
                                                      int parity) {
     const long long b = XCD ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
     const BatchProb &P = probs[find_prob(probs, nprob, b)];
     const GridInfo g = P.g;
     const TA h = (TA)(P.dt_mode == ADLBR_DT_CFL ? P.dt * P.dtcfl[0] : P.dt);
-    apply_block<DIM, WIDE, PER, true, TS, TA>(
+    apply_block<DIM, WIDE, PER, true, TS, TA, INLW>(
         g, strip_block(b - P.first_block, g, kApplyPoints), (const TS *)P.u[parity], (TS *)P.u[parity ^ 1],
         (const typename Slots<DIM, WIDE>::store_t *)P.sb, (const TS *)P.w, P.cnt, P.pos, P.ent,
         (const EntRec<TS> *)P.went, h);
@@ -2471,6 +2473,13 @@ template <int DIM, bool WIDE, bool PER, typename TS, typename TA> struct BatchF 
         if (copy) {
             hipLaunchKernelGGL((k_copy_batch<TS>), dim3((unsigned)nblocks), dim3(kBS), 0, s, probs,
                                nprob);
+        } else if (DIM == 2 && rep->went) {  // 2D records (the class has them all)
+            if (variant & 1)
+                hipLaunchKernelGGL((k_apply_batch<DIM, WIDE, PER, TS, TA, true, true>),
+                                   dim3((unsigned)nblocks), dim3(kBS), 0, s, probs, nprob, parity);
+            else
+                hipLaunchKernelGGL((k_apply_batch<DIM, WIDE, PER, TS, TA, false, true>),
+                                   dim3((unsigned)nblocks), dim3(kBS), 0, s, probs, nprob, parity);
         } else if (variant & 1) {
             hipLaunchKernelGGL((k_apply_batch<DIM, WIDE, PER, TS, TA, true>), dim3((unsigned)nblocks),
                                dim3(kBS), 0, s, probs, nprob, parity);
@@ -2557,7 +2566,11 @@ struct Layout {
         bincur, binoff, binbuf, total;
 };
 
-Layout layout(const GridInfo &g, int storage, int wide) {
+// records: 2D operators keep each incoming entry with its weight as well
+// (ADLBR_OP_RECORDS); 3D operators always do.
+bool has_records(const GridInfo &g, int records) { return g.dim == 3 ? ADLBR_W3D_INLINE : records != 0; }
+
+Layout layout(const GridInfo &g, int storage, int wide, int records) {
     const long long N = g.N;
     const int S = g.dim == 2 ? 3 : 6;
     const size_t sbsz = g.dim == 2 ? (wide ? 8 : 4) : (wide ? 24 : 12);
@@ -2569,7 +2582,7 @@ Layout layout(const GridInfo &g, int storage, int wide) {
     L.cnt = o;  o += align_up((size_t)N + 64);
     L.pos = o;  o += align_up(4 * (size_t)N + 256);
     L.ent = o;  o += align_up(4 * (size_t)(2 * S) * N);
-    L.went = o; o += g.dim == 3 && ADLBR_W3D_INLINE ? align_up((dtype_size(storage) == 4 ? 8 : dtype_size(storage)) * (size_t)(2 * S) * N) : 0;
+    L.went = o; o += has_records(g, records) ? align_up((dtype_size(storage) == 4 ? 8 : dtype_size(storage)) * (size_t)(2 * S) * N) : 0;
     L.diag = o; o += align_up((storage == ADLBR_F64 ? 8 : 4) * (size_t)N);
     L.scal = o; o += 256;
     L.mask = o; o += align_up((size_t)N + 64);
@@ -2595,8 +2608,9 @@ Layout layout(const GridInfo &g, int storage, int wide) {
 }  // namespace
 
 int batch_class(const adlbr_operator *op) {
-    return op->tiled * 10000 + op->gi.dim * 1000 + op->wide * 100 + op->gi.periodic * 10 +
-           op->storage;
+    const int rec2d = op->gi.dim == 2 && op->went ? 1 : 0;  // 2D records: their own class
+    return rec2d * 100000 + op->tiled * 10000 + op->gi.dim * 1000 + op->wide * 100 +
+           op->gi.periodic * 10 + op->storage;
 }
 
 long long batch_blocks(const adlbr_operator *op, int *block_points) {
@@ -2681,7 +2695,7 @@ extern "C" int adlbr_operator_workspace(const adlbr_grid *g, int storage, int fl
         set_error("adlbr_operator_workspace: bad storage dtype or null output");
         return ADLBR_E_INVALID;
     }
-    *bytes = layout(gi, storage, flags & ADLBR_OP_WIDE).total;
+    *bytes = layout(gi, storage, flags & ADLBR_OP_WIDE, flags & ADLBR_OP_RECORDS).total;
     return ADLBR_OK;
 }
 
@@ -2701,12 +2715,17 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
         set_error("adlbr_operator_create: weights must be F64/F32, storage F64/F32/BF16/F16");
         return ADLBR_E_INVALID;
     }
-    if (flags & ~(ADLBR_OP_WIDE | ADLBR_OP_TILED)) {
+    if (flags & ~(ADLBR_OP_WIDE | ADLBR_OP_TILED | ADLBR_OP_RECORDS)) {
         set_error("adlbr_operator_create: unknown flags 0x%x", flags);
         return ADLBR_E_INVALID;
     }
     const int wide = flags & ADLBR_OP_WIDE ? 1 : 0;
     const int tiled = flags & ADLBR_OP_TILED ? 1 : 0;
+    const int records = flags & ADLBR_OP_RECORDS ? 1 : 0;
+    if (tiled && records) {
+        set_error("adlbr_operator_create: ADLBR_OP_RECORDS needs the list layout");
+        return ADLBR_E_UNSUPPORTED;
+    }
     if (tiled && (gi.periodic || storage == ADLBR_F64)) {
         set_error("adlbr_operator_create: the tiled layout needs a Neumann grid and F32, BF16 or "
                   "F16 storage");
@@ -2716,7 +2735,7 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
         set_error("adlbr_operator_create: too many edges for 32-bit list positions");
         return ADLBR_E_RANGE;
     }
-    const Layout L = layout(gi, storage, wide);
+    const Layout L = layout(gi, storage, wide, records);
     if (ws_bytes < L.total) {
         set_error("adlbr_operator_create: workspace has %zu bytes, %zu needed", ws_bytes, L.total);
         return ADLBR_E_NOMEM;
@@ -2741,7 +2760,7 @@ extern "C" int adlbr_operator_create(const adlbr_grid *g, const int16_t *offsets
     op->cnt = (uint8_t *)(b + L.cnt);
     op->pos = (int32_t *)(b + L.pos);
     op->ent = (int32_t *)(b + L.ent);
-    op->went = gi.dim == 3 && ADLBR_W3D_INLINE ? b + L.went : nullptr;
+    op->went = has_records(gi, records) ? b + L.went : nullptr;
     op->diag = b + L.diag;
     op->maxdiag = (double *)(b + L.scal);
     op->dtcfl = (double *)(b + L.scal + 8);

@@ -3,8 +3,9 @@
 The grouped kernel runs the same per-block body as adlbr_step, so every
 problem of a batch must come out bit-identical to stepping it alone, for
 any launch variant, with and without the captured graph, for even and odd
-step counts and for replays of the graph.  One 2D problem is also checked
-against the FP64 oracle.
+step counts and for replays of the graph, with and without the 2D
+records (ADLBR_OP_RECORDS).  One 2D problem is also checked against the
+FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -23,7 +24,7 @@ def lib():
     return adlbr
 
 
-def _problems(lib, dtype, periodic=False):
+def _problems(lib, dtype, periodic=False, records=False):
     import torch
     specs = [((70, 45), 10.0), ((33, 90), 30.0), ((128, 64), 5.0), ((12, 11, 9), 8.0),
              ((20, 17, 15), 20.0), ((5, 3), 2.0)]
@@ -32,7 +33,7 @@ def _problems(lib, dtype, periodic=False):
         D = (synth.tensor2d_field(100 + k, *dims, kappa) if len(dims) == 2
              else synth.tensor3d_field(100 + k, dims, kappa))
         off, w, _ = lib.build_stencils(torch.from_numpy(D).cuda(), dims)
-        ops.append(lib.Operator(dims, off, w, storage=dtype, periodic=periodic))
+        ops.append(lib.Operator(dims, off, w, storage=dtype, periodic=periodic, records=records))
         us.append(torch.from_numpy(synth.uniform(200 + k, int(np.prod(dims)))).to(dtype).cuda())
     return ops, us
 
@@ -182,3 +183,49 @@ def test_tuner_cache_file_serves_a_new_batch(lib, tmp_path):
     for k, (u, r) in enumerate(zip(us2, ref)):
         assert torch.equal(u, r), k
     lib.tune_cache_clear()
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_records_batch_bitwise(lib, dtype, periodic):
+    """2D operators with records (ADLBR_OP_RECORDS) form a batch class of
+    their own, whose grouped step reads each incoming weight from the
+    entry's record.  With the same problems also present without records,
+    every problem comes out bit-identical to its single-operator steps
+    (which read the lists as without the flag), in both block orders, whole
+    or cut into chunks."""
+    import torch
+    td = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
+          "f16": torch.float16}[dtype]
+    rops, rus = _problems(lib, td, periodic, records=True)
+    pops, pus = _problems(lib, td, periodic)
+    ops = rops + pops
+    assert rops[0].workspace.numel() > pops[0].workspace.numel()  # the 2D records
+    u0 = [u.clone() for u in rus + pus]
+    ref = [u.clone() for u in u0]
+    for op, u in zip(ops, ref):
+        op.step(u, 0.9, 5, cfl_fraction=True)
+    for variant, chunk_bytes in ((1, 300_000), (0, 0)):
+        us = [u.clone() for u in u0]
+        b = lib.Batch(ops, us, dt=0.9, dt_mode="cfl")
+        keys = [v["class"] for v in b.variants()]
+        assert sum(1 for k in keys if k // 1000 % 10 == 2) == 2  # 2D with and without records
+        assert sum(1 for k in keys if k >= 100000) == 1
+        for cls in range(len(keys)):
+            b.set_variant(cls, variant, chunk_bytes)
+        b.run(2)
+        b.run(3)
+        torch.cuda.synchronize()
+        for k, (u, r) in enumerate(zip(us, ref)):
+            assert torch.equal(u, r), (variant, k)
+
+
+def test_records_need_the_list_layout(lib):
+    import torch
+    dims = (40, 30)
+    D = synth.tensor2d_field(7, *dims, 5.0)
+    off, w, _ = lib.build_stencils(torch.from_numpy(D).cuda(), dims)
+    with pytest.raises(lib.AdlbrError) as ei:
+        lib.Operator(dims, off, w, storage=torch.float32, tiled=True, records=True)
+    assert ei.value.code == lib.capi.E_UNSUPPORTED
+
