@@ -54,14 +54,16 @@ ALGO_BYTES = {(2, 8): 16 + 3 * 8 + 4, (2, 4): 8 + 3 * 4 + 4, (2, 2): 4 + 3 * 2 +
 # SHA-256 of the kernel sources they were taken on.  A change to those
 # sources makes the figure stale: traffic is then null.
 TRAFFIC = {
-    "c2": {"sha256": "3f82bf071d809f0f1fd50836255e62c4d096574d919565470a8a453e28762c8c",
-           "bytes_per_launch": 221604480},
-    "c3": {"sha256": "3f82bf071d809f0f1fd50836255e62c4d096574d919565470a8a453e28762c8c",
-           "bytes_per_launch": 2434432000},
-    "c3-bf16": {"sha256": "3f82bf071d809f0f1fd50836255e62c4d096574d919565470a8a453e28762c8c",
-                "bytes_per_launch": 1756694272},
-    "c4": {"sha256": "3f82bf071d809f0f1fd50836255e62c4d096574d919565470a8a453e28762c8c",
-           "bytes_per_launch": 6373427996},
+    "c2": {"sha256": "d3676bd68fc79b0d9177c3b6e1408435c139997d6e3b8b38eb5babe7dfa33d52",
+           "bytes_per_launch": 221648474},
+    "c3": {"sha256": "d3676bd68fc79b0d9177c3b6e1408435c139997d6e3b8b38eb5babe7dfa33d52",
+           "bytes_per_launch": 2434507093},
+    "c3-bf16": {"sha256": "d3676bd68fc79b0d9177c3b6e1408435c139997d6e3b8b38eb5babe7dfa33d52",
+                "bytes_per_launch": 1756668075},
+    "c4": {"sha256": "d3676bd68fc79b0d9177c3b6e1408435c139997d6e3b8b38eb5babe7dfa33d52",
+           "bytes_per_launch": 7710904372},
+    "c4-norecords": {"sha256": "d3676bd68fc79b0d9177c3b6e1408435c139997d6e3b8b38eb5babe7dfa33d52",
+                     "bytes_per_launch": 6373438063},
 }
 TRAFFIC_SOURCES = ("paper_1301_3925_amd/csrc/operator.hip", "paper_1301_3925_amd/csrc/common.h")
 
@@ -300,6 +302,7 @@ def run_c4(args, dev, stream, probs, fields, cpu):
     import paper_1301_3925_amd as adlbr
     nsteps = 100
     K = args.steps if args.steps is not None else 10
+    records = args.layout == "lists" and not args.no_records
     Ds, outs, ops, us = [], [], [], []
     for p, D in zip(probs, fields):
         N = int(np.prod(p["n"]))
@@ -310,8 +313,7 @@ def run_c4(args, dev, stream, probs, fields, cpu):
                torch.empty(2, dtype=torch.int32, device=dev))
         adlbr.build_stencils(Dg, p["n"], out=out)
         ops.append(adlbr.Operator(p["n"], out[0], out[1], storage=torch.float32,
-                                  tiled=args.layout == "tiled",
-                                  records=args.layout == "lists" and not args.no_records))
+                                  tiled=args.layout == "tiled", records=records))
         us.append(torch.from_numpy(synth_u0(p, N)).float().to(dev))
         Ds.append(Dg)
         outs.append(out)
@@ -416,7 +418,7 @@ def run_c4(args, dev, stream, probs, fields, cpu):
                    "layout": args.layout,
                    "dt": "0.9/max A_zz per problem",
                    "build_streams": max(1, args.build_streams),
-                   "records_2d": args.layout == "lists" and not args.no_records,
+                   "records_2d": records,
                    "pass": "stencils + assembly of all problems (on the build streams), then "
                            "100 explicit steps of every problem in one graph replay"},
         "phases_ms_per_pass": {"stencils_and_assembly": round(build_ms, 3),
@@ -431,7 +433,7 @@ def run_c4(args, dev, stream, probs, fields, cpu):
                      "unit_of_work": "one explicit step of every problem "
                                      f"({launches} launches)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for("c4"),
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_for("c4" if records else "c4-norecords"),
                      "algo_bytes": abytes, "avg_step_us": round(step_s * 1e6, 2)},
     }
     del b
