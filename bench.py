@@ -61,9 +61,9 @@ TRAFFIC = {
     "c3-bf16": {"sha256": "d3676bd68fc79b0d9177c3b6e1408435c139997d6e3b8b38eb5babe7dfa33d52",
                 "bytes_per_launch": 1756668075},
     "c4": {"sha256": "d3676bd68fc79b0d9177c3b6e1408435c139997d6e3b8b38eb5babe7dfa33d52",
-           "bytes_per_launch": 7710904372},
+           "bytes_per_launch": 8369979231},
     "c4-norecords": {"sha256": "d3676bd68fc79b0d9177c3b6e1408435c139997d6e3b8b38eb5babe7dfa33d52",
-                     "bytes_per_launch": 6373438063},
+                     "bytes_per_launch": 7031863903},
 }
 TRAFFIC_SOURCES = ("paper_1301_3925_amd/csrc/operator.hip", "paper_1301_3925_amd/csrc/common.h")
 
@@ -111,8 +111,14 @@ def parse():
     ap.add_argument("--build-streams", type=int, default=8,
                     help="c4: streams the per-problem stencil builds and assemblies run on")
     ap.add_argument("--batch-variant", type=int, default=1,
-                    help="c4: launch variant of every class (adlbr_batch_set_variant; "
-                         "1 = XCD-contiguous block order)")
+                    help="c4: launch variant of the 2D class (adlbr_batch_set_variant; "
+                         "1 = XCD-contiguous block order), in chunks of --chunk-mib")
+    ap.add_argument("--chunk-mib", type=int, default=224)
+    ap.add_argument("--batch-variant-3d", type=int, default=2,
+                    help="c4: launch variant of the 3D class (2 = largest volumes first), "
+                         "in chunks of --chunk-mib-3d")
+    ap.add_argument("--chunk-mib-3d", type=int, default=0,
+                    help="0: the whole class in one launch")
     ap.add_argument("--tune", action="store_true",
                     help="c4: pick each class's launch variant with the autotuner instead of "
                          "the fixed grouped launch with 224 MiB chunks")
@@ -325,15 +331,20 @@ def run_c4(args, dev, stream, probs, fields, cpu):
         variants = b.tune(steps=10)
         log(f"tuned: {variants}")
     else:
-        # grouped launch in XCD-contiguous block order, classes cut into
-        # chunks of about 224 MiB, fixed so that the counter runs see the
-        # launches that are timed.  Timed over every variant and chunk
-        # budget (100 steps of the batch): 218 ms; the plain block order
-        # takes 213 ms but reads 1.8x the bytes out of L2 (every XCD fetches
-        # the neighbour rows of blocks the other XCDs run); per-problem
-        # launches 226 ms; the other settings 214-271 ms
-        for c in range(len(b.variants())):
-            b.set_variant(c, args.batch_variant, 224 << 20)
+        # fixed, so that the counter runs see the launches that are timed:
+        # the images in XCD-contiguous block order, cut into chunks of
+        # about 224 MiB whose working sets fit the 256 MB cache; the
+        # volumes, each larger than a chunk, all in one launch, largest
+        # first.  100 steps of the batch (with 2D records): 193 ms; images
+        # in plain block order 192 ms, but they read 1.8x the bytes out of
+        # L2 (every XCD fetches the neighbour rows of blocks the other XCDs
+        # run); volumes in 224 MiB chunks 199 ms; images in 448 MiB chunks
+        # 214 ms
+        for c, v in enumerate(b.variants()):
+            if v["class"] // 1000 % 10 == 3:
+                b.set_variant(c, args.batch_variant_3d, args.chunk_mib_3d << 20)
+            else:
+                b.set_variant(c, args.batch_variant, args.chunk_mib << 20)
         variants = b.variants()
         log(f"variants: {variants}")
 
