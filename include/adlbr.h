@@ -224,7 +224,7 @@ int adlbr_step_multi(adlbr_operator *op, void *u, void *u_tmp, int ncomp, double
  * its state u[i] (device [N_i], in/out) and scratch u_tmp[i] (same size
  * and dtype), stepped as adlbr_step(ops[i], u[i], u_tmp[i], dt[i],
  * dt_mode, nsteps) would step it -- results are bit-identical.  Problems of
- * one class (dim, offset width, boundary, storage) share one grouped
+ * one class (dim, offset width, boundary, storage, 2D records) share one grouped
  * launch per step; adlbr_batch_run captures the nsteps of all classes
  * into one HIP graph (on the batch's own stream, ordered after and before
  * `stream` by events) and replays it on later calls with the same nsteps.
@@ -274,7 +274,9 @@ int adlbr_batch_tune_lookup(int class_key, int64_t points, int nprob, int *found
 int adlbr_batch_set_variant(adlbr_batch *batch, int cls, int variant, size_t chunk_bytes,
                             void *stream);
 /* Class cls (0-based, in order of first appearance): its class key
- * (tiled*10000 + dim*1000 + wide*100 + periodic*10 + storage), launch variant, number of
+ * (records*100000 + tiled*10000 + dim*1000 + wide*100 + periodic*10 +
+ * storage, records = 1 for 2D operators created with ADLBR_OP_RECORDS),
+ * launch variant, number of
  * problems and, where the pointers are not NULL, number of chunks and chunk
  * budget in bytes.  ADLBR_E_INVALID past the last class. */
 int adlbr_batch_variant(const adlbr_batch *batch, int cls, int *key, int *variant, int *nprob,
