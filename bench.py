@@ -110,10 +110,11 @@ def parse():
                          "from its source instead of stored with the entry)")
     ap.add_argument("--build-streams", type=int, default=8,
                     help="c4: streams the per-problem stencil builds and assemblies run on")
-    ap.add_argument("--batch-variant", type=int, default=1,
+    ap.add_argument("--batch-variant", type=int, default=9,
                     help="c4: launch variant of the 2D class (adlbr_batch_set_variant; "
-                         "1 = XCD-contiguous block order), in chunks of --chunk-mib")
-    ap.add_argument("--chunk-mib", type=int, default=224)
+                         "1 = XCD-contiguous block order, 8 = two chunks in flight), in "
+                         "chunks of --chunk-mib")
+    ap.add_argument("--chunk-mib", type=int, default=112)
     ap.add_argument("--batch-variant-3d", type=int, default=2,
                     help="c4: launch variant of the 3D class (2 = largest volumes first), "
                          "in chunks of --chunk-mib-3d")
@@ -333,11 +334,12 @@ def run_c4(args, dev, stream, probs, fields, cpu):
     else:
         # fixed, so that the counter runs see the launches that are timed:
         # the images in XCD-contiguous block order, cut into chunks of
-        # about 224 MiB whose working sets fit the 256 MB cache; the
-        # volumes, each larger than a chunk, all in one launch, largest
-        # first.  100 steps of the batch (with 2D records): 193 ms; images
-        # in plain block order 192 ms, but they read 1.8x the bytes out of
-        # L2 (every XCD fetches the neighbour rows of blocks the other XCDs
+        # about 112 MiB taken two at a time (two chunks' working sets fit
+        # the 256 MB cache); the volumes, each larger than a chunk, all in
+        # one launch, largest first.  100 steps of the batch (with 2D
+        # records): 187 ms; images one 224 MiB chunk at a time 193 ms (in
+        # plain block order 192 ms, but reading 1.8x the bytes out of L2:
+        # every XCD fetches the neighbour rows of blocks the other XCDs
         # run); volumes in 224 MiB chunks 199 ms; images in 448 MiB chunks
         # 214 ms
         for c, v in enumerate(b.variants()):

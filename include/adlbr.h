@@ -242,13 +242,16 @@ int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *const *u,
  * problem count, and reused without timing when use_cache is set.
  * Variants, bit by bit: 0 = XCD-contiguous block order of the grouped
  * launch, 1 = largest problems first, 2 = one launch per problem instead of
- * one grouped launch (bits 0 and 2 together are not timed).  Chunk budgets
- * (0, 64, 128, 224 MiB): the class is cut, in the variant's problem order,
- * into chunks whose working sets (u, u_tmp and the operator's arrays) stay
- * within the budget, and each chunk takes all its steps before the next
- * one starts, so that it runs out of the 256 MB last-level cache; 0 keeps
- * the class whole.  Every choice computes the same bits.  Synchronizes
- * `stream`. */
+ * one grouped launch (bits 0 and 2 together are not timed), 3 = two chunks
+ * in flight: chunks 2i and 2i + 1 take their steps at the same time on two
+ * streams (two branches of the captured graph), so that each step's launch
+ * tail overlaps the other chunk's work (not timed without chunks).  Chunk
+ * budgets (0, 64, 128, 224 MiB): the class is cut, in the variant's problem
+ * order, into chunks whose working sets (u, u_tmp and the operator's
+ * arrays) stay within the budget, and each chunk takes all its steps before
+ * the next one starts, so that it runs out of the 256 MB last-level cache
+ * (with bit 3, two chunks share it); 0 keeps the class whole.  Every choice
+ * computes the same bits.  Synchronizes `stream`. */
 int adlbr_batch_tune(adlbr_batch *batch, int steps, int use_cache, void *stream);
 /* The tuner's cache on disk (a JSON file, so that one process's timings
  * serve later ones):
@@ -267,7 +270,7 @@ int adlbr_batch_tune_load(const char *path);
 int adlbr_batch_tune_clear(void);
 int adlbr_batch_tune_lookup(int class_key, int64_t points, int nprob, int *found, int *variant,
                             size_t *chunk_bytes);
-/* Force launch variant (0..7) and chunk budget (bytes, 0 = no chunks; a
+/* Force launch variant (0..15) and chunk budget (bytes, 0 = no chunks; a
  * problem larger than the budget gets a chunk of its own) for class cls
  * instead of tuning.  Synchronizes `stream`; ADLBR_E_INVALID for a bad
  * class or variant. */

@@ -45,7 +45,9 @@ struct adlbr_batch {
     int nprob;
     std::vector<Class> classes;
     hipStream_t own;
+    hipStream_t side;  // the second chain of two chunks in flight (variant bit 3)
     hipEvent_t ev_in, ev_out;
+    std::vector<hipEvent_t> forks, joins;  // one pair per two-chunk group
     hipGraph_t graph;
     hipGraphExec_t exec;
     long long graph_steps;
@@ -56,8 +58,10 @@ namespace {
 
 // bit 0: XCD-contiguous blocks; bit 1: largest problems first; bit 2: one
 // launch per problem (in the variant's problem order) instead of one grouped
-// launch.  Each is timed with every chunk budget of kChunkMiB (0: no chunks).
-constexpr int kVariants = 8;
+// launch; bit 3: two chunks in flight, on two streams (parallel branches of
+// the graph), so that the tail of one chunk's step overlaps the other's.
+// Each is timed with every chunk budget of kChunkMiB (0: no chunks).
+constexpr int kVariants = 16;
 constexpr size_t kChunkMiB[4] = {0, 64, 128, 224};
 
 std::mutex g_cache_mu;
@@ -138,20 +142,63 @@ int launch_chunk(const adlbr_batch::Class &c, const adlbr_batch::Class::Chunk &k
                         parity, variant, copy, s);
 }
 
-// Chunk after chunk, every step of the chunk (u -> u_tmp -> u ...), and the
-// copy back into u after an odd count.
-int enqueue_steps(adlbr_batch *b, long long nsteps, hipStream_t s) {
-    for (auto &c : b->classes)
-        for (const auto &k : c.chunks) {
-            for (long long t = 0; t < nsteps; ++t) {
-                int rc = launch_chunk(c, k, (int)(t & 1), c.variant, 0, s);
-                if (rc) return rc;
-            }
-            if (nsteps & 1) {
-                int rc = launch_chunk(c, k, 0, c.variant, 1, s);
-                if (rc) return rc;
-            }
+// Every step of one chunk (u -> u_tmp -> u ...) and the copy back into u
+// after an odd count; with run = false (the tuner's timing) parity 0 only:
+// u is read and u_tmp written, nsteps times.
+int chunk_steps(const adlbr_batch::Class &c, const adlbr_batch::Class::Chunk &k, long long nsteps,
+                bool run, hipStream_t s) {
+    for (long long t = 0; t < nsteps; ++t) {
+        int rc = launch_chunk(c, k, run ? (int)(t & 1) : 0, c.variant, 0, s);
+        if (rc) return rc;
+    }
+    if (run && (nsteps & 1)) return launch_chunk(c, k, 0, c.variant, 1, s);
+    return ADLBR_OK;
+}
+
+// The chunks of one class, one after another on s; with bit 3, two at a
+// time: the second on the batch's side stream, forked from s and joined
+// back into it (separate problems, so the two chains share no data).
+int class_steps(adlbr_batch *b, const adlbr_batch::Class &c, long long nsteps, bool run,
+                hipStream_t s, size_t &group) {
+    const size_t nk = c.chunks.size();
+    const bool pair = (c.variant & 8) != 0;
+    for (size_t i = 0; i < nk; i += pair ? 2 : 1) {
+        if (!pair || i + 1 == nk) {
+            int rc = chunk_steps(c, c.chunks[i], nsteps, run, s);
+            if (rc) return rc;
+            continue;
         }
+        while (b->forks.size() <= group) {
+            hipEvent_t f = nullptr, j = nullptr;
+            if (hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+                if (f) (void)hipEventDestroy(f);
+                set_error("batch: event creation failed");
+                return ADLBR_E_HIP;
+            }
+            b->forks.push_back(f);
+            b->joins.push_back(j);
+        }
+        const hipEvent_t f = b->forks[group], j = b->joins[group];
+        ++group;
+        ADLBR_CHECK_HIP(hipEventRecord(f, s));
+        ADLBR_CHECK_HIP(hipStreamWaitEvent(b->side, f, 0));
+        int rc = chunk_steps(c, c.chunks[i], nsteps, run, s);
+        if (!rc) rc = chunk_steps(c, c.chunks[i + 1], nsteps, run, b->side);
+        ADLBR_CHECK_HIP(hipEventRecord(j, b->side));
+        ADLBR_CHECK_HIP(hipStreamWaitEvent(s, j, 0));
+        if (rc) return rc;
+    }
+    return ADLBR_OK;
+}
+
+// Class after class, chunk after chunk (or two at a time), every step.
+int enqueue_steps(adlbr_batch *b, long long nsteps, hipStream_t s) {
+    size_t group = 0;
+    for (auto &c : b->classes) {
+        int rc = class_steps(b, c, nsteps, true, s, group);
+        if (rc) return rc;
+    }
     return ADLBR_OK;
 }
 
@@ -214,7 +261,7 @@ extern "C" int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *c
         return ADLBR_E_NOMEM;
     }
     b->nprob = nprob;
-    b->own = nullptr;
+    b->own = b->side = nullptr;
     b->ev_in = b->ev_out = nullptr;
     b->graph = nullptr;
     b->exec = nullptr;
@@ -269,6 +316,7 @@ extern "C" int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *c
         if (rc) break;
     }
     if (!rc && (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
+                hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
                 hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)) {
         set_error("adlbr_batch_create: stream or event creation failed");
@@ -278,6 +326,7 @@ extern "C" int adlbr_batch_create(int nprob, adlbr_operator *const *ops, void *c
         if (b->ev_in) (void)hipEventDestroy(b->ev_in);
         if (b->ev_out) (void)hipEventDestroy(b->ev_out);
         if (b->own) (void)hipStreamDestroy(b->own);
+        if (b->side) (void)hipStreamDestroy(b->side);
         delete b;
         return rc;
     }
@@ -318,16 +367,18 @@ extern "C" int adlbr_batch_tune(adlbr_batch *b, int steps, int use_cache, void *
             if ((v & 4) && (v & 1)) continue;  // bit 0 has no meaning without a grouped launch
             // a budget that holds the whole class is the same as no chunking
             if (budget && class_bytes <= budget) continue;
+            if ((v & 8) && !budget) continue;  // one chunk: nothing to pair
             rc = upload(c, v, budget, s);
             if (rc) break;
-            // warm-up over all chunks, then `steps` steps chunk by chunk as a
-            // run takes them; parity 0 only: u is read, u_tmp written
+            // warm-up over all chunks, then `steps` steps of every chunk as a
+            // run takes them (bit 3: two chunks at a time); parity 0 only:
+            // u is read, u_tmp written
             for (const auto &k : c.chunks)
                 if (!rc) rc = launch_chunk(c, k, 0, v, 0, s);
             if (rc) break;
+            size_t group = 0;
             ADLBR_CHECK_HIP(hipEventRecord(e0, s));
-            for (const auto &k : c.chunks)
-                for (int t = 0; t < steps && !rc; ++t) rc = launch_chunk(c, k, 0, v, 0, s);
+            rc = class_steps(b, c, steps, false, s, group);
             ADLBR_CHECK_HIP(hipEventRecord(e1, s));
             ADLBR_CHECK_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -425,10 +476,14 @@ extern "C" int adlbr_batch_run(adlbr_batch *b, int64_t nsteps, int use_graph, vo
 extern "C" int adlbr_batch_destroy(adlbr_batch *b) {
     if (!b) return ADLBR_OK;
     if (b->own) (void)hipStreamSynchronize(b->own);
+    if (b->side) (void)hipStreamSynchronize(b->side);
     drop_graph(b);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    for (hipEvent_t e : b->forks) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->joins) (void)hipEventDestroy(e);
     if (b->own) (void)hipStreamDestroy(b->own);
+    if (b->side) (void)hipStreamDestroy(b->side);
     delete b;
     return ADLBR_OK;
 }

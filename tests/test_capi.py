@@ -103,7 +103,7 @@ def test_tuner_cache_file_round_trip(lib, tmp_path):
     # malformed files: refused, the cache unchanged
     for bad in ({"format": "something-else", "entries": []},
                 {"format": "adlbr-batch-tune", "entries": [{"class": 1, "log2_points": 3,
-                                                            "problems": 2, "variant": 9,
+                                                            "problems": 2, "variant": 16,
                                                             "chunk_bytes": 0}]},
                 {"format": "adlbr-batch-tune", "entries": [{"class": 1, "problems": 2,
                                                             "variant": 0, "chunk_bytes": 0}]}):

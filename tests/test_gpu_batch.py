@@ -72,10 +72,11 @@ def test_batch_every_variant_and_graph_replay(lib):
 
 
 @pytest.mark.parametrize("chunk_bytes", [0, 1, 300_000])
-@pytest.mark.parametrize("variant", range(8))
+@pytest.mark.parametrize("variant", range(16))
 def test_batch_forced_variant_bitwise(lib, variant, chunk_bytes):
     """Grouped or per-problem launches, in any block order, whole or cut into
-    chunks (1 byte: one problem per chunk), give the same bits."""
+    chunks (1 byte: one problem per chunk), one chunk at a time or two in
+    flight on two streams, give the same bits."""
     import torch
     ops, us = _problems(lib, torch.float32)
     ref = [u.clone() for u in us]
@@ -96,7 +97,7 @@ def test_batch_forced_variant_bitwise(lib, variant, chunk_bytes):
     for k, (u, r) in enumerate(zip(us, ref)):
         assert torch.equal(u, r), k
     with pytest.raises(Exception):
-        b.set_variant(0, 8)
+        b.set_variant(0, 16)
 
 
 def test_batch_absolute_dt_and_oracle(lib):
