@@ -61,9 +61,9 @@ TRAFFIC = {
     "c3-bf16": {"sha256": "d3676bd68fc79b0d9177c3b6e1408435c139997d6e3b8b38eb5babe7dfa33d52",
                 "bytes_per_launch": 1756668075},
     "c4": {"sha256": "d3676bd68fc79b0d9177c3b6e1408435c139997d6e3b8b38eb5babe7dfa33d52",
-           "bytes_per_launch": 8369979231},
+           "bytes_per_launch": 8376006510},
     "c4-norecords": {"sha256": "d3676bd68fc79b0d9177c3b6e1408435c139997d6e3b8b38eb5babe7dfa33d52",
-                     "bytes_per_launch": 7031863903},
+                     "bytes_per_launch": 7052699068},
 }
 TRAFFIC_SOURCES = ("paper_1301_3925_amd/csrc/operator.hip", "paper_1301_3925_amd/csrc/common.h")
 
