@@ -230,3 +230,36 @@ def test_records_need_the_list_layout(lib):
         lib.Operator(dims, off, w, storage=torch.float32, tiled=True, records=True)
     assert ei.value.code == lib.capi.E_UNSUPPORTED
 
+
+
+@pytest.mark.parametrize("variant", [8, 9, 10, 12])
+def test_two_chunks_in_flight_with_an_odd_chunk_count(lib, variant):
+    """One problem per chunk, two chunks in flight: three image operators
+    with records (a pair on the two streams, then the last chunk alone) and
+    two without (one pair), each set in a batch of its own; graph replays
+    and a direct run give the bits of single steps."""
+    import torch
+    ops, us = [], []
+    for k, dims in enumerate([(40, 31), (64, 17), (23, 50), (80, 40), (9, 70)]):
+        D = synth.tensor2d_field(300 + k, *dims, 20.0)
+        off, w, _ = lib.build_stencils(torch.from_numpy(D).cuda(), dims)
+        ops.append(lib.Operator(dims, off, w, storage=torch.float32, records=k % 2 == 0))
+        us.append(torch.from_numpy(synth.uniform(400 + k, int(np.prod(dims)))).float().cuda())
+    ref = [u.clone() for u in us]
+    for op, u in zip(ops, ref):
+        op.step(u, 0.9, 9, cfl_fraction=True)
+    rec = [k for k in range(5) if k % 2 == 0]
+    b = lib.Batch([ops[k] for k in rec], [us[k] for k in rec], dt=0.9, dt_mode="cfl")
+    b.set_variant(0, variant, 1)
+    assert b.variants()[0]["chunks"] == 3
+    b.run(4)
+    b.run(4)  # replay
+    b.run(1, graph=False)
+    b2 = lib.Batch([ops[k] for k in range(5) if k % 2], [us[k] for k in range(5) if k % 2],
+                   dt=0.9, dt_mode="cfl")
+    b2.set_variant(0, variant, 1)
+    assert b2.variants()[0]["chunks"] == 2
+    b2.run(9)
+    torch.cuda.synchronize()
+    for k, (u, r) in enumerate(zip(us, ref)):
+        assert torch.equal(u, r), k
