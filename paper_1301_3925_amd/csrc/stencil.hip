@@ -23,28 +23,46 @@ namespace {
 
 constexpr int kMaxIter = 200;
 
+// Both reductions run first in 32-bit integers, whose products and
+// coefficient sums are exact while every component stays within +-32767
+// (2 * 32767^2 < 2^31); a point whose reduction leaves that range is
+// reduced again, from the start, in 64-bit integers.  The coefficients are
+// the same integers either way, hence so are the doubles and every
+// decision taken from them.
+constexpr int kSmall = 32767;
+
 // ------------------------------------------------------------------- 2D --
 struct Form2 {
     double xx, xy, yy;
 };
 
-struct V2 {
-    ll x, y;
+template <typename I> struct V2T {
+    I x, y;
 };
+typedef V2T<ll> V2;
 
-__device__ __forceinline__ double form2(const Form2 &q, V2 a, V2 b) {
-    ll cxx = a.x * b.x;
-    ll cxy = a.x * b.y + a.y * b.x;
-    ll cyy = a.y * b.y;
+template <typename I> __device__ __forceinline__ double form2(const Form2 &q, V2T<I> a, V2T<I> b) {
+    const I cxx = a.x * b.x;
+    const I cxy = a.x * b.y + a.y * b.x;
+    const I cyy = a.y * b.y;
     return ((double)cxx * q.xx + (double)cxy * q.xy) + (double)cyy * q.yy;
 }
 
 // Lagrange: repeat (e, f) := (f, e - Round(<e,f>/<f,f>) f) while |e| > |f|.
-__device__ int reduce_pair2(const Form2 &q, V2 &e, V2 &f) {
+// Iterations used, -1 past kMaxIter, -2 when 32-bit integers overflow.
+template <typename I> __device__ int reduce_pair2(const Form2 &q, V2T<I> &e, V2T<I> &f) {
     for (int it = 1; it <= kMaxIter; ++it) {
         const double r = round(form2(q, e, f) / form2(q, f, f));
         const ll k = (ll)r;
-        const V2 g{e.x - k * f.x, e.y - k * f.y};
+        V2T<I> g;
+        if constexpr (sizeof(I) == 4) {
+            if (k < -kSmall || k > kSmall) return -2;
+            const int ki = (int)k;
+            g = V2T<I>{e.x - ki * f.x, e.y - ki * f.y};
+            if (g.x < -kSmall || g.x > kSmall || g.y < -kSmall || g.y > kSmall) return -2;
+        } else {
+            g = V2T<I>{e.x - k * f.x, e.y - k * f.y};
+        }
         e = f;
         f = g;
         if (!(form2(q, e, e) > form2(q, f, f))) return it;
@@ -67,7 +85,15 @@ __global__ void k_stencil2d(const TD *__restrict__ D, long long N, int16_t *__re
     } else {
         const Form2 q{dyy, -dxy, dxx};
         V2 e{1, 0}, f{0, 1};
-        if (reduce_pair2(q, e, f) < 0) st |= ADLBR_ST_ITER;
+        V2T<int> ei{1, 0}, fi{0, 1};
+        int red = reduce_pair2<int>(q, ei, fi);
+        if (red == -2) {
+            red = reduce_pair2<ll>(q, e, f);  // left the 32-bit range: again in 64 bits
+        } else {
+            e = V2{ei.x, ei.y};
+            f = V2{fi.x, fi.y};
+        }
+        if (red < 0) st |= ADLBR_ST_ITER;
         if (form2(q, e, f) > 0.0) f = V2{-f.x, -f.y};
         s[0] = e;
         s[1] = f;
@@ -104,17 +130,12 @@ struct Form3 {
     double xx, yy, zz, xy, xz, yz;
 };
 
-// Lattice vectors with integer components of type I.  The reduction runs
-// first in 32-bit integers, whose products and coefficient sums are exact
-// while every component stays within +-32767 (|2 * 32767^2| < 2^31); a
-// point whose reduction leaves that range is reduced again in 64-bit
-// integers.  Either way the coefficients, hence the doubles and every
-// decision, are the same as the 64-bit reduction's.
+// Lattice vectors with integer components of type I (32-bit first, see
+// kSmall).
 template <typename I> struct V3T {
     I x, y, z;
 };
 typedef V3T<ll> V3;
-constexpr int kSmall = 32767;
 
 template <typename I>
 __device__ __forceinline__ double form3(const Form3 &q, const V3T<I> &a, const V3T<I> &b) {

@@ -73,6 +73,20 @@ def test_random_tensors_2d(lib, kmax):
     _check(lib, D, (200, 100))
 
 
+@pytest.mark.parametrize("kmax", [1e5, 1e7])
+def test_extreme_anisotropy_2d(lib, kmax):
+    """Reduced bases with components in the thousands and, at kappa = 1e7,
+    beyond +-32767: there the 32-bit reduction overflows and the point is
+    reduced again in 64-bit integers (and its offsets leave int16: status
+    RANGE); offsets, weights and status still match the oracle."""
+    D = synth.random_spd2(100 + int(kmax), 20000, kmax)
+    off, _ = _check(lib, D, (200, 100))
+    assert np.abs(off).max() > 3000
+    if kmax >= 1e7:
+        b, _ = oracle.reduce2d(D)
+        assert (np.abs(b).max((0, 1)) > 32767).sum() >= 1  # the 64-bit path ran
+
+
 def test_rational_and_tie_tensors_2d(lib):
     """Exact rationals and exact ties (D = Id, axis-aligned, the
     spectral-figure tensor, 2 mu = lambda_1^2 ties): identical decisions."""
